@@ -1,0 +1,198 @@
+"""FP64 CPU oracle for the OpenFPM particle hot path (arXiv 1804.07598).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, the smoke check and the bench's
+CPU-baseline leg, never by the product package.  The C sources next to this
+file are compiled with gcc (see build.py) and loaded with ctypes.  Nothing here
+shares code with the HIP library.
+
+Functions take numpy arrays in the caller's particle order:
+positions (n, 3) float32 (the FP32 values the GPU sees, promoted exactly) or
+float64 for the oracle's own FP64 trajectories; box L (3,) float32 with origin
+0; per (3,) int periodic flags; pair tables eps/sig of 3 entries (AA, AB, BB).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+f32p = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
+f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+
+
+def _opt(ptype):
+    """ndpointer that also accepts None (NULL)."""
+    class _P(ptype):  # type: ignore[misc, valid-type]
+        @classmethod
+        def from_param(cls, obj):
+            if obj is None:
+                return None
+            return ptype.from_param(obj)
+    return _P
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = C.CDLL(_LIB_PATH)
+        L.oracle_radius2_f32.restype = C.c_float
+        L.oracle_radius2_f32.argtypes = [C.c_float, C.c_float]
+        L.oracle_cell_grid.argtypes = [f32p, C.c_float, C.c_float, i32p]
+        L.oracle_cell_index.argtypes = [C.c_int64, f32p, f32p, i32p, i32p]
+        L.oracle_cell_sort.argtypes = [C.c_int64, i32p, C.c_int32, i32p, i32p, i32p]
+        L.oracle_neighbors.restype = C.c_int
+        L.oracle_neighbors.argtypes = [C.c_int64, f32p, f32p, i32p, C.c_float, _opt(i64p),
+                                       C.c_int64, i32p, i32p, C.c_int64]
+        L.oracle_max_disp2.restype = C.c_float
+        L.oracle_max_disp2.argtypes = [C.c_int64, f32p, f32p, f32p, i32p]
+        L.oracle_lj_rows.argtypes = [C.c_int64, f32p, _opt(i32p), f32p, i32p, C.c_float, f64p,
+                                     f64p, _opt(i64p), C.c_int64, f64p, _opt(f64p), _opt(f64p)]
+        L.oracle_lj_virial_scale.restype = C.c_double
+        L.oracle_lj_virial_scale.argtypes = [C.c_int64, f32p, _opt(i32p), f32p, i32p, C.c_float,
+                                             f64p, f64p]
+        L.oracle_vv.argtypes = [C.c_int64, f64p, f64p, _opt(i32p), f64p, i32p, C.c_double, f64p,
+                                f64p, C.c_double, C.c_double, C.c_int32, _opt(f64p)]
+        L.oracle_lj_forces_f64.argtypes = [C.c_int64, f64p, _opt(i32p), f64p, i32p, C.c_double,
+                                           f64p, f64p, f64p, f64p]
+        if hasattr(L, "oracle_sph_rows"):
+            L.oracle_sph_rows.argtypes = [C.c_int64, f32p, f32p, f32p, i32p, f32p, i32p, C.c_float,
+                                          f64p, _opt(i64p), C.c_int64, f64p, f64p, f64p]
+            L.oracle_sph_kernel_w.restype = C.c_double
+            L.oracle_sph_kernel_w.argtypes = [C.c_double, C.c_double]
+        if hasattr(L, "oracle_lj_vjp"):
+            L.oracle_lj_vjp.argtypes = [C.c_int64, f32p, _opt(i32p), f32p, i32p, C.c_float, f64p,
+                                        f64p, f64p, f64p, f64p]
+            L.oracle_traj_adjoint.restype = C.c_double
+            L.oracle_traj_adjoint.argtypes = [C.c_int64, f64p, f64p, _opt(i32p), f64p, i32p,
+                                              C.c_double, f64p, f64p, C.c_double, C.c_double,
+                                              C.c_int32, C.c_int32, f64p, f64p, f64p]
+        _lib = L
+    return _lib
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _per(per):
+    return _i32(np.broadcast_to(np.asarray(per, dtype=np.int32), (3,)))
+
+
+def _box(L):
+    return _f32(np.broadcast_to(np.asarray(L, dtype=np.float32), (3,)))
+
+
+def radius2(r_cut: float, skin: float = 0.0) -> np.float32:
+    """R^2 rounded once to FP32 from (r_cut + skin) in FP64."""
+    return np.float32(lib().oracle_radius2_f32(float(np.float32(r_cut)), float(np.float32(skin))))
+
+
+def cell_grid(L, r_cut: float, skin: float = 0.0) -> np.ndarray:
+    out = np.zeros(3, np.int32)
+    lib().oracle_cell_grid(_box(L), float(np.float32(r_cut)), float(np.float32(skin)), out)
+    return out
+
+
+def cell_index(pos, L, ncell) -> np.ndarray:
+    pos = _f32(pos)
+    out = np.empty(len(pos), np.int32)
+    lib().oracle_cell_index(len(pos), pos, _box(L), _i32(ncell), out)
+    return out
+
+
+def cell_sort(cid, ncells: int):
+    """(counts, offsets, order) of a stable counting sort by cell."""
+    cid = _i32(cid)
+    counts = np.empty(ncells, np.int32)
+    offsets = np.empty(ncells + 1, np.int32)
+    order = np.empty(len(cid), np.int32)
+    lib().oracle_cell_sort(len(cid), cid, int(ncells), counts, offsets, order)
+    return counts, offsets, order
+
+
+def neighbors(pos, L, per, R2, rows=None, cap: int = 512):
+    """Brute-force neighbour sets: (counts, cols (nrows, cap)) in ascending j.
+
+    Raises OverflowError if a row has more than cap neighbours."""
+    pos = _f32(pos)
+    nr = len(pos) if rows is None else len(rows)
+    rows_a = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    counts = np.empty(nr, np.int32)
+    cols = np.full((nr, cap), -1, np.int32)
+    rc = lib().oracle_neighbors(len(pos), pos, _box(L), _per(per), float(np.float32(R2)), rows_a,
+                                nr, counts, cols, cap)
+    if rc != 0:
+        raise OverflowError("neighbour cap exceeded")
+    return counts, cols
+
+
+def neighbor_sets(pos, L, per, R2, rows=None, cap: int = 512):
+    counts, cols = neighbors(pos, L, per, R2, rows, cap)
+    return [tuple(cols[r, :counts[r]].tolist()) for r in range(len(counts))]
+
+
+def max_disp2(pos, ref, L, per) -> np.float32:
+    pos, ref = _f32(pos), _f32(ref)
+    return np.float32(lib().oracle_max_disp2(len(pos), pos, ref, _box(L), _per(per)))
+
+
+def lj(pos, L, per, rc2, eps=(1.0, 1.0, 1.0), sig=(1.0, 1.0, 1.0), typ=None, rows=None):
+    """FP64 LJ on the FP32 pair set.  Returns (F rows x 3, U total, W total (6,),
+    U per row, W per row).  Totals cover the requested rows only."""
+    pos = _f32(pos)
+    nr = len(pos) if rows is None else len(rows)
+    rows_a = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    F = np.empty((nr, 3), np.float64)
+    U = np.empty(nr, np.float64)
+    W = np.empty((nr, 6), np.float64)
+    lib().oracle_lj_rows(len(pos), pos, None if typ is None else _i32(typ), _box(L), _per(per),
+                         float(np.float32(rc2)), _f64(eps), _f64(sig), rows_a, nr, F, U, W)
+    return F, float(U.sum()), W.sum(axis=0), U, W
+
+
+def lj_virial_scale(pos, L, per, rc2, eps=(1.0, 1.0, 1.0), sig=(1.0, 1.0, 1.0), typ=None) -> float:
+    pos = _f32(pos)
+    return float(lib().oracle_lj_virial_scale(len(pos), pos, None if typ is None else _i32(typ),
+                                              _box(L), _per(per), float(np.float32(rc2)),
+                                              _f64(eps), _f64(sig)))
+
+
+def lj_forces_f64(x, L, per, rc, eps=(1.0, 1.0, 1.0), sig=(1.0, 1.0, 1.0), typ=None):
+    """FP64 forces of FP64 positions with an FP64 cut-off test: (F, U)."""
+    x = _f64(x)
+    F = np.empty_like(x)
+    U = np.zeros(1, np.float64)
+    lib().oracle_lj_forces_f64(len(x), x, None if typ is None else _i32(typ),
+                               _f64(np.broadcast_to(np.asarray(L, np.float64), (3,))), _per(per),
+                               float(rc), _f64(eps), _f64(sig), F, U)
+    return F, float(U[0])
+
+
+def vv(x, v, L, per, rc, dt, nsteps, eps=(1.0, 1.0, 1.0), sig=(1.0, 1.0, 1.0), typ=None,
+       mass: float = 1.0):
+    """FP64 velocity-Verlet trajectory.  Returns (x, v, thermo (nsteps+1, 2) = [U, KE])."""
+    x = _f64(x).copy()
+    v = _f64(v).copy()
+    thermo = np.empty((nsteps + 1, 2), np.float64)
+    lib().oracle_vv(len(x), x, v, None if typ is None else _i32(typ),
+                    _f64(np.broadcast_to(np.asarray(L, np.float64), (3,))), _per(per), float(rc),
+                    _f64(eps), _f64(sig), float(mass), float(dt), int(nsteps), thermo)
+    return x, v, thermo

@@ -1,0 +1,167 @@
+"""Seeded synthetic inputs shared by the tests, the bench and the smoke run.
+
+This module only draws and lays out input arrays; it contains none of the
+method's arithmetic (no neighbour search, no pair interaction, no time
+stepping).  Both the FP64 CPU oracle and the HIP path consume its output.
+
+Recipes (paper section 4.1 starts the LJ fluid on a regular Cartesian lattice;
+section 4.2 starts SPH from a fluid column resting on boundary particles):
+
+* LJ lattice: box side L64 = (N/rho)^(1/3) rounded once to FP32 (that FP32
+  value is *the* box for everyone); n = ceil(N^(1/3)) sites per axis, spacing
+  a = L32/n; site (i+1/2)*a plus a U(-jitter, +jitter) offset per coordinate,
+  computed in FP64 and rounded once to FP32.  When N < n^3 a random subset of
+  the n^3 sites is kept (in lattice order).  Draw order: site subset, jitter,
+  velocities, types.
+* Velocities: N(0, sqrt(T/m)) per component in FP64, minus the mean, rescaled
+  so that 2 KE / (3N - 3) = T exactly, then rounded to FP32.
+* Binary mixture: exactly N/2 particles of type 0 (A) and N - N/2 of type 1 (B)
+  chosen by a random permutation.
+* SPH column: a fluid lattice nf x nf x nz at spacing dx over a three-layer
+  floor of boundary particles, periodic in x and y, hydrostatic density.
+
+All generators use numpy.random.Generator(PCG64(seed)).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+__all__ = [
+    "LJSystem", "lj_lattice", "lj_config", "batched_table", "batched_system",
+    "SPHSystem", "sph_column", "LJ_CONFIGS",
+]
+
+
+@dataclasses.dataclass
+class LJSystem:
+    """One periodic LJ system in the caller's (original) particle order."""
+    pos: np.ndarray      # (N, 3) float32, in [0, L)
+    vel: np.ndarray      # (N, 3) float32
+    typ: np.ndarray      # (N,) int32, 0 = A, 1 = B
+    L: float             # FP32-representable box side (cubic)
+    seed: int
+    rho: float
+    T: float
+
+    @property
+    def n(self) -> int:
+        return int(self.pos.shape[0])
+
+    @property
+    def box(self) -> np.ndarray:
+        return np.full(3, self.L, dtype=np.float32)
+
+
+def _box_side(n: int, rho: float) -> float:
+    return float(np.float32((n / rho) ** (1.0 / 3.0)))
+
+
+def lj_lattice(n: int, rho: float, T: float, seed: int, *, jitter: float = 0.05,
+               mixture: bool = False, mass: float = 1.0) -> LJSystem:
+    """Jittered simple-cubic lattice with Gaussian velocities (recipe above)."""
+    if n < 2:
+        raise ValueError("need at least two particles")
+    rng = np.random.Generator(np.random.PCG64(seed))
+    L32 = _box_side(n, rho)
+    m = int(round(n ** (1.0 / 3.0)))
+    if m ** 3 < n:
+        m += 1
+    a = L32 / m
+    idx = np.indices((m, m, m)).reshape(3, -1).T  # x slowest
+    if m ** 3 != n:
+        keep = np.sort(rng.permutation(m ** 3)[:n])
+        idx = idx[keep]
+    sites = (idx.astype(np.float64) + 0.5) * a
+    sites += rng.uniform(-jitter, jitter, size=sites.shape)
+    pos = sites.astype(np.float32)
+    # guard the half-open box (never triggers for jitter < a/2)
+    pos = np.where(pos >= np.float32(L32), pos - np.float32(L32), pos)
+    pos = np.where(pos < 0, pos + np.float32(L32), pos).astype(np.float32)
+
+    v = rng.normal(0.0, math.sqrt(T / mass), size=(n, 3))
+    v -= v.mean(axis=0)
+    ke = 0.5 * mass * float((v * v).sum())
+    v *= math.sqrt(T / (2.0 * ke / (3 * n - 3)))
+    vel = v.astype(np.float32)
+
+    typ = np.zeros(n, dtype=np.int32)
+    if mixture:
+        perm = rng.permutation(n)
+        typ[perm[n // 2:]] = 1
+    return LJSystem(pos=pos, vel=vel, typ=typ, L=L32, seed=seed, rho=rho, T=T)
+
+
+# The five workloads.  Sizes follow the LJ benchmark of section 4.1 (a jittered
+# lattice liquid), the SPH column of section 4.2, a batch of independent boxes
+# and a binary mixture for the differentiable form.
+LJ_CONFIGS = {
+    "lj4096": dict(n=4096, rho=0.8442, T=1.0, seed=1),
+    "lj1m": dict(n=1_000_000, rho=0.8442, T=1.0, seed=2),
+    "mix32k": dict(n=32768, rho=1.2, T=1.0, seed=5, mixture=True),
+}
+
+# Pair tables in upper-triangular order (AA, AB, BB).
+LJ_SINGLE = dict(eps=(1.0, 1.0, 1.0), sig=(1.0, 1.0, 1.0))
+LJ_MIXTURE = dict(eps=(1.0, 1.5, 0.5), sig=(1.0, 0.8, 0.88))
+
+
+def lj_config(name: str) -> LJSystem:
+    return lj_lattice(**LJ_CONFIGS[name])
+
+
+def batched_table(n_sys: int = 512, seed: int = 4):
+    """(N_s, rho_s, T_s) for the batch of independent boxes."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ns = rng.integers(256, 8193, size=n_sys).astype(np.int64)
+    rhos = rng.uniform(0.6, 0.9, size=n_sys)
+    Ts = rng.uniform(0.8, 1.5, size=n_sys)
+    return ns, rhos, Ts
+
+
+def batched_system(s: int, ns, rhos, Ts) -> LJSystem:
+    return lj_lattice(int(ns[s]), float(rhos[s]), float(Ts[s]), 4000 + s)
+
+
+@dataclasses.dataclass
+class SPHSystem:
+    pos: np.ndarray      # (N, 3) float32
+    vel: np.ndarray      # (N, 3) float32
+    rho: np.ndarray      # (N,) float32
+    kind: np.ndarray     # (N,) int32, 0 = fluid, 1 = boundary
+    L: np.ndarray        # (3,) float32 box extent; x, y periodic, z not
+    dx: float
+    H: float             # fluid column height
+
+
+def sph_column(nf: int = 128, nz: int | None = None, dx: float = 0.01, *,
+               n_floor: int = 3, headroom: int = 32, rho0: float = 1000.0,
+               g: float = 9.81, gamma: float = 7.0, c0_factor: float = 20.0) -> SPHSystem:
+    """Fluid column of nf x nf x nz particles on an n_floor-layer floor.
+
+    The floor occupies z in [0, n_floor*dx); fluid particles start at
+    z = n_floor*dx + (k + 1/2) dx.  Density is set hydrostatically from the
+    Tait equation of state (section 4.2, Eqs. 3-4) with the sound speed
+    c0 = c0_factor * sqrt(g H) and b = c0^2 rho0 / gamma, so that the initial
+    pressure is rho0 g (H - z') at height z' above the floor.
+    """
+    nz = nf if nz is None else nz
+    H = nz * dx
+    c0 = c0_factor * math.sqrt(g * H)
+    b = c0 * c0 * rho0 / gamma
+    ii = (np.arange(nf) + 0.5) * dx
+    zf = n_floor * dx + (np.arange(nz) + 0.5) * dx
+    zb = (np.arange(n_floor) + 0.5) * dx
+    X, Y, Z = np.meshgrid(ii, ii, zf, indexing="ij")
+    fluid = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    Xb, Yb, Zb = np.meshgrid(ii, ii, zb, indexing="ij")
+    bnd = np.stack([Xb.ravel(), Yb.ravel(), Zb.ravel()], axis=1)
+    pos64 = np.concatenate([fluid, bnd], axis=0)
+    kind = np.concatenate([np.zeros(len(fluid), np.int32), np.ones(len(bnd), np.int32)])
+    depth = H - (pos64[:, 2] - n_floor * dx)
+    rho = rho0 * (1.0 + rho0 * g * depth / b) ** (1.0 / gamma)
+    L = np.array([nf * dx, nf * dx, (n_floor + nz + headroom) * dx], dtype=np.float32)
+    return SPHSystem(pos=pos64.astype(np.float32), vel=np.zeros_like(pos64, dtype=np.float32),
+                     rho=rho.astype(np.float32), kind=kind, L=L, dx=dx, H=H)
