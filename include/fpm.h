@@ -1,0 +1,186 @@
+/*
+ * fpm.h -- C ABI of the MI355X particle hot path (OpenFPM, arXiv 1804.07598).
+ *
+ * The library implements, in hand-written HIP kernels for gfx950, the
+ * data-parallel core of the paper's particle codes: cell lists and Verlet
+ * lists (section 2, refs [45, 46]), the Lennard-Jones interaction of the MD
+ * client (section 4.1 and its listing), the weakly compressible SPH sums of
+ * section 4.2 (Eqs. 1-5) and velocity-Verlet time stepping (section 4.1).
+ * Periodic images take the place of the paper's ghost layers: everything runs
+ * on one device.
+ *
+ * Conventions for every entry point
+ *  - Return value: FPM_OK (0) or a negative FPM_E* code; fpm_last_error()
+ *    gives a message.  No C++ exception crosses this interface.
+ *  - Pointers named d_* are device pointers; h_* are host pointers.  The
+ *    library never frees caller memory and never keeps a caller pointer beyond
+ *    the call, except the workspace (fpm_set_workspace) which it borrows until
+ *    fpm_destroy or the next fpm_set_workspace.
+ *  - The library allocates no device memory: the caller queries
+ *    fpm_workspace_size() and hands in one buffer.
+ *  - All device work is enqueued asynchronously on the stream given to
+ *    fpm_create (a hipStream_t passed as void*; NULL = the null stream).
+ *    Results in device memory are valid once the stream has been synchronised.
+ *    Only fpm_check and fpm_read_counters synchronise.
+ *  - Particle arrays in the caller's order are (n, 3) row-major float32.
+ *    Inside the library particles live in cell-sorted order; the caller's
+ *    order is restored by fpm_get_particles.
+ *  - The box is [0, L[0]) x [0, L[1]) x [0, L[2]); periodic axes wrap.
+ *    Positions are wrapped into the box at every neighbour-list rebuild;
+ *    between rebuilds a particle may sit up to skin/2 outside a periodic face.
+ *
+ * Neighbour sets are defined in FP32, identically for every kernel: per axis
+ * t = xj - xi; on a periodic axis, if t > L/2 the image (xj - L) - xi is used,
+ * if t < -L/2 the image xj - (xi - L), otherwise t; then
+ * d2 = (dx*dx + dy*dy) + dz*dz with every operation rounded separately (no
+ * fused multiply-add), and j != i is a neighbour iff d2 <= R2, where R2 is
+ * (r_cut + skin)^2 evaluated in FP64 and rounded once to FP32 (the listing of
+ * section 4.1 rejects a pair only when rn > r_cut2).  Pair physics is then
+ * evaluated in FP64 from the exact separation of the FP32 coordinates.
+ */
+#ifndef FPM_H
+#define FPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FPM_OK 0
+#define FPM_EINVAL (-1)     /* bad argument, call order or non-finite input */
+#define FPM_EHIP (-2)       /* HIP runtime error; message kept */
+#define FPM_ECUTOFF (-3)    /* r_cut + skin >= L/2 on a periodic axis */
+#define FPM_EOVERFLOW (-4)  /* a Verlet list exceeded max_nbr; lists invalid */
+#define FPM_ENOWS (-5)      /* workspace missing or too small */
+#define FPM_ENONFINITE (-6) /* a position or force became NaN/Inf */
+
+typedef struct fpm_ctx fpm_ctx;
+
+/* Pair table of the Lennard-Jones potential of section 4.1,
+ * V(r) = 4 eps ((sig/r)^12 - (sig/r)^6), truncated (not shifted) at r_cut.
+ * Entries are in upper-triangular order AA, AB, BB; with n_types == 1 only
+ * entry 0 is used.  Particle type is 0 (A) or 1 (B). */
+typedef struct {
+    int32_t n_types; /* 1 or 2 */
+    float eps[3];
+    float sig[3];
+} fpm_lj_params;
+
+/* Weakly compressible SPH of section 4.2 (Eqs. 1-5) with a Wendland C2
+ * kernel of support 2h.  Boundary particles (kind 1) enter every sum and
+ * evolve their density by Eq. 2, but do not move. */
+typedef struct {
+    float h;        /* smoothing length; neighbours within 2h (r_cut = 2h) */
+    float mass;     /* particle mass */
+    float rho0;     /* reference density of Eq. 3 */
+    float c0;       /* sound speed; Eq. 4 gives b = c0^2 rho0 / gamma */
+    float gamma;    /* Tait exponent (7) */
+    float alpha;    /* artificial-viscosity coefficient of Eq. 5 */
+    float eta2;     /* eta^2 of Eq. 5's mu (absolute, length^2) */
+    float g[3];     /* body acceleration (gravity) */
+    float cfl;      /* CFL factor of the dynamic time step */
+} fpm_sph_params;
+
+/* ---- context (the library-start/finish calls of the section 4.1 listing) ---- */
+
+/* Creates a context bound to `stream` (a hipStream_t, or NULL). */
+int fpm_create(fpm_ctx **out, void *stream);
+/* Destroys the context and any captured graphs; waits for its stream. */
+int fpm_destroy(fpm_ctx *ctx);
+/* Message of the last error on this context (never NULL). */
+const char *fpm_last_error(const fpm_ctx *ctx);
+
+/* ---- problem definition (the Box / bc / Ghost objects of the listing) ---- */
+
+/* Box side lengths (FP32, > 0) and periodic flags (0/1) per axis. */
+int fpm_set_box(fpm_ctx *ctx, const float h_L[3], const int32_t h_periodic[3]);
+/* Interaction radius, Verlet skin and Verlet-list capacity per particle.
+ * The list radius is r_cut + skin; cells are the largest grid whose side is
+ * >= that radius.  Returns FPM_ECUTOFF when r_cut + skin >= L/2 on a periodic
+ * axis, FPM_EINVAL for max_nbr outside [1, 4096]. */
+int fpm_set_neighbor_params(fpm_ctx *ctx, float r_cut, float skin, int32_t max_nbr);
+/* Bytes of device workspace needed for n particles with the current box and
+ * neighbour parameters (n <= 2^26 - 1). */
+int fpm_workspace_size(fpm_ctx *ctx, int64_t n, size_t *h_bytes);
+/* Lends the workspace (device memory, 256-byte aligned, >= the queried size
+ * for the n later passed to fpm_set_particles). */
+int fpm_set_workspace(fpm_ctx *ctx, void *d_ws, size_t bytes);
+
+/* ---- particles (the vector_dist of the listing) ---- */
+
+/* Copies n particles in (device arrays, caller order): positions inside the
+ * box, velocities (may be NULL = zero) and types (NULL = all 0; SPH: kind,
+ * 0 fluid / 1 boundary).  Builds the cell list and Verlet list. */
+int fpm_set_particles(fpm_ctx *ctx, int64_t n, const float *d_pos, const float *d_vel,
+                      const int32_t *d_type);
+/* SPH only: per-particle density (device, caller order, n entries). */
+int fpm_set_density(fpm_ctx *ctx, const float *d_rho);
+/* Gathers the state back into caller order; any pointer may be NULL.
+ * d_frc receives the last computed forces (LJ) or accelerations (SPH);
+ * d_rho the SPH density, d_drho its rate. */
+int fpm_get_particles(fpm_ctx *ctx, float *d_pos, float *d_vel, float *d_frc);
+int fpm_get_sph(fpm_ctx *ctx, float *d_rho, float *d_drho);
+
+/* ---- neighbour structures (getCellListSym / updateCellListSym) ---- */
+
+/* Wraps positions into the box and rebuilds the cell list: cell index per
+ * particle, per-cell counts, their exclusive prefix sum and a stable
+ * reordering of particles by cell (ties in ascending caller index). */
+int fpm_build_cell_list(fpm_ctx *ctx);
+/* Cell list in caller terms: d_offsets[ncells + 1] (exclusive scan of
+ * counts) and d_order[n] (slot -> caller index).  h_ncell receives the grid. */
+int fpm_get_cell_list(fpm_ctx *ctx, int32_t h_ncell[3], int32_t *d_offsets, int32_t *d_order);
+/* Rebuilds the Verlet list (radius r_cut + skin) from the current cell list. */
+int fpm_build_verlet(fpm_ctx *ctx);
+/* Verlet list in caller indices: d_counts[n], d_cols[n * max_nbr] (row i
+ * holds the neighbours of caller particle i, unordered).  Returns
+ * FPM_EOVERFLOW if the last build overflowed. */
+int fpm_get_neighbors(fpm_ctx *ctx, int32_t *d_counts, int32_t *d_cols);
+
+/* ---- interactions (applyKernel_in over the Verlet list) ---- */
+
+/* Lennard-Jones forces on all particles from the current Verlet list, with
+ * d_out[8] = {U, 0, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz} in FP64 (U = potential
+ * energy, W = sum over pairs of r (x) F).  Forces are kept in the context. */
+int fpm_lj_forces(fpm_ctx *ctx, const fpm_lj_params *prm, double *d_out);
+
+/* ---- time stepping (the getV kick/drift expressions of the listing) ---- */
+
+/* One half of velocity Verlet with unit mass: half == 0 applies
+ * v += dt/2 F; x += dt v (and updates the rebuild flag); half == 1 applies
+ * v += dt/2 F. */
+int fpm_integrate(fpm_ctx *ctx, float dt, int32_t half);
+/* nsteps full velocity-Verlet steps with automatic Verlet-list rebuilds when
+ * the largest displacement since the last build exceeds skin/2, all on the
+ * device (graph-launched, no host synchronisation).  d_thermo, if not NULL,
+ * receives nsteps rows of 8 FP64 values {U, KE, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz}
+ * for the state after each step. */
+int fpm_step(fpm_ctx *ctx, const fpm_lj_params *prm, float dt, int32_t nsteps,
+             double *d_thermo);
+
+/* ---- SPH (section 4.2) ---- */
+
+/* Rates of Eqs. 1-2 at the current state: accelerations (kept as forces) and
+ * density rates; d_dt[1] (FP32, may be NULL) receives the CFL time step
+ * dt = cfl * min(min_a sqrt(h/|f_a|), h / (c0 + max_ab |mu_ab|)). */
+int fpm_sph_rates(fpm_ctx *ctx, const fpm_sph_params *prm, float *d_dt);
+/* nsteps kick-drift-kick steps with the dynamic dt on the device;
+ * d_hist (may be NULL) receives nsteps FP64 rows {t, dt, KE, max|v|}. */
+int fpm_sph_step(fpm_ctx *ctx, const fpm_sph_params *prm, int32_t nsteps, double *d_hist);
+
+/* ---- status ---- */
+
+/* Synchronises the stream and reports device-side flags: FPM_EOVERFLOW if a
+ * list overflowed, FPM_ENONFINITE if a non-finite value was seen. */
+int fpm_check(fpm_ctx *ctx);
+/* Synchronises and reads counters: h_out[0] = rebuilds so far,
+ * h_out[1] = largest Verlet-list length seen in the last build,
+ * h_out[2] = total Verlet-list entries of the last build. */
+int fpm_read_counters(fpm_ctx *ctx, int64_t h_out[3]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FPM_H */

@@ -1,0 +1,216 @@
+"""ctypes binding of libfpm.so (include/fpm.h).  Argument marshalling only.
+
+Every function here has the name of the C entry point it calls and raises
+FpmError on a non-zero return code.  Device pointers are passed as integers
+(torch.Tensor.data_ptr()).  There is no fallback: if the library is not built,
+loading raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfpm.so")
+
+FPM_OK = 0
+FPM_EINVAL = -1
+FPM_EHIP = -2
+FPM_ECUTOFF = -3
+FPM_EOVERFLOW = -4
+FPM_ENOWS = -5
+FPM_ENONFINITE = -6
+_NAMES = {FPM_EINVAL: "FPM_EINVAL", FPM_EHIP: "FPM_EHIP", FPM_ECUTOFF: "FPM_ECUTOFF",
+          FPM_EOVERFLOW: "FPM_EOVERFLOW", FPM_ENOWS: "FPM_ENOWS",
+          FPM_ENONFINITE: "FPM_ENONFINITE"}
+
+
+class FpmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class fpm_lj_params(C.Structure):
+    _fields_ = [("n_types", C.c_int32), ("eps", C.c_float * 3), ("sig", C.c_float * 3)]
+
+
+class fpm_sph_params(C.Structure):
+    _fields_ = [("h", C.c_float), ("mass", C.c_float), ("rho0", C.c_float), ("c0", C.c_float),
+                ("gamma", C.c_float), ("alpha", C.c_float), ("eta2", C.c_float),
+                ("g", C.c_float * 3), ("cfl", C.c_float)]
+
+
+_P = C.c_void_p
+_SIGS = {
+    "fpm_create": [C.POINTER(_P), _P],
+    "fpm_destroy": [_P],
+    "fpm_set_box": [_P, C.POINTER(C.c_float), C.POINTER(C.c_int32)],
+    "fpm_set_neighbor_params": [_P, C.c_float, C.c_float, C.c_int32],
+    "fpm_workspace_size": [_P, C.c_int64, C.POINTER(C.c_size_t)],
+    "fpm_set_workspace": [_P, _P, C.c_size_t],
+    "fpm_set_particles": [_P, C.c_int64, _P, _P, _P],
+    "fpm_set_density": [_P, _P],
+    "fpm_get_particles": [_P, _P, _P, _P],
+    "fpm_get_sph": [_P, _P, _P],
+    "fpm_build_cell_list": [_P],
+    "fpm_get_cell_list": [_P, C.POINTER(C.c_int32), _P, _P],
+    "fpm_build_verlet": [_P],
+    "fpm_get_neighbors": [_P, _P, _P],
+    "fpm_lj_forces": [_P, C.POINTER(fpm_lj_params), _P],
+    "fpm_integrate": [_P, C.c_float, C.c_int32],
+    "fpm_step": [_P, C.POINTER(fpm_lj_params), C.c_float, C.c_int32, _P],
+    "fpm_sph_rates": [_P, C.POINTER(fpm_sph_params), _P],
+    "fpm_sph_step": [_P, C.POINTER(fpm_sph_params), C.c_int32, _P],
+    "fpm_check": [_P],
+    "fpm_read_counters": [_P, C.POINTER(C.c_int64)],
+}
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libfpm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                              "python paper_1804_07598_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            if not hasattr(L, name):
+                continue
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        L.fpm_last_error.argtypes = [_P]
+        L.fpm_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def exported_symbols(L=None):
+    L = L or lib()
+    return [n for n in list(_SIGS) + ["fpm_last_error"] if hasattr(L, n)]
+
+
+def _call(name: str, ctx, *args) -> int:
+    L = lib()
+    rc = getattr(L, name)(ctx, *args)
+    if rc != FPM_OK:
+        msg = L.fpm_last_error(ctx).decode() if ctx else "null context"
+        raise FpmError(rc, f"{name}: {msg}")
+    return rc
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else int(t.data_ptr())
+
+
+def fpm_create(stream: int = 0):
+    ctx = _P()
+    rc = lib().fpm_create(C.byref(ctx), _P(stream) if stream else None)
+    if rc != FPM_OK:
+        raise FpmError(rc, "fpm_create")
+    return ctx
+
+
+def fpm_destroy(ctx):
+    lib().fpm_destroy(ctx)
+
+
+def fpm_last_error(ctx) -> str:
+    return lib().fpm_last_error(ctx).decode()
+
+
+def fpm_set_box(ctx, L, periodic):
+    Lc = (C.c_float * 3)(*[float(x) for x in L])
+    pc = (C.c_int32 * 3)(*[int(x) for x in periodic])
+    _call("fpm_set_box", ctx, Lc, pc)
+
+
+def fpm_set_neighbor_params(ctx, r_cut: float, skin: float, max_nbr: int):
+    _call("fpm_set_neighbor_params", ctx, float(r_cut), float(skin), int(max_nbr))
+
+
+def fpm_workspace_size(ctx, n: int) -> int:
+    out = C.c_size_t(0)
+    _call("fpm_workspace_size", ctx, int(n), C.byref(out))
+    return int(out.value)
+
+
+def fpm_set_workspace(ctx, ws):
+    _call("fpm_set_workspace", ctx, _ptr(ws), ws.numel() * ws.element_size())
+
+
+def fpm_set_particles(ctx, pos, vel=None, typ=None):
+    _call("fpm_set_particles", ctx, int(pos.shape[0]), _ptr(pos), _ptr(vel), _ptr(typ))
+
+
+def fpm_set_density(ctx, rho):
+    _call("fpm_set_density", ctx, _ptr(rho))
+
+
+def fpm_get_particles(ctx, pos=None, vel=None, frc=None):
+    _call("fpm_get_particles", ctx, _ptr(pos), _ptr(vel), _ptr(frc))
+
+
+def fpm_get_sph(ctx, rho=None, drho=None):
+    _call("fpm_get_sph", ctx, _ptr(rho), _ptr(drho))
+
+
+def fpm_build_cell_list(ctx):
+    _call("fpm_build_cell_list", ctx)
+
+
+def fpm_get_cell_list(ctx, offsets=None, order=None):
+    nc = (C.c_int32 * 3)()
+    _call("fpm_get_cell_list", ctx, nc, _ptr(offsets), _ptr(order))
+    return tuple(nc)
+
+
+def fpm_build_verlet(ctx):
+    _call("fpm_build_verlet", ctx)
+
+
+def fpm_get_neighbors(ctx, counts, cols):
+    _call("fpm_get_neighbors", ctx, _ptr(counts), _ptr(cols))
+
+
+def lj_params(eps=(1.0, 1.0, 1.0), sig=(1.0, 1.0, 1.0), n_types: int = 1) -> fpm_lj_params:
+    p = fpm_lj_params()
+    p.n_types = int(n_types)
+    for k in range(3):
+        p.eps[k] = float(eps[k])
+        p.sig[k] = float(sig[k])
+    return p
+
+
+def fpm_lj_forces(ctx, prm: fpm_lj_params, out=None):
+    _call("fpm_lj_forces", ctx, C.byref(prm), _ptr(out))
+
+
+def fpm_integrate(ctx, dt: float, half: int):
+    _call("fpm_integrate", ctx, float(dt), int(half))
+
+
+def fpm_step(ctx, prm: fpm_lj_params, dt: float, nsteps: int, thermo=None):
+    _call("fpm_step", ctx, C.byref(prm), float(dt), int(nsteps), _ptr(thermo))
+
+
+def fpm_sph_rates(ctx, prm: fpm_sph_params, dt_out=None):
+    _call("fpm_sph_rates", ctx, C.byref(prm), _ptr(dt_out))
+
+
+def fpm_sph_step(ctx, prm: fpm_sph_params, nsteps: int, hist=None):
+    _call("fpm_sph_step", ctx, C.byref(prm), int(nsteps), _ptr(hist))
+
+
+def fpm_check(ctx):
+    _call("fpm_check", ctx)
+
+
+def fpm_read_counters(ctx):
+    out = (C.c_int64 * 3)()
+    _call("fpm_read_counters", ctx, out)
+    return tuple(int(x) for x in out)

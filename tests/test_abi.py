@@ -1,0 +1,69 @@
+"""The C-ABI library loads on the host and exports every entry point that
+include/*.h declares (no device work is started here)."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(fpm_\w+)\s*\(", text):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for required in ["fpm_create", "fpm_destroy", "fpm_set_box", "fpm_set_neighbor_params",
+                     "fpm_set_particles", "fpm_build_cell_list", "fpm_build_verlet",
+                     "fpm_lj_forces", "fpm_integrate", "fpm_step"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1804_07598_amd import _lib
+    L = _lib.lib()
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_symbol():
+    from paper_1804_07598_amd import _lib
+    bound = set(_lib._SIGS) | {"fpm_last_error"}
+    assert set(declared_functions()) <= bound
+
+
+def test_host_side_errors_without_device():
+    """Argument checks that return before any HIP call."""
+    from paper_1804_07598_amd import _lib as F
+    L = F.lib()
+    ctx = ctypes.c_void_p()
+    assert L.fpm_create(ctypes.byref(ctx), None) == 0
+    try:
+        bad = (ctypes.c_float * 3)(10.0, -1.0, 10.0)
+        per = (ctypes.c_int32 * 3)(1, 1, 1)
+        assert L.fpm_set_box(ctx, bad, per) == F.FPM_EINVAL
+        good = (ctypes.c_float * 3)(10.0, 10.0, 10.0)
+        assert L.fpm_set_box(ctx, good, per) == 0
+        # r_cut + skin must stay below L/2 on periodic axes
+        assert L.fpm_set_neighbor_params(ctx, 4.9, 0.3, 128) == F.FPM_ECUTOFF
+        assert b"half" in L.fpm_last_error(ctx)
+        assert L.fpm_set_neighbor_params(ctx, 2.5, 0.3, 0) == F.FPM_EINVAL
+        assert L.fpm_set_neighbor_params(ctx, 2.5, 0.3, 128) == 0
+        sz = ctypes.c_size_t()
+        assert L.fpm_workspace_size(ctx, 1000, ctypes.byref(sz)) == 0
+        assert sz.value > 1000 * 128 * 4
+        assert L.fpm_workspace_size(ctx, 0, ctypes.byref(sz)) == F.FPM_EINVAL
+        # calls that need particles fail cleanly
+        assert L.fpm_build_verlet(ctx) == F.FPM_EINVAL
+        assert L.fpm_step(ctx, None, ctypes.c_float(0.005), 1, None) == F.FPM_EINVAL
+    finally:
+        L.fpm_destroy(ctx)

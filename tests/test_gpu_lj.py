@@ -1,0 +1,240 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle for the
+LJ hot path: cell lists and Verlet sets bit-exact, forces within 1e-5 of the
+RMS force (max norm), energy and virial within 1e-6, velocity-Verlet steps,
+edge cases and error paths."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1804_07598_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+PER = (1, 1, 1)
+RC, SKIN = 2.5, 0.3
+FORCE_TOL = 1e-5
+ENERGY_TOL = 1e-6
+
+
+def make_sim(s, **kw):
+    from paper_1804_07598_amd.sim import ParticleSim
+    return ParticleSim(s.pos, s.box, PER, vel=s.vel, typ=s.typ, r_cut=kw.pop("r_cut", RC),
+                       skin=kw.pop("skin", SKIN), **kw)
+
+
+def np_(t):
+    return t.detach().cpu().numpy()
+
+
+def force_error(Fg, F64):
+    rms = math.sqrt((F64 ** 2).mean())
+    e = np.abs(Fg.astype(np.float64) - F64) / rms
+    return float(e.max()), rms
+
+
+def check_lj(sim, pos, L, eps=(1.0,) * 3, sig=(1.0,) * 3, typ=None, n_types=1, rows=None):
+    """Evaluate forces on the GPU and compare with the oracle at the same positions."""
+    out = np_(sim.lj_forces(eps, sig, n_types))
+    _, _, Fg = sim.get()
+    Fg = np_(Fg)
+    F64, U64, W64, Ur, _ = O.lj(pos, L, PER, O.radius2(RC), eps, sig, typ, rows=rows)
+    if rows is not None:
+        Fg = Fg[rows]
+    err, rms = force_error(Fg, F64)
+    assert err <= FORCE_TOL, (err, rms)
+    if rows is None:
+        assert abs(out[0] - U64) <= ENERGY_TOL * abs(U64), (out[0], U64)
+        scale = O.lj_virial_scale(pos, L, PER, O.radius2(RC), eps, sig, typ)
+        assert np.abs(out[2:] - W64).max() <= ENERGY_TOL * scale, (out[2:], W64)
+    return out, F64
+
+
+# ---------------------------------------------------------------- cell list
+
+@pytest.mark.parametrize("n,rho,seed", [(4096, 0.8442, 1), (1000, 0.8442, 7), (256, 0.6, 4001)])
+def test_cell_list_bit_exact(n, rho, seed):
+    s = inputs.lj_lattice(n, rho, 1.0, seed)
+    sim = make_sim(s)
+    sim.build_cell_list()
+    ncell, off, order = sim.cell_list()
+    nc = O.cell_grid(s.box, RC, SKIN)
+    assert tuple(ncell) == tuple(nc)
+    cid = O.cell_index(s.pos, s.box, nc)
+    counts, offsets, order64 = O.cell_sort(cid, int(np.prod(nc)))
+    assert np.array_equal(np_(off), offsets)
+    assert np.array_equal(np_(order), order64)
+
+
+# ---------------------------------------------------------------- Verlet sets
+
+def compare_sets(sim, pos, L, R2, rows=None):
+    counts, cols = sim.neighbors()
+    counts, cols = np_(counts), np_(cols)
+    ocnt, ocols = O.neighbors(pos, L, PER, R2, rows=rows, cap=sim.max_nbr)
+    idx = range(len(pos)) if rows is None else rows
+    for r, i in enumerate(idx):
+        got = np.sort(cols[i, :counts[i]])
+        exp = ocols[r, :ocnt[r]]
+        assert counts[i] == ocnt[r] and np.array_equal(got, exp), i
+
+
+@pytest.mark.parametrize("n,rho,seed", [(4096, 0.8442, 1), (1000, 0.8442, 7), (256, 0.6, 4001),
+                                        (4097, 0.8442, 9)])
+def test_verlet_sets_bit_exact(n, rho, seed):
+    s = inputs.lj_lattice(n, rho, 1.0, seed)
+    sim = make_sim(s)
+    compare_sets(sim, s.pos, s.box, O.radius2(RC, SKIN))
+
+
+# ---------------------------------------------------------------- forces
+
+@pytest.mark.parametrize("n,rho,seed", [(4096, 0.8442, 1), (1000, 0.8442, 7), (256, 0.6, 4001),
+                                        (4097, 0.8442, 9)])
+def test_lj_forces_match_oracle(n, rho, seed):
+    s = inputs.lj_lattice(n, rho, 1.0, seed)
+    sim = make_sim(s)
+    check_lj(sim, s.pos, s.box)
+
+
+def test_lj_mixture_forces():
+    s = inputs.lj_lattice(4096, 1.2, 1.0, seed=5, mixture=True)
+    sim = make_sim(s)
+    m = inputs.LJ_MIXTURE
+    check_lj(sim, s.pos, s.box, m["eps"], m["sig"], s.typ, n_types=2)
+
+
+def test_lj_deterministic_and_permutation_invariant():
+    import torch
+    s = inputs.lj_config("lj4096")
+    a = make_sim(s)
+    a.lj_forces()
+    _, _, Fa = a.get()
+    b = make_sim(s)
+    b.lj_forces()
+    _, _, Fb = b.get()
+    assert torch.equal(Fa, Fb)  # bitwise run-to-run
+    perm = np.random.default_rng(3).permutation(s.n)
+    sp = inputs.LJSystem(s.pos[perm], s.vel[perm], s.typ[perm], s.L, s.seed, s.rho, s.T)
+    c = make_sim(sp)
+    c.lj_forces()
+    _, _, Fc = c.get()
+    Fc = np_(Fc)
+    back = np.empty_like(Fc)
+    back[perm] = Fc
+    err, _ = force_error(back, np_(Fa).astype(np.float64))
+    assert err < 1e-6
+
+
+# ---------------------------------------------------------------- time stepping
+
+def test_velocity_verlet_steps():
+    s = inputs.lj_config("lj4096")
+    sim = make_sim(s)
+    th = np_(sim.step(10, dt=0.005))
+    sim.check()
+    p, v, f = (np_(t) for t in sim.get())
+    # (i) the oracle re-evaluated at the GPU's positions
+    check_lj(sim, p, s.box)
+    F64, U64, W64, _, _ = O.lj(p, s.box, PER, O.radius2(RC))
+    assert abs(th[-1, 0] - U64) <= ENERGY_TOL * abs(U64)
+    ke = 0.5 * float((v.astype(np.float64) ** 2).sum())
+    assert th[-1, 1] == pytest.approx(ke, rel=1e-6)
+    # (ii) the oracle's own FP64 trajectory from the same start
+    x64, v64, th64 = O.vv(s.pos.astype(np.float64), s.vel.astype(np.float64), s.box, PER, RC,
+                          0.005, 10)
+    d = p.astype(np.float64) - x64
+    d -= float(s.box[0]) * np.round(d / float(s.box[0]))
+    assert np.abs(d).max() < 1e-4
+    E = th[:, 0] + th[:, 1]
+    E64 = th64[1:, 0] + th64[1:, 1]
+    assert np.abs(E - E64).max() < 1e-4 * abs(E64[0])
+
+
+def test_rebuilds_follow_displacement():
+    s = inputs.lj_config("lj4096")
+    sim = make_sim(s)
+    sim.step(60, dt=0.005)
+    rebuilds, longest, total = sim.counters()
+    assert rebuilds >= 2  # the initial build plus at least one automatic rebuild
+    p, _, _ = (np_(t) for t in sim.get())
+    # the current Verlet list still covers the force set at r_cut
+    compare_sets_force = O.neighbors(p, s.box, PER, O.radius2(RC), cap=256)
+    counts, cols = (np_(t) for t in sim.neighbors())
+    ocnt, ocols = compare_sets_force
+    for i in range(s.n):
+        have = set(cols[i, :counts[i]].tolist())
+        assert set(ocols[i, :ocnt[i]].tolist()) <= have
+
+
+def test_nve_energy_bounded():
+    s = inputs.lj_config("lj4096")
+    sim = make_sim(s)
+    th = np_(sim.step(400, dt=0.005))
+    E = th[:, 0] + th[:, 1]
+    ref = O.vv(s.pos.astype(np.float64), s.vel.astype(np.float64), s.box, PER, RC, 0.005, 400)[2]
+    E64 = ref[1:, 0] + ref[1:, 1]
+    # same drift as the FP64 trajectory (truncated LJ drifts while the lattice melts)
+    assert abs((E[-1] - E[0]) - (E64[-1] - E64[0])) < 2e-3 * abs(E64[0])
+
+
+# ---------------------------------------------------------------- edges and errors
+
+def test_small_box_two_cells():
+    s = inputs.lj_lattice(256, 0.6, 1.0, seed=4000)
+    sim = make_sim(s)
+    assert sim.cell_list()[0] == (2, 2, 2)
+    compare_sets(sim, s.pos, s.box, O.radius2(RC, SKIN))
+    check_lj(sim, s.pos, s.box)
+
+
+def test_particles_on_faces_and_empty_cells():
+    rng = np.random.default_rng(5)
+    L = np.float32(16.0)
+    # half of the box empty, particles exactly on cell faces and on x = 0
+    pts = rng.uniform(0, 8.0, size=(900, 3)).astype(np.float32)
+    pts[:30, 0] = 0.0
+    pts[30:60, 1] = np.float32(16.0 / 5)  # a cell face (5 cells of 3.2)
+    pts = np.unique(pts, axis=0)
+    s = inputs.LJSystem(pts, np.zeros_like(pts), np.zeros(len(pts), np.int32), float(L), 0, 0, 0)
+    sim = make_sim(s, max_nbr=512)
+    compare_sets(sim, s.pos, s.box, O.radius2(RC, SKIN))
+
+
+def test_overflow_is_reported():
+    from paper_1804_07598_amd._lib import FpmError, FPM_EOVERFLOW
+    s = inputs.lj_lattice(1000, 0.8442, 1.0, seed=7)
+    sim = make_sim(s, max_nbr=8)
+    with pytest.raises(FpmError) as e:
+        sim.check()
+    assert e.value.code == FPM_EOVERFLOW
+    with pytest.raises(FpmError):
+        sim.neighbors()
+    # a larger capacity gives the exact sets again
+    sim2 = make_sim(s, max_nbr=160)
+    compare_sets(sim2, s.pos, s.box, O.radius2(RC, SKIN))
+
+
+def test_cutoff_error():
+    from paper_1804_07598_amd._lib import FpmError, FPM_ECUTOFF
+    s = inputs.lj_lattice(64, 0.8442, 1.0, seed=2)  # L = 4.2 < 2 * 2.8
+    with pytest.raises(FpmError) as e:
+        make_sim(s)
+    assert e.value.code == FPM_ECUTOFF
+
+
+# ---------------------------------------------------------------- 1M atoms, sampled
+
+def test_lj_1m_sampled_rows():
+    s = inputs.lj_config("lj1m")
+    sim = make_sim(s)
+    rows = np.random.default_rng(2).choice(s.n, 128, replace=False)
+    sim.lj_forces()
+    compare_sets(sim, s.pos, s.box, O.radius2(RC, SKIN), rows=rows)
+    check_lj(sim, s.pos, s.box, rows=rows)
+    # after steps with rebuilds, at the GPU's positions
+    sim.step(40, dt=0.005)
+    sim.check()
+    p, _, _ = (np_(t) for t in sim.get())
+    check_lj(sim, p, s.box, rows=rows)
