@@ -1,0 +1,202 @@
+#!/usr/bin/env python3
+"""Throughput of the LJ velocity-Verlet step at one million atoms on one GPU.
+
+Workload: LJ fluid, N = 1,000,000 on a jittered 100^3 lattice, rho = 0.8442,
+T = 1, r_cut = 2.5 sigma (truncated), Verlet skin 0.3 sigma with rebuilds when
+the largest displacement exceeds skin/2, dt = 0.005, periodic cube.  Inputs
+are synthetic (seeded) and resident in device memory before timing starts.
+
+One timed step = fused kick/drift with the displacement check, gated cell-list
+and Verlet-list rebuild, LJ force/energy/virial, closing kick with kinetic
+energy; all graph-launched.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "LJ atom-steps/s at 1M particles, %HBM roofline; batched & adjoint vs plain"
+PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "lj_force_lj1m_counters.txt")
+LJ_SOURCE = os.path.join(ROOT, "paper_1804_07598_amd", "csrc", "lj.hip")
+
+
+def log(msg: str, quiet: bool):
+    if not quiet:
+        print(msg, file=sys.stderr, flush=True)
+
+
+def source_hash(path: str) -> str:
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def stored_traffic(n_launch_atoms: int):
+    """HBM bytes per force launch from the committed rocprofv3 counter summary,
+    or None when the summary is missing or the kernel source changed since."""
+    if not os.path.exists(PROFILE_COUNTERS):
+        return None
+    kv = {}
+    for line in open(PROFILE_COUNTERS):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    try:
+        if kv.get("kernel_source_sha256_16") != source_hash(LJ_SOURCE):
+            return None
+        if int(kv.get("atoms", "0")) != n_launch_atoms:
+            return None
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(pos, box, target_s: float, quiet: bool):
+    """The FP64 O(N^2) oracle on a bounded sample: forces of R random atoms
+    against all N atoms, timed on the host's cores."""
+    import numpy as np
+    import oracle as O
+    rc2 = O.radius2(2.5)
+    rng = np.random.default_rng(0)
+    R = 64
+    O.lj(pos, box, (1, 1, 1), rc2, rows=rng.choice(len(pos), R, replace=False))  # warm
+    while True:
+        rows = rng.choice(len(pos), R, replace=False)
+        t0 = time.perf_counter()
+        O.lj(pos, box, (1, 1, 1), rc2, rows=rows)
+        dt = time.perf_counter() - t0
+        if dt >= target_s or R >= len(pos):
+            break
+        R = min(len(pos), max(R * 2, int(R * target_s / max(dt, 1e-3) * 1.1)))
+        log(f"cpu baseline: trying {R} rows", quiet)
+    return {"value": R / dt, "unit": "atom-steps/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"{R} random atoms' LJ forces against all {len(pos)} atoms (FP32 predicate, "
+                      f"FP64 physics) at the initial configuration; {dt:.1f} s"}
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quiet", action="store_true")
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only: this build has no multi-GPU path "
+              f"(asked for --gpus {a.gpus}).", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_1804_07598_amd import _lib as F
+    from paper_1804_07598_amd import inputs
+    from paper_1804_07598_amd.sim import ParticleSim
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    s = inputs.lj_config("lj1m")
+    log(f"workload lj1m: N={s.n} L={s.L:.5f}", a.quiet)
+    sim = ParticleSim(s.pos, s.box, (1, 1, 1), vel=s.vel, r_cut=2.5, skin=0.3, device=dev)
+    dt = 0.005
+    thermo = torch.zeros((max(a.steps, a.warmup, 1), 8), dtype=torch.float64, device=dev)
+
+    sim.step(a.warmup, dt=dt, thermo=thermo)
+    torch.cuda.synchronize()
+    sim.check()
+    reb0, _, _ = sim.counters()
+    log(f"warmup done ({a.warmup} steps)", a.quiet)
+
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    sim.step(a.steps, dt=dt, thermo=thermo)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    sim.check()
+    reb1, longest, total = sim.counters()
+    th = thermo[:a.steps].cpu().numpy()
+    assert np.isfinite(th).all(), "non-finite thermo"
+    rebuilds = reb1 - reb0
+    nbar = total / s.n
+    kbar = a.steps / max(rebuilds, 1)
+    value = s.n * a.steps / (ms / 1e3)
+    log(f"timed {a.steps} steps: {ms:.2f} ms (wall {wall * 1e3:.1f} ms), rebuilds {rebuilds}, "
+        f"mean list {nbar:.2f}", a.quiet)
+
+    # dominant kernel: LJ force, timed with HIP events around each launch on the
+    # stream it runs on
+    F.fpm_set_profiling(sim.ctx, True)
+    for _ in range(a.kernel_reps):
+        sim.lj_forces()
+    f_ms, f_n = F.fpm_kernel_time(sim.ctx, "lj_force")
+    # drop the records of the gated (no-op) list refreshes made by the force calls
+    F.fpm_kernel_time(sim.ctx, "cell_build")
+    F.fpm_kernel_time(sim.ctx, "verlet_build")
+    for _ in range(5):
+        sim.build_verlet()
+    c_ms, _ = F.fpm_kernel_time(sim.ctx, "cell_build")
+    v_ms, _ = F.fpm_kernel_time(sim.ctx, "verlet_build")
+    F.fpm_set_profiling(sim.ctx, False)
+    sim.check()
+    _, _, total2 = sim.counters()
+    nbar_k = total2 / s.n
+    bytes_force = s.n * (36.0 + 4.0 * nbar_k)
+    achieved = bytes_force / (f_ms / 1e3) / 1e9
+    traffic = stored_traffic(s.n)
+    log(f"force kernel {f_ms * 1e3:.1f} us over {f_n} launches -> {achieved:.0f} GB/s; "
+        f"cell build {c_ms * 1e3:.1f} us, Verlet build {v_ms * 1e3:.1f} us", a.quiet)
+
+    B = 132.0 + 4.0 * nbar + (164.0 + 4.0 * nbar) / kbar
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 state, f64 pair arithmetic",
+        "data": "synthetic",
+        "config": {"workload": "lj1m: LJ fluid N=1,000,000 (jittered 100^3 lattice), rho=0.8442, "
+                               "T=1, r_cut=2.5, skin=0.3, dt=0.005, periodic",
+                   "n": s.n, "dt": dt, "r_cut": 2.5, "skin": 0.3},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "lj_force", "kernel_ms": f_ms,
+                     "bytes_per_launch": bytes_force,
+                     "bytes_model": "N*(36 + 4*nbar): pos_i 16, count 4, list 4*nbar, force 16"},
+        "step_model": {"mean_list": nbar, "rebuilds": rebuilds, "rebuild_interval": kbar,
+                       "bytes_per_atom_step": B,
+                       "hbm_frac": B * value / (HBM_PEAK_GBS * 1e9),
+                       "cell_build_ms": c_ms, "verlet_build_ms": v_ms},
+        "cpu_baseline": None,
+    }
+    if not a.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(s.pos, s.box, a.cpu_seconds, a.quiet)
+    sim.close()
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -31,7 +31,8 @@
  *
  * Neighbour sets are defined in FP32, identically for every kernel: per axis
  * t = xj - xi; on a periodic axis, if t > L/2 the image (xj - L) - xi is used,
- * if t < -L/2 the image xj - (xi - L), otherwise t; then
+ * if t < -L/2 the image (xj + L) - xi (the ghost copy of j shifted by one
+ * period, rounded once), otherwise t; then
  * d2 = (dx*dx + dy*dy) + dz*dz with every operation rounded separately (no
  * fused multiply-add), and j != i is a neighbour iff d2 <= R2, where R2 is
  * (r_cut + skin)^2 evaluated in FP64 and rounded once to FP32 (the listing of
@@ -179,6 +180,18 @@ int fpm_check(fpm_ctx *ctx);
  * h_out[1] = largest Verlet-list length seen in the last build,
  * h_out[2] = total Verlet-list entries of the last build. */
 int fpm_read_counters(fpm_ctx *ctx, int64_t h_out[3]);
+
+/* ---- measurement ---- */
+
+/* With on = 1, every launch made outside a graph of the kernels named
+ * "lj_force", "verlet_build", "cell_build", "integrate", "sph_rates" is
+ * bracketed by two HIP events recorded on the context's stream; on = 0 stops
+ * recording and drops pending records. */
+int fpm_set_profiling(fpm_ctx *ctx, int32_t on);
+/* Synchronises, then returns the mean duration in milliseconds (h_ms) and the
+ * number (h_count) of the recorded launches of `kernel` since the last call
+ * for that name; the records are consumed. */
+int fpm_kernel_time(fpm_ctx *ctx, const char *kernel, double *h_ms, int64_t *h_count);
 
 #ifdef __cplusplus
 }

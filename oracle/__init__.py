@@ -64,6 +64,8 @@ def lib():
                                 f64p, C.c_double, C.c_double, C.c_int32, _opt(f64p)]
         L.oracle_lj_forces_f64.argtypes = [C.c_int64, f64p, _opt(i32p), f64p, i32p, C.c_double,
                                            f64p, f64p, f64p, f64p]
+        L.oracle_num_threads.restype = C.c_int
+        L.oracle_num_threads.argtypes = []
         if hasattr(L, "oracle_sph_rows"):
             L.oracle_sph_rows.argtypes = [C.c_int64, f32p, f32p, f32p, i32p, f32p, i32p, C.c_float,
                                           f64p, _opt(i64p), C.c_int64, f64p, f64p, f64p]
@@ -196,3 +198,45 @@ def vv(x, v, L, per, rc, dt, nsteps, eps=(1.0, 1.0, 1.0), sig=(1.0, 1.0, 1.0), t
                     _f64(np.broadcast_to(np.asarray(L, np.float64), (3,))), _per(per), float(rc),
                     _f64(eps), _f64(sig), float(mass), float(dt), int(nsteps), thermo)
     return x, v, thermo
+
+
+def sph_kernel_w(r: float, h: float) -> float:
+    """Wendland C2 kernel value W(r) with support 2h."""
+    return float(lib().oracle_sph_kernel_w(float(r), float(h)))
+
+
+def sph_params_array(h, mass, rho0, c0, gamma=7.0, alpha=0.1, eta2=None, g=(0.0, 0.0, -9.81)):
+    """The oracle's SPH parameter vector {h, m, rho0, c0, gamma, alpha, eta2, gx, gy, gz}."""
+    if eta2 is None:
+        eta2 = 0.01 * h * h
+    return np.array([h, mass, rho0, c0, gamma, alpha, eta2, g[0], g[1], g[2]], dtype=np.float64)
+
+
+def sph_rates(pos, vel, rho, kind, L, per, R2, prm, rows=None):
+    """FP64 SPH rates (Eqs. 1-2) on the FP32 pair set.
+
+    Returns (acc (rows, 3), drho (rows,), mumax (rows,))."""
+    pos, vel, rho = _f32(pos), _f32(vel), _f32(rho)
+    nr = len(pos) if rows is None else len(rows)
+    rows_a = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    acc = np.empty((nr, 3), np.float64)
+    drho = np.empty(nr, np.float64)
+    mu = np.empty(nr, np.float64)
+    lib().oracle_sph_rows(len(pos), pos, vel, rho, _i32(kind), _box(L), _per(per),
+                          float(np.float32(R2)), _f64(prm), rows_a, nr, acc, drho, mu)
+    return acc, drho, mu
+
+
+def sph_dt(acc, kind, mumax, prm, cfl):
+    """CFL time step from full-system rates: cfl * min(min_a sqrt(h/|a_a|), h/(c0 + max mu))."""
+    h, c0 = float(prm[0]), float(prm[3])
+    fl = np.asarray(kind) == 0
+    am = np.sqrt((np.asarray(acc)[fl] ** 2).sum(axis=1))
+    t1 = np.sqrt(h / am[am > 0].max()) if np.any(am > 0) else np.inf
+    t2 = h / (c0 + float(np.max(mumax)))
+    return cfl * min(t1, t2)
+
+
+def num_threads() -> int:
+    """OpenMP threads used by the oracle's loops."""
+    return int(lib().oracle_num_threads())

@@ -33,10 +33,13 @@
 /* pairs are candidates; the set of interacting pairs is "all j != i within    */
 /* distance R" (the cut-off test returns zero beyond r_cut, section 4.1        */
 /* listing).  The set is defined in FP32 so that it can be reproduced bit for  */
-/* bit: per axis t = xj - xi; if t > L/2 the image xj - L is used, if          */
-/* t < -L/2 the image xi - L; then d2 = (dx*dx + dy*dy) + dz*dz, each          */
-/* operation rounded to nearest, no fused multiply-add; a pair is in the set   */
-/* iff d2 <= R^2 (the listing rejects only rn > r_cut2).                      */
+/* bit: per axis t = xj - xi; if t > L/2 the separation is (xj - L) - xi, if   */
+/* t < -L/2 it is (xj + L) - xi: j is replaced by its periodic ghost copy      */
+/* (section 3.1 fills ghost layers with copies of particles from across the    */
+/* boundary), whose shifted coordinate is rounded once to FP32.  Then          */
+/* d2 = (dx*dx + dy*dy) + dz*dz, each operation rounded to nearest, no fused   */
+/* multiply-add; a pair is in the set iff d2 <= R^2 (the listing rejects only  */
+/* rn > r_cut2).                                                               */
 /* ------------------------------------------------------------------------- */
 
 static float img_delta_f32(float xi, float xj, float L, int periodic)
@@ -49,13 +52,13 @@ static float img_delta_f32(float xi, float xj, float L, int periodic)
         return xs - xi;
     }
     if (t < -half) {
-        float xs = xi - L;
-        return xj - xs;
+        float xs = xj + L;
+        return xs - xi;
     }
     return t;
 }
 
-/* Returns the branch taken: 0 = direct, +1 = xj shifted by -L, -1 = xi shifted. */
+/* Returns the branch taken: 0 = direct, +1 = xj shifted by -L, -1 = xj shifted by +L. */
 static int img_branch_f32(float xi, float xj, float L, int periodic)
 {
     float t = xj - xi;
@@ -86,7 +89,7 @@ static void sep_f64(const float *pi, const float *pj, const float *L, const int 
         int b = img_branch_f32(pi[a], pj[a], L[a], per[a]);
         double d = (double)pi[a] - (double)pj[a];
         if (b == 1) d += (double)L[a];       /* xj was replaced by xj - L */
-        else if (b == -1) d -= (double)L[a]; /* xi was replaced by xi - L */
+        else if (b == -1) d -= (double)L[a]; /* xj was replaced by xj + L */
         r[a] = d;
     }
 }
@@ -364,4 +367,15 @@ void oracle_lj_forces_f64(int64_t n, const double *x, const int32_t *type, const
                           const double sig[3], double *F, double *U)
 {
     lj_forces_f64(n, x, type, L, per, rc, eps, sig, F, U);
+}
+
+/* Number of OpenMP threads the oracle's loops use. */
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    extern int omp_get_max_threads(void);
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

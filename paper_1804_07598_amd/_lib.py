@@ -64,6 +64,8 @@ _SIGS = {
     "fpm_sph_step": [_P, C.POINTER(fpm_sph_params), C.c_int32, _P],
     "fpm_check": [_P],
     "fpm_read_counters": [_P, C.POINTER(C.c_int64)],
+    "fpm_set_profiling": [_P, C.c_int32],
+    "fpm_kernel_time": [_P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)],
 }
 
 _lib = None
@@ -186,6 +188,18 @@ def lj_params(eps=(1.0, 1.0, 1.0), sig=(1.0, 1.0, 1.0), n_types: int = 1) -> fpm
     return p
 
 
+def sph_params(h, mass, rho0, c0, gamma=7.0, alpha=0.1, eta2=None, g=(0.0, 0.0, -9.81),
+               cfl=0.2) -> fpm_sph_params:
+    p = fpm_sph_params()
+    p.h, p.mass, p.rho0, p.c0, p.gamma, p.alpha = (float(h), float(mass), float(rho0),
+                                                    float(c0), float(gamma), float(alpha))
+    p.eta2 = float(0.01 * h * h if eta2 is None else eta2)
+    for k in range(3):
+        p.g[k] = float(g[k])
+    p.cfl = float(cfl)
+    return p
+
+
 def fpm_lj_forces(ctx, prm: fpm_lj_params, out=None):
     _call("fpm_lj_forces", ctx, C.byref(prm), _ptr(out))
 
@@ -214,3 +228,15 @@ def fpm_read_counters(ctx):
     out = (C.c_int64 * 3)()
     _call("fpm_read_counters", ctx, out)
     return tuple(int(x) for x in out)
+
+
+def fpm_set_profiling(ctx, on: bool):
+    _call("fpm_set_profiling", ctx, 1 if on else 0)
+
+
+def fpm_kernel_time(ctx, kernel: str):
+    """(mean ms, count) of the event-timed launches of `kernel` (records consumed)."""
+    ms = C.c_double(0)
+    n = C.c_int64(0)
+    _call("fpm_kernel_time", ctx, kernel.encode(), C.byref(ms), C.byref(n))
+    return float(ms.value), int(n.value)

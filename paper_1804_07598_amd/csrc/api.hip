@@ -1,9 +1,9 @@
 // Host side of the C ABI declared in include/fpm.h: argument checks, the
-// workspace layout, the order of kernel launches and the graphs of fpm_step.
+// workspace layout, the order of kernel launches and the graphs of the step
+// loops.
 #include <math.h>
 #include <string.h>
 
-#include <climits>
 #include <new>
 
 #include "fpm_internal.h"
@@ -22,9 +22,9 @@ int hip_fail(fpm_ctx *c, hipError_t e, const char *where) {
     return fail(c, FPM_EHIP, m);
 }
 
-#define HIPCHK(c, expr)                                   \
-    do {                                                  \
-        hipError_t e_ = (expr);                           \
+#define HIPCHK(c, expr)                                      \
+    do {                                                     \
+        hipError_t e_ = (expr);                              \
         if (e_ != hipSuccess) return hip_fail(c, e_, #expr); \
     } while (0)
 
@@ -32,10 +32,29 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+int cap4_for(int cap) { return (cap + 7) / 8 * 2; }
+
+// Launch geometry for n particles.
+struct Plan {
+    int64_t n_pad;
+    int nblk, nblk_build, zb, nzb;
+};
+
+Plan plan_for(const fpm_ctx *c, int64_t n) {
+    Plan p;
+    p.n_pad = (n + 1 + kBlock - 1) / kBlock * kBlock;  // at least one padding slot
+    p.nblk = (int)(p.n_pad / kBlock);
+    p.zb = verlet_zblock(n, c->ncells, c->box.nc);
+    p.nzb = p.zb ? (c->box.nc[2] + p.zb - 1) / p.zb : 0;
+    p.nblk_build = p.zb ? c->box.nc[0] * c->box.nc[1] * p.nzb : p.nblk;
+    return p;
+}
+
 // Workspace layout for n particles; with base == nullptr only the size is computed.
-size_t layout(fpm_ctx *c, int64_t n, char *base, State *st) {
-    const int64_t n_pad = (n + kBlock - 1) / kBlock * kBlock;
-    const int64_t nblk = n_pad / kBlock;
+size_t layout(const fpm_ctx *c, int64_t n, char *base, State *st) {
+    const Plan pl = plan_for(c, n);
+    const int64_t n_pad = pl.n_pad;
+    const int64_t pstride = pl.nblk;  // only the particle kernels write partials
     size_t off = 0;
     auto take = [&](size_t bytes) -> char * {
         char *p = base ? base + off : nullptr;
@@ -51,20 +70,21 @@ size_t layout(fpm_ctx *c, int64_t n, char *base, State *st) {
     s.cid = (int32_t *)take(n_pad * sizeof(int32_t));
     s.rnk = (int32_t *)take(n_pad * sizeof(int32_t));
     s.tmp = (int2 *)take(n_pad * sizeof(int2));
-    s.cnt = (int32_t *)take(c->ncells * sizeof(int32_t));
-    s.off = (int32_t *)take((c->ncells + 1) * sizeof(int32_t));
-    s.nbr = (int32_t *)take((size_t)n_pad * c->cap * sizeof(int32_t));
+    s.cnt = (int32_t *)take((c->ncells + 4) * sizeof(int32_t));
+    s.off = (int32_t *)take((c->ncells + 4) * sizeof(int32_t));
+    s.nbr = (int32_t *)take((size_t)n_pad * cap4_for(c->cap) * 4 * sizeof(int32_t));
     s.nnb = (uint32_t *)take(n_pad * sizeof(uint32_t));
-    s.part = (double *)take((size_t)(nblk + 1) * 8 * sizeof(double));
+    s.part = (double *)take((size_t)pstride * kSlots * sizeof(double));
     s.ctl = (Ctl *)take(sizeof(Ctl));
+    s.pstride = (int32_t)pstride;
+    s.dummy = (int32_t)n;
     if (st) *st = s;
     return off;
 }
 
-bool finite3(const float *v) { return isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]); }
-
 void drop_graphs(fpm_ctx *c) {
-    for (hipGraphExec_t *g : {&c->g_first, &c->g_chunk, &c->g_one, &c->s_one}) {
+    for (hipGraphExec_t *g :
+         {&c->g_first, &c->g_chunk, &c->g_one, &c->s_first, &c->s_chunk, &c->s_one}) {
         if (*g) (void)hipGraphExecDestroy(*g);
         *g = nullptr;
     }
@@ -76,30 +96,57 @@ int ready(fpm_ctx *c) {
     return FPM_OK;
 }
 
-// Gated neighbour-structure refresh: both kernels return at once unless the
-// device rebuild flag is set.
-hipError_t refresh_lists(fpm_ctx *c) {
-    hipError_t e = launch_cell_build(c);
+// Brackets an eager launch with two events when profiling is on (never while
+// a graph is being captured).
+template <class F>
+hipError_t timed(fpm_ctx *c, const char *name, F &&launch) {
+    if (!c->profiling || (c->cap_stream && c->stream == c->cap_stream)) return launch();
+    fpm_ctx::Timed t{name, nullptr, nullptr};
+    hipError_t e = hipEventCreate(&t.start);
+    if (e == hipSuccess) e = hipEventCreate(&t.stop);
+    if (e == hipSuccess) e = hipEventRecord(t.start, c->stream);
     if (e != hipSuccess) return e;
-    return launch_verlet_build(c);
+    e = launch();
+    hipError_t e2 = hipEventRecord(t.stop, c->stream);
+    c->timed.push_back(t);
+    return e != hipSuccess ? e : e2;
+}
+
+void drop_timers(fpm_ctx *c) {
+    for (auto &t : c->timed) {
+        if (t.start) (void)hipEventDestroy(t.start);
+        if (t.stop) (void)hipEventDestroy(t.stop);
+    }
+    c->timed.clear();
+}
+
+// Gated neighbour-structure refresh: every kernel returns at once unless the
+// device rebuild flag is set.  The flag is cleared (and the build accounted)
+// by the next finalize with kFinBuild.
+hipError_t refresh_lists(fpm_ctx *c) {
+    hipError_t e = timed(c, "cell_build", [&] { return launch_cell_build(c); });
+    if (e != hipSuccess) return e;
+    return timed(c, "verlet_build", [&] { return launch_verlet_build(c); });
+}
+
+// Eager refresh that leaves the flag clear.
+hipError_t refresh_and_account(fpm_ctx *c) {
+    hipError_t e = refresh_lists(c);
+    if (e == hipSuccess) e = launch_finalize(c, kFinBuild, nullptr, nullptr);
+    if (e == hipSuccess) c->build_pending = false;
+    return e;
 }
 
 constexpr int kChunk = 25;  // steps per captured graph
 
-// Captures `steps` velocity-Verlet steps into an executable graph.
-int capture_steps(fpm_ctx *c, const fpm_lj_params &p, float dt, double *thermo, int steps,
-                  bool first, hipGraphExec_t *out) {
+template <class F>
+int capture(fpm_ctx *c, F &&body, hipGraphExec_t *out) {
     if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     hipStream_t user = c->stream;
     c->stream = c->cap_stream;
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
-    for (int s = 0; s < steps && e == hipSuccess; s++) {
-        e = launch_integrate(c, dt, (first && s == 0) ? kKickDriftFirst : kKickKickDrift, thermo,
-                             INT_MAX);
-        if (e == hipSuccess) e = refresh_lists(c);
-        if (e == hipSuccess) e = launch_lj_forces(c, p, nullptr, thermo, INT_MAX, 1);
-    }
+    if (e == hipSuccess) e = body();
     hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
     c->stream = user;
     if (e != hipSuccess) {
@@ -111,6 +158,45 @@ int capture_steps(fpm_ctx *c, const fpm_lj_params &p, float dt, double *thermo, 
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
     return FPM_OK;
+}
+
+// One LJ velocity-Verlet step: (fused) kicks and drift, finalize (accounts a
+// rebuild of the previous step, completes the previous step's thermo row,
+// decides this step's rebuild), gated rebuild, forces.
+hipError_t lj_step_body(fpm_ctx *c, const fpm_lj_params &p, float dt, double *thermo,
+                        bool first) {
+    hipError_t e = launch_integrate(c, dt, first ? kKickDriftFirst : kKickKickDrift);
+    const int fin = first ? kFinDisp : (kFinBuild | kFinForce | kFinKE | kFinRow | kFinDisp);
+    if (e == hipSuccess) e = launch_finalize(c, fin, nullptr, thermo);
+    if (e == hipSuccess) e = refresh_lists(c);
+    if (e == hipSuccess) e = launch_lj_forces(c, p);
+    return e;
+}
+
+// One SPH kick-drift-kick step with the device time step.
+hipError_t sph_step_body(fpm_ctx *c, const fpm_sph_params &p, double *hist, bool first) {
+    hipError_t e = launch_sph_integrate(c, p, first ? kKickDriftFirst : kKickKickDrift);
+    if (e == hipSuccess) e = launch_finalize(c, kFinBuild | kFinDisp, nullptr, nullptr);
+    if (e == hipSuccess) e = refresh_lists(c);
+    if (e == hipSuccess) e = launch_sph_rates(c, p);
+    if (e == hipSuccess) e = launch_sph_finalize(c, p, 1, nullptr, hist);
+    return e;
+}
+
+bool valid_lj(const fpm_lj_params *p) {
+    if (!p || (p->n_types != 1 && p->n_types != 2)) return false;
+    for (int k = 0; k < 3; k++)
+        if (!(isfinite(p->eps[k]) && isfinite(p->sig[k]) && p->sig[k] > 0.f)) return false;
+    return true;
+}
+
+bool valid_sph(const fpm_sph_params *p) {
+    if (!p) return false;
+    const float v[] = {p->h, p->mass, p->rho0, p->c0, p->gamma, p->cfl};
+    for (float x : v)
+        if (!(isfinite(x) && x > 0.f)) return false;
+    return isfinite(p->alpha) && p->alpha >= 0.f && isfinite(p->eta2) && p->eta2 >= 0.f &&
+           isfinite(p->g[0]) && isfinite(p->g[1]) && isfinite(p->g[2]);
 }
 
 }  // namespace
@@ -130,6 +216,7 @@ int fpm_destroy(fpm_ctx *c) {
     if (!c) return FPM_OK;
     (void)hipStreamSynchronize(c->stream);
     drop_graphs(c);
+    drop_timers(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
     return FPM_OK;
@@ -143,6 +230,8 @@ int fpm_set_box(fpm_ctx *c, const float L[3], const int32_t per[3]) {
     for (int a = 0; a < 3; a++) {
         if (!(isfinite(L[a]) && L[a] > 0.f)) return fail(c, FPM_EINVAL, "box side must be > 0");
         if (per[a] != 0 && per[a] != 1) return fail(c, FPM_EINVAL, "periodic flag must be 0/1");
+    }
+    for (int a = 0; a < 3; a++) {
         c->box.L[a] = L[a];
         c->box.half[a] = L[a] * 0.5f;
         c->box.per[a] = per[a];
@@ -161,21 +250,25 @@ int fpm_set_neighbor_params(fpm_ctx *c, float r_cut, float skin, int32_t max_nbr
         return fail(c, FPM_EINVAL, "r_cut must be > 0 and skin >= 0");
     if (max_nbr < 1 || max_nbr > kMaxNbrCap) return fail(c, FPM_EINVAL, "max_nbr out of range");
     const double R = (double)r_cut + (double)skin;
+    int nc[3];
     int64_t ncells = 1;
     for (int a = 0; a < 3; a++) {
         if (c->box.per[a] && !(R < 0.5 * (double)c->box.L[a] * (1.0 - 1e-6)))
             return fail(c, FPM_ECUTOFF, "r_cut + skin must be below half the periodic box");
         double m = floor((double)c->box.L[a] / (R * 1.000001));
-        int nc = m < 1.0 ? 1 : (m > 1 << 20 ? 1 << 20 : (int)m);
-        c->box.nc[a] = nc;
-        c->box.inv[a] = (float)nc / c->box.L[a];
-        ncells *= nc;
+        nc[a] = m < 1.0 ? 1 : (m > (1 << 20) ? (1 << 20) : (int)m);
+        ncells *= nc[a];
     }
-    if (ncells > (int64_t)1 << 30) return fail(c, FPM_EINVAL, "too many cells");
+    if (ncells > ((int64_t)1 << 30)) return fail(c, FPM_EINVAL, "too many cells");
+    for (int a = 0; a < 3; a++) {
+        c->box.nc[a] = nc[a];
+        c->box.inv[a] = (float)nc[a] / c->box.L[a];
+    }
     c->ncells = ncells;
     c->r_cut = r_cut;
     c->skin = skin;
     c->cap = max_nbr;
+    c->cap4 = cap4_for(max_nbr);
     c->R2 = (float)(R * R);
     c->rc2 = (float)((double)r_cut * (double)r_cut);
     const double hs = 0.5 * (double)skin;
@@ -216,15 +309,28 @@ int fpm_set_particles(fpm_ctx *c, int64_t n, const float *pos, const float *vel,
     const size_t need = layout(c, n, nullptr, nullptr);
     if (!c->ws || c->ws_bytes < need) return fail(c, FPM_ENOWS, "workspace missing or too small");
     layout(c, n, (char *)c->ws, &c->st);
+    const Plan pl = plan_for(c, n);
     c->n = n;
-    c->n_pad = (n + kBlock - 1) / kBlock * kBlock;
-    c->nblk = (int)(c->n_pad / kBlock);
+    c->n_pad = pl.n_pad;
+    c->nblk = pl.nblk;
+    c->nblk_build = pl.nblk_build;
+    c->zb = pl.zb;
+    c->nzb = pl.nzb;
     drop_graphs(c);
     HIPCHK(c, launch_fill_i32(c->stream, c->st.cnt, c->ncells, 0));
     HIPCHK(c, launch_init_state(c, pos, vel, type));
     HIPCHK(c, launch_force_rebuild(c));
-    HIPCHK(c, refresh_lists(c));
+    HIPCHK(c, refresh_and_account(c));
     c->have_particles = true;
+    c->forces_valid = false;
+    return FPM_OK;
+}
+
+int fpm_set_density(fpm_ctx *c, const float *rho) {
+    int r = ready(c);
+    if (r) return r;
+    if (!rho) return fail(c, FPM_EINVAL, "null density");
+    HIPCHK(c, launch_set_density(c, rho));
     c->forces_valid = false;
     return FPM_OK;
 }
@@ -236,11 +342,21 @@ int fpm_get_particles(fpm_ctx *c, float *pos, float *vel, float *frc) {
     return FPM_OK;
 }
 
+int fpm_get_sph(fpm_ctx *c, float *rho, float *drho) {
+    int r = ready(c);
+    if (r) return r;
+    HIPCHK(c, launch_gather_out(c, nullptr, nullptr, nullptr, rho, drho));
+    return FPM_OK;
+}
+
 int fpm_build_cell_list(fpm_ctx *c) {
     int r = ready(c);
     if (r) return r;
     HIPCHK(c, launch_force_rebuild(c));
-    HIPCHK(c, launch_cell_build(c));
+    HIPCHK(c, timed(c, "cell_build", [&] { return launch_cell_build(c); }));
+    HIPCHK(c, launch_copy_back(c));
+    c->build_pending = true;  // flag stays set: the Verlet list is rebuilt on next use
+    c->forces_valid = false;
     return FPM_OK;
 }
 
@@ -249,7 +365,7 @@ int fpm_get_cell_list(fpm_ctx *c, int32_t ncell[3], int32_t *offsets, int32_t *o
     if (r) return r;
     if (ncell)
         for (int a = 0; a < 3; a++) ncell[a] = c->box.nc[a];
-    HIPCHK(c, launch_cells_out(c, offsets, order));
+    if (offsets || order) HIPCHK(c, launch_cells_out(c, offsets, order));
     return FPM_OK;
 }
 
@@ -257,7 +373,8 @@ int fpm_build_verlet(fpm_ctx *c) {
     int r = ready(c);
     if (r) return r;
     HIPCHK(c, launch_force_rebuild(c));
-    HIPCHK(c, refresh_lists(c));
+    HIPCHK(c, refresh_and_account(c));
+    c->forces_valid = false;
     return FPM_OK;
 }
 
@@ -265,7 +382,7 @@ int fpm_get_neighbors(fpm_ctx *c, int32_t *counts, int32_t *cols) {
     int r = ready(c);
     if (r) return r;
     if (!counts || !cols) return fail(c, FPM_EINVAL, "null output");
-    HIPCHK(c, refresh_lists(c));
+    HIPCHK(c, refresh_and_account(c));
     HIPCHK(c, launch_neighbors_out(c, counts, cols));
     Ctl h;
     HIPCHK(c, hipMemcpyAsync(&h, c->st.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
@@ -277,9 +394,10 @@ int fpm_get_neighbors(fpm_ctx *c, int32_t *counts, int32_t *cols) {
 int fpm_lj_forces(fpm_ctx *c, const fpm_lj_params *p, double *out) {
     int r = ready(c);
     if (r) return r;
-    if (!p || (p->n_types != 1 && p->n_types != 2)) return fail(c, FPM_EINVAL, "bad LJ params");
-    HIPCHK(c, refresh_lists(c));
-    HIPCHK(c, launch_lj_forces(c, *p, out, nullptr, 0, 0));
+    if (!valid_lj(p)) return fail(c, FPM_EINVAL, "bad LJ params");
+    HIPCHK(c, refresh_and_account(c));
+    HIPCHK(c, timed(c, "lj_force", [&] { return launch_lj_forces(c, *p); }));
+    HIPCHK(c, launch_finalize(c, kFinForce, out, nullptr));
     c->forces_valid = true;
     return FPM_OK;
 }
@@ -289,29 +407,47 @@ int fpm_integrate(fpm_ctx *c, float dt, int32_t half) {
     if (r) return r;
     if (!isfinite(dt)) return fail(c, FPM_EINVAL, "dt must be finite");
     if (half != 0 && half != 1) return fail(c, FPM_EINVAL, "half must be 0 or 1");
-    HIPCHK(c, launch_integrate(c, dt, half ? kKickOnly : kKickDriftFirst, nullptr, 0));
+    HIPCHK(c, timed(c, "integrate", [&] {
+        return launch_integrate(c, dt, half ? kKickOnly : kKickDriftFirst);
+    }));
+    if (!half) {
+        HIPCHK(c, launch_finalize(c, kFinDisp, nullptr, nullptr));
+        c->forces_valid = false;
+    }
     return FPM_OK;
 }
 
 int fpm_step(fpm_ctx *c, const fpm_lj_params *p, float dt, int32_t nsteps, double *thermo) {
     int r = ready(c);
     if (r) return r;
-    if (!p || (p->n_types != 1 && p->n_types != 2)) return fail(c, FPM_EINVAL, "bad LJ params");
+    if (!valid_lj(p)) return fail(c, FPM_EINVAL, "bad LJ params");
     if (!isfinite(dt) || nsteps < 0) return fail(c, FPM_EINVAL, "bad dt or step count");
     if (nsteps == 0) return FPM_OK;
-    if (!c->forces_valid) {
-        HIPCHK(c, refresh_lists(c));
-        HIPCHK(c, launch_lj_forces(c, *p, nullptr, nullptr, 0, 0));
+    if (!c->forces_valid || c->build_pending || c->sph) {
+        HIPCHK(c, refresh_and_account(c));
+        HIPCHK(c, launch_lj_forces(c, *p));
         c->forces_valid = true;
     }
+    c->sph = false;
     const bool same = c->g_first && c->g_dt == dt && c->g_thermo == thermo &&
                       memcmp(&c->g_prm, p, sizeof(*p)) == 0;
     if (!same) {
         drop_graphs(c);
         int e;
-        if ((e = capture_steps(c, *p, dt, thermo, 1, true, &c->g_first))) return e;
-        if ((e = capture_steps(c, *p, dt, thermo, kChunk, false, &c->g_chunk))) return e;
-        if ((e = capture_steps(c, *p, dt, thermo, 1, false, &c->g_one))) return e;
+        const fpm_lj_params prm = *p;
+        e = capture(c, [&] { return lj_step_body(c, prm, dt, thermo, true); }, &c->g_first);
+        if (e) return e;
+        e = capture(c,
+                    [&] {
+                        hipError_t x = hipSuccess;
+                        for (int s = 0; s < kChunk && x == hipSuccess; s++)
+                            x = lj_step_body(c, prm, dt, thermo, false);
+                        return x;
+                    },
+                    &c->g_chunk);
+        if (e) return e;
+        e = capture(c, [&] { return lj_step_body(c, prm, dt, thermo, false); }, &c->g_one);
+        if (e) return e;
         c->g_dt = dt;
         c->g_thermo = thermo;
         c->g_prm = *p;
@@ -321,7 +457,63 @@ int fpm_step(fpm_ctx *c, const fpm_lj_params *p, float dt, int32_t nsteps, doubl
     int left = nsteps - 1;
     for (; left >= kChunk; left -= kChunk) HIPCHK(c, hipGraphLaunch(c->g_chunk, c->stream));
     for (; left > 0; left--) HIPCHK(c, hipGraphLaunch(c->g_one, c->stream));
-    HIPCHK(c, launch_integrate(c, dt, kKickOnly, thermo, INT_MAX));
+    HIPCHK(c, launch_integrate(c, dt, kKickOnly));
+    HIPCHK(c, launch_finalize(c, kFinBuild | kFinForce | kFinKE | kFinRow, nullptr, thermo));
+    return FPM_OK;
+}
+
+int fpm_sph_rates(fpm_ctx *c, const fpm_sph_params *p, float *dt_out) {
+    int r = ready(c);
+    if (r) return r;
+    if (!valid_sph(p)) return fail(c, FPM_EINVAL, "bad SPH params");
+    HIPCHK(c, refresh_and_account(c));
+    HIPCHK(c, timed(c, "sph_rates", [&] { return launch_sph_rates(c, *p); }));
+    HIPCHK(c, launch_sph_finalize(c, *p, 0, dt_out, nullptr));
+    c->sph = true;
+    c->forces_valid = true;
+    return FPM_OK;
+}
+
+int fpm_sph_step(fpm_ctx *c, const fpm_sph_params *p, int32_t nsteps, double *hist) {
+    int r = ready(c);
+    if (r) return r;
+    if (!valid_sph(p)) return fail(c, FPM_EINVAL, "bad SPH params");
+    if (nsteps < 0) return fail(c, FPM_EINVAL, "bad step count");
+    if (nsteps == 0) return FPM_OK;
+    if (!c->forces_valid || !c->sph || c->build_pending) {
+        HIPCHK(c, refresh_and_account(c));
+        HIPCHK(c, launch_sph_rates(c, *p));
+        HIPCHK(c, launch_sph_finalize(c, *p, 0, nullptr, nullptr));
+        c->forces_valid = true;
+        c->sph = true;
+    }
+    const bool same = c->s_first && c->s_hist == hist && memcmp(&c->s_prm, p, sizeof(*p)) == 0;
+    if (!same) {
+        drop_graphs(c);
+        const fpm_sph_params prm = *p;
+        int e = capture(c, [&] { return sph_step_body(c, prm, hist, true); }, &c->s_first);
+        if (e) return e;
+        e = capture(c,
+                    [&] {
+                        hipError_t x = hipSuccess;
+                        for (int s = 0; s < kChunk && x == hipSuccess; s++)
+                            x = sph_step_body(c, prm, hist, false);
+                        return x;
+                    },
+                    &c->s_chunk);
+        if (e) return e;
+        e = capture(c, [&] { return sph_step_body(c, prm, hist, false); }, &c->s_one);
+        if (e) return e;
+        c->s_hist = hist;
+        c->s_prm = *p;
+    }
+    HIPCHK(c, launch_reset_step(c));
+    HIPCHK(c, hipGraphLaunch(c->s_first, c->stream));
+    int left = nsteps - 1;
+    for (; left >= kChunk; left -= kChunk) HIPCHK(c, hipGraphLaunch(c->s_chunk, c->stream));
+    for (; left > 0; left--) HIPCHK(c, hipGraphLaunch(c->s_one, c->stream));
+    HIPCHK(c, launch_sph_integrate(c, *p, kKickOnly));
+    HIPCHK(c, launch_finalize(c, kFinBuild, nullptr, nullptr));
     return FPM_OK;
 }
 
@@ -340,12 +532,51 @@ int fpm_read_counters(fpm_ctx *c, int64_t out[3]) {
     int r = ready(c);
     if (r) return r;
     if (!out) return fail(c, FPM_EINVAL, "null output");
+    HIPCHK(c, launch_list_stats(c));
     Ctl h;
     HIPCHK(c, hipMemcpyAsync(&h, c->st.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     out[0] = h.n_rebuilds;
     out[1] = h.max_count;
     out[2] = h.total_count;
+    return FPM_OK;
+}
+
+int fpm_set_profiling(fpm_ctx *c, int32_t on) {
+    if (!c) return FPM_EINVAL;
+    if (!on) {
+        (void)hipStreamSynchronize(c->stream);
+        drop_timers(c);
+    }
+    c->profiling = on != 0;
+    return FPM_OK;
+}
+
+int fpm_kernel_time(fpm_ctx *c, const char *kernel, double *ms, int64_t *count) {
+    if (!c) return FPM_EINVAL;
+    if (!kernel || !ms || !count) return fail(c, FPM_EINVAL, "null argument");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double tot = 0.0;
+    int64_t k = 0;
+    hipError_t err = hipSuccess;
+    std::vector<fpm_ctx::Timed> keep;
+    for (auto &t : c->timed) {
+        if (t.name != kernel) {
+            keep.push_back(t);
+            continue;
+        }
+        float m = 0.f;
+        hipError_t e = hipEventElapsedTime(&m, t.start, t.stop);
+        (void)hipEventDestroy(t.start);
+        (void)hipEventDestroy(t.stop);
+        if (e != hipSuccess) err = e;
+        tot += m;
+        k++;
+    }
+    c->timed.swap(keep);
+    if (err != hipSuccess) return hip_fail(c, err, "hipEventElapsedTime");
+    *ms = k ? tot / (double)k : 0.0;
+    *count = k;
     return FPM_OK;
 }
 

@@ -1,5 +1,5 @@
-// Device geometry shared by the neighbour-search and interaction kernels:
-// the FP32 neighbour predicate, periodic images, cell coordinates.
+// Device helpers shared by the kernels: the FP32 neighbour predicate, periodic
+// images, cell coordinates, and wavefront/workgroup reductions.
 #pragma once
 
 #include "fpm_internal.h"
@@ -7,8 +7,9 @@
 namespace fpm {
 
 // One coordinate difference of the FP32 neighbour predicate (header of fpm.h):
-// t = xj - xi; on a periodic axis t > L/2 selects (xj - L) - xi and
-// t < -L/2 selects xj - (xi - L).  Every operation rounds separately.
+// t = xj - xi; on a periodic axis t > L/2 selects the image (xj - L) - xi and
+// t < -L/2 the image (xj + L) - xi, i.e. the ghost copy of j shifted by one
+// period.  Every operation rounds separately.
 __device__ __forceinline__ float img_delta(float xi, float xj, float L, float half, int per) {
 #pragma clang fp contract(off)
     float t = xj - xi;
@@ -17,11 +18,17 @@ __device__ __forceinline__ float img_delta(float xi, float xj, float L, float ha
             float s = xj - L;
             t = s - xi;
         } else if (t < -half) {
-            float s = xi - L;
-            t = xj - s;
+            float s = xj + L;
+            t = s - xi;
         }
     }
     return t;
+}
+
+// Image shift of j as seen from i on one axis: -1, 0 or +1 periods.
+__device__ __forceinline__ int img_shift(float xi, float xj, float half, int per) {
+    const float t = xj - xi;
+    return per ? (t > half ? -1 : (t < -half ? 1 : 0)) : 0;
 }
 
 // d2 = (dx*dx + dy*dy) + dz*dz without contraction.
@@ -30,6 +37,19 @@ __device__ __forceinline__ float dist2_pred(float3 pi, float3 pj, const Box &b) 
     float dx = img_delta(pi.x, pj.x, b.L[0], b.half[0], b.per[0]);
     float dy = img_delta(pi.y, pj.y, b.L[1], b.half[1], b.per[1]);
     float dz = img_delta(pi.z, pj.z, b.L[2], b.half[2], b.per[2]);
+    float xx = dx * dx;
+    float yy = dy * dy;
+    float zz = dz * dz;
+    float s = xx + yy;
+    return s + zz;
+}
+
+// The same predicate when no periodic image can be involved.
+__device__ __forceinline__ float dist2_direct(float3 pi, float3 pj) {
+#pragma clang fp contract(off)
+    float dx = pj.x - pi.x;
+    float dy = pj.y - pi.y;
+    float dz = pj.z - pi.z;
     float xx = dx * dx;
     float yy = dy * dy;
     float zz = dz * dz;
@@ -46,16 +66,10 @@ __device__ __forceinline__ bool uses_image(float3 pi, float3 pj, const Box &b) {
 
 // Exact FP64 separation xi - xj for the image chosen by the FP32 predicate.
 __device__ __forceinline__ double sep_axis(float xi, float xj, float L, float half, int per) {
-    double d = (double)xi - (double)xj;
-    if (per) {
-        float t = xj - xi;
-        if (t > half) d += (double)L;
-        else if (t < -half) d -= (double)L;
-    }
-    return d;
+    return (double)xi - (double)xj - (double)img_shift(xi, xj, half, per) * (double)L;
 }
 
-// Wrap a coordinate into [0, L) after at most one box length of travel.
+// Wrap a coordinate into [0, L) after less than one box length of travel.
 __device__ __forceinline__ float wrap_coord(float x, float L) {
 #pragma clang fp contract(off)
     if (x >= L) x = x - L;
@@ -82,11 +96,6 @@ __device__ __forceinline__ int cell_of(float3 p, const Box &b) {
     return (ix * b.nc[1] + iy) * b.nc[2] + iz;
 }
 
-// Blocked-ELL index of list entry k of slot i.
-__device__ __forceinline__ int64_t ell_index(int64_t i, int k, int cap) {
-    return ((i >> 6) * (int64_t)cap + k) * 64 + (i & 63);
-}
-
 __device__ __forceinline__ float3 xyz(float4 v) { return make_float3(v.x, v.y, v.z); }
 
 // Wavefront reductions (64 lanes).
@@ -95,41 +104,43 @@ __device__ __forceinline__ double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
-__device__ __forceinline__ float wave_max(float v) {
+__device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
     return v;
 }
-__device__ __forceinline__ float wave_min(float v) {
+__device__ __forceinline__ double wave_min(double v) {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
-    return v;
-}
-__device__ __forceinline__ int wave_max_i(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
     return v;
 }
 
-// Last-block-done protocol: every block calls this once after publishing its
-// partial results; it returns true in exactly one block (the last to arrive),
-// after which that block may read every block's partials.  The counter is
-// reset by the last block.
-__device__ __forceinline__ bool last_block(uint32_t *counter) {
-    __shared__ bool is_last;
+// Workgroup reduction of NV values (op 0 = sum, 1 = max, 2 = min) in a fixed
+// order; thread 0 writes the results to part[slot[k] * pstride + blockIdx.x]
+// (one array per slot, so the finalize kernel reads them coalesced).
+template <int NV>
+__device__ __forceinline__ void block_partials(double (&v)[NV], const int (&slot)[NV],
+                                               const int (&op)[NV], double *part,
+                                               int pstride) {
+    __shared__ double lds[kBlock / 64][NV];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < NV; c++)
+        v[c] = op[c] == 0 ? wave_sum(v[c]) : (op[c] == 1 ? wave_max(v[c]) : wave_min(v[c]));
+    if (lane == 0)
+#pragma unroll
+        for (int c = 0; c < NV; c++) lds[w][c] = v[c];
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
-        uint32_t t = atomicAdd(counter, 1u);
-        is_last = (t == gridDim.x - 1);
-        if (is_last) {
-            __threadfence();
-            atomicExch(counter, 0u);
+        const int nw = blockDim.x >> 6;
+#pragma unroll
+        for (int c = 0; c < NV; c++) {
+            double s = lds[0][c];
+            for (int k = 1; k < nw; k++)
+                s = op[c] == 0 ? s + lds[k][c] : (op[c] == 1 ? fmax(s, lds[k][c]) : fmin(s, lds[k][c]));
+            part[(int64_t)slot[c] * pstride + blockIdx.x] = s;
         }
     }
-    __syncthreads();
-    if (is_last) __threadfence();
-    return is_last;
 }
 
 }  // namespace fpm

@@ -3,16 +3,19 @@
 // 24 eps (2 sig^12 / rn^7 - sig^6 / rn^4) (xp - xq), rn = |xp - xq|^2, and the
 // pair is dropped when rn > r_cut^2).
 //
-// One lane per cell-sorted particle walks its list (full list: every pair is
-// seen from both sides, so no scattered writes).  Set membership follows the
-// FP32 predicate exactly; the pair physics is evaluated in FP64 from the exact
-// separation of the FP32 coordinates and accumulated per lane in FP64.  The
-// FP64 squared distance r2 decides membership directly unless it lies within
-// a relative 1e-6 of r_cut^2, where the FP32 predicate (whose error is below
-// 5 ulp, i.e. 3e-7 relative) is evaluated instead.  Energy and virial are
-// reduced per wavefront with shuffles, per workgroup through LDS, and across
-// workgroups by the last workgroup in a fixed order, so the totals do not
-// depend on scheduling.
+// One lane per cell-sorted particle walks its full list (every pair is seen
+// from both sides, so there are no scattered writes).  The list is read eight
+// entries at a time (two 16-byte loads per lane) and the eight neighbour
+// positions are gathered before any is used, so each lane keeps eight loads in
+// flight instead of waiting on every entry.
+//
+// Set membership follows the FP32 predicate exactly; the pair physics is
+// evaluated in FP64 from the exact separation of the FP32 coordinates and
+// accumulated per lane in FP64.  The FP64 squared distance decides membership
+// directly unless it lies within a relative 1e-6 of r_cut^2, where the FP32
+// predicate (whose error is below 5 ulp, about 3e-7 relative) is evaluated.
+// Energy and virial partials go to one row per workgroup; the finalize kernel
+// sums them in a fixed order.
 #include "geom.h"
 
 namespace fpm {
@@ -23,72 +26,96 @@ struct LJCoef {
     double c6[3];   // 4 eps sig^6
 };
 
-// 1/x in FP64 from the hardware estimate refined by two Newton steps.
+// 1/x in FP64: the hardware estimate refined by one Newton step.
 __device__ __forceinline__ double recip(double x) {
     double y = __builtin_amdgcn_rcp(x);
     double e = fma(-x, y, 1.0);
-    y = fma(y, e, y);
-    e = fma(-x, y, 1.0);
     return fma(y, e, y);
 }
 
-// Block-wide fixed-order sum of NV doubles per thread; result valid in thread 0.
-template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double (*lds)[NV]) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-    for (int c = 0; c < NV; c++) v[c] = wave_sum(v[c]);
-    if (lane == 0)
-#pragma unroll
-        for (int c = 0; c < NV; c++) lds[w][c] = v[c];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int nw = blockDim.x >> 6;
-#pragma unroll
-        for (int c = 0; c < NV; c++) {
-            double s = 0.0;
-            for (int k = 0; k < nw; k++) s += lds[k][c];
-            v[c] = s;
+// Per-lane accumulators.  The virial needs no per-pair work: summed over all
+// particles, 1/2 sum_ij r_ij (x) f_ij with r_ij = x_i - x_j + s_ij (s_ij the
+// periodic shift, f_ji = -f_ij, s_ji = -s_ij) equals
+// sum_i x_i (x) F_i + 1/2 sum_ij s_ij (x) f_ij, so each lane adds x_i (x) F_i
+// once and only image pairs add a shift term (wx*).
+struct Acc {
+    double fx = 0.0, fy = 0.0, fz = 0.0, u = 0.0;
+    double wxx = 0.0, wyy = 0.0, wzz = 0.0, wxy = 0.0, wxz = 0.0, wyz = 0.0;
+};
+
+// One list entry.  Padding entries point at a particle far away, so every
+// entry can be processed without a bounds test.
+template <int NT, bool IMG>
+__device__ __forceinline__ void pair(Acc &a, float3 pi, double xi, double yi, double zi, int ti,
+                                     float4 q, const Box &b, float rc2, double rc2lo,
+                                     double rc2hi, const LJCoef &cf) {
+    double dx = xi - (double)q.x, dy = yi - (double)q.y, dz = zi - (double)q.z;
+    double sx = 0.0, sy = 0.0, sz = 0.0;  // periodic shift of this pair
+    if (IMG) {
+        sx = -(double)img_shift(pi.x, q.x, b.half[0], b.per[0]) * (double)b.L[0];
+        sy = -(double)img_shift(pi.y, q.y, b.half[1], b.per[1]) * (double)b.L[1];
+        sz = -(double)img_shift(pi.z, q.z, b.half[2], b.per[2]) * (double)b.L[2];
+        dx += sx;
+        dy += sy;
+        dz += sz;
+    }
+    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    bool in = r2 <= rc2lo;
+    if (!in && r2 <= rc2hi)
+        in = (IMG ? dist2_pred(pi, xyz(q), b) : dist2_direct(pi, xyz(q))) <= rc2;
+    if (in) {
+        double c12 = cf.c12[0], c6 = cf.c6[0];
+        if (NT == 2) {
+            const int tp = ti + __float_as_int(q.w);
+            c12 = tp == 0 ? cf.c12[0] : (tp == 1 ? cf.c12[1] : cf.c12[2]);
+            c6 = tp == 0 ? cf.c6[0] : (tp == 1 ? cf.c6[1] : cf.c6[2]);
+        }
+        const double r2i = recip(r2);
+        const double r6i = r2i * r2i * r2i;
+        const double s = r6i * r2i * fma(12.0 * c12, r6i, -6.0 * c6);
+        a.u = fma(r6i, fma(c12, r6i, -c6), a.u);
+        a.fx = fma(s, dx, a.fx);
+        a.fy = fma(s, dy, a.fy);
+        a.fz = fma(s, dz, a.fz);
+        if (IMG) {
+            const double hx = 0.5 * s * sx, hy = 0.5 * s * sy, hz = 0.5 * s * sz;
+            a.wxx = fma(hx, dx, a.wxx);
+            a.wyy = fma(hy, dy, a.wyy);
+            a.wzz = fma(hz, dz, a.wzz);
+            a.wxy = fma(hx, dy, a.wxy);
+            a.wxz = fma(hx, dz, a.wxz);
+            a.wyz = fma(hy, dz, a.wyz);
         }
     }
 }
 
-// Sum of part[b * 8 + c] over all blocks b, by one block, in a fixed order.
-template <int NV>
-__device__ void reduce_partials(const double *part, int nblocks, double (&tot)[NV]) {
-    __shared__ double red[kBlock][NV];
-    const int t = threadIdx.x;
-    double acc[NV];
+// Walks a list padded to a multiple of eight entries.
+template <int NT, bool IMG>
+__device__ __forceinline__ void walk(Acc &a, const float4 *__restrict__ pos,
+                                     const int4 *__restrict__ lst, int cnt, float4 pi4,
+                                     const Box &b, float rc2, double rc2lo, double rc2hi,
+                                     const LJCoef &cf) {
+    const float3 pi = xyz(pi4);
+    const double xi = pi.x, yi = pi.y, zi = pi.z;
+    const int ti = __float_as_int(pi4.w);
+    for (int k = 0; k < cnt; k += 8) {
+        const int4 e0 = lst[(k >> 2) * 64];
+        const int4 e1 = lst[((k >> 2) + 1) * 64];
+        const int jj[8] = {e0.x, e0.y, e0.z, e0.w, e1.x, e1.y, e1.z, e1.w};
+        float4 q[8];
 #pragma unroll
-    for (int c = 0; c < NV; c++) acc[c] = 0.0;
-    for (int bidx = t; bidx < nblocks; bidx += blockDim.x)
+        for (int u = 0; u < 8; u++) q[u] = pos[jj[u]];
 #pragma unroll
-        for (int c = 0; c < NV; c++) acc[c] += part[(int64_t)bidx * 8 + c];
-#pragma unroll
-    for (int c = 0; c < NV; c++) red[t][c] = acc[c];
-    __syncthreads();
-    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
-        if (t < s)
-#pragma unroll
-            for (int c = 0; c < NV; c++) red[t][c] += red[t + s][c];
-        __syncthreads();
+        for (int u = 0; u < 8; u++)
+            pair<NT, IMG>(a, pi, xi, yi, zi, ti, q[u], b, rc2, rc2lo, rc2hi, cf);
     }
-#pragma unroll
-    for (int c = 0; c < NV; c++) tot[c] = red[0][c];
 }
 
 template <int NT>
 __global__ __launch_bounds__(kBlock) void k_lj(State st, Box b, int64_t n, float rc2,
-                                               double rc2lo, double rc2hi, LJCoef cf, int cap,
-                                               double *out, double *thermo, int rows,
-                                               int count_step) {
-    Ctl *ctl = st.ctl;
-    const int cur = ctl->cur;
-    const float4 *__restrict__ pos = st.pos[cur];
+                                               double rc2lo, double rc2hi, LJCoef cf, int cap4) {
+    const float4 *__restrict__ pos = st.pos[0];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-
-    double fx = 0.0, fy = 0.0, fz = 0.0, u = 0.0;
-    double wxx = 0.0, wyy = 0.0, wzz = 0.0, wxy = 0.0, wxz = 0.0, wyz = 0.0;
     uint32_t nn = 0;
     float4 pi4 = make_float4(0.f, 0.f, 0.f, 0.f);
     if (i < n) {
@@ -97,88 +124,34 @@ __global__ __launch_bounds__(kBlock) void k_lj(State st, Box b, int64_t n, float
     }
     const bool img_wave = __ballot((nn & kWrapBit) != 0) != 0;
     const int cnt = (int)(nn & ~kWrapBit);
-    const float3 pi = xyz(pi4);
-    const double xi = pi.x, yi = pi.y, zi = pi.z;
-    const int ti = __float_as_int(pi4.w);
-    const int32_t *__restrict__ lst = st.nbr + ((i >> 6) * (int64_t)cap) * 64 + (i & 63);
-
-    for (int k = 0; k < cnt; k++) {
-        const int j = lst[(int64_t)k * 64];
-        const float4 q = pos[j];
-        double dx, dy, dz;
-        if (img_wave) {
-            dx = sep_axis(pi.x, q.x, b.L[0], b.half[0], b.per[0]);
-            dy = sep_axis(pi.y, q.y, b.L[1], b.half[1], b.per[1]);
-            dz = sep_axis(pi.z, q.z, b.L[2], b.half[2], b.per[2]);
-        } else {
-            dx = xi - (double)q.x;
-            dy = yi - (double)q.y;
-            dz = zi - (double)q.z;
-        }
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        bool in = r2 <= rc2lo;
-        if (!in && r2 <= rc2hi) in = dist2_pred(pi, xyz(q), b) <= rc2;
-        if (in) {
-            double c12 = cf.c12[0], c6 = cf.c6[0];
-            if (NT == 2) {
-                const int tp = ti + __float_as_int(q.w);
-                c12 = tp == 0 ? cf.c12[0] : (tp == 1 ? cf.c12[1] : cf.c12[2]);
-                c6 = tp == 0 ? cf.c6[0] : (tp == 1 ? cf.c6[1] : cf.c6[2]);
-            }
-            const double r2i = recip(r2);
-            const double r6i = r2i * r2i * r2i;
-            const double s = r6i * r2i * fma(12.0 * c12, r6i, -6.0 * c6);
-            u = fma(r6i, fma(c12, r6i, -c6), u);
-            const double sx = s * dx, sy = s * dy, sz = s * dz;
-            fx += sx;
-            fy += sy;
-            fz += sz;
-            wxx = fma(sx, dx, wxx);
-            wyy = fma(sy, dy, wyy);
-            wzz = fma(sz, dz, wzz);
-            wxy = fma(sx, dy, wxy);
-            wxz = fma(sx, dz, wxz);
-            wyz = fma(sy, dz, wyz);
-        }
-    }
+    const int4 *lst = reinterpret_cast<const int4 *>(st.nbr) +
+                      ((i >> 6) * (int64_t)cap4) * 64 + (i & 63);
+    Acc a;
+    if (img_wave)
+        walk<NT, true>(a, pos, lst, cnt, pi4, b, rc2, rc2lo, rc2hi, cf);
+    else
+        walk<NT, false>(a, pos, lst, cnt, pi4, b, rc2, rc2lo, rc2hi, cf);
     if (i < n) {
-        st.frc[i] = make_float4((float)fx, (float)fy, (float)fz, 0.f);
-        if (!isfinite(fx) || !isfinite(fy) || !isfinite(fz)) atomicOr(&ctl->nonfinite, 1);
+        st.frc[i] = make_float4((float)a.fx, (float)a.fy, (float)a.fz, (float)(0.5 * a.u));
+        if (!isfinite(a.fx) || !isfinite(a.fy) || !isfinite(a.fz)) st.ctl->nonfinite = 1;
     }
-
-    __shared__ double lds[kBlock / 64][7];
-    double v[7] = {0.5 * u, 0.5 * wxx, 0.5 * wyy, 0.5 * wzz, 0.5 * wxy, 0.5 * wxz, 0.5 * wyz};
-    block_sum<7>(v, lds);
-    if (threadIdx.x == 0)
-#pragma unroll
-        for (int c = 0; c < 7; c++) st.part[(int64_t)blockIdx.x * 8 + c] = v[c];
-    if (last_block(&ctl->done[2])) {
-        double tot[7];
-        reduce_partials<7>(st.part, gridDim.x, tot);
-        if (threadIdx.x == 0) {
-            ctl->thermo[0] = tot[0];
-            for (int c = 1; c < 7; c++) ctl->thermo[c + 1] = tot[c];
-            if (out) {
-                out[0] = tot[0];
-                out[1] = 0.0;
-                for (int c = 1; c < 7; c++) out[c + 1] = tot[c];
-            }
-            if (count_step) {
-                const int row = ctl->step;
-                if (thermo && row < rows) {
-                    thermo[(int64_t)row * 8 + 0] = tot[0];
-                    for (int c = 1; c < 7; c++) thermo[(int64_t)row * 8 + c + 1] = tot[c];
-                }
-                ctl->step = row + 1;
-            }
-        }
-    }
+    const double xi = pi4.x, yi = pi4.y, zi = pi4.z;
+    double v[7] = {0.5 * a.u,
+                   fma(xi, a.fx, a.wxx),
+                   fma(yi, a.fy, a.wyy),
+                   fma(zi, a.fz, a.wzz),
+                   fma(xi, a.fy, a.wxy),
+                   fma(xi, a.fz, a.wxz),
+                   fma(yi, a.fz, a.wyz)};
+    const int slot[7] = {kSlotU, kSlotW, kSlotW + 1, kSlotW + 2, kSlotW + 3, kSlotW + 4,
+                         kSlotW + 5};
+    const int op[7] = {0, 0, 0, 0, 0, 0, 0};
+    block_partials<7>(v, slot, op, st.part, st.pstride);
 }
 
 }  // namespace
 
-hipError_t launch_lj_forces(fpm_ctx *c, const fpm_lj_params &p, double *out, double *thermo,
-                            int32_t rows, int count_step) {
+hipError_t launch_lj_forces(fpm_ctx *c, const fpm_lj_params &p) {
     LJCoef cf;
     for (int k = 0; k < 3; k++) {
         const double e = (double)p.eps[k], s = (double)p.sig[k];
@@ -186,14 +159,15 @@ hipError_t launch_lj_forces(fpm_ctx *c, const fpm_lj_params &p, double *out, dou
         cf.c12[k] = 4.0 * e * s6 * s6;
         cf.c6[k] = 4.0 * e * s6;
     }
-    const double rc2lo = (double)c->rc2 * (1.0 - 1e-6), rc2hi = (double)c->rc2 * (1.0 + 1e-6);
+    const double band = predicate_band(c);
+    const double rc2lo = (double)c->rc2 * (1.0 - band), rc2hi = (double)c->rc2 * (1.0 + band);
     const unsigned g = (unsigned)((c->n_pad + kBlock - 1) / kBlock);
     if (p.n_types == 2)
         hipLaunchKernelGGL(k_lj<2>, dim3(g), dim3(kBlock), 0, c->stream, c->st, c->box, c->n,
-                           c->rc2, rc2lo, rc2hi, cf, c->cap, out, thermo, rows, count_step);
+                           c->rc2, rc2lo, rc2hi, cf, c->cap4);
     else
         hipLaunchKernelGGL(k_lj<1>, dim3(g), dim3(kBlock), 0, c->stream, c->st, c->box, c->n,
-                           c->rc2, rc2lo, rc2hi, cf, c->cap, out, thermo, rows, count_step);
+                           c->rc2, rc2lo, rc2hi, cf, c->cap4);
     return hipGetLastError();
 }
 

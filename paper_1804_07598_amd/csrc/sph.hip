@@ -1,0 +1,314 @@
+// Weakly compressible SPH (section 4.2, Eqs. 1-5) over the Verlet list.
+//
+// Per particle a and each neighbour b within 2h (FP32 predicate, as for LJ):
+//   dv_a/dt   = -sum_b m ((P_a + P_b)/(rho_a rho_b) + Pi_ab) gradW_ab + g     (Eq. 1)
+//   drho_a/dt =  sum_b m v_ab . gradW_ab                                     (Eq. 2)
+//   P = B ((rho/rho0)^gamma - 1), B = c0^2 rho0 / gamma                      (Eqs. 3-4)
+//   Pi_ab = -alpha c0 mu_ab / rhobar_ab when v_ab . x_ab < 0, else 0,
+//   mu_ab = h v_ab . x_ab / (|x_ab|^2 + eta^2), rhobar_ab = (rho_a + rho_b)/2 (Eq. 5)
+// with x_ab = x_a - x_b, v_ab = v_a - v_b and the Wendland C2 kernel
+// W(q) = a_D (1 - q/2)^4 (2q + 1), q = r/h, a_D = 21 / (16 pi h^3), whose
+// gradient is gradW_ab = -(5 a_D / h^2) (1 - q/2)^3 x_ab.
+// Boundary particles (kind 1) take part in every sum and evolve their density
+// by Eq. 2, but carry no acceleration.  Pair terms are evaluated in FP64 from
+// exact FP32 separations (the pressure terms cancel to within a few percent of
+// gravity in a resting column, which FP32 pair terms cannot resolve to 1e-5).
+//
+// Time stepping is kick-drift-kick on (v, rho) with the time step chosen on
+// the device from the CFL terms of the latest rates:
+//   dt = cfl * min(min_a sqrt(h / |a_a|), h / (c0 + max_ab |mu_ab|)).
+#include "geom.h"
+
+namespace fpm {
+namespace {
+
+struct SphCoef {
+    double h, m, rho0, inv_rho0, B, gamma, alpha_c0, eta2, kgrad;  // kgrad = 5 a_D / h^2
+    double rc2lo, rc2hi;
+    float g[3];
+    int gamma7;
+};
+
+__device__ __forceinline__ double tait(double rho, const SphCoef &k) {
+    const double x = rho * k.inv_rho0;
+    double xg;
+    if (k.gamma7) {
+        const double x2 = x * x, x4 = x2 * x2;
+        xg = x4 * x2 * x;
+    } else {
+        xg = pow(x, k.gamma);
+    }
+    return k.B * (xg - 1.0);
+}
+
+struct SphAcc {
+    double ax = 0.0, ay = 0.0, az = 0.0, dr = 0.0, mu = 0.0;
+};
+
+template <bool IMG>
+__device__ __forceinline__ void sph_pair(SphAcc &s, float3 pi, double xi, double yi, double zi,
+                                         float4 vi, double Pa_over, float4 q, float4 w,
+                                         const Box &b, float rc2, const SphCoef &k) {
+    double dx, dy, dz;
+    if (IMG) {
+        dx = sep_axis(pi.x, q.x, b.L[0], b.half[0], b.per[0]);
+        dy = sep_axis(pi.y, q.y, b.L[1], b.half[1], b.per[1]);
+        dz = sep_axis(pi.z, q.z, b.L[2], b.half[2], b.per[2]);
+    } else {
+        dx = xi - (double)q.x;
+        dy = yi - (double)q.y;
+        dz = zi - (double)q.z;
+    }
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    bool in = r2 <= k.rc2lo;
+    if (!in && r2 <= k.rc2hi)
+        in = (IMG ? dist2_pred(pi, xyz(q), b) : dist2_direct(pi, xyz(q))) <= rc2;
+    if (in) {
+        const double r = sqrt(r2);
+        const double t = 1.0 - 0.5 * r / k.h;
+        const double gw = -k.kgrad * t * t * t;  // gradW = gw * x_ab
+        const double rho_b = (double)w.w;
+        const double vx = (double)vi.x - (double)w.x, vy = (double)vi.y - (double)w.y,
+                     vz = (double)vi.z - (double)w.z;
+        const double vr = vx * dx + vy * dy + vz * dz;
+        // continuity, Eq. 2
+        s.dr += k.m * gw * vr;
+        // momentum, Eq. 1 (pressure part uses (P_a + P_b) / (rho_a rho_b))
+        const double Pb = tait(rho_b, k);
+        const double rho_a = (double)vi.w;
+        double term = (Pa_over + Pb) / (rho_a * rho_b);
+        const double mu = k.h * vr / (r2 + k.eta2);
+        if (vr < 0.0) term += -k.alpha_c0 * mu / (0.5 * (rho_a + rho_b));
+        s.mu = fmax(s.mu, fabs(mu));
+        const double f = -k.m * term * gw;
+        s.ax += f * dx;
+        s.ay += f * dy;
+        s.az += f * dz;
+    }
+}
+
+template <bool IMG>
+__device__ __forceinline__ void sph_walk(SphAcc &s, const float4 *__restrict__ pos,
+                                         const float4 *__restrict__ vel,
+                                         const int4 *__restrict__ lst, int cnt, int self,
+                                         float4 pi4, float4 vi, double Pa, const Box &b,
+                                         float rc2, const SphCoef &k) {
+    const float3 pi = xyz(pi4);
+    const double xi = pi.x, yi = pi.y, zi = pi.z;
+    for (int kk = 0; kk < cnt; kk += 4) {
+        const int4 e = lst[(kk >> 2) * 64];
+        int jj[4] = {e.x, e.y, e.z, e.w};
+        float4 q[4], w[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int j = kk + u < cnt ? jj[u] : self;
+            q[u] = pos[j];
+            w[u] = vel[j];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            if (kk + u < cnt) sph_pair<IMG>(s, pi, xi, yi, zi, vi, Pa, q[u], w[u], b, rc2, k);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sph_rates(State st, Box b, int64_t n, float rc2,
+                                                      SphCoef k, int cap4) {
+    const float4 *__restrict__ pos = st.pos[0];
+    const float4 *__restrict__ vel = st.vel[0];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t nn = 0;
+    float4 pi4 = make_float4(0.f, 0.f, 0.f, 0.f), vi = make_float4(0.f, 0.f, 0.f, 1.f);
+    if (i < n) {
+        nn = st.nnb[i];
+        pi4 = pos[i];
+        vi = vel[i];
+    }
+    const bool img_wave = __ballot((nn & kWrapBit) != 0) != 0;
+    const int cnt = (int)(nn & ~kWrapBit);
+    const int4 *lst = reinterpret_cast<const int4 *>(st.nbr) +
+                      ((i >> 6) * (int64_t)cap4) * 64 + (i & 63);
+    const double Pa = tait((double)vi.w, k);
+    SphAcc s;
+    if (img_wave)
+        sph_walk<true>(s, pos, vel, lst, cnt, (int)i, pi4, vi, Pa, b, rc2, k);
+    else
+        sph_walk<false>(s, pos, vel, lst, cnt, (int)i, pi4, vi, Pa, b, rc2, k);
+    const bool fluid = __float_as_int(pi4.w) == 0;
+    double accmin = 1e300;
+    if (i < n) {
+        float4 out;
+        if (fluid) {
+            out = make_float4((float)(s.ax + k.g[0]), (float)(s.ay + k.g[1]),
+                              (float)(s.az + k.g[2]), (float)s.dr);
+            const double ax = s.ax + k.g[0], ay = s.ay + k.g[1], az = s.az + k.g[2];
+            const double am = sqrt(ax * ax + ay * ay + az * az);
+            accmin = am > 0.0 ? k.h / am : 1e300;
+        } else {
+            out = make_float4(0.f, 0.f, 0.f, (float)s.dr);
+        }
+        st.frc[i] = out;
+        if (!isfinite(out.x) || !isfinite(out.y) || !isfinite(out.z) || !isfinite(out.w))
+            st.ctl->nonfinite = 1;
+    }
+    double v[2] = {s.mu, accmin};
+    const int slot[2] = {kSlotMu, kSlotAcc};
+    const int op[2] = {1, 2};
+    block_partials<2>(v, slot, op, st.part, st.pstride);
+}
+
+// Kick-drift-kick on (v, rho): the closing half kick of the previous step and
+// the opening half kick of this one are fused; boundary particles keep x and v.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_sph_integrate(State st, Box b, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const Ctl *ctl = st.ctl;
+    const float dt = ctl->sph_dt, dtl = ctl->sph_dt_last;
+    const float hk = MODE == kKickDriftFirst ? 0.5f * dt
+                                             : (MODE == kKickOnly ? 0.5f * dtl : 0.5f * (dtl + dt));
+    double ke = 0.0, vmax = 0.0, d2 = 0.0;
+    if (i < n) {
+        float4 v = st.vel[0][i];
+        const float4 f = st.frc[i];
+        float4 p = st.pos[0][i];
+        const bool fluid = __float_as_int(p.w) == 0;
+        v.w += hk * f.w;
+        if (fluid) {
+            v.x += hk * f.x;
+            v.y += hk * f.y;
+            v.z += hk * f.z;
+            if (MODE != kKickOnly) {
+                p.x += dt * v.x;
+                p.y += dt * v.y;
+                p.z += dt * v.z;
+                st.pos[0][i] = p;
+                if (!isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z)) st.ctl->nonfinite = 1;
+            }
+        }
+        st.vel[0][i] = v;
+        const double v2 = (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z;
+        ke = 0.5 * v2;  // per unit mass; the finalize multiplies by m
+        vmax = sqrt(v2);
+        if (MODE != kKickOnly) d2 = dist2_pred(xyz(st.xbuild[i]), xyz(p), b);
+    }
+    double v3[3] = {ke, vmax, d2};
+    const int slot[3] = {kSlotKE, kSlotVmax, kSlotDisp};
+    const int op[3] = {0, 1, 1};
+    block_partials<3>(v3, slot, op, st.part, st.pstride);
+}
+
+// Reduces the CFL terms of the last rates into the next time step; with
+// `advance`, first moves the current step into the history (time, dt, kinetic
+// energy and largest speed of the last integrate).
+__global__ __launch_bounds__(1024) void k_sph_finalize(State st, int nblk, SphCoef k, float cfl,
+                                                       float c0, int advance, float *dt_out,
+                                                       double *hist) {
+    __shared__ double red[16][4];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    double mu = 0.0, acc = 1e300, ke = 0.0, vmax = 0.0;
+    const double *P = st.part;
+    const int64_t S = st.pstride;
+    for (int r = t; r < nblk; r += 1024) {
+        mu = fmax(mu, P[kSlotMu * S + r]);
+        acc = fmin(acc, P[kSlotAcc * S + r]);
+        if (advance) {
+            ke += P[kSlotKE * S + r];
+            vmax = fmax(vmax, P[kSlotVmax * S + r]);
+        }
+    }
+    mu = wave_max(mu);
+    acc = wave_min(acc);
+    ke = wave_sum(ke);
+    vmax = wave_max(vmax);
+    if (lane == 0) {
+        red[w][0] = mu;
+        red[w][1] = acc;
+        red[w][2] = ke;
+        red[w][3] = vmax;
+    }
+    __syncthreads();
+    if (t != 0) return;
+    for (int q = 1; q < 16; q++) {
+        mu = fmax(red[0][0], red[q][0]);
+        red[0][0] = mu;
+        red[0][1] = fmin(red[0][1], red[q][1]);
+        red[0][2] += red[q][2];
+        red[0][3] = fmax(red[0][3], red[q][3]);
+    }
+    mu = red[0][0];
+    acc = red[0][1];
+    ke = red[0][2];
+    vmax = red[0][3];
+    Ctl *ctl = st.ctl;
+    if (advance) {
+        const float dtu = ctl->sph_dt;
+        ctl->sph_dt_last = dtu;
+        ctl->sph_time += (double)dtu;
+        const int row = ctl->step;
+        if (hist) {
+            hist[(int64_t)row * 4 + 0] = ctl->sph_time;
+            hist[(int64_t)row * 4 + 1] = (double)dtu;
+            hist[(int64_t)row * 4 + 2] = ke * k.m;
+            hist[(int64_t)row * 4 + 3] = vmax;
+        }
+        ctl->step = row + 1;
+    }
+    const double dt = (double)cfl * fmin(sqrt(acc), k.h / ((double)c0 + mu));
+    ctl->sph_dt = (float)dt;
+    if (dt_out) *dt_out = (float)dt;
+}
+
+SphCoef make_coef(const fpm_ctx *c, const fpm_sph_params &p) {
+    SphCoef k;
+    k.h = p.h;
+    k.m = p.mass;
+    k.rho0 = p.rho0;
+    k.inv_rho0 = 1.0 / (double)p.rho0;
+    k.gamma = p.gamma;
+    k.gamma7 = p.gamma == 7.0f;
+    k.B = (double)p.c0 * (double)p.c0 * (double)p.rho0 / (double)p.gamma;
+    k.alpha_c0 = (double)p.alpha * (double)p.c0;
+    k.eta2 = p.eta2;
+    const double h = p.h;
+    const double aD = 21.0 / (16.0 * 3.14159265358979323846 * h * h * h);
+    k.kgrad = 5.0 * aD / (h * h);
+    const double rc = 2.0 * (double)p.h;
+    (void)rc;
+    const double band = predicate_band(c);
+    k.rc2lo = (double)c->rc2 * (1.0 - band);
+    k.rc2hi = (double)c->rc2 * (1.0 + band);
+    for (int a = 0; a < 3; a++) k.g[a] = p.g[a];
+    return k;
+}
+
+}  // namespace
+
+hipError_t launch_sph_rates(fpm_ctx *c, const fpm_sph_params &p) {
+    const SphCoef k = make_coef(c, p);
+    hipLaunchKernelGGL(k_sph_rates, dim3(c->nblk), dim3(kBlock), 0, c->stream, c->st, c->box, c->n,
+                       c->rc2, k, c->cap4);
+    return hipGetLastError();
+}
+
+hipError_t launch_sph_integrate(fpm_ctx *c, const fpm_sph_params &p, int mode) {
+    (void)p;
+    if (mode == kKickDriftFirst)
+        hipLaunchKernelGGL(k_sph_integrate<kKickDriftFirst>, dim3(c->nblk), dim3(kBlock), 0,
+                           c->stream, c->st, c->box, c->n);
+    else if (mode == kKickKickDrift)
+        hipLaunchKernelGGL(k_sph_integrate<kKickKickDrift>, dim3(c->nblk), dim3(kBlock), 0,
+                           c->stream, c->st, c->box, c->n);
+    else
+        hipLaunchKernelGGL(k_sph_integrate<kKickOnly>, dim3(c->nblk), dim3(kBlock), 0, c->stream,
+                           c->st, c->box, c->n);
+    return hipGetLastError();
+}
+
+hipError_t launch_sph_finalize(fpm_ctx *c, const fpm_sph_params &p, int advance, float *dt_out,
+                               double *hist) {
+    const SphCoef k = make_coef(c, p);
+    hipLaunchKernelGGL(k_sph_finalize, dim3(1), dim3(1024), 0, c->stream, c->st, c->nblk, k, p.cfl,
+                       p.c0, advance, dt_out, hist);
+    return hipGetLastError();
+}
+
+}  // namespace fpm

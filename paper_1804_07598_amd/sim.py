@@ -114,6 +114,32 @@ class ParticleSim:
         F.fpm_step(self.ctx, F.lj_params(eps, sig, n_types), dt, nsteps, thermo)
         return thermo
 
+    # ---- SPH ----
+    def set_density(self, rho):
+        r = torch.as_tensor(rho, dtype=torch.float32, device=self.device).contiguous()
+        F.fpm_set_density(self.ctx, r)
+        self._rho = r
+
+    def sph_rates(self, prm):
+        """Rates of Eqs. 1-2 at the current state; returns the CFL dt (device, FP32)."""
+        dt = torch.zeros(1, dtype=torch.float32, device=self.device)
+        F.fpm_sph_rates(self.ctx, prm, dt)
+        return dt
+
+    def sph_step(self, nsteps: int, prm, hist: torch.Tensor | None = None):
+        """nsteps KDK steps; returns the (nsteps, 4) FP64 history {t, dt, KE, max|v|}."""
+        if hist is None:
+            hist = torch.zeros((max(nsteps, 1), 4), dtype=torch.float64, device=self.device)
+        F.fpm_sph_step(self.ctx, prm, nsteps, hist)
+        return hist
+
+    def get_sph(self):
+        """(rho, drho/dt) in caller order."""
+        rho = torch.empty(self.n, dtype=torch.float32, device=self.device)
+        dr = torch.empty_like(rho)
+        F.fpm_get_sph(self.ctx, rho, dr)
+        return rho, dr
+
     # ---- status ----
     def check(self):
         F.fpm_check(self.ctx)
