@@ -74,10 +74,14 @@ def lib():
         if hasattr(L, "oracle_lj_vjp"):
             L.oracle_lj_vjp.argtypes = [C.c_int64, f32p, _opt(i32p), f32p, i32p, C.c_float, f64p,
                                         f64p, f64p, f64p, f64p]
-            L.oracle_traj_adjoint.restype = C.c_double
-            L.oracle_traj_adjoint.argtypes = [C.c_int64, f64p, f64p, _opt(i32p), f64p, i32p,
-                                              C.c_double, f64p, f64p, C.c_double, C.c_double,
-                                              C.c_int32, C.c_int32, f64p, f64p, f64p]
+            L.oracle_lj_vjp_f64.argtypes = [C.c_int64, f64p, _opt(i32p), f64p, i32p, C.c_double,
+                                            f64p, f64p, f64p, f64p, f64p]
+            L.oracle_lj_traj.argtypes = [C.c_int64, f64p, f64p, _opt(i32p), f64p, i32p,
+                                         C.c_double, f64p, f64p, C.c_double, C.c_int32, f64p,
+                                         f64p, _opt(f64p)]
+            L.oracle_lj_traj_adjoint.argtypes = [C.c_int64, f64p, _opt(i32p), f64p, i32p,
+                                                 C.c_double, f64p, f64p, C.c_double, C.c_int32,
+                                                 f64p, f64p, f64p, f64p]
         _lib = L
     return _lib
 
@@ -198,6 +202,61 @@ def vv(x, v, L, per, rc, dt, nsteps, eps=(1.0, 1.0, 1.0), sig=(1.0, 1.0, 1.0), t
                     _f64(np.broadcast_to(np.asarray(L, np.float64), (3,))), _per(per), float(rc),
                     _f64(eps), _f64(sig), float(mass), float(dt), int(nsteps), thermo)
     return x, v, thermo
+
+
+def _box64(L):
+    return _f64(np.broadcast_to(np.asarray(L, np.float64), (3,)))
+
+
+def lj_vjp(pos, L, per, rc2, lam, eps=(1.0, 1.0, 1.0), sig=(1.0, 1.0, 1.0), typ=None):
+    """Vector-Jacobian product of the forces at FP32 positions on the FP32 pair
+    set: (dL/dx (n, 3), dL/dtheta (6,) = eps AA, AB, BB, sig AA, AB, BB) for
+    lam = dL/dF."""
+    pos = _f32(pos)
+    gx = np.empty((len(pos), 3), np.float64)
+    gt = np.empty(6, np.float64)
+    lib().oracle_lj_vjp(len(pos), pos, None if typ is None else _i32(typ), _box(L), _per(per),
+                        float(np.float32(rc2)), _f64(eps), _f64(sig), _f64(lam), gx, gt)
+    return gx, gt
+
+
+def lj_vjp_f64(x, L, per, rc, lam, eps=(1.0, 1.0, 1.0), sig=(1.0, 1.0, 1.0), typ=None):
+    """The same at FP64 positions with the FP64 cut-off test u <= rc^2."""
+    x = _f64(x)
+    gx = np.empty_like(x)
+    gt = np.empty(6, np.float64)
+    lib().oracle_lj_vjp_f64(len(x), x, None if typ is None else _i32(typ), _box64(L), _per(per),
+                            float(rc), _f64(eps), _f64(sig), _f64(lam), gx, gt)
+    return gx, gt
+
+
+def lj_traj(x0, v0, L, per, rc, dt, nsteps, eps=(1.0, 1.0, 1.0), sig=(1.0, 1.0, 1.0), typ=None):
+    """FP64 velocity-Verlet trajectory: (xs, Fs, vs), each (nsteps + 1, n, 3)."""
+    x0 = _f64(x0)
+    n = len(x0)
+    xs = np.empty((nsteps + 1, n, 3), np.float64)
+    Fs = np.empty_like(xs)
+    vs = np.empty_like(xs)
+    lib().oracle_lj_traj(n, x0, _f64(v0), None if typ is None else _i32(typ), _box64(L),
+                         _per(per), float(rc), _f64(eps), _f64(sig), float(dt), int(nsteps), xs,
+                         Fs, vs)
+    return xs, Fs, vs
+
+
+def lj_traj_adjoint(xs, L, per, rc, dt, fbar, eps=(1.0, 1.0, 1.0), sig=(1.0, 1.0, 1.0),
+                    typ=None):
+    """Reverse-mode derivative through an FP64 trajectory xs (K + 1, n, 3) of a
+    loss with dL/dF_k = fbar (K + 1, n, 3): (dL/dx0, dL/dv0, dL/dtheta (6,))."""
+    xs = _f64(xs)
+    K = xs.shape[0] - 1
+    n = xs.shape[1]
+    xb = np.empty((n, 3), np.float64)
+    vb = np.empty((n, 3), np.float64)
+    gt = np.empty(6, np.float64)
+    lib().oracle_lj_traj_adjoint(n, xs, None if typ is None else _i32(typ), _box64(L), _per(per),
+                                 float(rc), _f64(eps), _f64(sig), float(dt), int(K), _f64(fbar),
+                                 xb, vb, gt)
+    return xb, vb, gt
 
 
 def sph_kernel_w(r: float, h: float) -> float:

@@ -94,6 +94,18 @@ static void sep_f64(const float *pi, const float *pj, const float *L, const int 
     }
 }
 
+/* Pair (i, j) of FP32 positions: 1 when j is in i's set of squared radius R2
+ * (the FP32 predicate above), with r = x_i - x_j in FP64 for that image.  Used
+ * by the other oracle files; j == i is the caller's to exclude. */
+int oracle_pair_f32(const float *pi, const float *pj, const float L[3], const int32_t per[3],
+                    float R2, double r[3])
+{
+    int perv[3] = {per[0], per[1], per[2]};
+    if (!(dist2_f32(pi, pj, L, perv) <= R2)) return 0;
+    sep_f64(pi, pj, L, perv, r);
+    return 1;
+}
+
 /* Squared radius of a set, R^2 rounded once to FP32 from (r_cut + skin) in FP64. */
 float oracle_radius2_f32(float r_cut, float skin)
 {
