@@ -82,6 +82,13 @@ def lib():
             L.oracle_lj_traj_adjoint.argtypes = [C.c_int64, f64p, _opt(i32p), f64p, i32p,
                                                  C.c_double, f64p, f64p, C.c_double, C.c_int32,
                                                  f64p, f64p, f64p, f64p]
+            L.oracle_lj_traj_f32.restype = C.c_int32
+            L.oracle_lj_traj_f32.argtypes = [C.c_int64, f32p, f32p, _opt(i32p), f32p, i32p,
+                                             C.c_float, f64p, f64p, C.c_float, C.c_float,
+                                             C.c_int32, C.c_int32, f32p, f32p, f32p]
+            L.oracle_lj_traj_adjoint_f32.argtypes = [C.c_int64, f32p, _opt(i32p), f32p, i32p,
+                                                     C.c_float, f64p, f64p, C.c_double,
+                                                     C.c_int32, f64p, f64p, f64p, f64p]
         _lib = L
     return _lib
 
@@ -259,6 +266,37 @@ def lj_traj_adjoint(xs, L, per, rc, dt, fbar, eps=(1.0, 1.0, 1.0), sig=(1.0, 1.0
     return xb, vb, gt
 
 
+def lj_traj_f32(x0, v0, L, per, rc2, dt, nsteps, disp2_thr, rebuild_every=0,
+                eps=(1.0, 1.0, 1.0), sig=(1.0, 1.0, 1.0), typ=None):
+    """Velocity-Verlet trajectory with FP32 particle state (see oracle_adjoint.c):
+    (xs, vs, Fs) float32 (nsteps + 1, n, 3) and the number of rebuilds."""
+    x0 = _f32(x0)
+    n = len(x0)
+    xs = np.empty((nsteps + 1, n, 3), np.float32)
+    vs = np.empty_like(xs)
+    Fs = np.empty_like(xs)
+    nb = lib().oracle_lj_traj_f32(n, x0, _f32(v0), None if typ is None else _i32(typ), _box(L),
+                                  _per(per), float(np.float32(rc2)), _f64(eps), _f64(sig),
+                                  float(np.float32(dt)), float(np.float32(disp2_thr)),
+                                  int(rebuild_every), int(nsteps), xs, vs, Fs)
+    return xs, vs, Fs, int(nb)
+
+
+def lj_traj_adjoint_f32(xs, L, per, rc2, dt, fbar, eps=(1.0, 1.0, 1.0), sig=(1.0, 1.0, 1.0),
+                        typ=None):
+    """lj_traj_adjoint over FP32 states with the FP32 pair set of each state."""
+    xs = _f32(xs)
+    K = xs.shape[0] - 1
+    n = xs.shape[1]
+    xb = np.empty((n, 3), np.float64)
+    vb = np.empty((n, 3), np.float64)
+    gt = np.empty(6, np.float64)
+    lib().oracle_lj_traj_adjoint_f32(n, xs, None if typ is None else _i32(typ), _box(L),
+                                     _per(per), float(np.float32(rc2)), _f64(eps), _f64(sig),
+                                     float(dt), int(K), _f64(fbar), xb, vb, gt)
+    return xb, vb, gt
+
+
 def sph_kernel_w(r: float, h: float) -> float:
     """Wendland C2 kernel value W(r) with support 2h."""
     return float(lib().oracle_sph_kernel_w(float(r), float(h)))
@@ -294,6 +332,42 @@ def sph_dt(acc, kind, mumax, prm, cfl):
     t1 = np.sqrt(h / am[am > 0].max()) if np.any(am > 0) else np.inf
     t2 = h / (c0 + float(np.max(mumax)))
     return cfl * min(t1, t2)
+
+
+def sph_kdk(pos, vel, rho, kind, L, per, R2, prm, cfl, nsteps):
+    """nsteps kick-drift-kick steps on (x, v, rho) with the CFL time step of the
+    latest rates (section 4.2 names the dynamic step but not the scheme; this is
+    the reading used throughout): with rates (a, D) and dt at step n,
+      rho += dt/2 D;  v += dt/2 a (fluid);  x += dt v (fluid);
+      rates at the new (x, v, rho);  rho += dt/2 D;  v += dt/2 a (fluid);
+      t += dt;  dt = CFL step of the new rates.
+    Boundary particles (kind 1) keep x and v; their density evolves.  The state
+    is kept in FP64; rates see it rounded to FP32 (the precision the particle
+    arrays have).  Returns (x, v, rho, hist (nsteps, 2) = [t, dt])."""
+    x = np.asarray(pos, np.float64).copy()
+    v = np.asarray(vel, np.float64).copy()
+    r = np.asarray(rho, np.float64).copy()
+    fl = np.asarray(kind) == 0
+
+    def rates():
+        return sph_rates(x.astype(np.float32), v.astype(np.float32), r.astype(np.float32),
+                         kind, L, per, R2, prm)
+
+    a, D, mu = rates()
+    dt = sph_dt(a, kind, mu, prm, cfl)
+    t = 0.0
+    hist = np.empty((nsteps, 2), np.float64)
+    for k in range(nsteps):
+        r += 0.5 * dt * D
+        v[fl] += 0.5 * dt * a[fl]
+        x[fl] += dt * v[fl]
+        a, D, mu = rates()
+        r += 0.5 * dt * D
+        v[fl] += 0.5 * dt * a[fl]
+        t += dt
+        hist[k] = (t, dt)
+        dt = sph_dt(a, kind, mu, prm, cfl)
+    return x, v, r, hist
 
 
 def num_threads() -> int:

@@ -172,11 +172,11 @@ void oracle_lj_traj(int64_t n, const double *x0, const double *v0, const int32_t
  *   v' = v_n + dt/2 F_n           : Fbar_n = dt/2 vbar + fbar_n
  * and finally xbar += VJP_x(Fbar_0) at x_0 (the periodic wrap is a
  * translation and passes cotangents through).  Outputs dL/dx_0, dL/dv_0 and
- * dL/dtheta (6). */
-void oracle_lj_traj_adjoint(int64_t n, const double *xs, const int32_t *type, const double L[3],
-                            const int32_t per[3], double rc, const double eps[3],
-                            const double sig[3], double dt, int32_t nsteps, const double *fbar,
-                            double *xbar, double *vbar, double gtheta[6])
+ * dL/dtheta (6).  `vjp(k, lam, g, th)` evaluates the force VJP at state k. */
+typedef void (*vjp_at_fn)(const void *ctx, int32_t k, const double *lam, double *g, double th[6]);
+
+static void traj_adjoint(int64_t n, int32_t nsteps, double dt, const double *fbar, vjp_at_fn vjp,
+                         const void *ctx, double *xbar, double *vbar, double gtheta[6])
 {
     const size_t m = (size_t)n * 3;
     double *Fb = (double *)malloc(sizeof(double) * m);
@@ -188,7 +188,7 @@ void oracle_lj_traj_adjoint(int64_t n, const double *xs, const int32_t *type, co
     memcpy(Fb, fbar + (size_t)nsteps * m, sizeof(double) * m);
     for (int32_t k = nsteps - 1; k >= 0; k--) {
         for (size_t q = 0; q < m; q++) Fb[q] += 0.5 * dt * vbar[q];
-        vjp_f64(n, xs + (k + 1) * m, type, L, per, rc, eps, sig, Fb, g, th);
+        vjp(ctx, k + 1, Fb, g, th);
         for (int p = 0; p < 6; p++) gtheta[p] += th[p];
         for (size_t q = 0; q < m; q++) {
             xbar[q] += g[q];
@@ -196,9 +196,153 @@ void oracle_lj_traj_adjoint(int64_t n, const double *xs, const int32_t *type, co
             Fb[q] = 0.5 * dt * vbar[q] + fbar[(size_t)k * m + q];
         }
     }
-    vjp_f64(n, xs, type, L, per, rc, eps, sig, Fb, g, th);
+    vjp(ctx, 0, Fb, g, th);
     for (int p = 0; p < 6; p++) gtheta[p] += th[p];
     for (size_t q = 0; q < m; q++) xbar[q] += g[q];
     free(Fb);
     free(g);
+}
+
+struct traj64 {
+    int64_t n;
+    const double *xs;
+    const int32_t *type;
+    const double *L;
+    const int32_t *per;
+    double rc;
+    const double *eps, *sig;
+};
+
+static void vjp_at64(const void *c, int32_t k, const double *lam, double *g, double th[6])
+{
+    const struct traj64 *t = (const struct traj64 *)c;
+    vjp_f64(t->n, t->xs + (size_t)k * t->n * 3, t->type, t->L, t->per, t->rc, t->eps, t->sig,
+            lam, g, th);
+}
+
+void oracle_lj_traj_adjoint(int64_t n, const double *xs, const int32_t *type, const double L[3],
+                            const int32_t per[3], double rc, const double eps[3],
+                            const double sig[3], double dt, int32_t nsteps, const double *fbar,
+                            double *xbar, double *vbar, double gtheta[6])
+{
+    struct traj64 t = {n, xs, type, L, per, rc, eps, sig};
+    traj_adjoint(n, nsteps, dt, fbar, vjp_at64, &t, xbar, vbar, gtheta);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Trajectories with FP32 particle state.  The same velocity-Verlet step, but  */
+/* x, v and F are stored in FP32 and each update rounds after every multiply   */
+/* and add (h = dt/2 in FP32):  v = v + h F;  x = x + dt v.  Forces are the     */
+/* FP64 sums on the FP32 pair set (squared radius rc2), rounded to FP32.       */
+/* Positions are wrapped into the box only when the neighbour structures are  */
+/* rebuilt: after a drift whose largest squared displacement since the last   */
+/* rebuild (FP32 predicate arithmetic) exceeds disp2_thr, and, when            */
+/* rebuild_every > 0, after every rebuild_every-th full step.  Wrap: x >= L:   */
+/* x - L; x < 0: x + L; a result equal to L becomes 0.  xs, vs, Fs: (K+1, n, 3) */
+/* FP32, state 0 first (x0 wrapped).                                           */
+/* ------------------------------------------------------------------------- */
+
+void oracle_lj_rows(int64_t n, const float *pos, const int32_t *type, const float L[3],
+                    const int32_t per[3], float rc2, const double eps[3], const double sig[3],
+                    const int64_t *rows, int64_t nrows, double *F, double *U, double *W);
+float oracle_max_disp2(int64_t n, const float *pos, const float *ref, const float L[3],
+                       const int32_t per[3]);
+
+static void wrap_all_f32(int64_t n, float *x, const float L[3], const int32_t per[3])
+{
+    for (int64_t i = 0; i < n; i++)
+        for (int a = 0; a < 3; a++) {
+            if (!per[a]) continue;
+            float t = x[3 * i + a];
+            if (t >= L[a]) t = t - L[a];
+            if (t < 0.0f) t = t + L[a];
+            if (t >= L[a]) t = 0.0f;
+            x[3 * i + a] = t;
+        }
+}
+
+static void forces_f32(int64_t n, const float *x, const int32_t *type, const float L[3],
+                       const int32_t per[3], float rc2, const double eps[3], const double sig[3],
+                       double *tmp, float *F)
+{
+    oracle_lj_rows(n, x, type, L, per, rc2, eps, sig, NULL, n, tmp, NULL, NULL);
+    for (int64_t q = 0; q < 3 * n; q++) F[q] = (float)tmp[q];
+}
+
+int32_t oracle_lj_traj_f32(int64_t n, const float *x0, const float *v0, const int32_t *type,
+                           const float L[3], const int32_t per[3], float rc2, const double eps[3],
+                           const double sig[3], float dt, float disp2_thr, int32_t rebuild_every,
+                           int32_t nsteps, float *xs, float *vs, float *Fs)
+{
+    const size_t m = (size_t)n * 3;
+    double *tmp = (double *)malloc(sizeof(double) * m);
+    float *xb = (float *)malloc(sizeof(float) * m);
+    float *v = (float *)malloc(sizeof(float) * m);
+    const float h = 0.5f * dt;
+    int32_t rebuilds = 1;
+    memcpy(xs, x0, sizeof(float) * m);
+    wrap_all_f32(n, xs, L, per);
+    memcpy(xb, xs, sizeof(float) * m);
+    memcpy(v, v0, sizeof(float) * m);
+    forces_f32(n, xs, type, L, per, rc2, eps, sig, tmp, Fs);
+    memcpy(vs, v, sizeof(float) * m);
+    for (int32_t k = 0; k < nsteps; k++) {
+        const float *F = Fs + k * m;
+        float *x = xs + (k + 1) * m, *Fn = Fs + (k + 1) * m;
+        memcpy(x, xs + k * m, sizeof(float) * m);
+        for (size_t q = 0; q < m; q++) {
+            float kick = h * F[q];
+            v[q] = v[q] + kick;
+            float drift = dt * v[q];
+            x[q] = x[q] + drift;
+        }
+        if (oracle_max_disp2(n, x, xb, L, per) > disp2_thr) {
+            wrap_all_f32(n, x, L, per);
+            memcpy(xb, x, sizeof(float) * m);
+            rebuilds++;
+        }
+        forces_f32(n, x, type, L, per, rc2, eps, sig, tmp, Fn);
+        for (size_t q = 0; q < m; q++) {
+            float kick = h * Fn[q];
+            v[q] = v[q] + kick;
+        }
+        if (rebuild_every > 0 && (k + 1) % rebuild_every == 0 && k + 1 < nsteps) {
+            wrap_all_f32(n, x, L, per);
+            memcpy(xb, x, sizeof(float) * m);
+            rebuilds++;
+        }
+        memcpy(vs + (k + 1) * m, v, sizeof(float) * m);
+    }
+    free(tmp);
+    free(xb);
+    free(v);
+    return rebuilds;
+}
+
+struct traj32 {
+    int64_t n;
+    const float *xs;
+    const int32_t *type;
+    const float *L;
+    const int32_t *per;
+    float rc2;
+    const double *eps, *sig;
+};
+
+static void vjp_at32(const void *c, int32_t k, const double *lam, double *g, double th[6])
+{
+    const struct traj32 *t = (const struct traj32 *)c;
+    oracle_lj_vjp(t->n, t->xs + (size_t)k * t->n * 3, t->type, t->L, t->per, t->rc2, t->eps,
+                  t->sig, lam, g, th);
+}
+
+/* The reverse recursion of oracle_lj_traj_adjoint over FP32 states, with the
+ * force VJP on the FP32 pair set of each state. */
+void oracle_lj_traj_adjoint_f32(int64_t n, const float *xs, const int32_t *type, const float L[3],
+                                const int32_t per[3], float rc2, const double eps[3],
+                                const double sig[3], double dt, int32_t nsteps,
+                                const double *fbar, double *xbar, double *vbar, double gtheta[6])
+{
+    struct traj32 t = {n, xs, type, L, per, rc2, eps, sig};
+    traj_adjoint(n, nsteps, dt, fbar, vjp_at32, &t, xbar, vbar, gtheta);
 }

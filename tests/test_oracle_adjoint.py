@@ -249,7 +249,7 @@ def test_trajectory_adjoint_matches_torch_autograd():
         if k in frames:
             tl = tl + ((F - torch.as_tensor(targets[frames.index(k)])) ** 2).sum()
     tl = tl / (3 * n * len(frames))
-    assert abs(float(tl) - loss) <= 1e-10 * loss
+    assert abs(float(tl.detach()) - loss) <= 1e-10 * loss
     tl.backward()
     assert np.abs(xt.grad.numpy() - xb).max() <= 1e-9 * np.abs(xb).max()
     assert np.abs(vt.grad.numpy() - vb).max() <= 1e-9 * np.abs(vb).max()
@@ -265,3 +265,53 @@ def test_trajectory_adjoint_of_zero_steps_is_the_force_vjp():
     gx, gt1 = oracle.lj_vjp_f64(x0, L, per, RC, lam, EPS, SIG, typ)
     assert np.array_equal(xb, gx) and np.array_equal(gt, gt1)
     assert not vb.any()
+
+
+# --- trajectories with FP32 particle state -----------------------------------
+
+def _f32_problem(seed=40, K=40):
+    x0, L, typ = _system(seed=seed)
+    v0 = _velocities(len(x0), seed + 1)
+    return (x0.astype(np.float32), v0.astype(np.float32), L.astype(np.float32), (1, 1, 1), typ,
+            K)
+
+
+def test_fp32_state_trajectory_follows_fp64_trajectory():
+    x32, v32, L32, per, typ, K = _f32_problem()
+    xs, vs, Fs, nb = oracle.lj_traj_f32(x32, v32, L32, per, RC * RC, 0.005, K, 0.15 ** 2, 0,
+                                        EPS, SIG, typ)
+    xs64, Fs64, vs64 = oracle.lj_traj(x32.astype(np.float64), v32.astype(np.float64),
+                                      L32.astype(np.float64), per, RC, 0.005, K, EPS, SIG, typ)
+    for k in (1, K // 2, K):
+        d = xs[k].astype(np.float64) - xs64[k]
+        d -= L32 * np.round(d / L32)
+        assert np.abs(d).max() < 1e-5, k
+        assert np.abs(vs[k] - vs64[k]).max() < 1e-4, k
+        assert np.abs(Fs[k] - Fs64[k]).max() < 1e-3 * np.abs(Fs64[k]).max(), k
+
+
+def test_fp32_state_wraps_only_at_rebuilds():
+    x32, v32, L32, per, typ, K = _f32_problem(seed=42, K=30)
+    v32 = v32 + np.float32([-4.0, 0.0, 0.0])  # a common drift: many leave through x = 0
+    always = oracle.lj_traj_f32(x32, v32, L32, per, RC * RC, 0.005, K, 0.0, 0, EPS, SIG, typ)
+    never = oracle.lj_traj_f32(x32, v32, L32, per, RC * RC, 0.005, K, 1e30, 0, EPS, SIG, typ)
+    every = oracle.lj_traj_f32(x32, v32, L32, per, RC * RC, 0.005, K, 1e30, 7, EPS, SIG, typ)
+    assert always[3] == K + 1 and never[3] == 1 and every[3] == 1 + (K - 1) // 7
+    xa, xn = always[0], never[0]
+    assert xa.min() >= 0 and np.all(xa < L32)                 # wrapped at every step
+    assert xn.min() < 0 or np.any(xn >= L32)                  # some particle left the box
+    d = xn.astype(np.float64) - xa
+    assert np.abs(d - L32 * np.round(d / L32)).max() < 1e-5   # same motion modulo L
+
+
+def test_fp32_state_adjoint_equals_fp64_adjoint_on_the_same_states():
+    x32, v32, L32, per, typ, K = _f32_problem(seed=44, K=20)
+    xs, vs, Fs, nb = oracle.lj_traj_f32(x32, v32, L32, per, RC * RC, 0.005, K, 0.15 ** 2, 0,
+                                        EPS, SIG, typ)
+    fb = np.random.default_rng(45).normal(size=xs.shape) * 1e-3
+    dt = float(np.float32(0.005))
+    a = oracle.lj_traj_adjoint_f32(xs, L32, per, RC * RC, dt, fb, EPS, SIG, typ)
+    b = oracle.lj_traj_adjoint(xs.astype(np.float64), L32.astype(np.float64), per, RC, dt, fb,
+                               EPS, SIG, typ)
+    for u, w in zip(a, b):
+        assert np.abs(u - w).max() <= 1e-10 * np.abs(w).max()
