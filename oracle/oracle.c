@@ -34,12 +34,13 @@
 /* distance R" (the cut-off test returns zero beyond r_cut, section 4.1        */
 /* listing).  The set is defined in FP32 so that it can be reproduced bit for  */
 /* bit: per axis t = xj - xi; if t > L/2 the separation is (xj - L) - xi, if   */
-/* t < -L/2 it is (xj + L) - xi: j is replaced by its periodic ghost copy      */
-/* (section 3.1 fills ghost layers with copies of particles from across the    */
-/* boundary), whose shifted coordinate is rounded once to FP32.  Then          */
-/* d2 = (dx*dx + dy*dy) + dz*dz, each operation rounded to nearest, no fused   */
-/* multiply-add; a pair is in the set iff d2 <= R^2 (the listing rejects only  */
-/* rn > r_cut2).                                                               */
+/* t < -L/2 it is xj - (xi - L): the periodic image (section 3.1's ghost      */
+/* copies) is taken by moving whichever of the two lies in the upper half of  */
+/* the box down by one period.  That subtraction is exact (Sterbenz), so the  */
+/* separation is rounded once, and swapping i and j negates it exactly: the   */
+/* sets are symmetric.  Then d2 = (dx*dx + dy*dy) + dz*dz, each operation      */
+/* rounded to nearest, no fused multiply-add; a pair is in the set iff         */
+/* d2 <= R^2 (the listing rejects only rn > r_cut2).                           */
 /* ------------------------------------------------------------------------- */
 
 static float img_delta_f32(float xi, float xj, float L, int periodic)
@@ -52,8 +53,8 @@ static float img_delta_f32(float xi, float xj, float L, int periodic)
         return xs - xi;
     }
     if (t < -half) {
-        float xs = xj + L;
-        return xs - xi;
+        float xs = xi - L;
+        return xj - xs;
     }
     return t;
 }

@@ -38,8 +38,8 @@ static float delta_f32(float xi, float xj, float L, int periodic)
         return s - xi;
     }
     if (b == -1) {
-        float s = xj + L;
-        return s - xi;
+        float s = xi - L;
+        return xj - s;
     }
     return t;
 }

@@ -133,6 +133,42 @@ def test_neighbors_symmetric_and_no_self():
             assert i in sets[j]
 
 
+def test_image_separation_is_rounded_once_and_symmetric():
+    # pairs across the x face at separations within a few ulp of R: the image
+    # separation must be the exact separation rounded once to FP32 (the larger
+    # coordinate minus L is exact), so membership is symmetric in i and j
+    rng = np.random.default_rng(21)
+    R2 = O.radius2(2.5, 0.3)
+    R = float(np.sqrt(np.float64(R2)))
+    L = np.array([20.0, 240.0, 240.0], np.float32)
+    g = np.stack(np.meshgrid(np.arange(40), np.arange(40), indexing="ij"), -1).reshape(-1, 2)
+    npair = len(g)
+    u = rng.uniform(0.01, 1.5, npair)                       # a near x = 0
+    ang = rng.uniform(0.0, 0.6, npair)                      # pair direction off the x axis
+    dx = R * np.cos(ang) * (1 + rng.uniform(-3e-7, 3e-7, npair))
+    a = np.zeros((npair, 3))
+    a[:, 0] = u
+    a[:, 1:] = g * 6.0 + 1.0
+    b = a.copy()
+    b[:, 0] = u - dx + L[0]                                 # b near x = L, image at u - dx
+    b[:, 1] += R * np.sin(ang)
+    pos = np.concatenate([a, b]).astype(np.float32)
+    sets = O.neighbor_sets(pos, L, PER, R2, cap=4)
+    p32 = pos.astype(np.float64)
+    hits = 0
+    for k in range(npair):
+        i, j = k, k + npair
+        assert (j in sets[i]) == (i in sets[j]), k
+        d = (p32[j] - p32[i]).copy()
+        d[0] -= L[0] * (1.0 if d[0] > L[0] / 2 else 0.0)    # exact in FP64
+        d32 = d.astype(np.float32)                          # exact separation, rounded once
+        d2 = np.float32(np.float32(d32[0] * d32[0]) + np.float32(d32[1] * d32[1]))
+        d2 = np.float32(d2 + np.float32(d32[2] * d32[2]))
+        assert (j in sets[i]) == bool(d2 <= R2), k
+        hits += j in sets[i]
+    assert 0 < hits < npair  # the ties really straddle R
+
+
 def test_neighbors_translation_and_permutation_invariant():
     s = inputs.lj_lattice(700, 0.8442, 1.0, seed=12)
     L = s.box
