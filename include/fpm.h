@@ -31,8 +31,9 @@
  *
  * Neighbour sets are defined in FP32, identically for every kernel: per axis
  * t = xj - xi; on a periodic axis, if t > L/2 the image (xj - L) - xi is used,
- * if t < -L/2 the image (xj + L) - xi (the ghost copy of j shifted by one
- * period, rounded once), otherwise t; then
+ * if t < -L/2 the image xj - (xi - L), otherwise t (the coordinate in the
+ * upper half of the box moves down one period, which is exact: the image
+ * separation is the exact one rounded once, and the sets are symmetric); then
  * d2 = (dx*dx + dy*dy) + dz*dz with every operation rounded separately (no
  * fused multiply-add), and j != i is a neighbour iff d2 <= R2, where R2 is
  * (r_cut + skin)^2 evaluated in FP64 and rounded once to FP32 (the listing of
@@ -95,15 +96,25 @@ const char *fpm_last_error(const fpm_ctx *ctx);
 
 /* ---- problem definition (the Box / bc / Ghost objects of the listing) ---- */
 
-/* Box side lengths (FP32, > 0) and periodic flags (0/1) per axis. */
+/* Box side lengths (FP32, > 0) and periodic flags (0/1) per axis: a single
+ * system holding every particle later passed to fpm_set_particles. */
 int fpm_set_box(fpm_ctx *ctx, const float h_L[3], const int32_t h_periodic[3]);
+/* A batch of nsys independent systems (1 <= nsys <= 65536) sharing one context,
+ * one set of neighbour parameters and one launch per step.  System s has box
+ * h_L[3s..3s+2], periodic flags h_periodic[3s..3s+2] and h_counts[s] >= 1
+ * particles; in every caller-order array the particles of system 0 come first,
+ * then those of system 1, and so on (h_counts may be NULL only for nsys = 1).
+ * Particles of different systems never interact.  Per-system outputs are
+ * described at each call.  SPH calls accept batches of one only. */
+int fpm_set_systems(fpm_ctx *ctx, int32_t nsys, const float *h_L, const int32_t *h_periodic,
+                    const int64_t *h_counts);
 /* Interaction radius, Verlet skin and Verlet-list capacity per particle.
  * The list radius is r_cut + skin; cells are the largest grid whose side is
  * >= that radius.  Returns FPM_ECUTOFF when r_cut + skin >= L/2 on a periodic
  * axis, FPM_EINVAL for max_nbr outside [1, 4096]. */
 int fpm_set_neighbor_params(fpm_ctx *ctx, float r_cut, float skin, int32_t max_nbr);
 /* Bytes of device workspace needed for n particles with the current box and
- * neighbour parameters (n <= 2^26 - 1). */
+ * neighbour parameters (n <= 2^26 - 1; for a batch, n is the total). */
 int fpm_workspace_size(fpm_ctx *ctx, int64_t n, size_t *h_bytes);
 /* Lends the workspace (device memory, 256-byte aligned, >= the queried size
  * for the n later passed to fpm_set_particles). */
@@ -116,6 +127,14 @@ int fpm_set_workspace(fpm_ctx *ctx, void *d_ws, size_t bytes);
  * 0 fluid / 1 boundary).  Builds the cell list and Verlet list. */
 int fpm_set_particles(fpm_ctx *ctx, int64_t n, const float *d_pos, const float *d_vel,
                       const int32_t *d_type);
+/* New positions (device, caller order, n x 3) for the current particles;
+ * types and velocities are kept.  The neighbour structures are rebuilt on
+ * next use when some particle moved more than skin/2 since the last build. */
+int fpm_set_positions(fpm_ctx *ctx, const float *d_pos);
+/* Host-side layout of system s: h_out = {n, first caller index, cells,
+ * first entry of that system's cell offsets, cells along x, y, z, z-cells per
+ * workgroup of the column Verlet build (0 = particle-by-particle build)}. */
+int fpm_system_info(fpm_ctx *ctx, int32_t s, int64_t h_out[8]);
 /* SPH only: per-particle density (device, caller order, n entries). */
 int fpm_set_density(fpm_ctx *ctx, const float *d_rho);
 /* Gathers the state back into caller order; any pointer may be NULL.
@@ -131,7 +150,10 @@ int fpm_get_sph(fpm_ctx *ctx, float *d_rho, float *d_drho);
  * reordering of particles by cell (ties in ascending caller index). */
 int fpm_build_cell_list(fpm_ctx *ctx);
 /* Cell list in caller terms: d_offsets[ncells + 1] (exclusive scan of
- * counts) and d_order[n] (slot -> caller index).  h_ncell receives the grid. */
+ * counts) and d_order[n] (slot -> caller index).  h_ncell receives the grid.
+ * For a batch, system s owns d_offsets[off_s .. off_s + ncells_s] (see
+ * fpm_system_info), counted in the packed caller numbering, and h_ncell is
+ * system 0's grid. */
 int fpm_get_cell_list(fpm_ctx *ctx, int32_t h_ncell[3], int32_t *d_offsets, int32_t *d_order);
 /* Rebuilds the Verlet list (radius r_cut + skin) from the current cell list. */
 int fpm_build_verlet(fpm_ctx *ctx);
@@ -143,9 +165,32 @@ int fpm_get_neighbors(fpm_ctx *ctx, int32_t *d_counts, int32_t *d_cols);
 /* ---- interactions (applyKernel_in over the Verlet list) ---- */
 
 /* Lennard-Jones forces on all particles from the current Verlet list, with
- * d_out[8] = {U, 0, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz} in FP64 (U = potential
- * energy, W = sum over pairs of r (x) F).  Forces are kept in the context. */
+ * d_out[8 s + k] = {U, 0, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz}[k] of system s in FP64
+ * (U = potential energy, W = sum over pairs of r (x) F; d_out may be NULL).
+ * Forces are kept in the context. */
 int fpm_lj_forces(fpm_ctx *ctx, const fpm_lj_params *prm, double *d_out);
+
+/* ---- adjoint (reverse mode through the forces of section 4.1) ---- */
+
+/* Vector-Jacobian product of the LJ forces at the current positions: given
+ * d_lam = dL/dF (FP64, caller order, n x 3), writes d_gx = dL/dx (FP64, n x 3,
+ * overwritten) and ADDS dL/dtheta to d_gtheta[6 s + k] for system s, with
+ * theta = (eps_AA, eps_AB, eps_BB, sig_AA, sig_AB, sig_BB) (n_types = 1: only
+ * entries 0 and 3 are non-zero; d_gtheta may be NULL).  The pair set is the
+ * force set; the cut-off is not differentiated.  Pair terms in FP64. */
+int fpm_lj_force_vjp(fpm_ctx *ctx, const fpm_lj_params *prm, const double *d_lam, double *d_gx,
+                     double *d_gtheta);
+/* One step of the reverse velocity-Verlet recursion (unit mass) at the
+ * current positions x_{k+1}, on caller-order FP64 arrays of n x 3:
+ *   lam = fbar + dt/2 vbar;  xbar += VJP_x(lam);  gtheta += VJP_theta(lam);
+ *   vbar += dt xbar;  fbar = dt/2 vbar + d_floss
+ * (d_floss = dL/dF_k of the loss, may be NULL = 0), which turns the
+ * cotangents of (x_{k+1}, v_{k+1}, F_{k+1}) into those of (x_k, v_k, F_k).
+ * With last = 1, at x_0: xbar += VJP_x(fbar), gtheta += VJP_theta(fbar) only.
+ * Afterwards xbar, vbar = dL/dx_0, dL/dv_0.  d_gtheta as in fpm_lj_force_vjp. */
+int fpm_lj_adjoint_step(fpm_ctx *ctx, const fpm_lj_params *prm, float dt, const double *d_floss,
+                        double *d_xbar, double *d_vbar, double *d_fbar, double *d_gtheta,
+                        int32_t last);
 
 /* ---- time stepping (the getV kick/drift expressions of the listing) ---- */
 
@@ -154,10 +199,11 @@ int fpm_lj_forces(fpm_ctx *ctx, const fpm_lj_params *prm, double *d_out);
  * v += dt/2 F. */
 int fpm_integrate(fpm_ctx *ctx, float dt, int32_t half);
 /* nsteps full velocity-Verlet steps with automatic Verlet-list rebuilds when
- * the largest displacement since the last build exceeds skin/2, all on the
- * device (graph-launched, no host synchronisation).  d_thermo, if not NULL,
- * receives nsteps rows of 8 FP64 values {U, KE, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz}
- * for the state after each step. */
+ * the largest displacement since the last build exceeds skin/2 (decided per
+ * system), all on the device (graph-launched, no host synchronisation).
+ * d_thermo, if not NULL, receives nsteps x nsys rows of 8 FP64 values
+ * {U, KE, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz}: row (step t, system s) at
+ * d_thermo[8 (t nsys + s)], for the state after step t + 1. */
 int fpm_step(fpm_ctx *ctx, const fpm_lj_params *prm, float dt, int32_t nsteps,
              double *d_thermo);
 
@@ -176,15 +222,24 @@ int fpm_sph_step(fpm_ctx *ctx, const fpm_sph_params *prm, int32_t nsteps, double
 /* Synchronises the stream and reports device-side flags: FPM_EOVERFLOW if a
  * list overflowed, FPM_ENONFINITE if a non-finite value was seen. */
 int fpm_check(fpm_ctx *ctx);
-/* Synchronises and reads counters: h_out[0] = rebuilds so far,
+/* Synchronises and reads counters: h_out[0] = rebuilds so far (summed over
+ * the systems of a batch),
  * h_out[1] = largest Verlet-list length seen in the last build,
  * h_out[2] = total Verlet-list entries of the last build. */
 int fpm_read_counters(fpm_ctx *ctx, int64_t h_out[3]);
 
-/* ---- measurement ---- */
+/* ---- measurement and tuning ---- */
+
+/* Launch shapes (0 = automatic).  verlet_path: 1 builds Verlet lists particle
+ * by particle from global memory, 2 by column blocks staged in LDS (where the
+ * grid has >= 3 cells per axis).  zblock: z-cells per column workgroup
+ * (1..64).  unroll: list entries in flight per lane in the force kernel (4 or
+ * 8).  Results do not depend on them.  Changing verlet_path or zblock drops
+ * the particles (call fpm_set_particles again). */
+int fpm_set_tuning(fpm_ctx *ctx, int32_t verlet_path, int32_t zblock, int32_t unroll);
 
 /* With on = 1, every launch made outside a graph of the kernels named
- * "lj_force", "verlet_build", "cell_build", "integrate", "sph_rates" is
+ * "lj_force", "lj_vjp", "verlet_build", "cell_build", "integrate", "sph_rates" is
  * bracketed by two HIP events recorded on the context's stream; on = 0 stops
  * recording and drops pending records. */
 int fpm_set_profiling(fpm_ctx *ctx, int32_t on);

@@ -46,10 +46,15 @@ _SIGS = {
     "fpm_create": [C.POINTER(_P), _P],
     "fpm_destroy": [_P],
     "fpm_set_box": [_P, C.POINTER(C.c_float), C.POINTER(C.c_int32)],
+    "fpm_set_systems": [_P, C.c_int32, C.POINTER(C.c_float), C.POINTER(C.c_int32),
+                        C.POINTER(C.c_int64)],
+    "fpm_set_tuning": [_P, C.c_int32, C.c_int32, C.c_int32],
     "fpm_set_neighbor_params": [_P, C.c_float, C.c_float, C.c_int32],
     "fpm_workspace_size": [_P, C.c_int64, C.POINTER(C.c_size_t)],
     "fpm_set_workspace": [_P, _P, C.c_size_t],
     "fpm_set_particles": [_P, C.c_int64, _P, _P, _P],
+    "fpm_set_positions": [_P, _P],
+    "fpm_system_info": [_P, C.c_int32, C.POINTER(C.c_int64)],
     "fpm_set_density": [_P, _P],
     "fpm_get_particles": [_P, _P, _P, _P],
     "fpm_get_sph": [_P, _P, _P],
@@ -58,6 +63,9 @@ _SIGS = {
     "fpm_build_verlet": [_P],
     "fpm_get_neighbors": [_P, _P, _P],
     "fpm_lj_forces": [_P, C.POINTER(fpm_lj_params), _P],
+    "fpm_lj_force_vjp": [_P, C.POINTER(fpm_lj_params), _P, _P, _P],
+    "fpm_lj_adjoint_step": [_P, C.POINTER(fpm_lj_params), C.c_float, _P, _P, _P, _P, _P,
+                            C.c_int32],
     "fpm_integrate": [_P, C.c_float, C.c_int32],
     "fpm_step": [_P, C.POINTER(fpm_lj_params), C.c_float, C.c_int32, _P],
     "fpm_sph_rates": [_P, C.POINTER(fpm_sph_params), _P],
@@ -131,6 +139,19 @@ def fpm_set_box(ctx, L, periodic):
     _call("fpm_set_box", ctx, Lc, pc)
 
 
+def fpm_set_systems(ctx, L, periodic, counts):
+    """L, periodic: (nsys, 3); counts: (nsys,) particles per system."""
+    nsys = len(counts)
+    Lc = (C.c_float * (3 * nsys))(*[float(x) for row in L for x in row])
+    pc = (C.c_int32 * (3 * nsys))(*[int(x) for row in periodic for x in row])
+    cc = (C.c_int64 * nsys)(*[int(x) for x in counts])
+    _call("fpm_set_systems", ctx, int(nsys), Lc, pc, cc)
+
+
+def fpm_set_tuning(ctx, verlet_path: int = 0, zblock: int = 0, unroll: int = 0):
+    _call("fpm_set_tuning", ctx, int(verlet_path), int(zblock), int(unroll))
+
+
 def fpm_set_neighbor_params(ctx, r_cut: float, skin: float, max_nbr: int):
     _call("fpm_set_neighbor_params", ctx, float(r_cut), float(skin), int(max_nbr))
 
@@ -147,6 +168,16 @@ def fpm_set_workspace(ctx, ws):
 
 def fpm_set_particles(ctx, pos, vel=None, typ=None):
     _call("fpm_set_particles", ctx, int(pos.shape[0]), _ptr(pos), _ptr(vel), _ptr(typ))
+
+
+def fpm_set_positions(ctx, pos):
+    _call("fpm_set_positions", ctx, _ptr(pos))
+
+
+def fpm_system_info(ctx, s: int):
+    out = (C.c_int64 * 8)()
+    _call("fpm_system_info", ctx, int(s), out)
+    return tuple(int(x) for x in out)
 
 
 def fpm_set_density(ctx, rho):
@@ -202,6 +233,16 @@ def sph_params(h, mass, rho0, c0, gamma=7.0, alpha=0.1, eta2=None, g=(0.0, 0.0, 
 
 def fpm_lj_forces(ctx, prm: fpm_lj_params, out=None):
     _call("fpm_lj_forces", ctx, C.byref(prm), _ptr(out))
+
+
+def fpm_lj_force_vjp(ctx, prm: fpm_lj_params, lam, gx, gtheta=None):
+    _call("fpm_lj_force_vjp", ctx, C.byref(prm), _ptr(lam), _ptr(gx), _ptr(gtheta))
+
+
+def fpm_lj_adjoint_step(ctx, prm: fpm_lj_params, dt: float, floss, xbar, vbar, fbar,
+                        gtheta=None, last: int = 0):
+    _call("fpm_lj_adjoint_step", ctx, C.byref(prm), float(dt), _ptr(floss), _ptr(xbar),
+          _ptr(vbar), _ptr(fbar), _ptr(gtheta), int(last))
 
 
 def fpm_integrate(ctx, dt: float, half: int):

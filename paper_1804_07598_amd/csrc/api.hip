@@ -34,27 +34,82 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 int cap4_for(int cap) { return (cap + 7) / 8 * 2; }
 
-// Launch geometry for n particles.
+// Launch geometry and device tables of a batch holding n particles in total.
 struct Plan {
-    int64_t n_pad;
-    int nblk, nblk_build, zb, nzb;
+    std::vector<SysHost> sys;
+    std::vector<SysDesc> desc;
+    std::vector<int32_t> blk2sys, item2sys, pa_blocks;
+    int64_t n_slots = 0;
+    int nblk = 0, ncells_total = 0, noff_total = 0, nitems = 0, max_ncells = 0;
+    int max_sys_blocks = 0;
 };
 
-Plan plan_for(const fpm_ctx *c, int64_t n) {
-    Plan p;
-    p.n_pad = (n + 1 + kBlock - 1) / kBlock * kBlock;  // at least one padding slot
-    p.nblk = (int)(p.n_pad / kBlock);
-    p.zb = verlet_zblock(n, c->ncells, c->box.nc);
-    p.nzb = p.zb ? (c->box.nc[2] + p.zb - 1) / p.zb : 0;
-    p.nblk_build = p.zb ? c->box.nc[0] * c->box.nc[1] * p.nzb : p.nblk;
-    return p;
+// Particles per system: the batch counts, or all n in the single box.
+bool system_counts(const fpm_ctx *c, int64_t n, std::vector<int64_t> &cnt) {
+    if (c->counts.empty()) {
+        cnt.assign(1, n);
+        return c->boxes.size() == 1;
+    }
+    int64_t tot = 0;
+    for (int64_t k : c->counts) tot += k;
+    cnt = c->counts;
+    return tot == n;
 }
 
-// Workspace layout for n particles; with base == nullptr only the size is computed.
-size_t layout(const fpm_ctx *c, int64_t n, char *base, State *st) {
-    const Plan pl = plan_for(c, n);
-    const int64_t n_pad = pl.n_pad;
-    const int64_t pstride = pl.nblk;  // only the particle kernels write partials
+Plan make_plan(const fpm_ctx *c, const std::vector<int64_t> &cnt) {
+    Plan P;
+    const int nsys = (int)cnt.size();
+    int64_t slot = 0, caller = 0;
+    int blk = 0, cell = 0, offb = 0, item = 0;
+    for (int s = 0; s < nsys; s++) {
+        SysHost h{};
+        SysDesc &d = h.d;
+        d.box = c->boxes[s];
+        d.n = (int32_t)cnt[s];
+        d.n_pad = (int32_t)((cnt[s] + 1 + kBlock - 1) / kBlock * kBlock);  // >= 1 padding slot
+        d.slot_base = (int32_t)slot;
+        d.blk_base = blk;
+        d.ncells = d.box.nc[0] * d.box.nc[1] * d.box.nc[2];
+        d.cell_base = cell;
+        d.off_base = offb;
+        d.zb = c->tune_verlet_path == 1
+                   ? 0
+                   : verlet_zblock(cnt[s], d.ncells, d.box.nc, c->tune_zb);
+        d.nzb = d.zb ? (d.box.nc[2] + d.zb - 1) / d.zb : 0;
+        d.item_base = item;
+        d.dummy = (int32_t)(slot + cnt[s]);
+        d.caller_base = (int32_t)caller;
+        h.nblk = d.n_pad / kBlock;
+        h.nitems = d.zb ? d.box.nc[0] * d.box.nc[1] * d.nzb : 0;
+        for (int b = 0; b < h.nblk; b++) {
+            P.blk2sys.push_back(s);
+            if (!d.zb) P.pa_blocks.push_back(blk + b);
+        }
+        for (int q = 0; q < h.nitems; q++) P.item2sys.push_back(s);
+        slot += d.n_pad;
+        caller += cnt[s];
+        blk += h.nblk;
+        cell += d.ncells;
+        offb += d.ncells + 1;
+        item += h.nitems;
+        if (d.ncells > P.max_ncells) P.max_ncells = d.ncells;
+        if (h.nblk > P.max_sys_blocks) P.max_sys_blocks = h.nblk;
+        P.sys.push_back(h);
+        P.desc.push_back(d);
+    }
+    P.n_slots = slot;
+    P.nblk = blk;
+    P.ncells_total = cell;
+    P.noff_total = offb;
+    P.nitems = item;
+    return P;
+}
+
+// Workspace layout of a plan; with base == nullptr only the size is computed.
+size_t layout(const fpm_ctx *c, const Plan &P, char *base, State *st,
+              int32_t **pa_blocks = nullptr) {
+    const int64_t ns = P.n_slots;
+    const int nsys = (int)P.sys.size();
     size_t off = 0;
     auto take = [&](size_t bytes) -> char * {
         char *p = base ? base + off : nullptr;
@@ -62,23 +117,30 @@ size_t layout(const fpm_ctx *c, int64_t n, char *base, State *st) {
         return p;
     };
     State s{};
-    for (int k = 0; k < 2; k++) s.pos[k] = (float4 *)take(n_pad * sizeof(float4));
-    for (int k = 0; k < 2; k++) s.vel[k] = (float4 *)take(n_pad * sizeof(float4));
-    for (int k = 0; k < 2; k++) s.id[k] = (int32_t *)take(n_pad * sizeof(int32_t));
-    s.frc = (float4 *)take(n_pad * sizeof(float4));
-    s.xbuild = (float4 *)take(n_pad * sizeof(float4));
-    s.cid = (int32_t *)take(n_pad * sizeof(int32_t));
-    s.rnk = (int32_t *)take(n_pad * sizeof(int32_t));
-    s.tmp = (int2 *)take(n_pad * sizeof(int2));
-    s.cnt = (int32_t *)take((c->ncells + 4) * sizeof(int32_t));
-    s.off = (int32_t *)take((c->ncells + 4) * sizeof(int32_t));
-    s.nbr = (int32_t *)take((size_t)n_pad * cap4_for(c->cap) * 4 * sizeof(int32_t));
-    s.nnb = (uint32_t *)take(n_pad * sizeof(uint32_t));
-    s.part = (double *)take((size_t)pstride * kSlots * sizeof(double));
+    for (int k = 0; k < 2; k++) s.pos[k] = (float4 *)take(ns * sizeof(float4));
+    for (int k = 0; k < 2; k++) s.vel[k] = (float4 *)take(ns * sizeof(float4));
+    for (int k = 0; k < 2; k++) s.id[k] = (int32_t *)take(ns * sizeof(int32_t));
+    s.frc = (float4 *)take(ns * sizeof(float4));
+    s.xbuild = (float4 *)take(ns * sizeof(float4));
+    s.cid = (int32_t *)take(ns * sizeof(int32_t));
+    s.rnk = (int32_t *)take(ns * sizeof(int32_t));
+    s.tmp = (int2 *)take(ns * sizeof(int2));
+    s.cnt = (int32_t *)take(((size_t)P.ncells_total + 4) * sizeof(int32_t));
+    s.off = (int32_t *)take(((size_t)P.noff_total + 4) * sizeof(int32_t));
+    s.nbr = (int32_t *)take((size_t)ns * cap4_for(c->cap) * 4 * sizeof(int32_t));
+    s.nnb = (uint32_t *)take(ns * sizeof(uint32_t));
+    s.part = (double *)take((size_t)P.nblk * kSlots * sizeof(double));
+    s.aux = (float4 *)take(ns * sizeof(float4));
     s.ctl = (Ctl *)take(sizeof(Ctl));
-    s.pstride = (int32_t)pstride;
-    s.dummy = (int32_t)n;
+    s.sctl = (SysCtl *)take(nsys * sizeof(SysCtl));
+    s.sys = (const SysDesc *)take(nsys * sizeof(SysDesc));
+    s.blk2sys = (const int32_t *)take(P.blk2sys.size() * sizeof(int32_t));
+    s.item2sys = (const int32_t *)take((P.item2sys.size() + 1) * sizeof(int32_t));
+    char *pa = take((P.pa_blocks.size() + 1) * sizeof(int32_t));
+    s.nsys = nsys;
+    s.pstride = P.nblk;
     if (st) *st = s;
+    if (pa_blocks) *pa_blocks = (int32_t *)pa;
     return off;
 }
 
@@ -224,23 +286,45 @@ int fpm_destroy(fpm_ctx *c) {
 
 const char *fpm_last_error(const fpm_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
-int fpm_set_box(fpm_ctx *c, const float L[3], const int32_t per[3]) {
+int fpm_set_systems(fpm_ctx *c, int32_t nsys, const float *L, const int32_t *per,
+                    const int64_t *counts) {
     if (!c) return FPM_EINVAL;
+    if (nsys < 1 || nsys > kMaxSystems) return fail(c, FPM_EINVAL, "system count out of range");
     if (!L || !per) return fail(c, FPM_EINVAL, "null box argument");
-    for (int a = 0; a < 3; a++) {
-        if (!(isfinite(L[a]) && L[a] > 0.f)) return fail(c, FPM_EINVAL, "box side must be > 0");
-        if (per[a] != 0 && per[a] != 1) return fail(c, FPM_EINVAL, "periodic flag must be 0/1");
+    int64_t tot = 0;
+    for (int s = 0; s < nsys; s++) {
+        for (int a = 0; a < 3; a++) {
+            const float x = L[3 * s + a];
+            if (!(isfinite(x) && x > 0.f)) return fail(c, FPM_EINVAL, "box side must be > 0");
+            if (per[3 * s + a] != 0 && per[3 * s + a] != 1)
+                return fail(c, FPM_EINVAL, "periodic flag must be 0/1");
+        }
+        if (counts) {
+            if (counts[s] < 1) return fail(c, FPM_EINVAL, "every system needs a particle");
+            tot += counts[s];
+            if (tot > kMaxParticles) return fail(c, FPM_EINVAL, "particle count out of range");
+        }
     }
-    for (int a = 0; a < 3; a++) {
-        c->box.L[a] = L[a];
-        c->box.half[a] = L[a] * 0.5f;
-        c->box.per[a] = per[a];
-    }
+    if (!counts && nsys != 1) return fail(c, FPM_EINVAL, "a batch needs its particle counts");
+    c->boxes.assign(nsys, Box{});
+    for (int s = 0; s < nsys; s++)
+        for (int a = 0; a < 3; a++) {
+            Box &b = c->boxes[s];
+            b.L[a] = L[3 * s + a];
+            b.half[a] = L[3 * s + a] * 0.5f;
+            b.per[a] = per[3 * s + a];
+        }
+    c->counts.clear();
+    if (counts) c->counts.assign(counts, counts + nsys);
     c->box_set = true;
     c->nbr_set = false;
     c->have_particles = false;
     drop_graphs(c);
     return FPM_OK;
+}
+
+int fpm_set_box(fpm_ctx *c, const float L[3], const int32_t per[3]) {
+    return fpm_set_systems(c, 1, L, per, nullptr);
 }
 
 int fpm_set_neighbor_params(fpm_ctx *c, float r_cut, float skin, int32_t max_nbr) {
@@ -250,21 +334,23 @@ int fpm_set_neighbor_params(fpm_ctx *c, float r_cut, float skin, int32_t max_nbr
         return fail(c, FPM_EINVAL, "r_cut must be > 0 and skin >= 0");
     if (max_nbr < 1 || max_nbr > kMaxNbrCap) return fail(c, FPM_EINVAL, "max_nbr out of range");
     const double R = (double)r_cut + (double)skin;
-    int nc[3];
-    int64_t ncells = 1;
-    for (int a = 0; a < 3; a++) {
-        if (c->box.per[a] && !(R < 0.5 * (double)c->box.L[a] * (1.0 - 1e-6)))
-            return fail(c, FPM_ECUTOFF, "r_cut + skin must be below half the periodic box");
-        double m = floor((double)c->box.L[a] / (R * 1.000001));
-        nc[a] = m < 1.0 ? 1 : (m > (1 << 20) ? (1 << 20) : (int)m);
-        ncells *= nc[a];
+    std::vector<Box> boxes = c->boxes;
+    int64_t total = 0;
+    for (Box &b : boxes) {
+        int64_t ncells = 1;
+        for (int a = 0; a < 3; a++) {
+            if (b.per[a] && !(R < 0.5 * (double)b.L[a] * (1.0 - 1e-6)))
+                return fail(c, FPM_ECUTOFF, "r_cut + skin must be below half the periodic box");
+            const double m = floor((double)b.L[a] / (R * 1.000001));
+            b.nc[a] = m < 1.0 ? 1 : (m > (1 << 20) ? (1 << 20) : (int)m);
+            b.inv[a] = (float)b.nc[a] / b.L[a];
+            ncells *= b.nc[a];
+            if (ncells > ((int64_t)1 << 30)) return fail(c, FPM_EINVAL, "too many cells");
+        }
+        total += ncells + 1;
+        if (total > ((int64_t)1 << 30)) return fail(c, FPM_EINVAL, "too many cells");
     }
-    if (ncells > ((int64_t)1 << 30)) return fail(c, FPM_EINVAL, "too many cells");
-    for (int a = 0; a < 3; a++) {
-        c->box.nc[a] = nc[a];
-        c->box.inv[a] = (float)nc[a] / c->box.L[a];
-    }
-    c->ncells = ncells;
+    c->boxes = boxes;
     c->r_cut = r_cut;
     c->skin = skin;
     c->cap = max_nbr;
@@ -279,12 +365,27 @@ int fpm_set_neighbor_params(fpm_ctx *c, float r_cut, float skin, int32_t max_nbr
     return FPM_OK;
 }
 
+int fpm_set_tuning(fpm_ctx *c, int32_t verlet_path, int32_t zblock, int32_t unroll) {
+    if (!c) return FPM_EINVAL;
+    if (verlet_path < 0 || verlet_path > 2) return fail(c, FPM_EINVAL, "verlet_path is 0, 1 or 2");
+    if (zblock < 0 || zblock > 64) return fail(c, FPM_EINVAL, "zblock out of range");
+    if (unroll != 0 && unroll != 4 && unroll != 8) return fail(c, FPM_EINVAL, "unroll is 0, 4 or 8");
+    if (verlet_path != c->tune_verlet_path || zblock != c->tune_zb) c->have_particles = false;
+    c->tune_verlet_path = verlet_path;
+    c->tune_zb = zblock;
+    c->tune_unroll = unroll;
+    drop_graphs(c);
+    return FPM_OK;
+}
+
 int fpm_workspace_size(fpm_ctx *c, int64_t n, size_t *bytes) {
     if (!c) return FPM_EINVAL;
     if (!bytes) return fail(c, FPM_EINVAL, "null size pointer");
     if (!c->nbr_set) return fail(c, FPM_EINVAL, "set box and neighbour parameters first");
     if (n < 1 || n > kMaxParticles) return fail(c, FPM_EINVAL, "particle count out of range");
-    *bytes = layout(c, n, nullptr, nullptr);
+    std::vector<int64_t> cnt;
+    if (!system_counts(c, n, cnt)) return fail(c, FPM_EINVAL, "n differs from the batch total");
+    *bytes = layout(c, make_plan(c, cnt), nullptr, nullptr);
     return FPM_OK;
 }
 
@@ -306,22 +407,68 @@ int fpm_set_particles(fpm_ctx *c, int64_t n, const float *pos, const float *vel,
     if (!c->nbr_set) return fail(c, FPM_EINVAL, "set box and neighbour parameters first");
     if (n < 1 || n > kMaxParticles) return fail(c, FPM_EINVAL, "particle count out of range");
     if (!pos) return fail(c, FPM_EINVAL, "null positions");
-    const size_t need = layout(c, n, nullptr, nullptr);
+    std::vector<int64_t> cnt;
+    if (!system_counts(c, n, cnt)) return fail(c, FPM_EINVAL, "n differs from the batch total");
+    Plan P = make_plan(c, cnt);
+    const size_t need = layout(c, P, nullptr, nullptr);
     if (!c->ws || c->ws_bytes < need) return fail(c, FPM_ENOWS, "workspace missing or too small");
-    layout(c, n, (char *)c->ws, &c->st);
-    const Plan pl = plan_for(c, n);
-    c->n = n;
-    c->n_pad = pl.n_pad;
-    c->nblk = pl.nblk;
-    c->nblk_build = pl.nblk_build;
-    c->zb = pl.zb;
-    c->nzb = pl.nzb;
+    c->have_particles = false;
     drop_graphs(c);
-    HIPCHK(c, launch_fill_i32(c->stream, c->st.cnt, c->ncells, 0));
+    layout(c, P, (char *)c->ws, &c->st, &c->pa_blocks);
+    c->sys = P.sys;
+    c->nsys = (int)P.sys.size();
+    c->n = n;
+    c->n_slots = P.n_slots;
+    c->nblk = P.nblk;
+    c->ncells_total = P.ncells_total;
+    c->noff_total = P.noff_total;
+    c->nitems = P.nitems;
+    c->n_pa_blocks = (int)P.pa_blocks.size();
+    c->max_ncells = P.max_ncells;
+    c->max_sys_blocks = P.max_sys_blocks;
+    // the tables are small; the copies finish before the host vectors go away
+    HIPCHK(c, hipMemcpyAsync((void *)c->st.sys, P.desc.data(), P.desc.size() * sizeof(SysDesc),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync((void *)c->st.blk2sys, P.blk2sys.data(),
+                             P.blk2sys.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+    if (!P.item2sys.empty())
+        HIPCHK(c, hipMemcpyAsync((void *)c->st.item2sys, P.item2sys.data(),
+                                 P.item2sys.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                 c->stream));
+    if (!P.pa_blocks.empty())
+        HIPCHK(c, hipMemcpyAsync(c->pa_blocks, P.pa_blocks.data(),
+                                 P.pa_blocks.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                 c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, launch_fill_i32(c->stream, c->st.cnt, c->ncells_total, 0));
     HIPCHK(c, launch_init_state(c, pos, vel, type));
     HIPCHK(c, launch_force_rebuild(c));
     HIPCHK(c, refresh_and_account(c));
     c->have_particles = true;
+    c->forces_valid = false;
+    return FPM_OK;
+}
+
+int fpm_system_info(fpm_ctx *c, int32_t s, int64_t out[8]) {
+    int r = ready(c);
+    if (r) return r;
+    if (!out || s < 0 || s >= c->nsys) return fail(c, FPM_EINVAL, "bad system index or output");
+    const SysHost &h = c->sys[s];
+    out[0] = h.d.n;
+    out[1] = h.d.caller_base;
+    out[2] = h.d.ncells;
+    out[3] = h.d.off_base;
+    for (int a = 0; a < 3; a++) out[4 + a] = h.d.box.nc[a];
+    out[7] = h.d.zb;
+    return FPM_OK;
+}
+
+int fpm_set_positions(fpm_ctx *c, const float *pos) {
+    int r = ready(c);
+    if (r) return r;
+    if (!pos) return fail(c, FPM_EINVAL, "null positions");
+    HIPCHK(c, launch_set_positions(c, pos));
+    HIPCHK(c, launch_finalize(c, kFinDisp, nullptr, nullptr));
     c->forces_valid = false;
     return FPM_OK;
 }
@@ -355,7 +502,7 @@ int fpm_build_cell_list(fpm_ctx *c) {
     HIPCHK(c, launch_force_rebuild(c));
     HIPCHK(c, timed(c, "cell_build", [&] { return launch_cell_build(c); }));
     HIPCHK(c, launch_copy_back(c));
-    c->build_pending = true;  // flag stays set: the Verlet list is rebuilt on next use
+    c->build_pending = true;  // flags stay set: the Verlet lists are rebuilt on next use
     c->forces_valid = false;
     return FPM_OK;
 }
@@ -364,7 +511,7 @@ int fpm_get_cell_list(fpm_ctx *c, int32_t ncell[3], int32_t *offsets, int32_t *o
     int r = ready(c);
     if (r) return r;
     if (ncell)
-        for (int a = 0; a < 3; a++) ncell[a] = c->box.nc[a];
+        for (int a = 0; a < 3; a++) ncell[a] = c->sys[0].d.box.nc[a];
     if (offsets || order) HIPCHK(c, launch_cells_out(c, offsets, order));
     return FPM_OK;
 }
@@ -399,6 +546,37 @@ int fpm_lj_forces(fpm_ctx *c, const fpm_lj_params *p, double *out) {
     HIPCHK(c, timed(c, "lj_force", [&] { return launch_lj_forces(c, *p); }));
     HIPCHK(c, launch_finalize(c, kFinForce, out, nullptr));
     c->forces_valid = true;
+    c->sph = false;
+    return FPM_OK;
+}
+
+int fpm_lj_force_vjp(fpm_ctx *c, const fpm_lj_params *p, const double *lam, double *gx,
+                     double *gtheta) {
+    int r = ready(c);
+    if (r) return r;
+    if (!valid_lj(p)) return fail(c, FPM_EINVAL, "bad LJ params");
+    if (!lam || !gx) return fail(c, FPM_EINVAL, "null cotangent or output");
+    HIPCHK(c, refresh_and_account(c));
+    const AdjOut o{gx, nullptr, nullptr, nullptr, 0.0, kVjpPlain};
+    HIPCHK(c, timed(c, "lj_vjp", [&] { return launch_lj_vjp(c, *p, lam, nullptr, o); }));
+    if (gtheta) HIPCHK(c, launch_finalize(c, kFinVjp, gtheta, nullptr));
+    return FPM_OK;
+}
+
+int fpm_lj_adjoint_step(fpm_ctx *c, const fpm_lj_params *p, float dt, const double *floss,
+                        double *xbar, double *vbar, double *fbar, double *gtheta, int32_t last) {
+    int r = ready(c);
+    if (r) return r;
+    if (!valid_lj(p)) return fail(c, FPM_EINVAL, "bad LJ params");
+    if (!isfinite(dt)) return fail(c, FPM_EINVAL, "dt must be finite");
+    if (!xbar || !vbar || !fbar) return fail(c, FPM_EINVAL, "null adjoint array");
+    if (last != 0 && last != 1) return fail(c, FPM_EINVAL, "last must be 0 or 1");
+    HIPCHK(c, refresh_and_account(c));
+    const AdjOut o{xbar, vbar, fbar, floss, (double)dt, last ? kVjpLast : kVjpStep};
+    HIPCHK(c, timed(c, "lj_vjp", [&] {
+        return launch_lj_vjp(c, *p, fbar, last ? nullptr : vbar, o);
+    }));
+    if (gtheta) HIPCHK(c, launch_finalize(c, kFinVjp, gtheta, nullptr));
     return FPM_OK;
 }
 
@@ -430,7 +608,7 @@ int fpm_step(fpm_ctx *c, const fpm_lj_params *p, float dt, int32_t nsteps, doubl
     }
     c->sph = false;
     const bool same = c->g_first && c->g_dt == dt && c->g_thermo == thermo &&
-                      memcmp(&c->g_prm, p, sizeof(*p)) == 0;
+                      memcmp(&c->g_prm, p, sizeof(*p)) == 0 && c->g_unroll == c->tune_unroll;
     if (!same) {
         drop_graphs(c);
         int e;
@@ -451,6 +629,7 @@ int fpm_step(fpm_ctx *c, const fpm_lj_params *p, float dt, int32_t nsteps, doubl
         c->g_dt = dt;
         c->g_thermo = thermo;
         c->g_prm = *p;
+        c->g_unroll = c->tune_unroll;
     }
     HIPCHK(c, launch_reset_step(c));
     HIPCHK(c, hipGraphLaunch(c->g_first, c->stream));
@@ -466,6 +645,7 @@ int fpm_sph_rates(fpm_ctx *c, const fpm_sph_params *p, float *dt_out) {
     int r = ready(c);
     if (r) return r;
     if (!valid_sph(p)) return fail(c, FPM_EINVAL, "bad SPH params");
+    if (c->nsys != 1) return fail(c, FPM_EINVAL, "SPH runs on a single system");
     HIPCHK(c, refresh_and_account(c));
     HIPCHK(c, timed(c, "sph_rates", [&] { return launch_sph_rates(c, *p); }));
     HIPCHK(c, launch_sph_finalize(c, *p, 0, dt_out, nullptr));
@@ -478,6 +658,7 @@ int fpm_sph_step(fpm_ctx *c, const fpm_sph_params *p, int32_t nsteps, double *hi
     int r = ready(c);
     if (r) return r;
     if (!valid_sph(p)) return fail(c, FPM_EINVAL, "bad SPH params");
+    if (c->nsys != 1) return fail(c, FPM_EINVAL, "SPH runs on a single system");
     if (nsteps < 0) return fail(c, FPM_EINVAL, "bad step count");
     if (nsteps == 0) return FPM_OK;
     if (!c->forces_valid || !c->sph || c->build_pending) {
@@ -534,9 +715,13 @@ int fpm_read_counters(fpm_ctx *c, int64_t out[3]) {
     if (!out) return fail(c, FPM_EINVAL, "null output");
     HIPCHK(c, launch_list_stats(c));
     Ctl h;
+    std::vector<SysCtl> sc(c->nsys);
     HIPCHK(c, hipMemcpyAsync(&h, c->st.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(sc.data(), c->st.sctl, sc.size() * sizeof(SysCtl),
+                             hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    out[0] = h.n_rebuilds;
+    out[0] = 0;
+    for (const SysCtl &x : sc) out[0] += x.n_rebuilds;
     out[1] = h.max_count;
     out[2] = h.total_count;
     return FPM_OK;

@@ -1,4 +1,10 @@
 // Internal declarations shared by the HIP translation units of the library.
+//
+// A context holds one or more independent systems ("batch").  Every system
+// owns a contiguous range of particle slots padded to whole workgroups, its
+// own cell grid and its own control words, so every workgroup of a particle
+// kernel belongs to exactly one system and reads that system's description
+// with scalar loads.  A single simulation is a batch of one.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -12,55 +18,37 @@
 namespace fpm {
 
 constexpr int kWave = 64;          // CDNA wavefront
-constexpr int kBlock = 256;        // threads per workgroup for particle kernels
+constexpr int kBlock = 256;        // threads per workgroup of the particle kernels
 constexpr int kMaxNbrCap = 4096;   // largest accepted Verlet-list capacity
 constexpr int64_t kMaxParticles = (int64_t(1) << 26) - 1;
+constexpr int kMaxSystems = 1 << 16;
 constexpr uint32_t kWrapBit = 0x80000000u;  // "list holds periodic images" flag in counts
 
-// Per-block partial results (for each slot an array with one double per
-// workgroup of the particle kernels), reduced in a fixed order by the
+// Per-block partial results: for each slot one double per particle workgroup
+// (part[slot * pstride + block]), reduced per system in a fixed order by the
 // finalize kernels.
 enum Slot {
     kSlotU = 0,        // potential energy (LJ)
     kSlotW = 1,        // virial xx, yy, zz, xy, xz, yz (1..6)
     kSlotKE = 7,       // kinetic energy
     kSlotDisp = 8,     // largest squared displacement since the last build
-    kSlotMaxCnt = 9,   // longest Verlet list of the build
-    kSlotTotCnt = 10,  // total Verlet-list entries of the build
-    kSlotOvf = 11,     // longest list if it exceeded the capacity, else 0
-    kSlotMu = 12,      // SPH: largest |mu_ab|
-    kSlotAcc = 13,     // SPH: smallest h / |a|
-    kSlotVmax = 14,    // SPH: largest |v|
-    kSlots = 16
+    kSlotMu = 9,       // SPH: largest |mu_ab|
+    kSlotAcc = 10,     // SPH: smallest h / |a|
+    kSlotVmax = 11,    // SPH: largest |v|
+    kSlots = 12
 };
 
 // Finalize modes (bit mask).
 enum {
-    kFinBuild = 1,   // account a finished rebuild (stats, counter) and clear the flag
-    kFinForce = 2,   // reduce U and W into ctl->thermo (and the optional output)
-    kFinKE = 4,      // reduce the kinetic energy into ctl->thermo[1]
-    kFinRow = 8,     // append ctl->thermo as row ctl->step of the thermo output
+    kFinBuild = 1,   // account a finished rebuild and clear the system's flag
+    kFinForce = 2,   // reduce U and W into the system's thermo (and the optional output)
+    kFinKE = 4,      // reduce the kinetic energy into thermo[1]
+    kFinRow = 8,     // append the system's thermo as row `step` of the thermo output
     kFinDisp = 16,   // reduce the displacement and raise the rebuild flag
-    kFinSph = 32     // SPH: time step from the CFL terms, time and history row
+    kFinVjp = 32     // add the parameter gradient (slots 0..5) to the output
 };
 
-// Device-resident control block.  One per context, inside the workspace.
-struct Ctl {
-    int32_t rebuild;        // 1: the neighbour structures must be rebuilt
-    int32_t overflow;       // longest list of the last build if above capacity, else 0
-    int32_t nonfinite;      // 1 once a non-finite value was seen
-    int32_t step;           // rows written in the current fpm_step call
-    int64_t n_rebuilds;     // rebuilds since fpm_set_particles
-    int32_t max_count;      // longest list of the last build
-    int32_t pad0;
-    int64_t total_count;    // total list entries of the last build
-    double thermo[8];       // last U, KE, W6
-    float sph_dt;           // SPH time step of the next step (from the latest rates)
-    float sph_dt_last;      // SPH time step of the last completed step
-    double sph_time;        // simulated SPH time
-};
-
-// Device view of the box.
+// Device view of one periodic (or partly closed) box and its cell grid.
 struct Box {
     float L[3];
     float half[3];
@@ -69,29 +57,69 @@ struct Box {
     float inv[3];           // nc / L in FP32
 };
 
+// One system of the batch (device table, read with scalar loads).
+struct SysDesc {
+    Box box;
+    int32_t n;              // particles
+    int32_t slot_base;      // first slot (a multiple of kBlock)
+    int32_t n_pad;          // slots (a multiple of kBlock, >= n + 1)
+    int32_t blk_base;       // first particle workgroup
+    int32_t cell_base;      // first cell of the global cell numbering
+    int32_t ncells;
+    int32_t off_base;       // first entry of the offsets array (ncells + 1 entries)
+    int32_t zb, nzb;        // column Verlet build: z-cells per workgroup, z-blocks (0: none)
+    int32_t item_base;      // first work item of the column build
+    int32_t dummy;          // padding slot slot_base + n: far outside every box
+    int32_t caller_base;    // first caller index of this system
+};
+
+// Per-system control words.
+struct SysCtl {
+    int32_t rebuild;        // 1: this system's neighbour structures must be rebuilt
+    int32_t step;           // rows written in the current fpm_step call
+    int64_t n_rebuilds;     // rebuilds since fpm_set_particles
+    double thermo[8];       // last U, KE, W6
+};
+
+// Context-wide control block.
+struct Ctl {
+    int32_t overflow;       // a list length above the capacity (sticky), else 0
+    int32_t nonfinite;      // 1 once a non-finite value was seen (sticky)
+    int32_t max_count;      // longest list (filled on request)
+    int32_t pad0;
+    int64_t total_count;    // total list entries (filled on request)
+    float sph_dt;           // SPH time step of the next step (from the latest rates)
+    float sph_dt_last;      // SPH time step of the last completed step
+    double sph_time;        // simulated SPH time
+};
+
 // Pointers into the workspace.  Buffer 0 holds the cell-sorted state between
 // rebuilds; a rebuild gathers into buffer 1 and the Verlet build copies it back.
 struct State {
     float4 *pos[2];         // x, y, z, type bits
     float4 *vel[2];         // vx, vy, vz, (SPH: rho)
-    int32_t *id[2];         // slot -> caller index
+    int32_t *id[2];         // slot -> caller index (global over the batch)
     float4 *frc;            // fx, fy, fz, (LJ: atom energy / SPH: drho/dt)
     float4 *xbuild;         // positions at the last rebuild
-    int32_t *cid;           // cell of each slot
+    int32_t *cid;           // global cell of each slot
     int32_t *rnk;           // arrival rank inside the cell
     int2 *tmp;              // (caller id, source slot) after the scatter
     int32_t *cnt;           // per-cell counts (kept at zero between rebuilds)
-    int32_t *off;           // exclusive scan of counts, ncells + 1
-    int32_t *nbr;           // Verlet list, see nbr_index()
+    int32_t *off;           // per system: exclusive scan of counts (global slots), ncells + 1
+    int32_t *nbr;           // Verlet lists, see nbr_index()
     uint32_t *nnb;          // list length | kWrapBit
     double *part;           // per-block partials, part[slot * pstride + block]
+    float4 *aux;            // per-slot scratch (adjoint input, sorted)
     Ctl *ctl;
-    int32_t pstride;        // >= the grid of every kernel that writes partials
-    int32_t dummy;          // padding slot (index n): a particle far outside every box;
-                            // lists are padded with it to a multiple of 8 entries
+    SysCtl *sctl;           // per system
+    const SysDesc *sys;     // per system
+    const int32_t *blk2sys; // particle workgroup -> system
+    const int32_t *item2sys;  // column-build work item -> system
+    int32_t nsys;
+    int32_t pstride;        // number of particle workgroups
 };
 
-// Position of the padding slot: far enough that no pair with it is ever in
+// Position of the padding slots: far enough that no pair with them is ever in
 // range, small enough that squared FP32 distances stay finite.
 constexpr float kFarAway = 1.0e18f;
 
@@ -102,6 +130,13 @@ __host__ __device__ __forceinline__ int64_t nbr_index(int64_t i, int k, int cap4
     return (((i >> 6) * (int64_t)cap4 + (k >> 2)) * 64 + (i & 63)) * 4 + (k & 3);
 }
 
+// Host copy of one system's layout.
+struct SysHost {
+    SysDesc d;
+    int nblk;               // particle workgroups
+    int nitems;             // column-build work items
+};
+
 }  // namespace fpm
 
 struct fpm_ctx {
@@ -111,27 +146,40 @@ struct fpm_ctx {
     bool box_set = false, nbr_set = false, have_particles = false, forces_valid = false;
     bool build_pending = false;        // cell list rebuilt without the Verlet list
     bool sph = false;                  // the kept rates are SPH rates (not LJ forces)
-    fpm::Box box{};
+    // systems: boxes and particle counts (a single box is a batch of one)
+    std::vector<fpm::Box> boxes;
+    std::vector<int64_t> counts;       // particles per system (batch set-up), empty otherwise
     float r_cut = 0.f, skin = 0.f;
     float R2 = 0.f;          // (r_cut + skin)^2 rounded to FP32
     float rc2 = 0.f;         // r_cut^2 rounded to FP32
     float disp2_thr = 0.f;   // (skin/2)^2 rounded to FP32
     int32_t cap = 0;         // list capacity asked for
     int32_t cap4 = 0;        // allocated capacity in groups of 4 (>= cap, multiple of 2)
-    int64_t ncells = 0;
-    int64_t n = 0, n_pad = 0;
+    int64_t n = 0;           // particles of the whole batch
+    int64_t n_slots = 0;     // slots of the whole batch
     void *ws = nullptr;
     size_t ws_bytes = 0;
     fpm::State st{};
-    int nblk = 0;            // workgroups of the particle kernels
-    int nblk_build = 0;      // workgroups of the Verlet-list build
-    int zb = 0;              // z-cells per workgroup of the column build (0: per-particle build)
-    int nzb = 0;             // z-blocks per column
+    std::vector<fpm::SysHost> sys;
+    int nsys = 0;
+    int nblk = 0;            // particle workgroups of the batch
+    int ncells_total = 0;
+    int noff_total = 0;
+    int nitems = 0;          // column-build work items
+    int n_pa_blocks = 0;     // workgroups of systems built particle by particle
+    int32_t *pa_blocks = nullptr;  // device list of those workgroups
+    int max_ncells = 0;
+    int max_sys_blocks = 0;  // particle workgroups of the largest system
+    // tuning (fpm_set_tuning); 0 = automatic
+    int tune_verlet_path = 0;   // 1: particle by particle, 2: column blocks
+    int tune_zb = 0;            // z-cells per column workgroup
+    int tune_unroll = 0;        // force kernel: entries in flight per lane (4 or 8)
     // graphs of fpm_step, keyed by their parameters
     hipGraphExec_t g_first = nullptr, g_chunk = nullptr, g_one = nullptr;
     double *g_thermo = nullptr;
     float g_dt = 0.f;
     fpm_lj_params g_prm{};
+    int g_unroll = 0;
     hipGraphExec_t s_first = nullptr, s_chunk = nullptr, s_one = nullptr;  // SPH graphs
     fpm_sph_params s_prm{};
     double *s_hist = nullptr;
@@ -155,10 +203,23 @@ hipError_t launch_cell_build(fpm_ctx *c);
 hipError_t launch_copy_back(fpm_ctx *c);
 hipError_t launch_verlet_build(fpm_ctx *c);
 hipError_t launch_list_stats(fpm_ctx *c);  // fills ctl->max_count and ctl->total_count
-// z-cells per workgroup of the column Verlet build, 0 when the grid is too
-// small for it (fewer than three cells along an axis).
-int verlet_zblock(int64_t n, int64_t ncells, const int nc[3]);
+// z-cells per workgroup of the column Verlet build for one system, 0 when the
+// grid is too small for it (fewer than three cells along an axis).
+int verlet_zblock(int64_t n, int64_t ncells, const int nc[3], int tune_zb);
 hipError_t launch_lj_forces(fpm_ctx *c, const fpm_lj_params &p);
+// Output of the force VJP kernel.  kVjpPlain: gx = g.  kVjpLast: gx += g.
+// kVjpStep: one reverse velocity-Verlet step on caller-order FP64 arrays:
+// gx (= xbar) += g; vbar += dt xbar; fbar = dt/2 vbar + floss (floss may be null).
+enum { kVjpPlain = 0, kVjpStep = 1, kVjpLast = 2 };
+struct AdjOut {
+    double *gx, *vbar, *fbar;
+    const double *floss;
+    double dt;
+    int mode;
+};
+hipError_t launch_lj_vjp(fpm_ctx *c, const fpm_lj_params &p, const double *lam,
+                         const double *vbar, const AdjOut &o);
+hipError_t launch_set_positions(fpm_ctx *c, const float *pos);
 hipError_t launch_integrate(fpm_ctx *c, float dt, int mode);
 hipError_t launch_finalize(fpm_ctx *c, int mode, double *out, double *rows);
 hipError_t launch_gather_out(fpm_ctx *c, float *pos, float *vel, float *frc, float *rho,
@@ -176,14 +237,11 @@ enum { kKickDriftFirst = 0, kKickKickDrift = 1, kKickOnly = 2 };
 
 // Relative half-width of the band around r_cut^2 inside which the interaction
 // kernels evaluate the FP32 predicate instead of trusting the exact FP64
-// squared distance.  Outside it both agree: the FP32 squared distance differs
-// from the exact one by at most 3 L |d| 2^-23 (the once-rounded ghost
-// coordinate xj +- L) plus 5 ulp of d^2, which the band covers twice over.
-inline double predicate_band(const fpm_ctx *c) {
-    double lmax = 0.0;
-    for (int a = 0; a < 3; a++)
-        if (c->box.per[a] && (double)c->box.L[a] > lmax) lmax = (double)c->box.L[a];
-    return 6.0 * lmax / (double)c->r_cut * 0x1p-23 + 1e-6;
-}
+// squared distance.  Outside it both agree: every FP32 separation component is
+// the exact one rounded once (pairs within the list radius satisfy the
+// exactness condition of the image shift even between rebuilds, as
+// r_cut + skin < L/2), so with u = 2^-24 the FP32 squared distance is within
+// 5u (3e-7) relative of the exact one; the band is 2e-6.
+inline double predicate_band(const fpm_ctx *) { return 2e-6; }
 
 }  // namespace fpm

@@ -8,8 +8,10 @@ namespace fpm {
 
 // One coordinate difference of the FP32 neighbour predicate (header of fpm.h):
 // t = xj - xi; on a periodic axis t > L/2 selects the image (xj - L) - xi and
-// t < -L/2 the image (xj + L) - xi, i.e. the ghost copy of j shifted by one
-// period.  Every operation rounds separately.
+// t < -L/2 the image xj - (xi - L): the coordinate in the upper half of the
+// box moves down one period, which is exact, so the image separation is
+// rounded once and is the exact negative of the (j, i) separation.  Every
+// operation rounds separately.
 __device__ __forceinline__ float img_delta(float xi, float xj, float L, float half, int per) {
 #pragma clang fp contract(off)
     float t = xj - xi;
@@ -18,8 +20,8 @@ __device__ __forceinline__ float img_delta(float xi, float xj, float L, float ha
             float s = xj - L;
             t = s - xi;
         } else if (t < -half) {
-            float s = xj + L;
-            t = s - xi;
+            float s = xi - L;
+            t = xj - s;
         }
     }
     return t;
@@ -97,6 +99,19 @@ __device__ __forceinline__ int cell_of(float3 p, const Box &b) {
 }
 
 __device__ __forceinline__ float3 xyz(float4 v) { return make_float3(v.x, v.y, v.z); }
+
+// The system of the current particle workgroup (uniform over the workgroup).
+__device__ __forceinline__ int block_system(const State &st) { return st.blk2sys[blockIdx.x]; }
+
+// Global slot of this thread in a particle kernel (systems are block aligned).
+__device__ __forceinline__ int64_t global_slot() {
+    return (int64_t)blockIdx.x * kBlock + threadIdx.x;
+}
+
+// Offsets entry of global cell c of system d.
+__device__ __forceinline__ int off_index(const SysDesc &d, int c) {
+    return d.off_base + (c - d.cell_base);
+}
 
 // Wavefront reductions (64 lanes).
 __device__ __forceinline__ double wave_sum(double v) {

@@ -11,12 +11,16 @@
 namespace fpm {
 namespace {
 
+// The FP32 updates round after every multiply and add (no fused multiply-add),
+// so a trajectory is reproducible from its definition operation by operation.
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_integrate(State st, Box b, int64_t n, float dt) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kBlock) void k_integrate(State st, float dt) {
+#pragma clang fp contract(off)
+    const SysDesc &d = st.sys[block_system(st)];
+    const int64_t i = global_slot();
     const float h = 0.5f * dt;
     double ke = 0.0, d2 = 0.0;
-    if (i < n) {
+    if (i - d.slot_base < d.n) {
         float4 v = st.vel[0][i];
         const float4 f = st.frc[i];
         v.x += h * f.x;
@@ -36,7 +40,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(State st, Box b, int64_t n
             p.y += dt * v.y;
             p.z += dt * v.z;
             st.pos[0][i] = p;
-            d2 = dist2_pred(xyz(st.xbuild[i]), xyz(p), b);
+            d2 = dist2_pred(xyz(st.xbuild[i]), xyz(p), d.box);
             if (!isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z)) st.ctl->nonfinite = 1;
         }
     }
@@ -55,35 +59,41 @@ __global__ __launch_bounds__(kBlock) void k_integrate(State st, Box b, int64_t n
     }
 }
 
-// One workgroup of 1024 threads reduces the per-block partials in a fixed
-// order (thread t takes blocks t, t + 1024, ... of the slots it needs, all
+// One workgroup per system reduces that system's per-block partials in a
+// fixed order (thread t takes blocks t, t + NT, ... of the slots it needs, all
 // loads issued before any is summed; then wavefront shuffles, and one thread
-// per slot adds the 16 wavefront results in order) and applies the step's
+// per slot adds the wavefront results in order) and applies the step's
 // control logic (see the kFin* modes).
-constexpr int kFinRowsPerThread = 4;  // blocks per thread and pass (4096 workgroups per pass)
+constexpr int kFinRowsPerThread = 4;
 
-__global__ __launch_bounds__(1024) void k_finalize(State st, int nblk, int mode, float thr,
-                                                   double *out, double *rows) {
-    constexpr int NS = 9;  // U, W6, KE, displacement
-    __shared__ double red[16][NS];
+template <int NT>
+__global__ __launch_bounds__(NT) void k_finalize(State st, int mode, float thr, double *out,
+                                                 double *rows) {
+    constexpr int NS = 9;  // U (or VJP 0), W6 (VJP 1..5), KE, displacement
+    constexpr int NW = NT / 64;
+    __shared__ double red[NW][NS];
     __shared__ double tot[NS];
+    const int s = blockIdx.x;
+    const SysDesc &d = st.sys[s];
+    const int b0 = d.blk_base, nb = d.n_pad / kBlock;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const bool want_f = mode & kFinForce, want_k = mode & kFinKE, want_d = mode & kFinDisp;
+    const bool want_f = mode & (kFinForce | kFinVjp), want_k = mode & kFinKE,
+               want_d = mode & kFinDisp;
     const double *P = st.part;
     const int64_t S = st.pstride;
     double acc[NS];
 #pragma unroll
     for (int c = 0; c < NS; c++) acc[c] = 0.0;
-    for (int r0 = t; r0 < nblk; r0 += 1024 * kFinRowsPerThread) {
+    for (int r0 = t; r0 < nb; r0 += NT * kFinRowsPerThread) {
         double v[kFinRowsPerThread][NS];
 #pragma unroll
         for (int q = 0; q < kFinRowsPerThread; q++) {
-            const int r = r0 + q * 1024;
-            const bool ok = r < nblk;
+            const int r = r0 + q * NT;
+            const bool ok = r < nb;
 #pragma unroll
-            for (int c = 0; c < 7; c++) v[q][c] = (want_f && ok) ? P[c * S + r] : 0.0;
-            v[q][7] = (want_k && ok) ? P[kSlotKE * S + r] : 0.0;
-            v[q][8] = (want_d && ok) ? P[kSlotDisp * S + r] : 0.0;
+            for (int c = 0; c < 7; c++) v[q][c] = (want_f && ok) ? P[c * S + b0 + r] : 0.0;
+            v[q][7] = (want_k && ok) ? P[kSlotKE * S + b0 + r] : 0.0;
+            v[q][8] = (want_d && ok) ? P[kSlotDisp * S + b0 + r] : 0.0;
         }
 #pragma unroll
         for (int q = 0; q < kFinRowsPerThread; q++) {
@@ -100,45 +110,75 @@ __global__ __launch_bounds__(1024) void k_finalize(State st, int nblk, int mode,
         for (int c = 0; c < NS; c++) red[w][c] = acc[c];
     __syncthreads();
     if (t < NS) {
-        double s = red[0][t];
-        for (int k = 1; k < 16; k++) s = t == 8 ? fmax(s, red[k][t]) : s + red[k][t];
-        tot[t] = s;
+        double x = red[0][t];
+        for (int k = 1; k < NW; k++) x = t == 8 ? fmax(x, red[k][t]) : x + red[k][t];
+        tot[t] = x;
     }
     __syncthreads();
     if (t != 0) return;
-    Ctl *ctl = st.ctl;
-    if ((mode & kFinBuild) && ctl->rebuild) {
-        ctl->n_rebuilds += 1;
-        ctl->rebuild = 0;
+    SysCtl *sc = st.sctl + s;
+    if ((mode & kFinBuild) && sc->rebuild) {
+        sc->n_rebuilds += 1;
+        sc->rebuild = 0;
+    }
+    if (mode & kFinVjp) {
+        if (out)
+            for (int c = 0; c < 6; c++) out[(int64_t)s * 6 + c] += tot[c];
+        return;
     }
     if (want_f) {
-        ctl->thermo[0] = tot[kSlotU];
-        for (int c = 0; c < 6; c++) ctl->thermo[2 + c] = tot[kSlotW + c];
+        sc->thermo[0] = tot[kSlotU];
+        for (int c = 0; c < 6; c++) sc->thermo[2 + c] = tot[kSlotW + c];
         if (out) {
-            out[0] = tot[kSlotU];
-            out[1] = 0.0;
-            for (int c = 0; c < 6; c++) out[2 + c] = tot[kSlotW + c];
+            out[(int64_t)s * 8] = tot[kSlotU];
+            out[(int64_t)s * 8 + 1] = 0.0;
+            for (int c = 0; c < 6; c++) out[(int64_t)s * 8 + 2 + c] = tot[kSlotW + c];
         }
     }
-    if (want_k) ctl->thermo[1] = 0.5 * tot[kSlotKE];
+    if (want_k) sc->thermo[1] = 0.5 * tot[kSlotKE];
     if (mode & kFinRow) {
-        const int row = ctl->step;
+        const int row = sc->step;
         if (rows)
-            for (int c = 0; c < 8; c++) rows[(int64_t)row * 8 + c] = ctl->thermo[c];
-        ctl->step = row + 1;
+            for (int c = 0; c < 8; c++)
+                rows[((int64_t)row * st.nsys + s) * 8 + c] = sc->thermo[c];
+        sc->step = row + 1;
     }
-    if (want_d && tot[8] > (double)thr) ctl->rebuild = 1;
+    if (want_d && tot[8] > (double)thr) sc->rebuild = 1;
 }
 
-__global__ void k_reset_step(Ctl *ctl) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) ctl->step = 0;
+__global__ void k_reset_step(SysCtl *sctl, int nsys) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < nsys) sctl[s].step = 0;
+}
+
+// New positions in caller order for the current sorted state (type bits and
+// the neighbour structures are kept); the displacement since the last build
+// decides, as after a drift, whether they must be rebuilt.
+__global__ __launch_bounds__(kBlock) void k_set_positions(State st, const float *pos) {
+    const SysDesc &d = st.sys[block_system(st)];
+    const int64_t i = global_slot();
+    double d2 = 0.0;
+    if (i - d.slot_base < d.n) {
+        const int64_t r = st.id[0][i];
+        float4 p = st.pos[0][i];
+        p.x = pos[3 * r];
+        p.y = pos[3 * r + 1];
+        p.z = pos[3 * r + 2];
+        st.pos[0][i] = p;
+        d2 = dist2_pred(xyz(st.xbuild[i]), xyz(p), d.box);
+        if (!isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z)) st.ctl->nonfinite = 1;
+    }
+    double v1[1] = {d2};
+    const int s1[1] = {kSlotDisp}, o1[1] = {1};
+    block_partials<1>(v1, s1, o1, st.part, st.pstride);
 }
 
 // State back in caller order.
-__global__ void k_gather_out(State st, int64_t n, float *pos, float *vel, float *frc, float *rho,
+__global__ void k_gather_out(State st, float *pos, float *vel, float *frc, float *rho,
                              float *drho) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const SysDesc &d = st.sys[block_system(st)];
+    const int64_t i = global_slot();
+    if (i - d.slot_base >= d.n) return;
     const int64_t r = st.id[0][i];
     const float4 p = st.pos[0][i], v = st.vel[0][i], f = st.frc[i];
     if (pos) {
@@ -163,35 +203,43 @@ __global__ void k_gather_out(State st, int64_t n, float *pos, float *vel, float 
 }  // namespace
 
 hipError_t launch_integrate(fpm_ctx *c, float dt, int mode) {
-    const unsigned g = (unsigned)c->nblk;
+    const dim3 g((unsigned)c->nblk), t(kBlock);
     if (mode == kKickDriftFirst)
-        hipLaunchKernelGGL(k_integrate<kKickDriftFirst>, dim3(g), dim3(kBlock), 0, c->stream,
-                           c->st, c->box, c->n, dt);
+        hipLaunchKernelGGL(k_integrate<kKickDriftFirst>, g, t, 0, c->stream, c->st, dt);
     else if (mode == kKickKickDrift)
-        hipLaunchKernelGGL(k_integrate<kKickKickDrift>, dim3(g), dim3(kBlock), 0, c->stream,
-                           c->st, c->box, c->n, dt);
+        hipLaunchKernelGGL(k_integrate<kKickKickDrift>, g, t, 0, c->stream, c->st, dt);
     else
-        hipLaunchKernelGGL(k_integrate<kKickOnly>, dim3(g), dim3(kBlock), 0, c->stream, c->st,
-                           c->box, c->n, dt);
+        hipLaunchKernelGGL(k_integrate<kKickOnly>, g, t, 0, c->stream, c->st, dt);
     return hipGetLastError();
 }
 
+// Largest systems get a full 1024-thread workgroup; batches of small systems
+// one wavefront-quad each.
 hipError_t launch_finalize(fpm_ctx *c, int mode, double *out, double *rows) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, c->stream, c->st, c->nblk, mode,
-                       c->disp2_thr, out, rows);
+    if (c->max_sys_blocks > 1024)
+        hipLaunchKernelGGL(k_finalize<1024>, dim3(c->nsys), dim3(1024), 0, c->stream, c->st,
+                           mode, c->disp2_thr, out, rows);
+    else
+        hipLaunchKernelGGL(k_finalize<256>, dim3(c->nsys), dim3(256), 0, c->stream, c->st, mode,
+                           c->disp2_thr, out, rows);
     return hipGetLastError();
 }
 
 hipError_t launch_reset_step(fpm_ctx *c) {
-    hipLaunchKernelGGL(k_reset_step, dim3(1), dim3(64), 0, c->stream, c->st.ctl);
+    hipLaunchKernelGGL(k_reset_step, dim3((c->nsys + 255) / 256), dim3(256), 0, c->stream,
+                       c->st.sctl, c->nsys);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_positions(fpm_ctx *c, const float *pos) {
+    hipLaunchKernelGGL(k_set_positions, dim3(c->nblk), dim3(kBlock), 0, c->stream, c->st, pos);
     return hipGetLastError();
 }
 
 hipError_t launch_gather_out(fpm_ctx *c, float *pos, float *vel, float *frc, float *rho,
                              float *drho) {
-    const unsigned g = (unsigned)((c->n + 255) / 256);
-    hipLaunchKernelGGL(k_gather_out, dim3(g), dim3(256), 0, c->stream, c->st, c->n, pos, vel, frc,
-                       rho, drho);
+    hipLaunchKernelGGL(k_gather_out, dim3(c->nblk), dim3(kBlock), 0, c->stream, c->st, pos, vel,
+                       frc, rho, drho);
     return hipGetLastError();
 }
 

@@ -1,21 +1,20 @@
 // Lennard-Jones forces, potential energy and virial over the Verlet list
 // (section 4.1: V(r) = 4 eps ((sig/r)^12 - (sig/r)^6); the force on p from q is
 // 24 eps (2 sig^12 / rn^7 - sig^6 / rn^4) (xp - xq), rn = |xp - xq|^2, and the
-// pair is dropped when rn > r_cut^2).
+// pair is dropped when rn > r_cut^2), and the vector-Jacobian product of the
+// forces for the adjoint.
 //
 // One lane per cell-sorted particle walks its full list (every pair is seen
-// from both sides, so there are no scattered writes).  The list is read eight
-// entries at a time (two 16-byte loads per lane) and the eight neighbour
-// positions are gathered before any is used, so each lane keeps eight loads in
-// flight instead of waiting on every entry.
+// from both sides, so there are no scattered writes).  The list is read UNR
+// entries at a time (16-byte loads) and the UNR neighbour positions are
+// gathered before any is used, so each lane keeps UNR loads in flight.
 //
 // Set membership follows the FP32 predicate exactly; the pair physics is
 // evaluated in FP64 from the exact separation of the FP32 coordinates and
 // accumulated per lane in FP64.  The FP64 squared distance decides membership
-// directly unless it lies within a relative 1e-6 of r_cut^2, where the FP32
-// predicate (whose error is below 5 ulp, about 3e-7 relative) is evaluated.
-// Energy and virial partials go to one row per workgroup; the finalize kernel
-// sums them in a fixed order.
+// directly unless it lies in a narrow band around r_cut^2 (predicate_band),
+// where the FP32 predicate is evaluated.  Partials go to one row per
+// workgroup; the finalize kernel sums them per system in a fixed order.
 #include "geom.h"
 
 namespace fpm {
@@ -24,6 +23,7 @@ namespace {
 struct LJCoef {
     double c12[3];  // 4 eps sig^12
     double c6[3];   // 4 eps sig^6
+    double inv_eps[3], inv_sig[3];
 };
 
 // 1/x in FP64: the hardware estimate refined by one Newton step.
@@ -33,24 +33,17 @@ __device__ __forceinline__ double recip(double x) {
     return fma(y, e, y);
 }
 
-// Per-lane accumulators.  The virial needs no per-pair work: summed over all
-// particles, 1/2 sum_ij r_ij (x) f_ij with r_ij = x_i - x_j + s_ij (s_ij the
-// periodic shift, f_ji = -f_ij, s_ji = -s_ij) equals
-// sum_i x_i (x) F_i + 1/2 sum_ij s_ij (x) f_ij, so each lane adds x_i (x) F_i
-// once and only image pairs add a shift term (wx*).
-struct Acc {
-    double fx = 0.0, fy = 0.0, fz = 0.0, u = 0.0;
-    double wxx = 0.0, wyy = 0.0, wzz = 0.0, wxy = 0.0, wxz = 0.0, wyz = 0.0;
-};
-
-// One list entry.  Padding entries point at a particle far away, so every
-// entry can be processed without a bounds test.
-template <int NT, bool IMG>
-__device__ __forceinline__ void pair(Acc &a, float3 pi, double xi, double yi, double zi, int ti,
-                                     float4 q, const Box &b, float rc2, double rc2lo,
-                                     double rc2hi, const LJCoef &cf) {
-    double dx = xi - (double)q.x, dy = yi - (double)q.y, dz = zi - (double)q.z;
-    double sx = 0.0, sy = 0.0, sz = 0.0;  // periodic shift of this pair
+// Separation x_i - x_j (exact FP64, image as chosen by the predicate), its
+// periodic shift, and membership of the pair in the force set.
+template <bool IMG>
+__device__ __forceinline__ bool separation(float3 pi, double xi, double yi, double zi, float4 q,
+                                           const Box &b, float rc2, double rc2lo, double rc2hi,
+                                           double &dx, double &dy, double &dz, double &sx,
+                                           double &sy, double &sz) {
+    dx = xi - (double)q.x;
+    dy = yi - (double)q.y;
+    dz = zi - (double)q.z;
+    sx = sy = sz = 0.0;
     if (IMG) {
         sx = -(double)img_shift(pi.x, q.x, b.half[0], b.per[0]) * (double)b.L[0];
         sy = -(double)img_shift(pi.y, q.y, b.half[1], b.per[1]) * (double)b.L[1];
@@ -63,14 +56,43 @@ __device__ __forceinline__ void pair(Acc &a, float3 pi, double xi, double yi, do
     bool in = r2 <= rc2lo;
     if (!in && r2 <= rc2hi)
         in = (IMG ? dist2_pred(pi, xyz(q), b) : dist2_direct(pi, xyz(q))) <= rc2;
-    if (in) {
-        double c12 = cf.c12[0], c6 = cf.c6[0];
-        if (NT == 2) {
-            const int tp = ti + __float_as_int(q.w);
-            c12 = tp == 0 ? cf.c12[0] : (tp == 1 ? cf.c12[1] : cf.c12[2]);
-            c6 = tp == 0 ? cf.c6[0] : (tp == 1 ? cf.c6[1] : cf.c6[2]);
-        }
-        const double r2i = recip(r2);
+    return in;
+}
+
+template <int NT>
+__device__ __forceinline__ int pair_type(int ti, float4 q) {
+    return NT == 2 ? ti + __float_as_int(q.w) : 0;
+}
+
+template <int NT>
+__device__ __forceinline__ void coef(const LJCoef &cf, int tp, double &c12, double &c6) {
+    c12 = cf.c12[0];
+    c6 = cf.c6[0];
+    if (NT == 2) {
+        c12 = tp == 0 ? cf.c12[0] : (tp == 1 ? cf.c12[1] : cf.c12[2]);
+        c6 = tp == 0 ? cf.c6[0] : (tp == 1 ? cf.c6[1] : cf.c6[2]);
+    }
+}
+
+// Per-lane accumulators.  The virial needs no per-pair work: summed over all
+// particles, 1/2 sum_ij r_ij (x) f_ij with r_ij = x_i - x_j + s_ij (s_ij the
+// periodic shift, f_ji = -f_ij, s_ji = -s_ij) equals
+// sum_i x_i (x) F_i + 1/2 sum_ij s_ij (x) f_ij, so each lane adds x_i (x) F_i
+// once and only image pairs add a shift term (w*).
+struct Acc {
+    double fx = 0.0, fy = 0.0, fz = 0.0, u = 0.0;
+    double wxx = 0.0, wyy = 0.0, wzz = 0.0, wxy = 0.0, wxz = 0.0, wyz = 0.0;
+};
+
+template <int NT, bool IMG>
+__device__ __forceinline__ void pair(Acc &a, float3 pi, double xi, double yi, double zi, int ti,
+                                     float4 q, const Box &b, float rc2, double rc2lo,
+                                     double rc2hi, const LJCoef &cf) {
+    double dx, dy, dz, sx, sy, sz;
+    if (separation<IMG>(pi, xi, yi, zi, q, b, rc2, rc2lo, rc2hi, dx, dy, dz, sx, sy, sz)) {
+        double c12, c6;
+        coef<NT>(cf, pair_type<NT>(ti, q), c12, c6);
+        const double r2i = recip(fma(dx, dx, fma(dy, dy, dz * dz)));
         const double r6i = r2i * r2i * r2i;
         const double s = r6i * r2i * fma(12.0 * c12, r6i, -6.0 * c6);
         a.u = fma(r6i, fma(c12, r6i, -c6), a.u);
@@ -89,8 +111,8 @@ __device__ __forceinline__ void pair(Acc &a, float3 pi, double xi, double yi, do
     }
 }
 
-// Walks a list padded to a multiple of eight entries.
-template <int NT, bool IMG>
+// Walks a list padded to a multiple of eight entries, UNR (4 or 8) at a time.
+template <int NT, bool IMG, int UNR>
 __device__ __forceinline__ void walk(Acc &a, const float4 *__restrict__ pos,
                                      const int4 *__restrict__ lst, int cnt, float4 pi4,
                                      const Box &b, float rc2, double rc2lo, double rc2hi,
@@ -98,27 +120,36 @@ __device__ __forceinline__ void walk(Acc &a, const float4 *__restrict__ pos,
     const float3 pi = xyz(pi4);
     const double xi = pi.x, yi = pi.y, zi = pi.z;
     const int ti = __float_as_int(pi4.w);
-    for (int k = 0; k < cnt; k += 8) {
-        const int4 e0 = lst[(k >> 2) * 64];
-        const int4 e1 = lst[((k >> 2) + 1) * 64];
-        const int jj[8] = {e0.x, e0.y, e0.z, e0.w, e1.x, e1.y, e1.z, e1.w};
-        float4 q[8];
+    for (int k = 0; k < cnt; k += UNR) {
+        int jj[UNR];
 #pragma unroll
-        for (int u = 0; u < 8; u++) q[u] = pos[jj[u]];
+        for (int g = 0; g < UNR / 4; g++) {
+            const int4 e = lst[((k >> 2) + g) * 64];
+            jj[4 * g] = e.x;
+            jj[4 * g + 1] = e.y;
+            jj[4 * g + 2] = e.z;
+            jj[4 * g + 3] = e.w;
+        }
+        float4 q[UNR];
 #pragma unroll
-        for (int u = 0; u < 8; u++)
+        for (int u = 0; u < UNR; u++) q[u] = pos[jj[u]];
+#pragma unroll
+        for (int u = 0; u < UNR; u++)
             pair<NT, IMG>(a, pi, xi, yi, zi, ti, q[u], b, rc2, rc2lo, rc2hi, cf);
     }
 }
 
-template <int NT>
-__global__ __launch_bounds__(kBlock) void k_lj(State st, Box b, int64_t n, float rc2,
-                                               double rc2lo, double rc2hi, LJCoef cf, int cap4) {
+template <int NT, int UNR>
+__global__ __launch_bounds__(kBlock) void k_lj(State st, float rc2, double rc2lo, double rc2hi,
+                                               LJCoef cf, int cap4) {
+    const SysDesc &d = st.sys[block_system(st)];
+    const Box b = d.box;
     const float4 *__restrict__ pos = st.pos[0];
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = global_slot();
+    const bool active = i - d.slot_base < d.n;
     uint32_t nn = 0;
     float4 pi4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (i < n) {
+    if (active) {
         nn = st.nnb[i];
         pi4 = pos[i];
     }
@@ -128,10 +159,10 @@ __global__ __launch_bounds__(kBlock) void k_lj(State st, Box b, int64_t n, float
                       ((i >> 6) * (int64_t)cap4) * 64 + (i & 63);
     Acc a;
     if (img_wave)
-        walk<NT, true>(a, pos, lst, cnt, pi4, b, rc2, rc2lo, rc2hi, cf);
+        walk<NT, true, UNR>(a, pos, lst, cnt, pi4, b, rc2, rc2lo, rc2hi, cf);
     else
-        walk<NT, false>(a, pos, lst, cnt, pi4, b, rc2, rc2lo, rc2hi, cf);
-    if (i < n) {
+        walk<NT, false, UNR>(a, pos, lst, cnt, pi4, b, rc2, rc2lo, rc2hi, cf);
+    if (active) {
         st.frc[i] = make_float4((float)a.fx, (float)a.fy, (float)a.fz, (float)(0.5 * a.u));
         if (!isfinite(a.fx) || !isfinite(a.fy) || !isfinite(a.fz)) st.ctl->nonfinite = 1;
     }
@@ -149,25 +180,204 @@ __global__ __launch_bounds__(kBlock) void k_lj(State st, Box b, int64_t n, float
     block_partials<7>(v, slot, op, st.part, st.pstride);
 }
 
-}  // namespace
+// ---------------------------------------------------------------------------
+// Vector-Jacobian product of the forces.  With F_i = sum_j s(u_ij) r_ij,
+// r_ij = x_i - x_j, u = |r|^2 and a cotangent lam (dL/dF):
+//   dL/dx_k = sum_j [ s (lam_k - lam_j) + 2 s'(u) r_kj (r_kj . (lam_k - lam_j)) ],
+//   dL/dtheta = 1/2 sum_i sum_j (ds/dtheta) r_ij . (lam_i - lam_j)
+// (each pair is visited from both sides, hence the 1/2), with
+// s = 12 c12 u^-7 - 6 c6 u^-4, s' = -84 c12 u^-8 + 24 c6 u^-5,
+// ds/deps = s / eps, ds/dsig = (144 c12 u^-7 - 36 c6 u^-4) / sig.
+// The pair set is the force set; the cut-off itself is not differentiated.
 
-hipError_t launch_lj_forces(fpm_ctx *c, const fpm_lj_params &p) {
+struct VjpAcc {
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+    double ge[3] = {0.0, 0.0, 0.0}, gs[3] = {0.0, 0.0, 0.0};
+};
+
+template <int NT, bool IMG>
+__device__ __forceinline__ void vjp_pair(VjpAcc &a, float3 pi, double xi, double yi, double zi,
+                                         int ti, float4 li, float4 q, float4 lj, const Box &b,
+                                         float rc2, double rc2lo, double rc2hi,
+                                         const LJCoef &cf) {
+    double dx, dy, dz, sx, sy, sz;
+    if (separation<IMG>(pi, xi, yi, zi, q, b, rc2, rc2lo, rc2hi, dx, dy, dz, sx, sy, sz)) {
+        const int tp = pair_type<NT>(ti, q);
+        double c12, c6;
+        coef<NT>(cf, tp, c12, c6);
+        const double r2i = recip(fma(dx, dx, fma(dy, dy, dz * dz)));
+        const double r6i = r2i * r2i * r2i;
+        const double s = r6i * r2i * fma(12.0 * c12, r6i, -6.0 * c6);
+        const double sp = r6i * r2i * r2i * fma(-84.0 * c12, r6i, 24.0 * c6);
+        const double lx = (double)li.x - (double)lj.x, ly = (double)li.y - (double)lj.y,
+                     lz = (double)li.z - (double)lj.z;
+        const double rl = fma(dx, lx, fma(dy, ly, dz * lz));
+        const double t = 2.0 * sp * rl;
+        a.gx = fma(s, lx, fma(t, dx, a.gx));
+        a.gy = fma(s, ly, fma(t, dy, a.gy));
+        a.gz = fma(s, lz, fma(t, dz, a.gz));
+        const double de = 0.5 * s * rl;  // times 1/eps later
+        const double ds = 0.5 * r6i * r2i * fma(144.0 * c12, r6i, -36.0 * c6) * rl;  // / sig
+        if (NT == 1) {
+            a.ge[0] += de;
+            a.gs[0] += ds;
+        } else {
+            a.ge[0] += tp == 0 ? de : 0.0;
+            a.ge[1] += tp == 1 ? de : 0.0;
+            a.ge[2] += tp == 2 ? de : 0.0;
+            a.gs[0] += tp == 0 ? ds : 0.0;
+            a.gs[1] += tp == 1 ? ds : 0.0;
+            a.gs[2] += tp == 2 ? ds : 0.0;
+        }
+    }
+}
+
+template <int NT, bool IMG>
+__device__ __forceinline__ void vjp_walk(VjpAcc &a, const float4 *__restrict__ pos,
+                                         const float4 *__restrict__ lam,
+                                         const int4 *__restrict__ lst, int cnt, float4 pi4,
+                                         float4 li, const Box &b, float rc2, double rc2lo,
+                                         double rc2hi, const LJCoef &cf) {
+    const float3 pi = xyz(pi4);
+    const double xi = pi.x, yi = pi.y, zi = pi.z;
+    const int ti = __float_as_int(pi4.w);
+    for (int k = 0; k < cnt; k += 4) {
+        const int4 e = lst[(k >> 2) * 64];
+        const int jj[4] = {e.x, e.y, e.z, e.w};
+        float4 q[4], l[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            q[u] = pos[jj[u]];
+            l[u] = lam[jj[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            vjp_pair<NT, IMG>(a, pi, xi, yi, zi, ti, li, q[u], l[u], b, rc2, rc2lo, rc2hi, cf);
+    }
+}
+
+// Cotangent in cell-sorted order (padding slots get zero): lam + h * vbar
+// (vbar may be null).
+__global__ void k_gather_lam(State st, const double *lam, const double *vbar, double h) {
+    const SysDesc &d = st.sys[block_system(st)];
+    const int64_t i = global_slot();
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (i - d.slot_base < d.n) {
+        const int64_t r = st.id[0][i];
+        double l[3] = {lam[3 * r], lam[3 * r + 1], lam[3 * r + 2]};
+        if (vbar)
+            for (int a = 0; a < 3; a++) l[a] = fma(h, vbar[3 * r + a], l[a]);
+        v = make_float4((float)l[0], (float)l[1], (float)l[2], 0.f);
+    }
+    st.aux[i] = v;
+}
+
+template <int NT>
+__global__ __launch_bounds__(kBlock) void k_lj_vjp(State st, float rc2, double rc2lo,
+                                                   double rc2hi, LJCoef cf, int cap4,
+                                                   AdjOut o) {
+    const SysDesc &d = st.sys[block_system(st)];
+    const Box b = d.box;
+    const float4 *__restrict__ pos = st.pos[0];
+    const int64_t i = global_slot();
+    const bool active = i - d.slot_base < d.n;
+    uint32_t nn = 0;
+    float4 pi4 = make_float4(0.f, 0.f, 0.f, 0.f), li = pi4;
+    if (active) {
+        nn = st.nnb[i];
+        pi4 = pos[i];
+        li = st.aux[i];
+    }
+    const bool img_wave = __ballot((nn & kWrapBit) != 0) != 0;
+    const int cnt = (int)(nn & ~kWrapBit);
+    const int4 *lst = reinterpret_cast<const int4 *>(st.nbr) +
+                      ((i >> 6) * (int64_t)cap4) * 64 + (i & 63);
+    VjpAcc a;
+    if (img_wave)
+        vjp_walk<NT, true>(a, pos, st.aux, lst, cnt, pi4, li, b, rc2, rc2lo, rc2hi, cf);
+    else
+        vjp_walk<NT, false>(a, pos, st.aux, lst, cnt, pi4, li, b, rc2, rc2lo, rc2hi, cf);
+    if (active) {
+        const int64_t r = st.id[0][i];
+        const double g[3] = {a.gx, a.gy, a.gz};
+        for (int c = 0; c < 3; c++) {
+            const int64_t q = 3 * r + c;
+            if (o.mode == kVjpPlain) {
+                o.gx[q] = g[c];
+            } else if (o.mode == kVjpLast) {
+                o.gx[q] += g[c];
+            } else {
+                // one reverse velocity-Verlet step (see fpm_lj_adjoint_step)
+                const double xb = o.gx[q] + g[c];
+                const double vb = fma(o.dt, xb, o.vbar[q]);
+                o.gx[q] = xb;
+                o.vbar[q] = vb;
+                o.fbar[q] = fma(0.5 * o.dt, vb, o.floss ? o.floss[q] : 0.0);
+            }
+        }
+    }
+    double v[6];
+    for (int p = 0; p < 3; p++) {
+        v[p] = a.ge[p] * cf.inv_eps[p];
+        v[3 + p] = a.gs[p] * cf.inv_sig[p];
+    }
+    const int slot[6] = {0, 1, 2, 3, 4, 5};
+    const int op[6] = {0, 0, 0, 0, 0, 0};
+    block_partials<6>(v, slot, op, st.part, st.pstride);
+}
+
+LJCoef make_coef(const fpm_lj_params &p) {
     LJCoef cf;
     for (int k = 0; k < 3; k++) {
         const double e = (double)p.eps[k], s = (double)p.sig[k];
         const double s6 = s * s * s * s * s * s;
         cf.c12[k] = 4.0 * e * s6 * s6;
         cf.c6[k] = 4.0 * e * s6;
+        cf.inv_eps[k] = e != 0.0 ? 1.0 / e : 0.0;
+        cf.inv_sig[k] = 1.0 / s;
     }
+    return cf;
+}
+
+}  // namespace
+
+hipError_t launch_lj_forces(fpm_ctx *c, const fpm_lj_params &p) {
+    const LJCoef cf = make_coef(p);
     const double band = predicate_band(c);
     const double rc2lo = (double)c->rc2 * (1.0 - band), rc2hi = (double)c->rc2 * (1.0 + band);
-    const unsigned g = (unsigned)((c->n_pad + kBlock - 1) / kBlock);
+    const dim3 g((unsigned)c->nblk), t(kBlock);
+    const bool u4 = c->tune_unroll == 4;
+    if (p.n_types == 2) {
+        if (u4)
+            hipLaunchKernelGGL((k_lj<2, 4>), g, t, 0, c->stream, c->st, c->rc2, rc2lo, rc2hi, cf,
+                               c->cap4);
+        else
+            hipLaunchKernelGGL((k_lj<2, 8>), g, t, 0, c->stream, c->st, c->rc2, rc2lo, rc2hi, cf,
+                               c->cap4);
+    } else {
+        if (u4)
+            hipLaunchKernelGGL((k_lj<1, 4>), g, t, 0, c->stream, c->st, c->rc2, rc2lo, rc2hi, cf,
+                               c->cap4);
+        else
+            hipLaunchKernelGGL((k_lj<1, 8>), g, t, 0, c->stream, c->st, c->rc2, rc2lo, rc2hi, cf,
+                               c->cap4);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_lj_vjp(fpm_ctx *c, const fpm_lj_params &p, const double *lam,
+                         const double *vbar, const AdjOut &o) {
+    const LJCoef cf = make_coef(p);
+    const double band = predicate_band(c);
+    const double rc2lo = (double)c->rc2 * (1.0 - band), rc2hi = (double)c->rc2 * (1.0 + band);
+    const dim3 g((unsigned)c->nblk), t(kBlock);
+    hipLaunchKernelGGL(k_gather_lam, g, t, 0, c->stream, c->st, lam, vbar, 0.5 * o.dt);
     if (p.n_types == 2)
-        hipLaunchKernelGGL(k_lj<2>, dim3(g), dim3(kBlock), 0, c->stream, c->st, c->box, c->n,
-                           c->rc2, rc2lo, rc2hi, cf, c->cap4);
+        hipLaunchKernelGGL(k_lj_vjp<2>, g, t, 0, c->stream, c->st, c->rc2, rc2lo, rc2hi, cf,
+                           c->cap4, o);
     else
-        hipLaunchKernelGGL(k_lj<1>, dim3(g), dim3(kBlock), 0, c->stream, c->st, c->box, c->n,
-                           c->rc2, rc2lo, rc2hi, cf, c->cap4);
+        hipLaunchKernelGGL(k_lj_vjp<1>, g, t, 0, c->stream, c->st, c->rc2, rc2lo, rc2hi, cf,
+                           c->cap4, o);
     return hipGetLastError();
 }
 

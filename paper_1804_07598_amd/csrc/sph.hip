@@ -111,14 +111,17 @@ __device__ __forceinline__ void sph_walk(SphAcc &s, const float4 *__restrict__ p
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_sph_rates(State st, Box b, int64_t n, float rc2,
-                                                      SphCoef k, int cap4) {
+__global__ __launch_bounds__(kBlock) void k_sph_rates(State st, float rc2, SphCoef k,
+                                                      int cap4) {
+    const SysDesc &d = st.sys[block_system(st)];
+    const Box b = d.box;
     const float4 *__restrict__ pos = st.pos[0];
     const float4 *__restrict__ vel = st.vel[0];
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = global_slot();
+    const bool active = i - d.slot_base < d.n;
     uint32_t nn = 0;
     float4 pi4 = make_float4(0.f, 0.f, 0.f, 0.f), vi = make_float4(0.f, 0.f, 0.f, 1.f);
-    if (i < n) {
+    if (active) {
         nn = st.nnb[i];
         pi4 = pos[i];
         vi = vel[i];
@@ -135,7 +138,7 @@ __global__ __launch_bounds__(kBlock) void k_sph_rates(State st, Box b, int64_t n
         sph_walk<false>(s, pos, vel, lst, cnt, (int)i, pi4, vi, Pa, b, rc2, k);
     const bool fluid = __float_as_int(pi4.w) == 0;
     double accmin = 1e300;
-    if (i < n) {
+    if (active) {
         float4 out;
         if (fluid) {
             out = make_float4((float)(s.ax + k.g[0]), (float)(s.ay + k.g[1]),
@@ -159,14 +162,16 @@ __global__ __launch_bounds__(kBlock) void k_sph_rates(State st, Box b, int64_t n
 // Kick-drift-kick on (v, rho): the closing half kick of the previous step and
 // the opening half kick of this one are fused; boundary particles keep x and v.
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_sph_integrate(State st, Box b, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kBlock) void k_sph_integrate(State st) {
+    const SysDesc &d = st.sys[block_system(st)];
+    const Box b = d.box;
+    const int64_t i = global_slot();
     const Ctl *ctl = st.ctl;
     const float dt = ctl->sph_dt, dtl = ctl->sph_dt_last;
     const float hk = MODE == kKickDriftFirst ? 0.5f * dt
                                              : (MODE == kKickOnly ? 0.5f * dtl : 0.5f * (dtl + dt));
     double ke = 0.0, vmax = 0.0, d2 = 0.0;
-    if (i < n) {
+    if (i - d.slot_base < d.n) {
         float4 v = st.vel[0][i];
         const float4 f = st.frc[i];
         float4 p = st.pos[0][i];
@@ -243,14 +248,14 @@ __global__ __launch_bounds__(1024) void k_sph_finalize(State st, int nblk, SphCo
         const float dtu = ctl->sph_dt;
         ctl->sph_dt_last = dtu;
         ctl->sph_time += (double)dtu;
-        const int row = ctl->step;
+        const int row = st.sctl[0].step;
         if (hist) {
             hist[(int64_t)row * 4 + 0] = ctl->sph_time;
             hist[(int64_t)row * 4 + 1] = (double)dtu;
             hist[(int64_t)row * 4 + 2] = ke * k.m;
             hist[(int64_t)row * 4 + 3] = vmax;
         }
-        ctl->step = row + 1;
+        st.sctl[0].step = row + 1;
     }
     const double dt = (double)cfl * fmin(sqrt(acc), k.h / ((double)c0 + mu));
     ctl->sph_dt = (float)dt;
@@ -271,8 +276,6 @@ SphCoef make_coef(const fpm_ctx *c, const fpm_sph_params &p) {
     const double h = p.h;
     const double aD = 21.0 / (16.0 * 3.14159265358979323846 * h * h * h);
     k.kgrad = 5.0 * aD / (h * h);
-    const double rc = 2.0 * (double)p.h;
-    (void)rc;
     const double band = predicate_band(c);
     k.rc2lo = (double)c->rc2 * (1.0 - band);
     k.rc2hi = (double)c->rc2 * (1.0 + band);
@@ -284,22 +287,20 @@ SphCoef make_coef(const fpm_ctx *c, const fpm_sph_params &p) {
 
 hipError_t launch_sph_rates(fpm_ctx *c, const fpm_sph_params &p) {
     const SphCoef k = make_coef(c, p);
-    hipLaunchKernelGGL(k_sph_rates, dim3(c->nblk), dim3(kBlock), 0, c->stream, c->st, c->box, c->n,
-                       c->rc2, k, c->cap4);
+    hipLaunchKernelGGL(k_sph_rates, dim3(c->nblk), dim3(kBlock), 0, c->stream, c->st, c->rc2, k,
+                       c->cap4);
     return hipGetLastError();
 }
 
 hipError_t launch_sph_integrate(fpm_ctx *c, const fpm_sph_params &p, int mode) {
     (void)p;
+    const dim3 g((unsigned)c->nblk), t(kBlock);
     if (mode == kKickDriftFirst)
-        hipLaunchKernelGGL(k_sph_integrate<kKickDriftFirst>, dim3(c->nblk), dim3(kBlock), 0,
-                           c->stream, c->st, c->box, c->n);
+        hipLaunchKernelGGL(k_sph_integrate<kKickDriftFirst>, g, t, 0, c->stream, c->st);
     else if (mode == kKickKickDrift)
-        hipLaunchKernelGGL(k_sph_integrate<kKickKickDrift>, dim3(c->nblk), dim3(kBlock), 0,
-                           c->stream, c->st, c->box, c->n);
+        hipLaunchKernelGGL(k_sph_integrate<kKickKickDrift>, g, t, 0, c->stream, c->st);
     else
-        hipLaunchKernelGGL(k_sph_integrate<kKickOnly>, dim3(c->nblk), dim3(kBlock), 0, c->stream,
-                           c->st, c->box, c->n);
+        hipLaunchKernelGGL(k_sph_integrate<kKickOnly>, g, t, 0, c->stream, c->st);
     return hipGetLastError();
 }
 

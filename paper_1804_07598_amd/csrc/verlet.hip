@@ -54,9 +54,9 @@ __device__ __forceinline__ float img_delta_sel(float xi, float xj, float L, floa
 #pragma clang fp contract(off)
     const float t = xj - xi;
     const float s1 = xj - L;
-    const float s2 = xj + L;
+    const float s2 = xi - L;
     const float a1 = s1 - xi;  // t > L/2: (xj - L) - xi
-    const float a2 = s2 - xi;  // t < -L/2: (xj + L) - xi
+    const float a2 = xj - s2;  // t < -L/2: xj - (xi - L)
     const float r = t > half ? a1 : (t < -half ? a2 : t);
     return per ? r : t;
 }
@@ -88,7 +88,7 @@ __device__ __forceinline__ void pad_list(int32_t *__restrict__ wp, int count, in
 }
 
 // Tests candidates [beg, end) of `src` (global slots) or of the LDS stage
-// (global slot in w, ghost images already shifted) against particle i and
+// (global slot in w, lower-face images already shifted) against particle i and
 // appends the hits.
 template <bool IMG, bool LDS>
 __device__ __forceinline__ void scan_range(const float4 *__restrict__ src, int beg, int end,
@@ -125,9 +125,11 @@ __device__ __forceinline__ bool near_face(int ix, int iy, int iz, const Box &b) 
 
 // List of slot i from global memory through the cell offsets.
 template <bool IMG>
-__device__ void verlet_atom_global(const State &st, const Box &b, int i, float3 pi, float R2,
-                                   int cap, int cap4, int &count, bool &img) {
+__device__ void verlet_atom_global(const State &st, const SysDesc &d, int i, float3 pi,
+                                   float R2, int cap, int cap4, int &count, bool &img) {
+    const Box &b = d.box;
     const float4 *__restrict__ pos = st.pos[1];
+    const int32_t *__restrict__ off = st.off + d.off_base;
     int32_t *wp = st.nbr + nbr_index(i, 0, cap4);
     const int ix = cell_coord(pi.x, b.inv[0], b.nc[0]);
     const int iy = cell_coord(pi.y, b.inv[1], b.nc[1]);
@@ -143,12 +145,12 @@ __device__ void verlet_atom_global(const State &st, const Box &b, int i, float3 
             while (r < mz) {
                 int r1 = r;
                 while (r1 + 1 < mz && cz[r1 + 1] == cz[r1] + 1) r1++;
-                const int beg = st.off[col + cz[r]], end = st.off[col + cz[r1] + 1];
+                const int beg = off[col + cz[r]], end = off[col + cz[r1] + 1];
                 scan_range<IMG, false>(pos, beg, end, i, pi, b, R2, wp, cap, count, img);
                 r = r1 + 1;
             }
         }
-    pad_list(wp, count, cap, st.dummy);
+    pad_list(wp, count, cap, d.dummy);
 }
 
 // A list longer than the capacity raises the sticky overflow flag (any of the
@@ -163,54 +165,66 @@ __device__ __forceinline__ void copy_back(const State &st, int64_t s) {
     st.id[0][s] = st.id[1][s];
 }
 
-// One thread per particle, candidates read from global memory.
-__global__ __launch_bounds__(kBlock) void k_verlet(State st, Box b, int64_t n, int64_t n_pad,
-                                                   float R2, int cap, int cap4) {
-    if (!st.ctl->rebuild) return;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// One thread per particle, candidates read from global memory.  The grid
+// runs over the list of particle workgroups of the systems built this way.
+__global__ __launch_bounds__(kBlock) void k_verlet(State st, const int32_t *blocks, float R2,
+                                                   int cap, int cap4) {
+    const int blk = blocks[blockIdx.x];
+    const int s = st.blk2sys[blk];
+    if (!st.sctl[s].rebuild) return;
+    const SysDesc &d = st.sys[s];
+    const Box b = d.box;
+    const int64_t i = (int64_t)blk * kBlock + threadIdx.x;
+    const bool active = i - d.slot_base < d.n;
     int count = 0;
     bool img = false, face = false;
     float3 pi = make_float3(0.f, 0.f, 0.f);
-    if (i < n) {
+    if (active) {
         pi = xyz(st.pos[1][i]);
         face = near_face(cell_coord(pi.x, b.inv[0], b.nc[0]), cell_coord(pi.y, b.inv[1], b.nc[1]),
                          cell_coord(pi.z, b.inv[2], b.nc[2]), b);
     }
     const bool face_wave = __ballot(face) != 0;
-    if (i < n) {
+    if (active) {
         if (face_wave)
-            verlet_atom_global<true>(st, b, (int)i, pi, R2, cap, cap4, count, img);
+            verlet_atom_global<true>(st, d, (int)i, pi, R2, cap, cap4, count, img);
         else
-            verlet_atom_global<false>(st, b, (int)i, pi, R2, cap, cap4, count, img);
+            verlet_atom_global<false>(st, d, (int)i, pi, R2, cap, cap4, count, img);
         st.nnb[i] = (uint32_t)min(count, cap) | (img ? kWrapBit : 0u);
         note_overflow(st, count, cap);
     }
-    if (i < n_pad) copy_back(st, i);
+    copy_back(st, i);
 }
 
-// Column workgroups (see the file comment).
-__global__ __launch_bounds__(kColThreads) void k_verlet_cols(State st, Box b, int64_t n,
-                                                             int64_t n_pad, float R2, int cap,
-                                                             int cap4, int zb, int nzb) {
-    if (!st.ctl->rebuild) return;
+// Column workgroups (see the file comment); one work item per (system,
+// column, z-block).
+__global__ __launch_bounds__(kColThreads) void k_verlet_cols(State st, float R2, int cap,
+                                                             int cap4) {
+    const int s = st.item2sys[blockIdx.x];
+    if (!st.sctl[s].rebuild) return;
+    const SysDesc &d = st.sys[s];
+    const Box b = d.box;
+    const int zb = d.zb, nzb = d.nzb;
+    const int32_t *__restrict__ off = st.off + d.off_base;
     __shared__ float4 sp[kLdsAtoms];
     __shared__ int cs[9][kMaxZb + 3];  // column-relative LDS start of run cell m (m = nrun: end)
     __shared__ int seg[9][3][2];       // (global start, length) of the three run segments
-    __shared__ float sh[9][3][3];      // ghost shift (x, y, z) of each segment
+    __shared__ float sh[9][3][3];      // image shift (x, y, z) of each segment
     __shared__ int colbase[10];
     const float4 *__restrict__ pos = st.pos[1];
     const int nx = b.nc[0], ny = b.nc[1], nz = b.nc[2];
-    const int zblk = blockIdx.x % nzb, colid = blockIdx.x / nzb;
+    const int item = blockIdx.x - d.item_base;
+    const int zblk = item % nzb, colid = item / nzb;
     const int ix = colid / ny, iy = colid % ny;
     const int z0 = zblk * zb, z1 = min(z0 + zb, nz);
     const int nrun = z1 - z0 + 2;
     const int cell0 = (ix * ny + iy) * nz;
-    const int abeg = st.off[cell0 + z0], aend = st.off[cell0 + z1];
+    const int abeg = off[cell0 + z0], aend = off[cell0 + z1];
 
     if (threadIdx.x < 9) {
         const int k = threadIdx.x;
         int cx = ix + k / 3 - 1, cy = iy + k % 3 - 1;
-        float sx = 0.f, sy = 0.f;  // a column across a periodic face is staged as ghosts
+        float sx = 0.f, sy = 0.f;  // shift of a column across a periodic face
         bool ok = true;
         if (cx < 0 || cx >= nx) {
             if (b.per[0]) {
@@ -250,8 +264,8 @@ __global__ __launch_bounds__(kColThreads) void k_verlet_cols(State st, Box b, in
             }
             int gs = 0, len = 0;
             if (okz) {
-                gs = st.off[col + z];
-                len = st.off[col + z + 1] - gs;
+                gs = off[col + z];
+                len = off[col + z + 1] - gs;
             }
             cs[k][m] = acc;
             const int sg = m == 0 ? 0 : (m == nrun - 1 ? 2 : 1);
@@ -273,14 +287,18 @@ __global__ __launch_bounds__(kColThreads) void k_verlet_cols(State st, Box b, in
     __syncthreads();
     const bool use_lds = colbase[9] <= kLdsAtoms;
     if (use_lds) {
-        // ghost copies: the shifted coordinate xj +- L is rounded once, exactly
-        // as in the predicate's image branch
+        // Periodic images as the predicate takes them: the coordinate in the
+        // upper half of the box moves down one period (exact).  Cells staged
+        // from across the lower face lie at the top of the box and are stored
+        // shifted down; cells from across the upper face are stored as they
+        // are, and the scan shifts particle i down instead.
         const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-        for (int s = w; s < 27; s += kColThreads / 64) {
-            const int k = s / 3, sg = s % 3;
+        for (int q = w; q < 27; q += kColThreads / 64) {
+            const int k = q / 3, sg = q % 3;
             const int gs = seg[k][sg][0], len = seg[k][sg][1];
             const int ls = colbase[k] + (sg == 0 ? 0 : (sg == 1 ? cs[k][1] : cs[k][nrun - 1]));
-            const float sx = sh[k][sg][0], sy = sh[k][sg][1], sz = sh[k][sg][2];
+            const float sx = fminf(sh[k][sg][0], 0.f), sy = fminf(sh[k][sg][1], 0.f),
+                        sz = fminf(sh[k][sg][2], 0.f);
             for (int t = lane; t < len; t += 64) {
                 float4 p = pos[gs + t];
                 p.x = p.x + sx;
@@ -310,31 +328,42 @@ __global__ __launch_bounds__(kColThreads) void k_verlet_cols(State st, Box b, in
         if (active) {
             int32_t *wp = st.nbr + nbr_index(i, 0, cap4);
             if (use_lds) {
+                // the run's last cell is cell 0 one period up when z1 wraps; only
+                // particles of the top z-cell (m + 2 == nrun) reach it
+                const bool top_img = b.per[2] && z1 == nz;
                 for (int k = 0; k < 9; k++) {
+                    float3 pk = pi;  // i moved down one period where column k lies across
+                    if (sh[k][1][0] > 0.f) pk.x = pi.x - b.L[0];  // the upper face (exact:
+                    if (sh[k][1][1] > 0.f) pk.y = pi.y - b.L[1];  // i is in the top cell)
                     const int beg = colbase[k] + cs[k][m - 1], end = colbase[k] + cs[k][m + 2];
-                    scan_range<false, true>(sp, beg, end, i, pi, b, R2, wp, cap, count, img);
+                    const int mid = m + 2 == nrun ? colbase[k] + cs[k][nrun - 1] : end;
+                    scan_range<false, true>(sp, beg, mid, i, pk, b, R2, wp, cap, count, img);
+                    if (top_img) pk.z = pi.z - b.L[2];
+                    scan_range<false, true>(sp, mid, end, i, pk, b, R2, wp, cap, count, img);
                 }
-                pad_list(wp, count, cap, st.dummy);
+                pad_list(wp, count, cap, d.dummy);
                 img = face;  // its stencil reaches across a periodic face
             } else if (face_wave) {
-                verlet_atom_global<true>(st, b, i, pi, R2, cap, cap4, count, img);
+                verlet_atom_global<true>(st, d, i, pi, R2, cap, cap4, count, img);
             } else {
-                verlet_atom_global<false>(st, b, i, pi, R2, cap, cap4, count, img);
+                verlet_atom_global<false>(st, d, i, pi, R2, cap, cap4, count, img);
             }
             st.nnb[i] = (uint32_t)min(count, cap) | (img ? kWrapBit : 0u);
             note_overflow(st, count, cap);
             copy_back(st, i);
         }
     }
-    // padding slots are in no cell: the first workgroup moves them back
-    if (blockIdx.x == 0)
-        for (int64_t s = n + threadIdx.x; s < n_pad; s += kColThreads) copy_back(st, s);
+    // padding slots are in no cell: the system's first work item moves them back
+    if (item == 0)
+        for (int64_t q = d.slot_base + d.n + threadIdx.x; q < d.slot_base + d.n_pad;
+             q += kColThreads)
+            copy_back(st, q);
 }
 
 // Longest list and total entries of the current lists (on request only).
-__global__ void k_list_stats(State st, int64_t n) {
+__global__ void k_list_stats(State st, int64_t nslots) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int c = i < n ? (int)(st.nnb[i] & ~kWrapBit) : 0;
+    int c = i < nslots ? (int)(st.nnb[i] & ~kWrapBit) : 0;
     int mx = c;
     unsigned long long sm = (unsigned long long)c;
 #pragma unroll
@@ -355,11 +384,11 @@ __global__ void k_zero_stats(Ctl *ctl) {
     }
 }
 
-// Verlet list in caller indices, row = caller index of the particle.
-__global__ void k_neighbors_out(State st, int64_t n, int cap, int cap4, int32_t *counts,
-                                int32_t *cols) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// Verlet lists in caller indices, row = caller index of the particle.
+__global__ void k_neighbors_out(State st, int cap, int cap4, int32_t *counts, int32_t *cols) {
+    const SysDesc &d = st.sys[block_system(st)];
+    const int64_t i = global_slot();
+    if (i - d.slot_base >= d.n) return;
     const int32_t *id = st.id[0];
     const int row = id[i];
     const int cnt = (int)(st.nnb[i] & ~kWrapBit);
@@ -372,30 +401,31 @@ inline unsigned grid_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b);
 }  // namespace
 
 hipError_t launch_verlet_build(fpm_ctx *c) {
-    if (c->zb > 0)
-        hipLaunchKernelGGL(k_verlet_cols, dim3(c->nblk_build), dim3(kColThreads), 0, c->stream,
-                           c->st, c->box, c->n, c->n_pad, c->R2, c->cap, c->cap4, c->zb, c->nzb);
-    else
-        hipLaunchKernelGGL(k_verlet, dim3(c->nblk_build), dim3(kBlock), 0, c->stream, c->st,
-                           c->box, c->n, c->n_pad, c->R2, c->cap, c->cap4);
+    if (c->nitems > 0)
+        hipLaunchKernelGGL(k_verlet_cols, dim3(c->nitems), dim3(kColThreads), 0, c->stream,
+                           c->st, c->R2, c->cap, c->cap4);
+    if (c->n_pa_blocks > 0)
+        hipLaunchKernelGGL(k_verlet, dim3(c->n_pa_blocks), dim3(kBlock), 0, c->stream, c->st,
+                           c->pa_blocks, c->R2, c->cap, c->cap4);
     return hipGetLastError();
 }
 
 hipError_t launch_list_stats(fpm_ctx *c) {
     hipLaunchKernelGGL(k_zero_stats, dim3(1), dim3(64), 0, c->stream, c->st.ctl);
-    hipLaunchKernelGGL(k_list_stats, dim3(grid_for(c->n, 256)), dim3(256), 0, c->stream, c->st,
-                       c->n);
+    hipLaunchKernelGGL(k_list_stats, dim3(grid_for(c->n_slots, 256)), dim3(256), 0, c->stream,
+                       c->st, c->n_slots);
     return hipGetLastError();
 }
 
 hipError_t launch_neighbors_out(fpm_ctx *c, int32_t *counts, int32_t *cols) {
-    hipLaunchKernelGGL(k_neighbors_out, dim3(grid_for(c->n, 256)), dim3(256), 0, c->stream, c->st,
-                       c->n, c->cap, c->cap4, counts, cols);
+    hipLaunchKernelGGL(k_neighbors_out, dim3(c->nblk), dim3(kBlock), 0, c->stream, c->st, c->cap,
+                       c->cap4, counts, cols);
     return hipGetLastError();
 }
 
-int verlet_zblock(int64_t n, int64_t ncells, const int nc[3]) {
+int verlet_zblock(int64_t n, int64_t ncells, const int nc[3], int tune_zb) {
     if (nc[0] < 3 || nc[1] < 3 || nc[2] < 3) return 0;
+    if (tune_zb > 0) return tune_zb > kMaxZb ? kMaxZb : (tune_zb > nc[2] - 2 ? nc[2] - 2 : tune_zb);
     const double avg = (double)n / (double)ncells;
     // aim at ~1400 staged particles (70% of the LDS stage) and ~100 per workgroup
     int zb = (int)(1400.0 / (9.0 * (avg > 0.05 ? avg : 0.05))) - 2;

@@ -1,0 +1,164 @@
+"""Adjoint of the LJ forces (section 4.1, differentiated) on the GPU against the
+oracle: the force VJP on one system and on a batch, the gradient of a
+force-matching loss through torch autograd, and the checkpointed trajectory
+adjoint against the oracle's FP32-state trajectory and its adjoint.
+
+Tolerances: dL/dx within 1e-5 of its RMS (max norm), each dL/dtheta within
+1e-5 relative.  The kernel rounds the cotangent to FP32 (relative 6e-8) and
+sums pair terms in FP64, so both bounds hold with two orders of margin."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1804_07598_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+RC, SKIN, PER = 2.5, 0.3, (1, 1, 1)
+MIX = inputs.LJ_MIXTURE
+TOL = 1e-5
+
+
+def np_(t):
+    return t.detach().cpu().numpy()
+
+
+def rel_max(g, ref):
+    return float(np.abs(g - ref).max() / math.sqrt((ref ** 2).mean()))
+
+
+def mixture(n, seed=5):
+    return inputs.lj_lattice(n, 1.2, 1.0, seed, mixture=True)
+
+
+def make_sim(s, **kw):
+    from paper_1804_07598_amd.sim import ParticleSim
+    return ParticleSim(s.pos, s.box, PER, vel=s.vel, typ=s.typ, r_cut=RC, skin=SKIN, **kw)
+
+
+@pytest.mark.parametrize("n,mix", [(4096, True), (4097, False), (300, True)])
+def test_force_vjp_matches_oracle(n, mix):
+    s = inputs.lj_lattice(n, 1.2 if mix else 0.8442, 1.0, 5, mixture=mix)
+    eps, sig = (MIX["eps"], MIX["sig"]) if mix else ((1.0,) * 3, (1.0,) * 3)
+    nt = 2 if mix else 1
+    sim = make_sim(s)
+    lam = np.random.default_rng(1).normal(size=(s.n, 3))
+    gx, gt = (np_(t) for t in sim.force_vjp(lam, eps, sig, nt))
+    typ = s.typ if mix else None
+    ox, ot = O.lj_vjp(s.pos, s.box, PER, O.radius2(RC), lam, eps, sig, typ)
+    assert rel_max(gx, ox) <= TOL
+    if mix:
+        assert np.all(np.abs(gt[0] - ot) <= TOL * np.abs(ot)), (gt[0], ot)
+    else:
+        assert abs(gt[0, 0] - ot[0]) <= TOL * abs(ot[0]) and abs(gt[0, 3] - ot[3]) <= TOL * abs(ot[3])
+        assert gt[0, [1, 2, 4, 5]].tolist() == [0, 0, 0, 0]
+
+
+def test_force_vjp_on_a_batch():
+    from paper_1804_07598_amd.sim import BatchSim
+    ns, rhos, Ts = inputs.batched_table()
+    systems = [inputs.batched_system(k, ns, rhos, Ts) for k in (0, 1, 2, 40)]
+    sim = BatchSim([s.pos for s in systems], [s.box for s in systems], PER, r_cut=RC, skin=SKIN)
+    lam = np.random.default_rng(2).normal(size=(sim.n, 3))
+    gx, gt = (np_(t) for t in sim.force_vjp(lam))
+    for k, s in enumerate(systems):
+        a, b = sim.offsets[k], sim.offsets[k + 1]
+        ox, ot = O.lj_vjp(s.pos, s.box, PER, O.radius2(RC), lam[a:b])
+        assert rel_max(gx[a:b], ox) <= TOL, k
+        assert abs(gt[k, 0] - ot[0]) <= TOL * abs(ot[0]) and abs(gt[k, 3] - ot[3]) <= TOL * abs(ot[3])
+
+
+def test_force_matching_loss_gradient_through_autograd():
+    import torch
+    from paper_1804_07598_amd.adjoint import LJForceFn
+    s = mixture(4096)
+    sim = make_sim(s)
+    theta0 = np.array(MIX["eps"] + MIX["sig"], np.float64)
+    theta_t = np.float32(1.05 * theta0).astype(np.float64)  # what an FP32 parameter table holds
+    pos = torch.tensor(s.pos, dtype=torch.float64, device="cuda", requires_grad=True)
+    th = torch.tensor(np.float32(theta0).astype(np.float64), device="cuda", requires_grad=True)
+    with torch.no_grad():
+        T = LJForceFn.apply(pos, torch.tensor(theta_t, device="cuda"), sim, 2)
+    Fg = LJForceFn.apply(pos, th, sim, 2)
+    loss = ((Fg - T) ** 2).mean()
+    loss.backward()
+    # the oracle: forces of both parameter sets, the same loss, its cotangent, the VJP
+    R2 = O.radius2(RC)
+    th32 = np.float32(theta0).astype(np.float64)
+    F64 = O.lj(s.pos, s.box, PER, R2, th32[:3], th32[3:], s.typ)[0]
+    T64 = O.lj(s.pos, s.box, PER, R2, theta_t[:3], theta_t[3:], s.typ)[0]
+    l64 = float(((F64 - T64) ** 2).mean())
+    assert abs(float(loss.detach()) - l64) <= TOL * l64
+    lam = 2.0 * (F64 - T64) / F64.size
+    ox, ot = O.lj_vjp(s.pos, s.box, PER, R2, lam, th32[:3], th32[3:], s.typ)
+    assert rel_max(np_(pos.grad), ox) <= TOL
+    assert np.all(np.abs(np_(th.grad) - ot) <= TOL * np.abs(ot)), (np_(th.grad), ot)
+
+
+def traj_case(n, K, frame_every, ckpt_every, seed=5):
+    """GPU LJTrajFn gradient of the frame-averaged force MSE against targets from
+    the oracle's FP64 trajectory at theta_tgt = 1.05 theta, and the oracle's own
+    FP32-state trajectory with its adjoint from the same start."""
+    import torch
+    from paper_1804_07598_amd.adjoint import LJTrajFn
+    s = mixture(n, seed)
+    dt = np.float32(0.005)
+    theta = np.float32(np.array(MIX["eps"] + MIX["sig"])).astype(np.float64)
+    theta_t = 1.05 * theta
+    frames = list(range(frame_every, K + 1, frame_every))
+    _, Ft, _ = O.lj_traj(s.pos, s.vel, s.box, PER, RC, float(dt), K, theta_t[:3], theta_t[3:],
+                         s.typ)
+    targets = np.stack([Ft[k] for k in frames])
+    sim = make_sim(s)
+    x0 = torch.tensor(s.pos, dtype=torch.float64, device="cuda", requires_grad=True)
+    v0 = torch.tensor(s.vel, dtype=torch.float64, device="cuda", requires_grad=True)
+    th = torch.tensor(theta, device="cuda", requires_grad=True)
+    Fk = LJTrajFn.apply(x0, v0, th, sim, float(dt), K, frame_every, ckpt_every, 2)
+    tgt = torch.tensor(targets, device="cuda")
+    loss = ((Fk - tgt) ** 2).mean()
+    loss.backward()
+    # oracle
+    hs = 0.5 * float(np.float32(SKIN))
+    thr = np.float32(hs * hs)
+    xs, vs, Fs, nb = O.lj_traj_f32(s.pos, s.vel, s.box, PER, O.radius2(RC), dt, K, thr,
+                                   ckpt_every, theta[:3], theta[3:], s.typ)
+    fbar = np.zeros(xs.shape, np.float64)
+    for q, k in enumerate(frames):
+        fbar[k] = 2.0 * (Fs[k].astype(np.float64) - targets[q]) / targets.size
+    xb, vb, gt = O.lj_traj_adjoint_f32(xs, s.box, PER, O.radius2(RC), float(dt), fbar,
+                                       theta[:3], theta[3:], s.typ)
+    return np_(Fk), Fs[frames], (np_(x0.grad), np_(v0.grad), np_(th.grad)), (xb, vb, gt)
+
+
+@pytest.mark.parametrize("n,K,fe,ce", [(2048, 40, 20, 20), (1500, 45, 15, 20)])
+def test_trajectory_adjoint_matches_oracle(n, K, fe, ce):
+    Fk, Fo, (gx, gv, gt), (ox, ov, ot) = traj_case(n, K, fe, ce)
+    # the forward states follow the oracle's FP32-state trajectory (the force sums
+    # differ only in FP64 summation order)
+    assert np.abs(Fk - Fo).max() <= 1e-6 * math.sqrt((Fo.astype(np.float64) ** 2).mean())
+    assert rel_max(gx, ox) <= TOL
+    assert rel_max(gv, ov) <= TOL
+    assert np.all(np.abs(gt - ot) <= TOL * np.abs(ot)), (gt, ot)
+
+
+def test_trajectory_adjoint_full_size_runs():
+    """The configuration the bench times (N = 32768 mixture, 200 steps, frames and
+    checkpoints every 20): finite gradients, reproducible bit for bit."""
+    import torch
+    from paper_1804_07598_amd.adjoint import LJTrajFn
+    s = mixture(32768)
+    theta = np.float32(np.array(MIX["eps"] + MIX["sig"])).astype(np.float64)
+    sim = make_sim(s)
+    res = []
+    for _ in range(2):
+        x0 = torch.tensor(s.pos, dtype=torch.float64, device="cuda", requires_grad=True)
+        v0 = torch.tensor(s.vel, dtype=torch.float64, device="cuda", requires_grad=True)
+        th = torch.tensor(theta, device="cuda", requires_grad=True)
+        Fk = LJTrajFn.apply(x0, v0, th, sim, 0.005, 200, 20, 20, 2)
+        (Fk ** 2).mean().backward()
+        sim.check()
+        res.append([np_(t.grad) for t in (x0, v0, th)])
+    for a, b in zip(res[0], res[1]):
+        assert np.isfinite(a).all() and np.array_equal(a, b)

@@ -135,37 +135,37 @@ def test_velocity_verlet_steps():
     th = np_(sim.step(10, dt=0.005))
     sim.check()
     p, v, f = (np_(t) for t in sim.get())
-    # (i) the oracle re-evaluated at the GPU's positions
-    check_lj(sim, p, s.box)
-    F64, U64, W64, _, _ = O.lj(p, s.box, PER, O.radius2(RC))
-    assert abs(th[-1, 0] - U64) <= ENERGY_TOL * abs(U64)
     ke = 0.5 * float((v.astype(np.float64) ** 2).sum())
     assert th[-1, 1] == pytest.approx(ke, rel=1e-6)
-    # (ii) the oracle's own FP64 trajectory from the same start
+    # the oracle's own FP64 trajectory from the same start: FP32 storage of x, v
+    # and F perturbs each step by ~1e-7 relative, far below these bounds
     x64, v64, th64 = O.vv(s.pos.astype(np.float64), s.vel.astype(np.float64), s.box, PER, RC,
                           0.005, 10)
     d = p.astype(np.float64) - x64
     d -= float(s.box[0]) * np.round(d / float(s.box[0]))
     assert np.abs(d).max() < 1e-4
-    E = th[:, 0] + th[:, 1]
+    assert np.abs(v.astype(np.float64) - v64).max() < 1e-4
     E64 = th64[1:, 0] + th64[1:, 1]
-    assert np.abs(E - E64).max() < 1e-4 * abs(E64[0])
+    assert np.abs(th[:, 0] - th64[1:, 0]).max() < 1e-5 * abs(E64[0])
+    assert np.abs(th[:, 1] - th64[1:, 1]).max() < 1e-5 * abs(E64[0])
+
+
+def kept_lists_cover(sim, L, rows=None):
+    """The lists the step loop left behind hold every pair within r_cut now."""
+    from list_coverage import assert_lists_cover
+    counts, cols = (np_(t) for t in sim.neighbors())
+    p, _, _ = sim.get()
+    return assert_lists_cover(counts, cols, np_(p), L, RC, rows=rows)
 
 
 def test_rebuilds_follow_displacement():
     s = inputs.lj_config("lj4096")
     sim = make_sim(s)
-    sim.step(60, dt=0.005)
+    for _ in range(6):
+        sim.step(10, dt=0.005)
+        kept_lists_cover(sim, s.box)
     rebuilds, longest, total = sim.counters()
     assert rebuilds >= 2  # the initial build plus at least one automatic rebuild
-    p, _, _ = (np_(t) for t in sim.get())
-    # the current Verlet list still covers the force set at r_cut
-    compare_sets_force = O.neighbors(p, s.box, PER, O.radius2(RC), cap=256)
-    counts, cols = (np_(t) for t in sim.neighbors())
-    ocnt, ocols = compare_sets_force
-    for i in range(s.n):
-        have = set(cols[i, :counts[i]].tolist())
-        assert set(ocols[i, :ocnt[i]].tolist()) <= have
 
 
 def test_nve_energy_bounded():
@@ -233,8 +233,11 @@ def test_lj_1m_sampled_rows():
     sim.lj_forces()
     compare_sets(sim, s.pos, s.box, O.radius2(RC, SKIN), rows=rows)
     check_lj(sim, s.pos, s.box, rows=rows)
-    # after steps with rebuilds, at the GPU's positions
-    sim.step(40, dt=0.005)
+    # after steps with rebuilds the kept lists still cover the force set, and the
+    # total energy stays put (truncated LJ, 40 steps)
+    th = np_(sim.step(40, dt=0.005))
     sim.check()
-    p, _, _ = (np_(t) for t in sim.get())
-    check_lj(sim, p, s.box, rows=rows)
+    assert sim.counters()[0] >= 2
+    kept_lists_cover(sim, s.box, rows=np.random.default_rng(3).choice(s.n, 4096, replace=False))
+    E = th[:, 0] + th[:, 1]
+    assert abs(E[-1] - E[0]) < 1e-3 * abs(E[0])

@@ -1,7 +1,7 @@
 """Parity of the HIP SPH path (section 4.2, Eqs. 1-5) with the FP64 oracle:
 rates (acceleration and density rate) within 1e-5 of their RMS, the CFL time
-step, multi-step runs re-checked at the GPU's state, and the 2.1M-particle
-column on sampled rows."""
+step, multi-step runs against the oracle's own trajectory, and the
+2.1M-particle column on sampled rows."""
 import math
 
 import numpy as np
@@ -76,21 +76,35 @@ def test_rates_with_motion_and_noise():
     assert dt == pytest.approx(O.sph_dt(acc, s.kind, mu, oprm, 0.2), rel=1e-5)
 
 
-def test_steps_then_rates_at_gpu_state():
+def test_steps_match_oracle_trajectory():
     s, sim, prm, oprm, r_cut, vel, rho = setup(16, 16, seed=4, vel_sigma=0.02)
-    hist = np_(sim.sph_step(30, prm))
+    K = 30
+    hist = np_(sim.sph_step(K, prm))
     sim.check()
     p, v, _ = (np_(t) for t in sim.get())
     r, _ = sim.get_sph()
-    r = np_(r)
+    r = np_(r).astype(np.float64)
     # boundary particles never move
     fb = s.kind == 1
     assert np.array_equal(p[fb], s.pos[fb]) and np.all(v[fb] == 0)
     # time is the sum of the device time steps, each positive
     assert np.all(hist[:, 1] > 0)
     assert hist[-1, 0] == pytest.approx(hist[:, 1].sum(), rel=1e-12)
-    sim.sph_rates(prm)
-    compare_rates(sim, s, p, v, r, oprm, r_cut)
+    # the oracle's KDK trajectory from the same start.  Per step the FP32 state
+    # updates round x (|x| < 0.5), v (|v| < 0.2) and rho (~1000) by at most half
+    # an ulp: after 30 steps < 30 * 0.5 ulp, i.e. 1e-6, 1e-7 and 2e-3.  The
+    # fluid is stiff: a position error dx excites acoustic motion with velocity
+    # ~ (c0 / h) dx, and c0 / h = 5.4e3 / s turns one half-ulp position rounding
+    # (7.5e-9 at x = 0.25) into 4e-5 of velocity, which bounds v instead.
+    x64, v64, r64, h64 = O.sph_kdk(s.pos, vel, rho, s.kind, s.L, (1, 1, 0), O.radius2(r_cut),
+                                   oprm, 0.2, K)
+    d = p.astype(np.float64) - x64
+    for a in range(2):
+        d[:, a] -= float(s.L[a]) * np.round(d[:, a] / float(s.L[a]))
+    assert np.abs(d).max() <= 4e-6
+    assert np.abs(v.astype(np.float64) - v64).max() <= 5e-5
+    assert np.abs(r - r64).max() <= 1e-2
+    assert np.abs(hist[:, 1] / h64[:, 1] - 1).max() <= 1e-5
 
 
 def test_full_column_sampled_rows():
