@@ -82,6 +82,109 @@ def cpu_baseline(pos, box, target_s: float, quiet: bool):
                       f"FP64 physics) at the initial configuration; {dt:.1f} s"}
 
 
+def timed_steps(sim, nsteps, dt, warmup, eps=(1.0,) * 3, sig=(1.0,) * 3, n_types=1):
+    """Milliseconds of nsteps graph-launched steps after warmup steps (HIP events
+    on the stream the library launches on)."""
+    import torch
+    sim.step(warmup, dt, eps, sig, n_types)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    sim.step(nsteps, dt, eps, sig, n_types)
+    e1.record()
+    torch.cuda.synchronize()
+    sim.check()
+    return e0.elapsed_time(e1)
+
+
+def bench_batched(dev, nsteps: int, quiet: bool):
+    """512 independent boxes of 256..8192 atoms stepped together, against one
+    box holding the same total number of atoms."""
+    import numpy as np
+    from paper_1804_07598_amd import inputs
+    from paper_1804_07598_amd.sim import BatchSim, ParticleSim
+    ns, rhos, Ts = inputs.batched_table()
+    systems = [inputs.batched_system(k, ns, rhos, Ts) for k in range(len(ns))]
+    n = int(ns.sum())
+    sim = BatchSim([s.pos for s in systems], [s.box for s in systems], (1, 1, 1),
+                   vel_list=[s.vel for s in systems], r_cut=2.5, skin=0.3, device=dev)
+    ms_b = timed_steps(sim, nsteps, 0.005, 20)
+    reb_b = sim.counters()[0]
+    sim.close()
+    one = inputs.lj_lattice(n, float(np.mean(rhos)), float(np.mean(Ts)), 6)
+    sim = ParticleSim(one.pos, one.box, (1, 1, 1), vel=one.vel, r_cut=2.5, skin=0.3,
+                      max_nbr=184, device=dev)
+    ms_p = timed_steps(sim, nsteps, 0.005, 20)
+    sim.close()
+    vb, vp = n * nsteps / (ms_b / 1e3), n * nsteps / (ms_p / 1e3)
+    log(f"batched: {len(ns)} systems, {n} atoms, {ms_b / nsteps * 1e3:.1f} us/step "
+        f"({vb:.3g} atom-steps/s); one box of {n}: {ms_p / nsteps * 1e3:.1f} us/step", quiet)
+    return {"workload": f"{len(ns)} periodic LJ boxes, N_s uniform in [256, 8192], rho_s in "
+                        "[0.6, 0.9], T_s in [0.8, 1.5], r_cut=2.5, skin=0.3, dt=0.005",
+            "systems": len(ns), "atoms": n, "steps": nsteps, "value": vb, "unit": "atom-steps/s",
+            "ms_per_step": ms_b / nsteps, "rebuilds": reb_b,
+            "plain_value": vp, "plain_workload": f"one box of {n} atoms at the mean rho and T",
+            "vs_plain": vb / vp}
+
+
+def bench_adjoint(dev, quiet: bool):
+    """Gradient of a force-matching loss through a 200-step trajectory of the
+    N = 32768 binary mixture (checkpoints and loss frames every 20 steps), and
+    the single-evaluation force VJP, each against the plain forward."""
+    import numpy as np
+    import torch
+    from paper_1804_07598_amd import _lib as F
+    from paper_1804_07598_amd import inputs
+    from paper_1804_07598_amd.adjoint import LJTrajFn
+    from paper_1804_07598_amd.sim import ParticleSim
+    s = inputs.lj_config("mix32k")
+    mix = inputs.LJ_MIXTURE
+    theta = np.float32(np.array(mix["eps"] + mix["sig"])).astype(np.float64)
+    sim = ParticleSim(s.pos, s.box, (1, 1, 1), vel=s.vel, typ=s.typ, r_cut=2.5, skin=0.3,
+                      device=dev)
+    K, every = 200, 20
+    ms_plain = timed_steps(sim, K, 0.005, 20, mix["eps"], mix["sig"], 2)
+    # single evaluation: force kernel against VJP kernel
+    lam = torch.randn((s.n, 3), dtype=torch.float64, device=dev)
+    F.fpm_set_profiling(sim.ctx, True)
+    for _ in range(20):
+        sim.lj_forces(mix["eps"], mix["sig"], 2)
+        sim.force_vjp(lam, mix["eps"], mix["sig"], 2)
+    f_ms, _ = F.fpm_kernel_time(sim.ctx, "lj_force")
+    v_ms, _ = F.fpm_kernel_time(sim.ctx, "lj_vjp")
+    F.fpm_set_profiling(sim.ctx, False)
+    res = []
+    for rep in range(2):  # the first call captures the step graphs
+        x0 = torch.tensor(s.pos, dtype=torch.float64, device=dev, requires_grad=True)
+        v0 = torch.tensor(s.vel, dtype=torch.float64, device=dev, requires_grad=True)
+        th = torch.tensor(theta, device=dev, requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Fk = LJTrajFn.apply(x0, v0, th, sim, 0.005, K, every, every, 2)
+        loss = (Fk ** 2).mean()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        res.append(((t1 - t0) * 1e3, (t2 - t1) * 1e3))
+    sim.check()
+    sim.close()
+    fwd, bwd = res[-1]
+    log(f"adjoint: plain {K} steps {ms_plain:.1f} ms, forward {fwd:.1f} ms, backward "
+        f"{bwd:.1f} ms; force {f_ms * 1e3:.1f} us, VJP {v_ms * 1e3:.1f} us", quiet)
+    return {"workload": "LJ binary mixture N=32768, rho=1.2, T=1, 200 steps dt=0.005, "
+                        "checkpoints and force-matching frames every 20 steps",
+            "steps": K, "plain_ms": ms_plain, "forward_ms": fwd, "backward_ms": bwd,
+            "value": s.n * K / ((fwd + bwd) / 1e3), "unit": "atom-steps/s (forward + backward)",
+            "vs_plain": ms_plain / (fwd + bwd),
+            "backward_over_forward": (fwd + bwd) / fwd,
+            "force_kernel_us": f_ms * 1e3, "vjp_kernel_us": v_ms * 1e3,
+            "vjp_over_force": v_ms / f_ms,
+            "timing": "plain: HIP events; forward/backward: host wall clock incl. launches"}
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +193,11 @@ def main(argv=None) -> int:
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the batched and adjoint measurements")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-MiB device buffer 5 times (reference for the "
+                         "FETCH_SIZE / WRITE_SIZE counters) and exit")
     ap.add_argument("--quiet", action="store_true")
     a = ap.parse_args(argv)
     if a.gpus != 1:
@@ -106,6 +214,15 @@ def main(argv=None) -> int:
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    if a.copy_calibration:
+        n = a.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}), flush=True)
+        return 0
     s = inputs.lj_config("lj1m")
     log(f"workload lj1m: N={s.n} L={s.L:.5f}", a.quiet)
     sim = ParticleSim(s.pos, s.box, (1, 1, 1), vel=s.vel, r_cut=2.5, skin=0.3, device=dev)
@@ -191,9 +308,12 @@ def main(argv=None) -> int:
                        "cell_build_ms": c_ms, "verlet_build_ms": v_ms},
         "cpu_baseline": None,
     }
+    sim.close()
+    if not a.no_forms:
+        result["batched"] = bench_batched(dev, 100, a.quiet)
+        result["adjoint"] = bench_adjoint(dev, a.quiet)
     if not a.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(s.pos, s.box, a.cpu_seconds, a.quiet)
-    sim.close()
     print(json.dumps(result), flush=True)
     return 0
 
