@@ -26,7 +26,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "LJ atom-steps/s at 1M particles, %HBM roofline; batched & adjoint vs plain"
 PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "lj_force_lj1m_counters.txt")
-LJ_SOURCE = os.path.join(ROOT, "paper_1804_07598_amd", "csrc", "lj.hip")
+# the sources the force kernel is compiled from
+LJ_SOURCES = [os.path.join(ROOT, "paper_1804_07598_amd", "csrc", f)
+              for f in ("lj.hip", "geom.h", "fpm_internal.h")]
 
 
 def log(msg: str, quiet: bool):
@@ -34,9 +36,12 @@ def log(msg: str, quiet: bool):
         print(msg, file=sys.stderr, flush=True)
 
 
-def source_hash(path: str) -> str:
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def source_hash(paths) -> str:
+    h = hashlib.sha256()
+    for p in paths:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def stored_traffic(n_launch_atoms: int):
@@ -50,7 +55,7 @@ def stored_traffic(n_launch_atoms: int):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
     try:
-        if kv.get("kernel_source_sha256_16") != source_hash(LJ_SOURCE):
+        if kv.get("kernel_source_sha256_16") != source_hash(LJ_SOURCES):
             return None
         if int(kv.get("atoms", "0")) != n_launch_atoms:
             return None
@@ -109,12 +114,15 @@ def bench_batched(dev, nsteps: int, quiet: bool):
     n = int(ns.sum())
     sim = BatchSim([s.pos for s in systems], [s.box for s in systems], (1, 1, 1),
                    vel_list=[s.vel for s in systems], r_cut=2.5, skin=0.3, device=dev)
+    from paper_1804_07598_amd.tune import tune
+    knobs, _ = tune(sim, float(np.mean(rhos)), cache=None)
     ms_b = timed_steps(sim, nsteps, 0.005, 20)
     reb_b = sim.counters()[0]
     sim.close()
     one = inputs.lj_lattice(n, float(np.mean(rhos)), float(np.mean(Ts)), 6)
     sim = ParticleSim(one.pos, one.box, (1, 1, 1), vel=one.vel, r_cut=2.5, skin=0.3,
                       max_nbr=184, device=dev)
+    tune(sim, float(np.mean(rhos)), cache=None)
     ms_p = timed_steps(sim, nsteps, 0.005, 20)
     sim.close()
     vb, vp = n * nsteps / (ms_b / 1e3), n * nsteps / (ms_p / 1e3)
@@ -123,7 +131,7 @@ def bench_batched(dev, nsteps: int, quiet: bool):
     return {"workload": f"{len(ns)} periodic LJ boxes, N_s uniform in [256, 8192], rho_s in "
                         "[0.6, 0.9], T_s in [0.8, 1.5], r_cut=2.5, skin=0.3, dt=0.005",
             "systems": len(ns), "atoms": n, "steps": nsteps, "value": vb, "unit": "atom-steps/s",
-            "ms_per_step": ms_b / nsteps, "rebuilds": reb_b,
+            "ms_per_step": ms_b / nsteps, "rebuilds": reb_b, "tuning": list(knobs),
             "plain_value": vp, "plain_workload": f"one box of {n} atoms at the mean rho and T",
             "vs_plain": vb / vp}
 
@@ -193,6 +201,8 @@ def main(argv=None) -> int:
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the library's default launch shapes")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched and adjoint measurements")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -226,6 +236,13 @@ def main(argv=None) -> int:
     s = inputs.lj_config("lj1m")
     log(f"workload lj1m: N={s.n} L={s.L:.5f}", a.quiet)
     sim = ParticleSim(s.pos, s.box, (1, 1, 1), vel=s.vel, r_cut=2.5, skin=0.3, device=dev)
+    knobs = (0, 0, 0)
+    if not a.no_tune:
+        from paper_1804_07598_amd.tune import tune
+        knobs, table = tune(sim, s.rho, cache=None)
+        for k, f_ms, b_ms, cost in table:
+            log(f"tune {k}: force {f_ms * 1e3:.1f} us, rebuild {b_ms * 1e3:.1f} us, "
+                f"cost {cost * 1e3:.1f} us", a.quiet)
     dt = 0.005
     thermo = torch.zeros((max(a.steps, a.warmup, 1), 8), dtype=torch.float64, device=dev)
 
@@ -296,7 +313,8 @@ def main(argv=None) -> int:
         "data": "synthetic",
         "config": {"workload": "lj1m: LJ fluid N=1,000,000 (jittered 100^3 lattice), rho=0.8442, "
                                "T=1, r_cut=2.5, skin=0.3, dt=0.005, periodic",
-                   "n": s.n, "dt": dt, "r_cut": 2.5, "skin": 0.3},
+                   "n": s.n, "dt": dt, "r_cut": 2.5, "skin": 0.3,
+                   "tuning": {"verlet_path": knobs[0], "zblock": knobs[1], "unroll": knobs[2]}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "lj_force", "kernel_ms": f_ms,

@@ -216,7 +216,7 @@ __global__ void k_cells_out(State st, int32_t *offsets, int32_t *order) {
     if (order && local < d.n) order[d.caller_base + local] = st.id[0][i];
     if (offsets) {
         // the system's first workgroup writes its ncells + 1 offsets
-        if (blockIdx.x != d.blk_base) return;
+        if (pblock() != d.blk_base) return;
         for (int c = threadIdx.x; c <= d.ncells; c += blockDim.x)
             offsets[d.off_base + c] = st.off[d.off_base + c] - d.slot_base + d.caller_base;
     }

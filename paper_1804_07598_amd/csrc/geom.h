@@ -100,12 +100,26 @@ __device__ __forceinline__ int cell_of(float3 p, const Box &b) {
 
 __device__ __forceinline__ float3 xyz(float4 v) { return make_float3(v.x, v.y, v.z); }
 
+// Workgroups of a launch are dealt to the 8 XCDs in turn (workgroup b runs on
+// XCD b % 8), and each XCD has its own L2.  This maps b to a logical index so
+// that every XCD works through one contiguous range: neighbouring particles,
+// whose positions the neighbour gathers share, then meet in the same L2.
+// A bijection of [0, nb) for any nb.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int x = b & 7, q = b >> 3;
+    const int full = nb >> 3, rem = nb & 7;
+    return x * full + min(x, rem) + q;
+}
+
+// Logical particle workgroup of the current workgroup.
+__device__ __forceinline__ int pblock() { return xcd_block((int)blockIdx.x, (int)gridDim.x); }
+
 // The system of the current particle workgroup (uniform over the workgroup).
-__device__ __forceinline__ int block_system(const State &st) { return st.blk2sys[blockIdx.x]; }
+__device__ __forceinline__ int block_system(const State &st) { return st.blk2sys[pblock()]; }
 
 // Global slot of this thread in a particle kernel (systems are block aligned).
 __device__ __forceinline__ int64_t global_slot() {
-    return (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    return (int64_t)pblock() * kBlock + threadIdx.x;
 }
 
 // Offsets entry of global cell c of system d.
@@ -131,7 +145,7 @@ __device__ __forceinline__ double wave_min(double v) {
 }
 
 // Workgroup reduction of NV values (op 0 = sum, 1 = max, 2 = min) in a fixed
-// order; thread 0 writes the results to part[slot[k] * pstride + blockIdx.x]
+// order; thread 0 writes the results to part[slot[k] * pstride + pblock()]
 // (one array per slot, so the finalize kernel reads them coalesced).
 template <int NV>
 __device__ __forceinline__ void block_partials(double (&v)[NV], const int (&slot)[NV],
@@ -153,7 +167,7 @@ __device__ __forceinline__ void block_partials(double (&v)[NV], const int (&slot
             double s = lds[0][c];
             for (int k = 1; k < nw; k++)
                 s = op[c] == 0 ? s + lds[k][c] : (op[c] == 1 ? fmax(s, lds[k][c]) : fmin(s, lds[k][c]));
-            part[(int64_t)slot[c] * pstride + blockIdx.x] = s;
+            part[(int64_t)slot[c] * pstride + pblock()] = s;
         }
     }
 }

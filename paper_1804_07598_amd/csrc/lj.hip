@@ -111,31 +111,62 @@ __device__ __forceinline__ void pair(Acc &a, float3 pi, double xi, double yi, do
     }
 }
 
-// Walks a list padded to a multiple of eight entries, UNR (4 or 8) at a time.
+// UNR list entries starting at entry k (k a multiple of UNR; groups of four
+// entries are one 16-byte load per lane).
+template <int UNR>
+struct Entries {
+    int4 e[UNR / 4];
+};
+
+template <int UNR>
+__device__ __forceinline__ Entries<UNR> list_group(const int4 *__restrict__ lst, int k) {
+    Entries<UNR> r;
+#pragma unroll
+    for (int g = 0; g < UNR / 4; g++) r.e[g] = lst[((k >> 2) + g) * 64];
+    return r;
+}
+
+// Neighbour positions of a group of entries.  Slots are below 2^27, so the
+// byte offset fits 32 bits and each gather is one shift plus one load with a
+// scalar base.
+template <int UNR>
+__device__ __forceinline__ void gather(const float4 *__restrict__ pos, const Entries<UNR> &en,
+                                       float4 (&q)[UNR]) {
+    const char *base = reinterpret_cast<const char *>(pos);
+#pragma unroll
+    for (int g = 0; g < UNR / 4; g++) {
+        const int j[4] = {en.e[g].x, en.e[g].y, en.e[g].z, en.e[g].w};
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            q[4 * g + u] = *reinterpret_cast<const float4 *>(base + ((uint32_t)j[u] << 4));
+    }
+}
+
+// Walks a list padded to a multiple of eight entries, UNR (4 or 8) at a time,
+// software-pipelined: the neighbour positions of the next group and the list
+// entries of the one after are requested before the current group is
+// computed, so their latency overlaps the pair arithmetic.
 template <int NT, bool IMG, int UNR>
 __device__ __forceinline__ void walk(Acc &a, const float4 *__restrict__ pos,
                                      const int4 *__restrict__ lst, int cnt, float4 pi4,
                                      const Box &b, float rc2, double rc2lo, double rc2hi,
                                      const LJCoef &cf) {
+    if (cnt <= 0) return;
     const float3 pi = xyz(pi4);
     const double xi = pi.x, yi = pi.y, zi = pi.z;
     const int ti = __float_as_int(pi4.w);
+    float4 q[UNR];
+    gather<UNR>(pos, list_group<UNR>(lst, 0), q);
+    Entries<UNR> nxt = list_group<UNR>(lst, UNR < cnt ? UNR : 0);
     for (int k = 0; k < cnt; k += UNR) {
-        int jj[UNR];
-#pragma unroll
-        for (int g = 0; g < UNR / 4; g++) {
-            const int4 e = lst[((k >> 2) + g) * 64];
-            jj[4 * g] = e.x;
-            jj[4 * g + 1] = e.y;
-            jj[4 * g + 2] = e.z;
-            jj[4 * g + 3] = e.w;
-        }
-        float4 q[UNR];
-#pragma unroll
-        for (int u = 0; u < UNR; u++) q[u] = pos[jj[u]];
+        float4 qn[UNR];
+        gather<UNR>(pos, nxt, qn);  // the last round re-reads a group in range: harmless
+        nxt = list_group<UNR>(lst, k + 2 * UNR < cnt ? k + 2 * UNR : k);
 #pragma unroll
         for (int u = 0; u < UNR; u++)
             pair<NT, IMG>(a, pi, xi, yi, zi, ti, q[u], b, rc2, rc2lo, rc2hi, cf);
+#pragma unroll
+        for (int u = 0; u < UNR; u++) q[u] = qn[u];
     }
 }
 

@@ -200,7 +200,8 @@ __global__ __launch_bounds__(kBlock) void k_verlet(State st, const int32_t *bloc
 // column, z-block).
 __global__ __launch_bounds__(kColThreads) void k_verlet_cols(State st, float R2, int cap,
                                                              int cap4) {
-    const int s = st.item2sys[blockIdx.x];
+    const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);  // consecutive columns per XCD
+    const int s = st.item2sys[lb];
     if (!st.sctl[s].rebuild) return;
     const SysDesc &d = st.sys[s];
     const Box b = d.box;
@@ -213,7 +214,7 @@ __global__ __launch_bounds__(kColThreads) void k_verlet_cols(State st, float R2,
     __shared__ int colbase[10];
     const float4 *__restrict__ pos = st.pos[1];
     const int nx = b.nc[0], ny = b.nc[1], nz = b.nc[2];
-    const int item = blockIdx.x - d.item_base;
+    const int item = lb - d.item_base;
     const int zblk = item % nzb, colid = item / nzb;
     const int ix = colid / ny, iy = colid % ny;
     const int z0 = zblk * zb, z1 = min(z0 + zb, nz);

@@ -139,3 +139,18 @@ def test_tuning_knobs_change_nothing_but_speed(tuning):
     F, F0 = np_(F).astype(np.float64), np_(F0).astype(np.float64)
     assert np.abs(F - F0).max() <= 1e-6 * math.sqrt((F0 ** 2).mean())
     assert np.abs(out - out0).max() <= 1e-9 * np.abs(out0).max()
+
+
+def test_autotuner_picks_a_candidate_and_caches_it(tmp_path):
+    from paper_1804_07598_amd.tune import CANDIDATES, tune
+    systems = systems_of([1, 2, 72, 400])
+    sim = make_batch(systems)
+    c0, l0 = (np_(t) for t in sim.neighbors())
+    cache = str(tmp_path / "tuning.json")
+    knobs, table = tune(sim, 0.75, cache=cache, reps=2)
+    assert knobs in CANDIDATES and len(table) == len(CANDIDATES)
+    assert all(f > 0 and b > 0 for _, f, b, _ in table)
+    c, l = (np_(t) for t in sim.neighbors())
+    assert np.array_equal(c, c0)
+    again, table2 = tune(sim, 0.75, cache=cache)
+    assert again == knobs and table2 == []  # served from the cache
