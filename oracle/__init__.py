@@ -49,7 +49,7 @@ def lib():
         L.oracle_radius2_f32.argtypes = [C.c_float, C.c_float]
         L.oracle_cell_grid.argtypes = [f32p, C.c_float, C.c_float, i32p]
         L.oracle_cell_index.argtypes = [C.c_int64, f32p, f32p, i32p, i32p]
-        L.oracle_cell_sort.argtypes = [C.c_int64, i32p, C.c_int32, i32p, i32p, i32p]
+        L.oracle_cell_sort.argtypes = [C.c_int64, i32p, _opt(f32p), C.c_int32, i32p, i32p, i32p]
         L.oracle_neighbors.restype = C.c_int
         L.oracle_neighbors.argtypes = [C.c_int64, f32p, f32p, i32p, C.c_float, _opt(i64p),
                                        C.c_int64, i32p, i32p, C.c_int64]
@@ -131,13 +131,15 @@ def cell_index(pos, L, ncell) -> np.ndarray:
     return out
 
 
-def cell_sort(cid, ncells: int):
-    """(counts, offsets, order) of a stable counting sort by cell."""
+def cell_sort(cid, ncells: int, z=None):
+    """(counts, offsets, order) of a counting sort by cell; inside a cell by z
+    then particle index (by particle index alone when z is None)."""
     cid = _i32(cid)
     counts = np.empty(ncells, np.int32)
     offsets = np.empty(ncells + 1, np.int32)
     order = np.empty(len(cid), np.int32)
-    lib().oracle_cell_sort(len(cid), cid, int(ncells), counts, offsets, order)
+    lib().oracle_cell_sort(len(cid), cid, None if z is None else _f32(z), int(ncells), counts,
+                           offsets, order)
     return counts, offsets, order
 
 

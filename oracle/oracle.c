@@ -152,12 +152,23 @@ void oracle_cell_index(int64_t n, const float *pos, const float L[3], const int3
     }
 }
 
-/* Counting sort by cell, ties kept in particle-index order: counts per cell,
- * their exclusive prefix sum (offsets, ncells + 1 entries) and the resulting
- * order (order[slot] = particle index).  This is the cache-friendly reordering
- * of particles by cell (section 3.6). */
-void oracle_cell_sort(int64_t n, const int32_t *cid, int32_t ncells, int32_t *counts,
-                      int32_t *offsets, int32_t *order)
+/* Counting sort by cell: counts per cell, their exclusive prefix sum (offsets,
+ * ncells + 1 entries) and the resulting order (order[slot] = particle index).
+ * This is the cache-friendly reordering of particles by cell (section 3.6).
+ * Inside a cell particles are ordered by z ascending (FP32 values as given),
+ * ties by particle index; with z == NULL by particle index alone. */
+static const float *g_sort_z; /* key of the comparison below (single-threaded use) */
+
+static int cmp_z_then_index(const void *a, const void *b)
+{
+    int32_t i = *(const int32_t *)a, j = *(const int32_t *)b;
+    if (g_sort_z[i] < g_sort_z[j]) return -1;
+    if (g_sort_z[i] > g_sort_z[j]) return 1;
+    return (i > j) - (i < j);
+}
+
+void oracle_cell_sort(int64_t n, const int32_t *cid, const float *z, int32_t ncells,
+                      int32_t *counts, int32_t *offsets, int32_t *order)
 {
     memset(counts, 0, sizeof(int32_t) * (size_t)ncells);
     for (int64_t i = 0; i < n; i++) counts[cid[i]]++;
@@ -167,6 +178,12 @@ void oracle_cell_sort(int64_t n, const int32_t *cid, int32_t ncells, int32_t *co
     memcpy(fill, offsets, sizeof(int32_t) * (size_t)ncells);
     for (int64_t i = 0; i < n; i++) order[fill[cid[i]]++] = (int32_t)i;
     free(fill);
+    if (z) {
+        g_sort_z = z;
+        for (int32_t c = 0; c < ncells; c++)
+            qsort(order + offsets[c], (size_t)counts[c], sizeof(int32_t), cmp_z_then_index);
+        g_sort_z = NULL;
+    }
 }
 
 /* ------------------------------------------------------------------------- */

@@ -206,6 +206,20 @@ def test_cell_sort_invariants():
         members = order[offsets[c]:offsets[c + 1]]
         assert np.all(cid[members] == c)
         assert np.all(np.diff(members) > 0)
+    # with the z key: same cells and offsets, each cell ordered by (z, index),
+    # which makes every column of cells one run sorted by z
+    z = s.pos[:, 2]
+    counts_z, offsets_z, order_z = O.cell_sort(cid, ncells, z)
+    assert np.array_equal(offsets_z, offsets)
+    assert np.array_equal(order_z, np.lexsort((np.arange(s.n), z, cid)))  # cell, z, index
+    col = nc[2]
+    for c0 in range(0, ncells, col):
+        run = order_z[offsets_z[c0]:offsets_z[c0 + col]]
+        assert np.all(np.diff(z[run]) >= 0)
+    zt = z.copy()
+    zt[::2] = zt[1::2]  # pairs of equal keys, broken by index
+    _, _, order_t = O.cell_sort(cid, ncells, zt)
+    assert np.array_equal(order_t, np.lexsort((np.arange(s.n), zt, cid)))
     # each particle lies in (or within rounding of) its cell's geometric bounds
     side = s.box.astype(np.float64) / nc
     ijk = np.stack([cid // (nc[1] * nc[2]), (cid // nc[2]) % nc[1], cid % nc[2]], axis=1)
