@@ -136,6 +136,59 @@ def bench_batched(dev, nsteps: int, quiet: bool):
             "vs_plain": vb / vp}
 
 
+def bench_sph(dev, nsteps: int, quiet: bool):
+    """Weakly compressible SPH water column: 128 x 128 x 128 fluid particles at
+    dx = 0.01 on a 3-layer floor (N = 2,146,304), Wendland C2 with h = 1.3 dx,
+    Tait EOS (c0 = 20 sqrt(g H), gamma = 7), alpha = 0.1, CFL 0.2."""
+    import math
+    import numpy as np
+    import torch
+    from paper_1804_07598_amd import _lib as F
+    from paper_1804_07598_amd import inputs
+    from paper_1804_07598_amd.sim import ParticleSim
+    s = inputs.sph_column(128, 128)
+    dx, H, g = s.dx, s.H, 9.81
+    h = 1.3 * dx
+    c0 = 20.0 * math.sqrt(g * H)
+    prm = F.sph_params(h, 1000.0 * dx ** 3, 1000.0, c0, 7.0, 0.1, 0.01 * h * h, (0, 0, -g), 0.2)
+    r_cut = float(np.float32(2 * h))
+    sim = ParticleSim(s.pos, s.L, (1, 1, 0), vel=s.vel, typ=s.kind, r_cut=r_cut, skin=0.1 * h,
+                      max_nbr=160, device=dev)
+    sim.set_density(s.rho)
+    sim.sph_step(20, prm)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    hist = sim.sph_step(nsteps, prm)
+    e1.record()
+    torch.cuda.synchronize()
+    sim.check()
+    ms = e0.elapsed_time(e1)
+    F.fpm_set_profiling(sim.ctx, True)
+    for _ in range(10):
+        sim.sph_rates(prm)
+    r_ms, _ = F.fpm_kernel_time(sim.ctx, "sph_rates")
+    F.fpm_set_profiling(sim.ctx, False)
+    reb, _, total = sim.counters()
+    sim.close()
+    n = len(s.pos)
+    nbar = total / n
+    bytes_rates = n * (52.0 + 4.0 * nbar)
+    achieved = bytes_rates / (r_ms / 1e3) / 1e9
+    t_sim = float(hist[-1, 0].item())
+    log(f"sph: {n} particles, {ms / nsteps * 1e3:.1f} us/step, rates kernel {r_ms * 1e3:.1f} us "
+        f"({achieved:.0f} GB/s), mean list {nbar:.1f}, simulated {t_sim:.4g} s", quiet)
+    return {"workload": "SPH water column 128^3 fluid + 3-layer floor, N=2,146,304, dx=0.01, "
+                        "Wendland C2 h=1.3dx, Tait gamma=7, c0=20 sqrt(gH), alpha=0.1, CFL 0.2",
+            "particles": n, "steps": nsteps, "value": n * nsteps / (ms / 1e3),
+            "unit": "particle-steps/s", "ms_per_step": ms / nsteps, "simulated_s": t_sim,
+            "rates_kernel_us": r_ms * 1e3, "mean_list": nbar, "rebuilds": reb,
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                         "bytes_model": "N*(52 + 4*nbar): pos, vel 32, count 4, list, out 16"}}
+
+
 def bench_adjoint(dev, quiet: bool):
     """Gradient of a force-matching loss through a 200-step trajectory of the
     N = 32768 binary mixture (checkpoints and loss frames every 20 steps), and
@@ -329,6 +382,7 @@ def main(argv=None) -> int:
     sim.close()
     if not a.no_forms:
         result["batched"] = bench_batched(dev, 100, a.quiet)
+        result["sph"] = bench_sph(dev, 500, a.quiet)
         result["adjoint"] = bench_adjoint(dev, a.quiet)
     if not a.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(s.pos, s.box, a.cpu_seconds, a.quiet)

@@ -231,8 +231,9 @@ int fpm_read_counters(fpm_ctx *ctx, int64_t h_out[3]);
 /* ---- measurement and tuning ---- */
 
 /* Launch shapes (0 = automatic).  verlet_path: 1 builds Verlet lists particle
- * by particle from global memory, 2 by column blocks staged in LDS (where the
- * grid has >= 3 cells per axis).  zblock: z-cells per column workgroup
+ * by particle over whole neighbour cells, 2 by column blocks staged in LDS,
+ * 3 particle by particle over candidate windows (2 and 3 where the grid has
+ * >= 3 cells per axis; automatic takes 3 there).  zblock: z-cells per column workgroup
  * (1..64).  unroll: list entries in flight per lane in the force kernel (4 or
  * 8).  Results do not depend on them.  Changing verlet_path or zblock drops
  * the particles (call fpm_set_particles again). */

@@ -72,18 +72,24 @@ Plan make_plan(const fpm_ctx *c, const std::vector<int64_t> &cnt) {
         d.ncells = d.box.nc[0] * d.box.nc[1] * d.box.nc[2];
         d.cell_base = cell;
         d.off_base = offb;
-        d.zb = c->tune_verlet_path == 1
-                   ? 0
-                   : verlet_zblock(cnt[s], d.ncells, d.box.nc, c->tune_zb);
-        d.nzb = d.zb ? (d.box.nc[2] + d.zb - 1) / d.zb : 0;
+        // Verlet build: zb > 0 column workgroups, 0 particle by particle over
+        // whole cells, -1 particle by particle over candidate windows
+        const bool big = d.box.nc[0] >= 3 && d.box.nc[1] >= 3 && d.box.nc[2] >= 3;
+        if (c->tune_verlet_path == 1)
+            d.zb = 0;
+        else if (c->tune_verlet_path == 3 || (c->tune_verlet_path == 0 && big))
+            d.zb = big ? -1 : 0;
+        else
+            d.zb = verlet_zblock(cnt[s], d.ncells, d.box.nc, c->tune_zb);
+        d.nzb = d.zb > 0 ? (d.box.nc[2] + d.zb - 1) / d.zb : 0;
         d.item_base = item;
         d.dummy = (int32_t)(slot + cnt[s]);
         d.caller_base = (int32_t)caller;
         h.nblk = d.n_pad / kBlock;
-        h.nitems = d.zb ? d.box.nc[0] * d.box.nc[1] * d.nzb : 0;
+        h.nitems = d.zb > 0 ? d.box.nc[0] * d.box.nc[1] * d.nzb : 0;
         for (int b = 0; b < h.nblk; b++) {
             P.blk2sys.push_back(s);
-            if (!d.zb) P.pa_blocks.push_back(blk + b);
+            if (d.zb <= 0) P.pa_blocks.push_back(blk + b);
         }
         for (int q = 0; q < h.nitems; q++) P.item2sys.push_back(s);
         slot += d.n_pad;
@@ -124,7 +130,7 @@ size_t layout(const fpm_ctx *c, const Plan &P, char *base, State *st,
     s.xbuild = (float4 *)take(ns * sizeof(float4));
     s.cid = (int32_t *)take(ns * sizeof(int32_t));
     s.rnk = (int32_t *)take(ns * sizeof(int32_t));
-    s.tmp = (int2 *)take(ns * sizeof(int2));
+    s.tmp = (int4 *)take(ns * sizeof(int4));
     s.cnt = (int32_t *)take(((size_t)P.ncells_total + 4) * sizeof(int32_t));
     s.off = (int32_t *)take(((size_t)P.noff_total + 4) * sizeof(int32_t));
     s.nbr = (int32_t *)take((size_t)ns * cap4_for(c->cap) * 4 * sizeof(int32_t));
@@ -367,7 +373,7 @@ int fpm_set_neighbor_params(fpm_ctx *c, float r_cut, float skin, int32_t max_nbr
 
 int fpm_set_tuning(fpm_ctx *c, int32_t verlet_path, int32_t zblock, int32_t unroll) {
     if (!c) return FPM_EINVAL;
-    if (verlet_path < 0 || verlet_path > 2) return fail(c, FPM_EINVAL, "verlet_path is 0, 1 or 2");
+    if (verlet_path < 0 || verlet_path > 3) return fail(c, FPM_EINVAL, "verlet_path is 0..3");
     if (zblock < 0 || zblock > 64) return fail(c, FPM_EINVAL, "zblock out of range");
     if (unroll != 0 && unroll != 4 && unroll != 8) return fail(c, FPM_EINVAL, "unroll is 0, 4 or 8");
     if (verlet_path != c->tune_verlet_path || zblock != c->tune_zb) c->have_particles = false;

@@ -156,7 +156,7 @@ __global__ __launch_bounds__(1024) void k_scan(State st) {
     if (t == 0) off[ncells] = carry;
 }
 
-// Scatter (caller id, source slot) to the cell's offset + arrival rank.
+// Scatter (caller id, source slot, z) to the cell's offset + arrival rank.
 __global__ void k_scatter(State st) {
     const int s = block_system(st);
     if (!st.sctl[s].rebuild) return;
@@ -165,24 +165,30 @@ __global__ void k_scatter(State st) {
     if (i - d.slot_base >= d.n) return;
     const int c = st.cid[i];
     const int slot = st.off[off_index(d, c)] + st.rnk[i];
-    st.tmp[slot] = make_int2(st.id[0][i], (int32_t)i);
+    st.tmp[slot] = make_int4(st.id[0][i], (int32_t)i, __float_as_int(st.pos[0][i].z), 0);
 }
 
-// The final slot inside the cell is the number of cell members with a smaller
-// caller index, which makes the order independent of the atomics' arrival
-// order.  Gathers position, velocity and id into buffer 1 and records the
-// build positions.
+// The final slot inside the cell is the number of cell members that come
+// before it in (z, caller index) order, which makes the order independent of
+// the atomics' arrival order and every column of cells one run sorted by z.
+// Gathers position, velocity and id into buffer 1 and records the build
+// positions.
 __global__ void k_rank_gather(State st) {
     const int s = block_system(st);
     if (!st.sctl[s].rebuild) return;
     const SysDesc &d = st.sys[s];
     const int64_t i = global_slot();
     if (i - d.slot_base < d.n) {
-        const int2 me = st.tmp[i];
+        const int4 me = st.tmp[i];
+        const float mz = __int_as_float(me.z);
         const int c = st.cid[me.y];
         const int beg = st.off[off_index(d, c)], end = st.off[off_index(d, c) + 1];
         int r = 0;
-        for (int k = beg; k < end; k++) r += st.tmp[k].x < me.x;
+        for (int k = beg; k < end; k++) {
+            const int4 o = st.tmp[k];
+            const float oz = __int_as_float(o.z);
+            r += oz < mz || (oz == mz && o.x < me.x);
+        }
         const int f = beg + r;
         const float4 p = st.pos[0][me.y];
         st.pos[1][f] = p;

@@ -75,16 +75,52 @@ __device__ __forceinline__ float cand_d2(float3 pi, float3 pj, const Box &b) {
     return s + zz;
 }
 
-// Where list entry k of a slot goes, relative to the slot's entry 0.
-__device__ __forceinline__ int ell_off(int k) { return ((k & ~3) << 6) | (k & 3); }
+// One particle's list being written.  Entries are collected four at a time
+// and stored as one 16-byte group (the list layout's unit), which takes a
+// quarter of the store instructions of entry-by-entry writes and never leaves
+// a group half written.
+struct ListOut {
+    int4 *g0;    // the slot's group 0; group q is at g0[64 q]
+    int cap;     // capacity in entries
+    int count;   // entries found so far (may exceed cap: overflow)
+    int4 buf;    // the group being filled
+};
 
-// Fills entries count .. (count rounded up to 8) with the far-away padding
-// slot, so that list readers can consume whole groups of eight.
-__device__ __forceinline__ void pad_list(int32_t *__restrict__ wp, int count, int cap,
-                                         int dummy) {
-    const int c = min(count, cap);
+__device__ __forceinline__ ListOut list_out(const State &st, int64_t i, int cap, int cap4) {
+    ListOut o;
+    o.g0 = reinterpret_cast<int4 *>(st.nbr) + ((i >> 6) * (int64_t)cap4) * 64 + (i & 63);
+    o.cap = cap;
+    o.count = 0;
+    o.buf = make_int4(0, 0, 0, 0);
+    return o;
+}
+
+__device__ __forceinline__ void push(ListOut &o, int gj) {
+    const int k = o.count & 3;
+    o.buf.x = k == 0 ? gj : o.buf.x;
+    o.buf.y = k == 1 ? gj : o.buf.y;
+    o.buf.z = k == 2 ? gj : o.buf.z;
+    o.buf.w = k == 3 ? gj : o.buf.w;
+    if (k == 3 && o.count < o.cap) o.g0[(o.count >> 2) * 64] = o.buf;
+    o.count++;
+}
+
+// Completes the list with the far-away padding slot up to a multiple of eight
+// entries, so that list readers can consume whole groups of eight.
+__device__ __forceinline__ void finish(ListOut &o, int dummy) {
+    const int c = min(o.count, o.cap);
     const int c8 = (c + 7) & ~7;
-    for (int k = c; k < c8; k++) wp[ell_off(k)] = dummy;
+    int g = c >> 2;
+    if (c & 3) {
+        const int k = c & 3;
+        int4 v = o.buf;
+        v.y = k <= 1 ? dummy : v.y;
+        v.z = k <= 2 ? dummy : v.z;
+        v.w = dummy;
+        o.g0[g * 64] = v;
+        g++;
+    }
+    for (; g * 4 < c8; g++) o.g0[g * 64] = make_int4(dummy, dummy, dummy, dummy);
 }
 
 // Tests candidates [beg, end) of `src` (global slots) or of the LDS stage
@@ -93,27 +129,39 @@ __device__ __forceinline__ void pad_list(int32_t *__restrict__ wp, int count, in
 template <bool IMG, bool LDS>
 __device__ __forceinline__ void scan_range(const float4 *__restrict__ src, int beg, int end,
                                            int i, float3 pi, const Box &b, float R2,
-                                           int32_t *__restrict__ wp, int cap, int &count,
-                                           bool &img) {
+                                           ListOut &o, bool &img) {
     for (int c0 = beg; c0 < end; c0 += 32) {
         const int len = min(32, end - c0);
         uint32_t mask = 0;
 #pragma unroll 4
         for (int u = 0; u < len; u++) {
             const float4 q = src[c0 + u];
-            const int gj = LDS ? __float_as_int(q.w) : c0 + u;
-            const bool hit = cand_d2<IMG>(pi, xyz(q), b) <= R2 && gj != i;
+            const bool hit = cand_d2<IMG>(pi, xyz(q), b) <= R2;
             mask |= (uint32_t)hit << u;
-            if (IMG) img |= hit && uses_image(pi, xyz(q), b);
+            if (IMG) img |= hit && uses_image(pi, xyz(q), b) && c0 + u != i;
         }
         while (mask) {
             const int u = __ffs(mask) - 1;
             mask &= mask - 1;
             const int gj = LDS ? __float_as_int(src[c0 + u].w) : c0 + u;
-            if (count < cap) wp[ell_off(count)] = gj;
-            count++;
+            if (gj != i) push(o, gj);  // i itself is always a hit
         }
     }
+}
+
+// First index of the z-sorted stage range [lo, hi) whose z is >= z (or > z
+// with STRICT), hi if there is none.
+template <bool STRICT>
+__device__ __forceinline__ int z_bound(const float4 *sp, int lo, int hi, float z) {
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const float zm = sp[mid].z;
+        if (STRICT ? zm <= z : zm < z)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
 }
 
 // True when some stencil cell of cell (ix, iy, iz) lies across a periodic face.
@@ -126,11 +174,10 @@ __device__ __forceinline__ bool near_face(int ix, int iy, int iz, const Box &b) 
 // List of slot i from global memory through the cell offsets.
 template <bool IMG>
 __device__ void verlet_atom_global(const State &st, const SysDesc &d, int i, float3 pi,
-                                   float R2, int cap, int cap4, int &count, bool &img) {
+                                   float R2, ListOut &o, bool &img) {
     const Box &b = d.box;
     const float4 *__restrict__ pos = st.pos[1];
     const int32_t *__restrict__ off = st.off + d.off_base;
-    int32_t *wp = st.nbr + nbr_index(i, 0, cap4);
     const int ix = cell_coord(pi.x, b.inv[0], b.nc[0]);
     const int iy = cell_coord(pi.y, b.inv[1], b.nc[1]);
     const int iz = cell_coord(pi.z, b.inv[2], b.nc[2]);
@@ -146,11 +193,138 @@ __device__ void verlet_atom_global(const State &st, const SysDesc &d, int i, flo
                 int r1 = r;
                 while (r1 + 1 < mz && cz[r1 + 1] == cz[r1] + 1) r1++;
                 const int beg = off[col + cz[r]], end = off[col + cz[r1] + 1];
-                scan_range<IMG, false>(pos, beg, end, i, pi, b, R2, wp, cap, count, img);
+                scan_range<IMG, false>(pos, beg, end, i, pi, b, R2, o, img);
                 r = r1 + 1;
             }
         }
-    pad_list(wp, count, cap, d.dummy);
+    finish(o, d.dummy);
+}
+
+// One z-run of a neighbouring column, [beg, end) of the sorted buffer, whose
+// z (after subtracting the image shift a.z) ascends.  Candidates below zlo are
+// skipped and the scan stops above zhi; the rest are tested with the exact
+// predicate: separation (q - a) - pk per axis, where a holds the shift of
+// candidates moved down one period and pk the particle itself moved down for
+// runs across the upper face (both subtractions exact).  Hits are appended.
+__device__ __forceinline__ void scan_window(const float4 *__restrict__ pos, int beg, int end,
+                                            float3 a, float3 pk, float zlo, float zhi, int i,
+                                            float R2, ListOut &o, bool &hit_any) {
+#pragma clang fp contract(off)
+    constexpr int B = 8;  // candidates requested together (latency is the cost here)
+    int c = beg;
+    // skip to the window: z only, B at a time (the run is sorted)
+    while (c < end) {
+        int below = 0;
+#pragma unroll
+        for (int u = 0; u < B; u++) {
+            const float z = c + u < end ? pos[c + u].z - a.z : INFINITY;
+            below += z < zlo;
+        }
+        c += below;
+        if (below < B) break;
+    }
+    // scan the window, B at a time
+    while (c < end) {
+        float4 q[B];
+#pragma unroll
+        for (int u = 0; u < B; u++) q[u] = pos[min(c + u, end - 1)];
+        bool past = false;
+#pragma unroll
+        for (int u = 0; u < B; u++) {
+            const int j = c + u;
+            const float qz = q[u].z - a.z;
+            past |= qz > zhi;
+            const float dx = (q[u].x - a.x) - pk.x, dy = (q[u].y - a.y) - pk.y, dz = qz - pk.z;
+            const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
+            const float s = xx + yy;
+            if (j < end && qz <= zhi && s + zz <= R2 && j != i) {
+                push(o, j);
+                hit_any = true;
+            }
+        }
+        if (past) break;
+        c += B;
+    }
+}
+
+// List of slot i from global memory with candidate windows, for grids of at
+// least three cells per axis.  Column (ox, oy) is at least dxy from i
+// horizontally (the distance to the face of i's cell that faces it), so only
+// |dz| <= sqrt(R^2 - dxy^2) can pass and columns beyond R are skipped; cells
+// are ordered by z inside a column, so the window is found by a short skip.
+// Bounds are widened (R^2 by 1e-4, cell faces by 1e-5 L) so that rounding
+// can only add candidates; the predicate decides exactly.
+__device__ void verlet_atom_window(const State &st, const SysDesc &d, int i, float3 pi,
+                                   float R2, ListOut &o, bool &img) {
+    const Box &b = d.box;
+    const float4 *__restrict__ pos = st.pos[1];
+    const int32_t *__restrict__ off = st.off + d.off_base;
+    const int nx = b.nc[0], ny = b.nc[1], nz = b.nc[2];
+    const int ix = cell_coord(pi.x, b.inv[0], nx);
+    const int iy = cell_coord(pi.y, b.inv[1], ny);
+    const int iz = cell_coord(pi.z, b.inv[2], nz);
+    const float marg = 1e-5f * fmaxf(b.L[0], fmaxf(b.L[1], b.L[2]));
+    const float dxl = fmaxf(pi.x - (float)ix / b.inv[0] - marg, 0.f);
+    const float dxh = fmaxf((float)(ix + 1) / b.inv[0] - pi.x - marg, 0.f);
+    const float dyl = fmaxf(pi.y - (float)iy / b.inv[1] - marg, 0.f);
+    const float dyh = fmaxf((float)(iy + 1) / b.inv[1] - pi.y - marg, 0.f);
+    const float Rw2 = R2 * 1.0001f;
+    // z-runs: cells iz-1 .. iz+1 as at most two contiguous pieces
+    int zc0[2], zc1[2];
+    float azs[2], pks[2];
+    int nseg = 0;
+    if (iz == 0) {
+        if (b.per[2]) {  // cell nz-1, one period down
+            zc0[nseg] = nz - 1, zc1[nseg] = nz - 1, azs[nseg] = b.L[2], pks[nseg] = pi.z;
+            nseg++;
+        }
+        zc0[nseg] = 0, zc1[nseg] = 1, azs[nseg] = 0.f, pks[nseg] = pi.z;
+        nseg++;
+    } else if (iz == nz - 1) {
+        zc0[nseg] = nz - 2, zc1[nseg] = nz - 1, azs[nseg] = 0.f, pks[nseg] = pi.z;
+        nseg++;
+        if (b.per[2]) {  // cell 0, particle i moved down one period
+            zc0[nseg] = 0, zc1[nseg] = 0, azs[nseg] = 0.f, pks[nseg] = pi.z - b.L[2];
+            nseg++;
+        }
+    } else {
+        zc0[nseg] = iz - 1, zc1[nseg] = iz + 1, azs[nseg] = 0.f, pks[nseg] = pi.z;
+        nseg++;
+    }
+    for (int ox = -1; ox <= 1; ox++) {
+        int cx = ix + ox;
+        float ax = 0.f, px = pi.x;
+        if (cx < 0 || cx >= nx) {
+            if (!b.per[0]) continue;
+            if (cx < 0) cx += nx, ax = b.L[0];
+            else cx -= nx, px = pi.x - b.L[0];
+        }
+        const float ddx = ox < 0 ? dxl : (ox > 0 ? dxh : 0.f);
+        for (int oy = -1; oy <= 1; oy++) {
+            int cy = iy + oy;
+            float ay = 0.f, py = pi.y;
+            if (cy < 0 || cy >= ny) {
+                if (!b.per[1]) continue;
+                if (cy < 0) cy += ny, ay = b.L[1];
+                else cy -= ny, py = pi.y - b.L[1];
+            }
+            const float ddy = oy < 0 ? dyl : (oy > 0 ? dyh : 0.f);
+            const float h2 = Rw2 - ddx * ddx - ddy * ddy;
+            if (h2 < 0.f) continue;
+            const float hz = sqrtf(h2);
+            const int col = (cx * ny + cy) * nz;
+            for (int g = 0; g < nseg; g++) {
+                bool hit = false;
+                const float3 a = make_float3(ax, ay, azs[g]);
+                const float3 pk = make_float3(px, py, pks[g]);
+                scan_window(pos, off[col + zc0[g]], off[col + zc1[g] + 1], a, pk, pk.z - hz,
+                            pk.z + hz, i, R2, o, hit);
+                img |= hit && (ax != 0.f || px != pi.x || ay != 0.f || py != pi.y ||
+                               azs[g] != 0.f || pks[g] != pi.z);
+            }
+        }
+    }
+    finish(o, d.dummy);
 }
 
 // A list longer than the capacity raises the sticky overflow flag (any of the
@@ -176,7 +350,7 @@ __global__ __launch_bounds__(kBlock) void k_verlet(State st, const int32_t *bloc
     const Box b = d.box;
     const int64_t i = (int64_t)blk * kBlock + threadIdx.x;
     const bool active = i - d.slot_base < d.n;
-    int count = 0;
+    ListOut o = list_out(st, i, cap, cap4);
     bool img = false, face = false;
     float3 pi = make_float3(0.f, 0.f, 0.f);
     if (active) {
@@ -186,12 +360,14 @@ __global__ __launch_bounds__(kBlock) void k_verlet(State st, const int32_t *bloc
     }
     const bool face_wave = __ballot(face) != 0;
     if (active) {
-        if (face_wave)
-            verlet_atom_global<true>(st, d, (int)i, pi, R2, cap, cap4, count, img);
+        if (d.zb < 0)
+            verlet_atom_window(st, d, (int)i, pi, R2, o, img);
+        else if (face_wave)
+            verlet_atom_global<true>(st, d, (int)i, pi, R2, o, img);
         else
-            verlet_atom_global<false>(st, d, (int)i, pi, R2, cap, cap4, count, img);
-        st.nnb[i] = (uint32_t)min(count, cap) | (img ? kWrapBit : 0u);
-        note_overflow(st, count, cap);
+            verlet_atom_global<false>(st, d, (int)i, pi, R2, o, img);
+        st.nnb[i] = (uint32_t)min(o.count, cap) | (img ? kWrapBit : 0u);
+        note_overflow(st, o.count, cap);
     }
     copy_back(st, i);
 }
@@ -221,6 +397,10 @@ __global__ __launch_bounds__(kColThreads) void k_verlet_cols(State st, float R2,
     const int nrun = z1 - z0 + 2;
     const int cell0 = (ix * ny + iy) * nz;
     const int abeg = off[cell0 + z0], aend = off[cell0 + z1];
+    // faces of the column's cells (FP32, within a few ulp of the cell test)
+    const float xlo = (float)ix / b.inv[0], xhi = (float)(ix + 1) / b.inv[0];
+    const float ylo = (float)iy / b.inv[1], yhi = (float)(iy + 1) / b.inv[1];
+    const float marg = 1e-5f * fmaxf(b.L[0], fmaxf(b.L[1], b.L[2]));
 
     if (threadIdx.x < 9) {
         const int k = threadIdx.x;
@@ -315,7 +495,6 @@ __global__ __launch_bounds__(kColThreads) void k_verlet_cols(State st, float R2,
     for (int base = abeg; base < aend; base += kColThreads) {
         const int i = base + (int)threadIdx.x;
         const bool active = i < aend;
-        int count = 0;
         bool img = false, face = false;
         int m = 1;
         float3 pi = make_float3(0.f, 0.f, 0.f);
@@ -327,30 +506,49 @@ __global__ __launch_bounds__(kColThreads) void k_verlet_cols(State st, float R2,
         }
         const bool face_wave = __ballot(face) != 0;
         if (active) {
-            int32_t *wp = st.nbr + nbr_index(i, 0, cap4);
+            ListOut o = list_out(st, i, cap, cap4);
             if (use_lds) {
-                // the run's last cell is cell 0 one period up when z1 wraps; only
-                // particles of the top z-cell (m + 2 == nrun) reach it
+                // The run's last cell is cell 0 one period up when z1 wraps; only
+                // particles of the top z-cell (m + 2 == nrun) reach it.
                 const bool top_img = b.per[2] && z1 == nz;
+                // Candidate windows: column k is at least dxy from i horizontally
+                // (distance to the side of i's cell that faces it), so only
+                // |dz| <= sqrt(R^2 - dxy^2) can pass; each stage range is sorted by
+                // z, so that window is a subrange found by bisection.  Bounds are
+                // widened (R^2 by 1e-4, cell faces by 1e-5 L) so that rounding
+                // can only add candidates; the predicate then decides exactly.
+                const float Rw2 = R2 * 1.0001f;
+                const float dxl = fmaxf(pi.x - xlo - marg, 0.f), dxh = fmaxf(xhi - pi.x - marg, 0.f);
+                const float dyl = fmaxf(pi.y - ylo - marg, 0.f), dyh = fmaxf(yhi - pi.y - marg, 0.f);
                 for (int k = 0; k < 9; k++) {
+                    const int ox = k / 3 - 1, oy = k % 3 - 1;
+                    const float ddx = ox < 0 ? dxl : (ox > 0 ? dxh : 0.f);
+                    const float ddy = oy < 0 ? dyl : (oy > 0 ? dyh : 0.f);
+                    const float h2 = Rw2 - ddx * ddx - ddy * ddy;
+                    if (h2 < 0.f) continue;
+                    const float hz = sqrtf(h2);
                     float3 pk = pi;  // i moved down one period where column k lies across
                     if (sh[k][1][0] > 0.f) pk.x = pi.x - b.L[0];  // the upper face (exact:
                     if (sh[k][1][1] > 0.f) pk.y = pi.y - b.L[1];  // i is in the top cell)
                     const int beg = colbase[k] + cs[k][m - 1], end = colbase[k] + cs[k][m + 2];
                     const int mid = m + 2 == nrun ? colbase[k] + cs[k][nrun - 1] : end;
-                    scan_range<false, true>(sp, beg, mid, i, pk, b, R2, wp, cap, count, img);
+                    int lo = z_bound<false>(sp, beg, mid, pk.z - hz);
+                    int hi = z_bound<true>(sp, lo, mid, pk.z + hz);
+                    scan_range<false, true>(sp, lo, hi, i, pk, b, R2, o, img);
                     if (top_img) pk.z = pi.z - b.L[2];
-                    scan_range<false, true>(sp, mid, end, i, pk, b, R2, wp, cap, count, img);
+                    lo = z_bound<false>(sp, mid, end, pk.z - hz);
+                    hi = z_bound<true>(sp, lo, end, pk.z + hz);
+                    scan_range<false, true>(sp, lo, hi, i, pk, b, R2, o, img);
                 }
-                pad_list(wp, count, cap, d.dummy);
+                finish(o, d.dummy);
                 img = face;  // its stencil reaches across a periodic face
             } else if (face_wave) {
-                verlet_atom_global<true>(st, d, i, pi, R2, cap, cap4, count, img);
+                verlet_atom_global<true>(st, d, i, pi, R2, o, img);
             } else {
-                verlet_atom_global<false>(st, d, i, pi, R2, cap, cap4, count, img);
+                verlet_atom_global<false>(st, d, i, pi, R2, o, img);
             }
-            st.nnb[i] = (uint32_t)min(count, cap) | (img ? kWrapBit : 0u);
-            note_overflow(st, count, cap);
+            st.nnb[i] = (uint32_t)min(o.count, cap) | (img ? kWrapBit : 0u);
+            note_overflow(st, o.count, cap);
             copy_back(st, i);
         }
     }

@@ -1,8 +1,9 @@
 """Launch-shape autotuner.
 
 The library exposes three knobs through fpm_set_tuning: how Verlet lists are
-built (particle by particle from global memory, or by column workgroups that
-stage the 3 x 3 neighbouring cell columns in LDS), how many z-cells a column
+built (particle by particle over whole neighbour cells or over candidate
+windows, or by column workgroups that stage the 3 x 3 neighbouring cell
+columns in LDS), how many z-cells a column
 workgroup takes, and how many list entries each lane of the force kernel keeps
 in flight.  None of them changes a result.  `tune()` times every candidate on
 the caller's own system (or batch) with the library's event timing and keeps
@@ -29,8 +30,8 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_1804_0759
                              "tuning.json")
 
 # (verlet_path, zblock, unroll); zblock 0 lets the library size the column blocks
-CANDIDATES = [(2, 0, 8), (2, 0, 4), (2, 2, 8), (2, 3, 8), (2, 4, 8), (2, 6, 8), (2, 8, 8),
-              (1, 0, 8), (1, 0, 4)]
+CANDIDATES = [(3, 0, 8), (3, 0, 4), (2, 0, 8), (2, 0, 4), (2, 3, 8), (2, 6, 8), (1, 0, 8),
+              (1, 0, 4)]
 
 
 def _device_key(device) -> str:

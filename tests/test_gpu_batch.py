@@ -49,20 +49,22 @@ def check_system(sim, k, s, F_all, out, counts, cols, sets=True):
     assert np.abs(out[k, 2:] - W64).max() <= ENERGY_TOL * scale, k
 
 
-def test_batch_matches_oracle_per_system():
+@pytest.mark.parametrize("tuning", [None, (2, 0, 8)])
+def test_batch_matches_oracle_per_system(tuning):
     idx = list(range(10)) + [72, 130]  # 72 and 130 have boxes of 2 cells per axis
     systems = systems_of(idx)
-    sim = make_batch(systems)
-    # both Verlet build paths occur: grids below 3 cells per axis and above
+    sim = make_batch(systems, tuning=tuning)
+    # two Verlet build paths occur: whole cells for grids below 3 cells per axis,
+    # candidate windows (default) or column workgroups (tuned) above
     zb = [sim.system_info(k)["zblock"] for k in range(len(idx))]
-    assert 0 in zb and any(z > 0 for z in zb)
+    assert 0 in zb and any((z < 0 if tuning is None else z > 0) for z in zb)
     off, order = (np_(t) for t in sim.cell_list())
     for k, s in enumerate(systems):
         info = sim.system_info(k)
         nc = O.cell_grid(s.box, RC, SKIN)
         assert (info["ncx"], info["ncy"], info["ncz"]) == tuple(nc)
         cid = O.cell_index(s.pos, s.box, nc)
-        _, offsets, order64 = O.cell_sort(cid, int(np.prod(nc)))
+        _, offsets, order64 = O.cell_sort(cid, int(np.prod(nc)), s.pos[:, 2])
         base = info["caller_base"]
         got_off = off[info["off_base"]:info["off_base"] + info["ncells"] + 1] - base
         assert np.array_equal(got_off, offsets), k
@@ -122,7 +124,8 @@ def test_full_batch_sampled_systems():
                            n=systems[k].n)
 
 
-@pytest.mark.parametrize("tuning", [(1, 0, 4), (1, 0, 8), (2, 1, 8), (2, 3, 4), (0, 0, 4)])
+@pytest.mark.parametrize("tuning", [(1, 0, 4), (1, 0, 8), (2, 1, 8), (2, 3, 4), (2, 0, 8),
+                                    (3, 0, 4)])
 def test_tuning_knobs_change_nothing_but_speed(tuning):
     systems = systems_of([0, 5, 9, 72, 200, 300])
     ref = make_batch(systems)

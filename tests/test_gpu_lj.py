@@ -62,7 +62,7 @@ def test_cell_list_bit_exact(n, rho, seed):
     nc = O.cell_grid(s.box, RC, SKIN)
     assert tuple(ncell) == tuple(nc)
     cid = O.cell_index(s.pos, s.box, nc)
-    counts, offsets, order64 = O.cell_sort(cid, int(np.prod(nc)))
+    counts, offsets, order64 = O.cell_sort(cid, int(np.prod(nc)), s.pos[:, 2])
     assert np.array_equal(np_(off), offsets)
     assert np.array_equal(np_(order), order64)
 
