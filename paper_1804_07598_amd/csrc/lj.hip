@@ -26,7 +26,10 @@ struct LJCoef {
     double inv_eps[3], inv_sig[3];
 };
 
-// 1/x in FP64: the hardware estimate refined by one Newton step.
+// 1/x in FP64: the hardware estimate (relative error up to 5e-8) refined by
+// one Newton step.  The step matters: without it the FP32 forces differ from
+// correctly rounded ones in many last bits, and trajectories then drift away
+// from their reference.
 __device__ __forceinline__ double recip(double x) {
     double y = __builtin_amdgcn_rcp(x);
     double e = fma(-x, y, 1.0);
@@ -45,9 +48,13 @@ __device__ __forceinline__ bool separation(float3 pi, double xi, double yi, doub
     dz = zi - (double)q.z;
     sx = sy = sz = 0.0;
     if (IMG) {
-        sx = -(double)img_shift(pi.x, q.x, b.half[0], b.per[0]) * (double)b.L[0];
-        sy = -(double)img_shift(pi.y, q.y, b.half[1], b.per[1]) * (double)b.L[1];
-        sz = -(double)img_shift(pi.z, q.z, b.half[2], b.per[2]) * (double)b.L[2];
+        // the image as chosen by the predicate, with selects rather than branches
+        const float tx = q.x - pi.x, ty = q.y - pi.y, tz = q.z - pi.z;
+        const double Lx = b.per[0] ? (double)b.L[0] : 0.0, Ly = b.per[1] ? (double)b.L[1] : 0.0,
+                     Lz = b.per[2] ? (double)b.L[2] : 0.0;
+        sx = tx > b.half[0] ? Lx : (tx < -b.half[0] ? -Lx : 0.0);
+        sy = ty > b.half[1] ? Ly : (ty < -b.half[1] ? -Ly : 0.0);
+        sz = tz > b.half[2] ? Lz : (tz < -b.half[2] ? -Lz : 0.0);
         dx += sx;
         dy += sy;
         dz += sz;
