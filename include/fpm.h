@@ -232,11 +232,15 @@ int fpm_read_counters(fpm_ctx *ctx, int64_t h_out[3]);
 
 /* Launch shapes (0 = automatic).  verlet_path: 1 builds Verlet lists particle
  * by particle over whole neighbour cells, 2 by column blocks staged in LDS,
- * 3 particle by particle over candidate windows (2 and 3 where the grid has
- * >= 3 cells per axis; automatic takes 3 there).  zblock: z-cells per column workgroup
- * (1..64).  unroll: list entries in flight per lane in the force kernel (4 or
- * 8).  Results do not depend on them.  Changing verlet_path or zblock drops
- * the particles (call fpm_set_particles again). */
+ * 3 particle by particle over candidate windows, 4 over the same windows with
+ * a group of lanes per particle and each 64-slot row of lists staged in LDS
+ * (2, 3 and 4 where the grid has >= 3 cells per axis, 4 also needs
+ * max_nbr <= 240; elsewhere path 1 is taken; automatic takes 3).  zblock:
+ * z-cells per column workgroup (1..64); for path 4, lanes per particle (0 =
+ * 8, 4, 8 or 16; other values are FPM_EINVAL).  unroll: list entries in
+ * flight per lane in the force kernel (4 or 8).  Results do not depend on
+ * them.  Changing verlet_path or zblock drops the particles (call
+ * fpm_set_particles again). */
 int fpm_set_tuning(fpm_ctx *ctx, int32_t verlet_path, int32_t zblock, int32_t unroll);
 
 /* With on = 1, every launch made outside a graph of the kernels named

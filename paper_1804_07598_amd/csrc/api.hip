@@ -38,7 +38,7 @@ int cap4_for(int cap) { return (cap + 7) / 8 * 2; }
 struct Plan {
     std::vector<SysHost> sys;
     std::vector<SysDesc> desc;
-    std::vector<int32_t> blk2sys, item2sys, pa_blocks;
+    std::vector<int32_t> blk2sys, item2sys, pa_blocks, grp_blocks;
     int64_t n_slots = 0;
     int nblk = 0, ncells_total = 0, noff_total = 0, nitems = 0, max_ncells = 0;
     int max_sys_blocks = 0;
@@ -73,10 +73,13 @@ Plan make_plan(const fpm_ctx *c, const std::vector<int64_t> &cnt) {
         d.cell_base = cell;
         d.off_base = offb;
         // Verlet build: zb > 0 column workgroups, 0 particle by particle over
-        // whole cells, -1 particle by particle over candidate windows
+        // whole cells, -1 particle by particle over candidate windows, -2 lane
+        // groups over candidate windows (rows of lists staged in LDS)
         const bool big = d.box.nc[0] >= 3 && d.box.nc[1] >= 3 && d.box.nc[2] >= 3;
         if (c->tune_verlet_path == 1)
             d.zb = 0;
+        else if (c->tune_verlet_path == 4)
+            d.zb = big ? (verlet_group_fits(c->cap4) ? -2 : -1) : 0;
         else if (c->tune_verlet_path == 3 || (c->tune_verlet_path == 0 && big))
             d.zb = big ? -1 : 0;
         else
@@ -89,7 +92,8 @@ Plan make_plan(const fpm_ctx *c, const std::vector<int64_t> &cnt) {
         h.nitems = d.zb > 0 ? d.box.nc[0] * d.box.nc[1] * d.nzb : 0;
         for (int b = 0; b < h.nblk; b++) {
             P.blk2sys.push_back(s);
-            if (d.zb <= 0) P.pa_blocks.push_back(blk + b);
+            if (d.zb == 0 || d.zb == -1) P.pa_blocks.push_back(blk + b);
+            if (d.zb == -2) P.grp_blocks.push_back(blk + b);
         }
         for (int q = 0; q < h.nitems; q++) P.item2sys.push_back(s);
         slot += d.n_pad;
@@ -142,7 +146,7 @@ size_t layout(const fpm_ctx *c, const Plan &P, char *base, State *st,
     s.sys = (const SysDesc *)take(nsys * sizeof(SysDesc));
     s.blk2sys = (const int32_t *)take(P.blk2sys.size() * sizeof(int32_t));
     s.item2sys = (const int32_t *)take((P.item2sys.size() + 1) * sizeof(int32_t));
-    char *pa = take((P.pa_blocks.size() + 1) * sizeof(int32_t));
+    char *pa = take((P.pa_blocks.size() + P.grp_blocks.size() + 1) * sizeof(int32_t));
     s.nsys = nsys;
     s.pstride = P.nblk;
     if (st) *st = s;
@@ -373,8 +377,10 @@ int fpm_set_neighbor_params(fpm_ctx *c, float r_cut, float skin, int32_t max_nbr
 
 int fpm_set_tuning(fpm_ctx *c, int32_t verlet_path, int32_t zblock, int32_t unroll) {
     if (!c) return FPM_EINVAL;
-    if (verlet_path < 0 || verlet_path > 3) return fail(c, FPM_EINVAL, "verlet_path is 0..3");
+    if (verlet_path < 0 || verlet_path > 4) return fail(c, FPM_EINVAL, "verlet_path is 0..4");
     if (zblock < 0 || zblock > 64) return fail(c, FPM_EINVAL, "zblock out of range");
+    if (verlet_path == 4 && zblock != 0 && zblock != 4 && zblock != 8 && zblock != 16)
+        return fail(c, FPM_EINVAL, "lanes per particle (zblock of path 4) is 0, 4, 8 or 16");
     if (unroll != 0 && unroll != 4 && unroll != 8) return fail(c, FPM_EINVAL, "unroll is 0, 4 or 8");
     if (verlet_path != c->tune_verlet_path || zblock != c->tune_zb) c->have_particles = false;
     c->tune_verlet_path = verlet_path;
@@ -430,6 +436,7 @@ int fpm_set_particles(fpm_ctx *c, int64_t n, const float *pos, const float *vel,
     c->noff_total = P.noff_total;
     c->nitems = P.nitems;
     c->n_pa_blocks = (int)P.pa_blocks.size();
+    c->n_grp_blocks = (int)P.grp_blocks.size();
     c->max_ncells = P.max_ncells;
     c->max_sys_blocks = P.max_sys_blocks;
     // the tables are small; the copies finish before the host vectors go away
@@ -444,6 +451,10 @@ int fpm_set_particles(fpm_ctx *c, int64_t n, const float *pos, const float *vel,
     if (!P.pa_blocks.empty())
         HIPCHK(c, hipMemcpyAsync(c->pa_blocks, P.pa_blocks.data(),
                                  P.pa_blocks.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                 c->stream));
+    if (!P.grp_blocks.empty())  // after the particle-by-particle blocks
+        HIPCHK(c, hipMemcpyAsync(c->pa_blocks + P.pa_blocks.size(), P.grp_blocks.data(),
+                                 P.grp_blocks.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                                  c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, launch_fill_i32(c->stream, c->st.cnt, c->ncells_total, 0));

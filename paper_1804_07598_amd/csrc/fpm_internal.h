@@ -167,12 +167,13 @@ struct fpm_ctx {
     int noff_total = 0;
     int nitems = 0;          // column-build work items
     int n_pa_blocks = 0;     // workgroups of systems built particle by particle
-    int32_t *pa_blocks = nullptr;  // device list of those workgroups
+    int n_grp_blocks = 0;    // workgroups of systems built by lane groups
+    int32_t *pa_blocks = nullptr;  // device list of those workgroups, then of these
     int max_ncells = 0;
     int max_sys_blocks = 0;  // particle workgroups of the largest system
     // tuning (fpm_set_tuning); 0 = automatic
-    int tune_verlet_path = 0;   // 1: particle by particle, 2: column blocks
-    int tune_zb = 0;            // z-cells per column workgroup
+    int tune_verlet_path = 0;   // 1: whole cells, 2: column blocks, 3: windows, 4: lane groups
+    int tune_zb = 0;            // z-cells per column workgroup (path 4: lanes per particle)
     int tune_unroll = 0;        // force kernel: entries in flight per lane (4 or 8)
     // graphs of fpm_step, keyed by their parameters
     hipGraphExec_t g_first = nullptr, g_chunk = nullptr, g_one = nullptr;
@@ -206,6 +207,8 @@ hipError_t launch_list_stats(fpm_ctx *c);  // fills ctl->max_count and ctl->tota
 // z-cells per workgroup of the column Verlet build for one system, 0 when the
 // grid is too small for it (fewer than three cells along an axis).
 int verlet_zblock(int64_t n, int64_t ncells, const int nc[3], int tune_zb);
+// True when a 64-slot row of lists of cap4 groups fits the LDS of the lane-group build.
+bool verlet_group_fits(int cap4);
 hipError_t launch_lj_forces(fpm_ctx *c, const fpm_lj_params &p);
 // Output of the force VJP kernel.  kVjpPlain: gx = g.  kVjpLast: gx += g.
 // kVjpStep: one reverse velocity-Verlet step on caller-order FP64 arrays:

@@ -22,6 +22,7 @@ namespace {
 constexpr int kColThreads = 128;  // threads of a column workgroup
 constexpr int kLdsAtoms = 2048;   // staged positions per column workgroup (32 KiB)
 constexpr int kMaxZb = 32;        // z-cells per workgroup, at most
+constexpr size_t kGroupLds = 61440;  // LDS for one row of lists in the lane-group build
 
 // Neighbour cell coordinates of c along one axis, ascending, without repeats
 // (grids of one or two cells) and without crossing a closed face.
@@ -339,6 +340,198 @@ __device__ __forceinline__ void copy_back(const State &st, int64_t s) {
     st.id[0][s] = st.id[1][s];
 }
 
+// ---------------------------------------------------------------------------
+// Cooperative build: G lanes per particle.  A workgroup of 64 G threads owns
+// one 64-slot row of the list layout.  A particle's G lanes walk each
+// candidate run 32 consecutive candidates at a time (32 / G loads per lane in
+// flight, coalesced, no divergence inside the run), hits are compacted with
+// ballots and written to the row's lists in LDS, in list layout, and the
+// whole row is stored with contiguous 16-byte writes at the end.  The run
+// bounds of all nine columns are fetched at once, spread over the group's
+// lanes and broadcast by shuffles.  Runs, windows and image shifts are those
+// of verlet_atom_window, so the lists are identical entry for entry.
+
+// The G-lane group of this thread inside its wavefront: bit offset of the
+// group in the ballot mask and this lane's index in the group.
+template <int G>
+struct Group {
+    int base, l;
+    __device__ __forceinline__ Group() {
+        const int lane = (int)(threadIdx.x & 63);
+        base = lane & ~(G - 1);
+        l = lane & (G - 1);
+    }
+    // this group's bits of a wavefront ballot
+    __device__ __forceinline__ uint32_t bits(uint64_t m) const {
+        return (uint32_t)(m >> base) & (uint32_t)((1ull << G) - 1);
+    }
+};
+
+// LDS row of lists: entry k of row position p, as in the global list layout.
+__device__ __forceinline__ int row_entry(int p, int k) { return ((k >> 2) * 64 + p) * 4 + (k & 3); }
+
+// One z-run [beg, end), shifts as in scan_window; hits are appended at
+// row[p][cnt..] (only below the capacity).  Returns true when some hit was
+// found.  The scan stops after the first batch reaching above zhi; every
+// candidate tested is decided by the predicate alone.
+template <int G>
+__device__ __forceinline__ bool scan_run_group(const Group<G> &gr, const float4 *__restrict__ pos,
+                                               int beg, int end, float3 a, float3 pk, float zhi,
+                                               int i, float R2, int *row, int p, int cap, int &cnt) {
+#pragma clang fp contract(off)
+    constexpr int U = 32 / G;  // loads in flight per lane
+    bool any = false;
+    for (int c = beg; c < end; c += U * G) {
+        float4 q[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) q[u] = pos[min(c + u * G + gr.l, end - 1)];
+        bool past = false;
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int j = c + u * G + gr.l;
+            const float qz = q[u].z - a.z;
+            past |= qz > zhi;
+            const float dx = (q[u].x - a.x) - pk.x, dy = (q[u].y - a.y) - pk.y, dz = qz - pk.z;
+            const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
+            const float sxy = xx + yy;
+            const bool hit = j < end && sxy + zz <= R2 && j != i;
+            const uint32_t hm = gr.bits(__ballot(hit));
+            if (hit) {
+                const int k = cnt + __popc(hm & ((1u << gr.l) - 1));
+                if (k < cap) row[row_entry(p, k)] = j;
+            }
+            cnt += __popc(hm);
+            any |= hm != 0;
+        }
+        if (gr.bits(__ballot(past))) break;
+    }
+    return any;
+}
+
+template <int G>
+__global__ __launch_bounds__(64 * G) void k_verlet_grp(State st, const int32_t *blocks, float R2,
+                                                      int cap, int cap4) {
+    constexpr int NC = (9 + G - 1) / G;  // neighbour columns held per lane
+    extern __shared__ int4 lrow[];       // cap4 * 64 int4: the row's lists
+    __shared__ int rowc8[64];            // padded list lengths of the row
+    const int r = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int blk = blocks[r >> 2];
+    const int s = st.blk2sys[blk];
+    if (!st.sctl[s].rebuild) return;
+    const SysDesc &d = st.sys[s];
+    const Box &b = d.box;
+    const Group<G> gr;
+    const int p = (int)threadIdx.x / G;
+    const int64_t row0 = (int64_t)blk * kBlock + (r & 3) * 64;
+    const int64_t i = row0 + p;
+    int *row = reinterpret_cast<int *>(lrow);
+    const float4 *__restrict__ pos = st.pos[1];
+    const int32_t *__restrict__ off = st.off + d.off_base;
+    int cnt = 0;
+    bool img = false;
+    if (i - d.slot_base < d.n) {
+        const float3 pi = xyz(pos[i]);
+        const int nx = b.nc[0], ny = b.nc[1], nz = b.nc[2];
+        const int ix = cell_coord(pi.x, b.inv[0], nx);
+        const int iy = cell_coord(pi.y, b.inv[1], ny);
+        const int iz = cell_coord(pi.z, b.inv[2], nz);
+        // z-runs: cells iz-1 .. iz+1 as at most two contiguous pieces
+        // (first and last cell, shift of the candidates, particle's own z)
+        int zc0[2], zc1[2];
+        float azs[2], pks[2];
+        int nseg = 1;
+        azs[0] = azs[1] = 0.f, pks[0] = pks[1] = pi.z;
+        zc0[1] = zc1[1] = 0;
+        if (iz == 0 && b.per[2]) {  // cell nz-1 one period down, then cells 0, 1
+            zc0[0] = zc1[0] = nz - 1, azs[0] = b.L[2];
+            zc0[1] = 0, zc1[1] = 1, nseg = 2;
+        } else if (iz == 0) {
+            zc0[0] = 0, zc1[0] = 1;
+        } else if (iz == nz - 1) {  // cells nz-2, nz-1, then cell 0 with i moved down
+            zc0[0] = nz - 2, zc1[0] = nz - 1;
+            if (b.per[2]) zc0[1] = zc1[1] = 0, pks[1] = pi.z - b.L[2], nseg = 2;
+        } else {
+            zc0[0] = iz - 1, zc1[0] = iz + 1;
+        }
+        // run bounds: this lane fetches those of columns l, l + G, ...
+        int rb[NC][2], re[NC][2];
+#pragma unroll
+        for (int m = 0; m < NC; m++) {
+            const int k = gr.l + m * G;
+            int cx = ix + k / 3 - 1, cy = iy + k % 3 - 1;
+            const bool ok = k < 9 && (b.per[0] || (cx >= 0 && cx < nx)) &&
+                            (b.per[1] || (cy >= 0 && cy < ny));
+            cx = cx < 0 ? cx + nx : (cx >= nx ? cx - nx : cx);
+            cy = cy < 0 ? cy + ny : (cy >= ny ? cy - ny : cy);
+            const int col = ok ? (cx * ny + cy) * nz : 0;
+#pragma unroll
+            for (int g = 0; g < 2; g++) {
+                const bool okg = ok && g < nseg;
+                const int e0 = off[okg ? col + zc0[g] : 0], e1 = off[okg ? col + zc1[g] + 1 : 0];
+                rb[m][g] = okg ? e0 : 0;
+                re[m][g] = okg ? e1 : 0;
+            }
+        }
+        const float marg = 1e-5f * fmaxf(b.L[0], fmaxf(b.L[1], b.L[2]));
+        const float dxl = fmaxf(pi.x - (float)ix / b.inv[0] - marg, 0.f);
+        const float dxh = fmaxf((float)(ix + 1) / b.inv[0] - pi.x - marg, 0.f);
+        const float dyl = fmaxf(pi.y - (float)iy / b.inv[1] - marg, 0.f);
+        const float dyh = fmaxf((float)(iy + 1) / b.inv[1] - pi.y - marg, 0.f);
+        const float Rw2 = R2 * 1.0001f;
+        for (int k = 0; k < 9; k++) {
+            const int ox = k / 3 - 1, oy = k % 3 - 1;
+            const int cx = ix + ox, cy = iy + oy;
+            const float ax = cx < 0 ? b.L[0] : 0.f, px = cx >= nx ? pi.x - b.L[0] : pi.x;
+            const float ay = cy < 0 ? b.L[1] : 0.f, py = cy >= ny ? pi.y - b.L[1] : pi.y;
+            const float ddx = ox < 0 ? dxl : (ox > 0 ? dxh : 0.f);
+            const float ddy = oy < 0 ? dyl : (oy > 0 ? dyh : 0.f);
+            const float h2 = Rw2 - ddx * ddx - ddy * ddy;
+            // bounds of column k from lane k % G of the group (empty runs where
+            // the column lies across a closed face)
+            int kb[2], ke[2];
+#pragma unroll
+            for (int g = 0; g < 2; g++) {
+                int vb = rb[0][g], ve = re[0][g];
+#pragma unroll
+                for (int m = 1; m < NC; m++) {
+                    vb = k / G == m ? rb[m][g] : vb;
+                    ve = k / G == m ? re[m][g] : ve;
+                }
+                kb[g] = __shfl(vb, k % G, G);
+                ke[g] = __shfl(ve, k % G, G);
+            }
+            if (h2 < 0.f) continue;
+            const float hz = sqrtf(h2);
+#pragma unroll
+            for (int g = 0; g < 2; g++) {
+                if (kb[g] >= ke[g]) continue;
+                const float3 a = make_float3(ax, ay, azs[g]);
+                const float3 pk = make_float3(px, py, pks[g]);
+                const bool hit = scan_run_group<G>(gr, pos, kb[g], ke[g], a, pk, pk.z + hz,
+                                                   (int)i, R2, row, p, cap, cnt);
+                img |= hit && (ax != 0.f || px != pi.x || ay != 0.f || py != pi.y ||
+                               azs[g] != 0.f || pks[g] != pi.z);
+            }
+        }
+        const int c = min(cnt, cap);
+        const int c8 = (c + 7) & ~7;
+        for (int k = c + gr.l; k < c8; k += G) row[row_entry(p, k)] = d.dummy;
+        if (gr.l == 0) {
+            st.nnb[i] = (uint32_t)c | (img ? kWrapBit : 0u);
+            note_overflow(st, cnt, cap);
+        }
+        rowc8[p] = c8;
+    } else {
+        rowc8[p] = 0;
+    }
+    if (gr.l == 0) copy_back(st, i);
+    __syncthreads();
+    // the row's lists, in list layout, written group by group over the row
+    int4 *dst = reinterpret_cast<int4 *>(st.nbr) + (row0 >> 6) * (int64_t)cap4 * 64;
+    for (int t = (int)threadIdx.x; t < cap4 * 64; t += 64 * G)
+        if ((t >> 6) * 4 < rowc8[t & 63]) dst[t] = lrow[t];
+}
+
 // One thread per particle, candidates read from global memory.  The grid
 // runs over the list of particle workgroups of the systems built this way.
 __global__ __launch_bounds__(kBlock) void k_verlet(State st, const int32_t *blocks, float R2,
@@ -606,8 +799,29 @@ hipError_t launch_verlet_build(fpm_ctx *c) {
     if (c->n_pa_blocks > 0)
         hipLaunchKernelGGL(k_verlet, dim3(c->n_pa_blocks), dim3(kBlock), 0, c->stream, c->st,
                            c->pa_blocks, c->R2, c->cap, c->cap4);
+    if (c->n_grp_blocks > 0) {
+        // four 64-slot rows per particle workgroup
+        const dim3 grid(4 * c->n_grp_blocks);
+        const size_t lds = (size_t)c->cap4 * 64 * sizeof(int4);
+        const int32_t *blocks = c->pa_blocks + c->n_pa_blocks;
+        switch (c->tune_zb) {
+        case 4:
+            hipLaunchKernelGGL(k_verlet_grp<4>, grid, dim3(256), lds, c->stream, c->st, blocks,
+                               c->R2, c->cap, c->cap4);
+            break;
+        case 16:
+            hipLaunchKernelGGL(k_verlet_grp<16>, grid, dim3(1024), lds, c->stream, c->st, blocks,
+                               c->R2, c->cap, c->cap4);
+            break;
+        default:
+            hipLaunchKernelGGL(k_verlet_grp<8>, grid, dim3(512), lds, c->stream, c->st, blocks,
+                               c->R2, c->cap, c->cap4);
+        }
+    }
     return hipGetLastError();
 }
+
+bool verlet_group_fits(int cap4) { return (size_t)cap4 * 64 * sizeof(int4) <= kGroupLds; }
 
 hipError_t launch_list_stats(fpm_ctx *c) {
     hipLaunchKernelGGL(k_zero_stats, dim3(1), dim3(64), 0, c->stream, c->st.ctl);

@@ -2,10 +2,10 @@
 
 The library exposes three knobs through fpm_set_tuning: how Verlet lists are
 built (particle by particle over whole neighbour cells or over candidate
-windows, or by column workgroups that stage the 3 x 3 neighbouring cell
-columns in LDS), how many z-cells a column
-workgroup takes, and how many list entries each lane of the force kernel keeps
-in flight.  None of them changes a result.  `tune()` times every candidate on
+windows, by column workgroups that stage the 3 x 3 neighbouring cell columns
+in LDS, or by lane groups that stage rows of lists in LDS), how many z-cells a
+column workgroup takes (lanes per particle for lane groups), and how many list
+entries each lane of the force kernel keeps in flight.  None of them changes a result.  `tune()` times every candidate on
 the caller's own system (or batch) with the library's event timing and keeps
 the one with the smallest cost per step,
 
@@ -29,9 +29,10 @@ from . import _lib as F
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_1804_07598_amd",
                              "tuning.json")
 
-# (verlet_path, zblock, unroll); zblock 0 lets the library size the column blocks
-CANDIDATES = [(3, 0, 8), (3, 0, 4), (2, 0, 8), (2, 0, 4), (2, 3, 8), (2, 6, 8), (1, 0, 8),
-              (1, 0, 4)]
+# (verlet_path, zblock, unroll); zblock 0 lets the library size the column blocks,
+# for path 4 it is the number of lanes per particle
+CANDIDATES = [(4, 8, 8), (4, 8, 4), (3, 0, 8), (3, 0, 4), (2, 0, 8), (2, 0, 4), (2, 6, 8),
+              (1, 0, 8)]
 
 
 def _device_key(device) -> str:

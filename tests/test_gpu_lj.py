@@ -202,17 +202,18 @@ def test_particles_on_faces_and_empty_cells():
     compare_sets(sim, s.pos, s.box, O.radius2(RC, SKIN))
 
 
-def test_overflow_is_reported():
+@pytest.mark.parametrize("tuning", [None, (4, 8, 8)])
+def test_overflow_is_reported(tuning):
     from paper_1804_07598_amd._lib import FpmError, FPM_EOVERFLOW
     s = inputs.lj_lattice(1000, 0.8442, 1.0, seed=7)
-    sim = make_sim(s, max_nbr=8)
+    sim = make_sim(s, max_nbr=8, tuning=tuning)
     with pytest.raises(FpmError) as e:
         sim.check()
     assert e.value.code == FPM_EOVERFLOW
     with pytest.raises(FpmError):
         sim.neighbors()
     # a larger capacity gives the exact sets again
-    sim2 = make_sim(s, max_nbr=160)
+    sim2 = make_sim(s, max_nbr=160, tuning=tuning)
     compare_sets(sim2, s.pos, s.box, O.radius2(RC, SKIN))
 
 
