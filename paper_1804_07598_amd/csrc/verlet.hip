@@ -370,14 +370,18 @@ struct Group {
 // LDS row of lists: entry k of row position p, as in the global list layout.
 __device__ __forceinline__ int row_entry(int p, int k) { return ((k >> 2) * 64 + p) * 4 + (k & 3); }
 
-// One z-run [beg, end), shifts as in scan_window; hits are appended at
-// row[p][cnt..] (only below the capacity).  Returns true when some hit was
-// found.  The scan stops after the first batch reaching above zhi; every
-// candidate tested is decided by the predicate alone.
-template <int G>
+// One z-run [beg, end), shifts as in scan_window (SH: some shift is nonzero;
+// without, the subtractions of zero are left out, which rounds identically);
+// hits are appended at row[p][cnt..], those beyond the capacity go to the
+// spare word row[trash].  Returns true when some hit was found.  The scan
+// stops after the first batch reaching above zhi; every candidate tested is
+// decided by the predicate alone.  The hit test has no short-circuit, so no
+// branch splits a batch and all of its loads stay in flight together.
+template <int G, bool SH>
 __device__ __forceinline__ bool scan_run_group(const Group<G> &gr, const float4 *__restrict__ pos,
                                                int beg, int end, float3 a, float3 pk, float zhi,
-                                               int i, float R2, int *row, int p, int cap, int &cnt) {
+                                               int i, float R2, int *row, int p, int cap,
+                                               int trash, int &cnt) {
 #pragma clang fp contract(off)
     constexpr int U = 32 / G;  // loads in flight per lane
     bool any = false;
@@ -389,17 +393,17 @@ __device__ __forceinline__ bool scan_run_group(const Group<G> &gr, const float4 
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const int j = c + u * G + gr.l;
-            const float qz = q[u].z - a.z;
+            const float qx = SH ? q[u].x - a.x : q[u].x;
+            const float qy = SH ? q[u].y - a.y : q[u].y;
+            const float qz = SH ? q[u].z - a.z : q[u].z;
             past |= qz > zhi;
-            const float dx = (q[u].x - a.x) - pk.x, dy = (q[u].y - a.y) - pk.y, dz = qz - pk.z;
+            const float dx = qx - pk.x, dy = qy - pk.y, dz = qz - pk.z;
             const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
             const float sxy = xx + yy;
-            const bool hit = j < end && sxy + zz <= R2 && j != i;
+            const bool hit = (j < end) & (sxy + zz <= R2) & (j != i);
             const uint32_t hm = gr.bits(__ballot(hit));
-            if (hit) {
-                const int k = cnt + __popc(hm & ((1u << gr.l) - 1));
-                if (k < cap) row[row_entry(p, k)] = j;
-            }
+            const int k = cnt + __popc(hm & ((1u << gr.l) - 1));
+            if (hit) row[k < cap ? row_entry(p, k) : trash] = j;
             cnt += __popc(hm);
             any |= hm != 0;
         }
@@ -412,7 +416,7 @@ template <int G>
 __global__ __launch_bounds__(64 * G) void k_verlet_grp(State st, const int32_t *blocks, float R2,
                                                       int cap, int cap4) {
     constexpr int NC = (9 + G - 1) / G;  // neighbour columns held per lane
-    extern __shared__ int4 lrow[];       // cap4 * 64 int4: the row's lists
+    extern __shared__ int4 lrow[];       // cap4 * 64 int4: the row's lists, then 64 spare words
     __shared__ int rowc8[64];            // padded list lengths of the row
     const int r = xcd_block((int)blockIdx.x, (int)gridDim.x);
     const int blk = blocks[r >> 2];
@@ -425,6 +429,7 @@ __global__ __launch_bounds__(64 * G) void k_verlet_grp(State st, const int32_t *
     const int64_t row0 = (int64_t)blk * kBlock + (r & 3) * 64;
     const int64_t i = row0 + p;
     int *row = reinterpret_cast<int *>(lrow);
+    const int trash = cap4 * 256 + p;    // where entries beyond the capacity go
     const float4 *__restrict__ pos = st.pos[1];
     const int32_t *__restrict__ off = st.off + d.off_base;
     int cnt = 0;
@@ -507,10 +512,14 @@ __global__ __launch_bounds__(64 * G) void k_verlet_grp(State st, const int32_t *
                 if (kb[g] >= ke[g]) continue;
                 const float3 a = make_float3(ax, ay, azs[g]);
                 const float3 pk = make_float3(px, py, pks[g]);
-                const bool hit = scan_run_group<G>(gr, pos, kb[g], ke[g], a, pk, pk.z + hz,
-                                                   (int)i, R2, row, p, cap, cnt);
-                img |= hit && (ax != 0.f || px != pi.x || ay != 0.f || py != pi.y ||
-                               azs[g] != 0.f || pks[g] != pi.z);
+                const bool sh = ax != 0.f || px != pi.x || ay != 0.f || py != pi.y ||
+                                azs[g] != 0.f || pks[g] != pi.z;
+                const bool hit =
+                    sh ? scan_run_group<G, true>(gr, pos, kb[g], ke[g], a, pk, pk.z + hz, (int)i,
+                                                 R2, row, p, cap, trash, cnt)
+                       : scan_run_group<G, false>(gr, pos, kb[g], ke[g], a, pk, pk.z + hz, (int)i,
+                                                  R2, row, p, cap, trash, cnt);
+                img |= hit && sh;
             }
         }
         const int c = min(cnt, cap);
@@ -802,7 +811,7 @@ hipError_t launch_verlet_build(fpm_ctx *c) {
     if (c->n_grp_blocks > 0) {
         // four 64-slot rows per particle workgroup
         const dim3 grid(4 * c->n_grp_blocks);
-        const size_t lds = (size_t)c->cap4 * 64 * sizeof(int4);
+        const size_t lds = (size_t)c->cap4 * 64 * sizeof(int4) + 64 * sizeof(int);
         const int32_t *blocks = c->pa_blocks + c->n_pa_blocks;
         switch (c->tune_zb) {
         case 4:
@@ -821,7 +830,9 @@ hipError_t launch_verlet_build(fpm_ctx *c) {
     return hipGetLastError();
 }
 
-bool verlet_group_fits(int cap4) { return (size_t)cap4 * 64 * sizeof(int4) <= kGroupLds; }
+bool verlet_group_fits(int cap4) {
+    return (size_t)cap4 * 64 * sizeof(int4) + 64 * sizeof(int) <= kGroupLds;
+}
 
 hipError_t launch_list_stats(fpm_ctx *c) {
     hipLaunchKernelGGL(k_zero_stats, dim3(1), dim3(64), 0, c->stream, c->st.ctl);
