@@ -132,8 +132,10 @@ int fpm_set_particles(fpm_ctx *ctx, int64_t n, const float *d_pos, const float *
  * next use when some particle moved more than skin/2 since the last build. */
 int fpm_set_positions(fpm_ctx *ctx, const float *d_pos);
 /* Host-side layout of system s: h_out = {n, first caller index, cells,
- * first entry of that system's cell offsets, cells along x, y, z, z-cells per
- * workgroup of the column Verlet build (0 = particle-by-particle build)}. */
+ * first entry of that system's cell offsets, cells along x, y, z, Verlet
+ * build of the system: z-cells per workgroup of the column build (> 0), or
+ * 0 particle by particle over whole cells, -1 particle by particle over
+ * candidate windows, -2 lane groups over candidate windows}. */
 int fpm_system_info(fpm_ctx *ctx, int32_t s, int64_t h_out[8]);
 /* SPH only: per-particle density (device, caller order, n entries). */
 int fpm_set_density(fpm_ctx *ctx, const float *d_rho);
@@ -234,10 +236,10 @@ int fpm_read_counters(fpm_ctx *ctx, int64_t h_out[3]);
  * by particle over whole neighbour cells, 2 by column blocks staged in LDS,
  * 3 particle by particle over candidate windows, 4 over the same windows with
  * a group of lanes per particle and each 64-slot row of lists staged in LDS
- * (2, 3 and 4 where the grid has >= 3 cells per axis, 4 also needs
- * max_nbr <= 240; elsewhere path 1 is taken; automatic takes 3).  zblock:
- * z-cells per column workgroup (1..64); for path 4, lanes per particle (0 =
- * 8, 4, 8 or 16; other values are FPM_EINVAL).  unroll: list entries in
+ * (2, 3 and 4 where the grid has >= 3 cells per axis, elsewhere path 1 is
+ * taken; automatic takes 4).  zblock: z-cells per column workgroup (1..64);
+ * for path 4, lanes per particle (0 = 8, 4, 8 or 16; other values are
+ * FPM_EINVAL).  unroll: list entries in
  * flight per lane in the force kernel (4 or 8).  Results do not depend on
  * them.  Changing verlet_path or zblock drops the particles (call
  * fpm_set_particles again). */

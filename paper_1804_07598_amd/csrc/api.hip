@@ -78,9 +78,9 @@ Plan make_plan(const fpm_ctx *c, const std::vector<int64_t> &cnt) {
         const bool big = d.box.nc[0] >= 3 && d.box.nc[1] >= 3 && d.box.nc[2] >= 3;
         if (c->tune_verlet_path == 1)
             d.zb = 0;
-        else if (c->tune_verlet_path == 4)
-            d.zb = big ? (verlet_group_fits(c->cap4) ? -2 : -1) : 0;
-        else if (c->tune_verlet_path == 3 || (c->tune_verlet_path == 0 && big))
+        else if (c->tune_verlet_path == 4 || c->tune_verlet_path == 0)
+            d.zb = big ? -2 : 0;
+        else if (c->tune_verlet_path == 3)
             d.zb = big ? -1 : 0;
         else
             d.zb = verlet_zblock(cnt[s], d.ncells, d.box.nc, c->tune_zb);

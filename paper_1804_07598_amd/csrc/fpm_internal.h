@@ -207,8 +207,6 @@ hipError_t launch_list_stats(fpm_ctx *c);  // fills ctl->max_count and ctl->tota
 // z-cells per workgroup of the column Verlet build for one system, 0 when the
 // grid is too small for it (fewer than three cells along an axis).
 int verlet_zblock(int64_t n, int64_t ncells, const int nc[3], int tune_zb);
-// True when a 64-slot row of lists of cap4 groups fits the LDS of the lane-group build.
-bool verlet_group_fits(int cap4);
 hipError_t launch_lj_forces(fpm_ctx *c, const fpm_lj_params &p);
 // Output of the force VJP kernel.  kVjpPlain: gx = g.  kVjpLast: gx += g.
 // kVjpStep: one reverse velocity-Verlet step on caller-order FP64 arrays:

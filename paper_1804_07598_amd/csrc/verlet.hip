@@ -22,7 +22,7 @@ namespace {
 constexpr int kColThreads = 128;  // threads of a column workgroup
 constexpr int kLdsAtoms = 2048;   // staged positions per column workgroup (32 KiB)
 constexpr int kMaxZb = 32;        // z-cells per workgroup, at most
-constexpr size_t kGroupLds = 61440;  // LDS for one row of lists in the lane-group build
+constexpr int kRowGroups = 32;    // groups of four entries per slot kept in LDS by the lane-group build
 
 // Neighbour cell coordinates of c along one axis, ascending, without repeats
 // (grids of one or two cells) and without crossing a closed face.
@@ -372,23 +372,27 @@ __device__ __forceinline__ int row_entry(int p, int k) { return ((k >> 2) * 64 +
 
 // One z-run [beg, end), shifts as in scan_window (SH: some shift is nonzero;
 // without, the subtractions of zero are left out, which rounds identically);
-// hits are appended at row[p][cnt..], those beyond the capacity go to the
-// spare word row[trash].  Returns true when some hit was found.  The scan
+// hits are appended at row[p][cnt..] for entries below lcap and straight to
+// the slot's list in global memory (gl, list layout) from there up to the
+// capacity.  Returns true when some hit was found.  The scan
 // stops after the first batch reaching above zhi; every candidate tested is
 // decided by the predicate alone.  The hit test has no short-circuit, so no
 // branch splits a batch and all of its loads stay in flight together.
 template <int G, bool SH>
 __device__ __forceinline__ bool scan_run_group(const Group<G> &gr, const float4 *__restrict__ pos,
                                                int beg, int end, float3 a, float3 pk, float zhi,
-                                               int i, float R2, int *row, int p, int cap,
-                                               int trash, int &cnt) {
+                                               int i, float R2, int *row, int p, int lcap,
+                                               int *gl, int cap, int &cnt) {
 #pragma clang fp contract(off)
     constexpr int U = 32 / G;  // loads in flight per lane
+    const char *base = reinterpret_cast<const char *>(pos);  // slots < 2^26: 32-bit offsets
     bool any = false;
     for (int c = beg; c < end; c += U * G) {
         float4 q[U];
 #pragma unroll
-        for (int u = 0; u < U; u++) q[u] = pos[min(c + u * G + gr.l, end - 1)];
+        for (int u = 0; u < U; u++)
+            q[u] = *reinterpret_cast<const float4 *>(
+                base + ((uint32_t)min(c + u * G + gr.l, end - 1) << 4));
         bool past = false;
 #pragma unroll
         for (int u = 0; u < U; u++) {
@@ -403,7 +407,12 @@ __device__ __forceinline__ bool scan_run_group(const Group<G> &gr, const float4 
             const bool hit = (j < end) & (sxy + zz <= R2) & (j != i);
             const uint32_t hm = gr.bits(__ballot(hit));
             const int k = cnt + __popc(hm & ((1u << gr.l) - 1));
-            if (hit) row[k < cap ? row_entry(p, k) : trash] = j;
+            if (hit) {
+                if (k < lcap)
+                    row[row_entry(p, k)] = j;
+                else if (k < cap)
+                    gl[(k >> 2) * 256 + (k & 3)] = j;
+            }
             cnt += __popc(hm);
             any |= hm != 0;
         }
@@ -414,9 +423,9 @@ __device__ __forceinline__ bool scan_run_group(const Group<G> &gr, const float4 
 
 template <int G>
 __global__ __launch_bounds__(64 * G) void k_verlet_grp(State st, const int32_t *blocks, float R2,
-                                                      int cap, int cap4) {
+                                                      int cap, int cap4, int lcap4) {
     constexpr int NC = (9 + G - 1) / G;  // neighbour columns held per lane
-    extern __shared__ int4 lrow[];       // cap4 * 64 int4: the row's lists, then 64 spare words
+    extern __shared__ int4 lrow[];       // lcap4 * 64 int4: the row's first lcap4 groups
     __shared__ int rowc8[64];            // padded list lengths of the row
     const int r = xcd_block((int)blockIdx.x, (int)gridDim.x);
     const int blk = blocks[r >> 2];
@@ -429,7 +438,8 @@ __global__ __launch_bounds__(64 * G) void k_verlet_grp(State st, const int32_t *
     const int64_t row0 = (int64_t)blk * kBlock + (r & 3) * 64;
     const int64_t i = row0 + p;
     int *row = reinterpret_cast<int *>(lrow);
-    const int trash = cap4 * 256 + p;    // where entries beyond the capacity go
+    const int lcap = 4 * lcap4;
+    int *gl = st.nbr + ((row0 >> 6) * (int64_t)cap4 * 64 + p) * 4;  // the slot's list
     const float4 *__restrict__ pos = st.pos[1];
     const int32_t *__restrict__ off = st.off + d.off_base;
     int cnt = 0;
@@ -516,15 +526,20 @@ __global__ __launch_bounds__(64 * G) void k_verlet_grp(State st, const int32_t *
                                 azs[g] != 0.f || pks[g] != pi.z;
                 const bool hit =
                     sh ? scan_run_group<G, true>(gr, pos, kb[g], ke[g], a, pk, pk.z + hz, (int)i,
-                                                 R2, row, p, cap, trash, cnt)
+                                                 R2, row, p, lcap, gl, cap, cnt)
                        : scan_run_group<G, false>(gr, pos, kb[g], ke[g], a, pk, pk.z + hz, (int)i,
-                                                  R2, row, p, cap, trash, cnt);
+                                                  R2, row, p, lcap, gl, cap, cnt);
                 img |= hit && sh;
             }
         }
         const int c = min(cnt, cap);
         const int c8 = (c + 7) & ~7;
-        for (int k = c + gr.l; k < c8; k += G) row[row_entry(p, k)] = d.dummy;
+        for (int k = c + gr.l; k < c8; k += G) {
+            if (k < lcap)
+                row[row_entry(p, k)] = d.dummy;
+            else
+                gl[(k >> 2) * 256 + (k & 3)] = d.dummy;
+        }
         if (gr.l == 0) {
             st.nnb[i] = (uint32_t)c | (img ? kWrapBit : 0u);
             note_overflow(st, cnt, cap);
@@ -537,7 +552,7 @@ __global__ __launch_bounds__(64 * G) void k_verlet_grp(State st, const int32_t *
     __syncthreads();
     // the row's lists, in list layout, written group by group over the row
     int4 *dst = reinterpret_cast<int4 *>(st.nbr) + (row0 >> 6) * (int64_t)cap4 * 64;
-    for (int t = (int)threadIdx.x; t < cap4 * 64; t += 64 * G)
+    for (int t = (int)threadIdx.x; t < lcap4 * 64; t += 64 * G)
         if ((t >> 6) * 4 < rowc8[t & 63]) dst[t] = lrow[t];
 }
 
@@ -811,27 +826,24 @@ hipError_t launch_verlet_build(fpm_ctx *c) {
     if (c->n_grp_blocks > 0) {
         // four 64-slot rows per particle workgroup
         const dim3 grid(4 * c->n_grp_blocks);
-        const size_t lds = (size_t)c->cap4 * 64 * sizeof(int4) + 64 * sizeof(int);
+        const int lcap4 = c->cap4 < kRowGroups ? c->cap4 : kRowGroups;
+        const size_t lds = (size_t)lcap4 * 64 * sizeof(int4);
         const int32_t *blocks = c->pa_blocks + c->n_pa_blocks;
         switch (c->tune_zb) {
         case 4:
             hipLaunchKernelGGL(k_verlet_grp<4>, grid, dim3(256), lds, c->stream, c->st, blocks,
-                               c->R2, c->cap, c->cap4);
+                               c->R2, c->cap, c->cap4, lcap4);
             break;
         case 16:
             hipLaunchKernelGGL(k_verlet_grp<16>, grid, dim3(1024), lds, c->stream, c->st, blocks,
-                               c->R2, c->cap, c->cap4);
+                               c->R2, c->cap, c->cap4, lcap4);
             break;
         default:
             hipLaunchKernelGGL(k_verlet_grp<8>, grid, dim3(512), lds, c->stream, c->st, blocks,
-                               c->R2, c->cap, c->cap4);
+                               c->R2, c->cap, c->cap4, lcap4);
         }
     }
     return hipGetLastError();
-}
-
-bool verlet_group_fits(int cap4) {
-    return (size_t)cap4 * 64 * sizeof(int4) + 64 * sizeof(int) <= kGroupLds;
 }
 
 hipError_t launch_list_stats(fpm_ctx *c) {

@@ -198,11 +198,13 @@ def test_particles_on_faces_and_empty_cells():
     pts[30:60, 1] = np.float32(16.0 / 5)  # a cell face (5 cells of 3.2)
     pts = np.unique(pts, axis=0)
     s = inputs.LJSystem(pts, np.zeros_like(pts), np.zeros(len(pts), np.int32), float(L), 0, 0, 0)
+    # lists longer than the lane-group build keeps in LDS (128) occur here
     sim = make_sim(s, max_nbr=512)
+    assert sim.counters()[1] > 128
     compare_sets(sim, s.pos, s.box, O.radius2(RC, SKIN))
 
 
-@pytest.mark.parametrize("tuning", [None, (4, 8, 8)])
+@pytest.mark.parametrize("tuning", [None, (3, 0, 8)])
 def test_overflow_is_reported(tuning):
     from paper_1804_07598_amd._lib import FpmError, FPM_EOVERFLOW
     s = inputs.lj_lattice(1000, 0.8442, 1.0, seed=7)
