@@ -44,9 +44,10 @@ def source_hash(paths) -> str:
     return h.hexdigest()[:16]
 
 
-def stored_traffic(n_launch_atoms: int):
+def stored_traffic(n_launch_atoms: int, unroll: int):
     """HBM bytes per force launch from the committed rocprofv3 counter summary,
-    or None when the summary is missing or the kernel source changed since."""
+    or None when the summary is missing, was taken on another kernel variant or
+    the kernel source changed since."""
     if not os.path.exists(PROFILE_COUNTERS):
         return None
     kv = {}
@@ -58,6 +59,8 @@ def stored_traffic(n_launch_atoms: int):
         if kv.get("kernel_source_sha256_16") != source_hash(LJ_SOURCES):
             return None
         if int(kv.get("atoms", "0")) != n_launch_atoms:
+            return None
+        if int(kv.get("unroll", "0")) != unroll:
             return None
         return float(kv["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
@@ -346,7 +349,7 @@ def main(argv=None) -> int:
     nbar_k = total2 / s.n
     bytes_force = s.n * (36.0 + 4.0 * nbar_k)
     achieved = bytes_force / (f_ms / 1e3) / 1e9
-    traffic = stored_traffic(s.n)
+    traffic = stored_traffic(s.n, knobs[2] or 8)  # unroll 0 = automatic = 8
     log(f"force kernel {f_ms * 1e3:.1f} us over {f_n} launches -> {achieved:.0f} GB/s; "
         f"cell build {c_ms * 1e3:.1f} us, Verlet build {v_ms * 1e3:.1f} us", a.quiet)
 
