@@ -135,7 +135,8 @@ int fpm_set_positions(fpm_ctx *ctx, const float *d_pos);
  * first entry of that system's cell offsets, cells along x, y, z, Verlet
  * build of the system: z-cells per workgroup of the column build (> 0), or
  * 0 particle by particle over whole cells, -1 particle by particle over
- * candidate windows, -2 lane groups over candidate windows}. */
+ * candidate windows, -2 lane groups over candidate windows, -3 lane groups
+ * over whole cells}. */
 int fpm_system_info(fpm_ctx *ctx, int32_t s, int64_t h_out[8]);
 /* SPH only: per-particle density (device, caller order, n entries). */
 int fpm_set_density(fpm_ctx *ctx, const float *d_rho);
@@ -236,8 +237,9 @@ int fpm_read_counters(fpm_ctx *ctx, int64_t h_out[3]);
  * by particle over whole neighbour cells, 2 by column blocks staged in LDS,
  * 3 particle by particle over candidate windows, 4 over the same windows with
  * a group of lanes per particle and each 64-slot row of lists staged in LDS
- * (2, 3 and 4 where the grid has >= 3 cells per axis, elsewhere path 1 is
- * taken; automatic takes 4).  zblock: z-cells per column workgroup (1..64);
+ * (2, 3 and 4 where the grid has >= 3 cells per axis; elsewhere paths 2 and
+ * 3 take path 1 and path 4 runs its lane groups over whole cells; automatic
+ * takes 4).  zblock: z-cells per column workgroup (1..64);
  * for path 4, lanes per particle (0 = 8, 4, 8 or 16; other values are
  * FPM_EINVAL).  unroll: list entries in
  * flight per lane in the force kernel (4 or 8).  Results do not depend on

@@ -74,12 +74,13 @@ Plan make_plan(const fpm_ctx *c, const std::vector<int64_t> &cnt) {
         d.off_base = offb;
         // Verlet build: zb > 0 column workgroups, 0 particle by particle over
         // whole cells, -1 particle by particle over candidate windows, -2 lane
-        // groups over candidate windows (rows of lists staged in LDS)
+        // groups over candidate windows, -3 lane groups over whole cells (the
+        // lane-group builds stage rows of lists in LDS)
         const bool big = d.box.nc[0] >= 3 && d.box.nc[1] >= 3 && d.box.nc[2] >= 3;
         if (c->tune_verlet_path == 1)
             d.zb = 0;
         else if (c->tune_verlet_path == 4 || c->tune_verlet_path == 0)
-            d.zb = big ? -2 : 0;
+            d.zb = big ? -2 : -3;
         else if (c->tune_verlet_path == 3)
             d.zb = big ? -1 : 0;
         else
@@ -93,7 +94,7 @@ Plan make_plan(const fpm_ctx *c, const std::vector<int64_t> &cnt) {
         for (int b = 0; b < h.nblk; b++) {
             P.blk2sys.push_back(s);
             if (d.zb == 0 || d.zb == -1) P.pa_blocks.push_back(blk + b);
-            if (d.zb == -2) P.grp_blocks.push_back(blk + b);
+            if (d.zb == -2 || d.zb == -3) P.grp_blocks.push_back(blk + b);
         }
         for (int q = 0; q < h.nitems; q++) P.item2sys.push_back(s);
         slot += d.n_pad;

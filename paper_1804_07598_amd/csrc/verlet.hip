@@ -349,7 +349,9 @@ __device__ __forceinline__ void copy_back(const State &st, int64_t s) {
 // whole row is stored with contiguous 16-byte writes at the end.  The run
 // bounds of all nine columns are fetched at once, spread over the group's
 // lanes and broadcast by shuffles.  Runs, windows and image shifts are those
-// of verlet_atom_window, so the lists are identical entry for entry.
+// of verlet_atom_window (grids of at least three cells per axis) or the whole
+// cells of verlet_atom_global (smaller grids), so the lists are identical
+// entry for entry to those of the particle-by-particle builds.
 
 // The G-lane group of this thread inside its wavefront: bit offset of the
 // group in the ballot mask and this lane's index in the group.
@@ -421,6 +423,43 @@ __device__ __forceinline__ bool scan_run_group(const Group<G> &gr, const float4 
     return any;
 }
 
+// Whole cells (grids with fewer than three cells along some axis): one run of
+// the de-duplicated stencil, every candidate tested with the full predicate
+// (image chosen per axis), as in verlet_atom_global.  Returns true when a hit
+// uses a periodic image.
+template <int G>
+__device__ __forceinline__ bool scan_cells_group(const Group<G> &gr, const float4 *__restrict__ pos,
+                                                 int beg, int end, float3 pi, const Box &b, int i,
+                                                 float R2, int *row, int p, int lcap, int *gl,
+                                                 int cap, int &cnt) {
+    constexpr int U = 32 / G;
+    const char *base = reinterpret_cast<const char *>(pos);
+    bool img = false;
+    for (int c = beg; c < end; c += U * G) {
+        float4 q[U];
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            q[u] = *reinterpret_cast<const float4 *>(
+                base + ((uint32_t)min(c + u * G + gr.l, end - 1) << 4));
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int j = c + u * G + gr.l;
+            const bool hit = (j < end) & (cand_d2<true>(pi, xyz(q[u]), b) <= R2) & (j != i);
+            const uint32_t hm = gr.bits(__ballot(hit));
+            const int k = cnt + __popc(hm & ((1u << gr.l) - 1));
+            if (hit) {
+                if (k < lcap)
+                    row[row_entry(p, k)] = j;
+                else if (k < cap)
+                    gl[(k >> 2) * 256 + (k & 3)] = j;
+            }
+            cnt += __popc(hm);
+            img |= gr.bits(__ballot(hit && uses_image(pi, xyz(q[u]), b))) != 0;
+        }
+    }
+    return img;
+}
+
 template <int G>
 __global__ __launch_bounds__(64 * G) void k_verlet_grp(State st, const int32_t *blocks, float R2,
                                                       int cap, int cap4, int lcap4) {
@@ -450,86 +489,106 @@ __global__ __launch_bounds__(64 * G) void k_verlet_grp(State st, const int32_t *
         const int ix = cell_coord(pi.x, b.inv[0], nx);
         const int iy = cell_coord(pi.y, b.inv[1], ny);
         const int iz = cell_coord(pi.z, b.inv[2], nz);
-        // z-runs: cells iz-1 .. iz+1 as at most two contiguous pieces
-        // (first and last cell, shift of the candidates, particle's own z)
-        int zc0[2], zc1[2];
-        float azs[2], pks[2];
-        int nseg = 1;
-        azs[0] = azs[1] = 0.f, pks[0] = pks[1] = pi.z;
-        zc0[1] = zc1[1] = 0;
-        if (iz == 0 && b.per[2]) {  // cell nz-1 one period down, then cells 0, 1
-            zc0[0] = zc1[0] = nz - 1, azs[0] = b.L[2];
-            zc0[1] = 0, zc1[1] = 1, nseg = 2;
-        } else if (iz == 0) {
-            zc0[0] = 0, zc1[0] = 1;
-        } else if (iz == nz - 1) {  // cells nz-2, nz-1, then cell 0 with i moved down
-            zc0[0] = nz - 2, zc1[0] = nz - 1;
-            if (b.per[2]) zc0[1] = zc1[1] = 0, pks[1] = pi.z - b.L[2], nseg = 2;
-        } else {
-            zc0[0] = iz - 1, zc1[0] = iz + 1;
-        }
-        // run bounds: this lane fetches those of columns l, l + G, ...
-        int rb[NC][2], re[NC][2];
-#pragma unroll
-        for (int m = 0; m < NC; m++) {
-            const int k = gr.l + m * G;
-            int cx = ix + k / 3 - 1, cy = iy + k % 3 - 1;
-            const bool ok = k < 9 && (b.per[0] || (cx >= 0 && cx < nx)) &&
-                            (b.per[1] || (cy >= 0 && cy < ny));
-            cx = cx < 0 ? cx + nx : (cx >= nx ? cx - nx : cx);
-            cy = cy < 0 ? cy + ny : (cy >= ny ? cy - ny : cy);
-            const int col = ok ? (cx * ny + cy) * nz : 0;
-#pragma unroll
-            for (int g = 0; g < 2; g++) {
-                const bool okg = ok && g < nseg;
-                const int e0 = off[okg ? col + zc0[g] : 0], e1 = off[okg ? col + zc1[g] + 1 : 0];
-                rb[m][g] = okg ? e0 : 0;
-                re[m][g] = okg ? e1 : 0;
-            }
-        }
-        const float marg = 1e-5f * fmaxf(b.L[0], fmaxf(b.L[1], b.L[2]));
-        const float dxl = fmaxf(pi.x - (float)ix / b.inv[0] - marg, 0.f);
-        const float dxh = fmaxf((float)(ix + 1) / b.inv[0] - pi.x - marg, 0.f);
-        const float dyl = fmaxf(pi.y - (float)iy / b.inv[1] - marg, 0.f);
-        const float dyh = fmaxf((float)(iy + 1) / b.inv[1] - pi.y - marg, 0.f);
-        const float Rw2 = R2 * 1.0001f;
-        for (int k = 0; k < 9; k++) {
-            const int ox = k / 3 - 1, oy = k % 3 - 1;
-            const int cx = ix + ox, cy = iy + oy;
-            const float ax = cx < 0 ? b.L[0] : 0.f, px = cx >= nx ? pi.x - b.L[0] : pi.x;
-            const float ay = cy < 0 ? b.L[1] : 0.f, py = cy >= ny ? pi.y - b.L[1] : pi.y;
-            const float ddx = ox < 0 ? dxl : (ox > 0 ? dxh : 0.f);
-            const float ddy = oy < 0 ? dyl : (oy > 0 ? dyh : 0.f);
-            const float h2 = Rw2 - ddx * ddx - ddy * ddy;
-            // bounds of column k from lane k % G of the group (empty runs where
-            // the column lies across a closed face)
-            int kb[2], ke[2];
-#pragma unroll
-            for (int g = 0; g < 2; g++) {
-                int vb = rb[0][g], ve = re[0][g];
-#pragma unroll
-                for (int m = 1; m < NC; m++) {
-                    vb = k / G == m ? rb[m][g] : vb;
-                    ve = k / G == m ? re[m][g] : ve;
+        if (d.zb == -3) {
+            // whole cells of the de-duplicated stencil, z pieces merged
+            int sx[3], sy[3], sz[3];
+            const int mx = stencil_axis(ix, nx, b.per[0], sx);
+            const int my = stencil_axis(iy, ny, b.per[1], sy);
+            const int mz = stencil_axis(iz, nz, b.per[2], sz);
+            for (int a = 0; a < mx; a++)
+                for (int q = 0; q < my; q++) {
+                    const int col = (sx[a] * ny + sy[q]) * nz;
+                    int z = 0;
+                    while (z < mz) {
+                        int z1 = z;
+                        while (z1 + 1 < mz && sz[z1 + 1] == sz[z1] + 1) z1++;
+                        img |= scan_cells_group<G>(gr, pos, off[col + sz[z]], off[col + sz[z1] + 1],
+                                                   pi, b, (int)i, R2, row, p, lcap, gl, cap, cnt);
+                        z = z1 + 1;
+                    }
                 }
-                kb[g] = __shfl(vb, k % G, G);
-                ke[g] = __shfl(ve, k % G, G);
+        } else {
+            // z-runs: cells iz-1 .. iz+1 as at most two contiguous pieces
+            // (first and last cell, shift of the candidates, particle's own z)
+            int zc0[2], zc1[2];
+            float azs[2], pks[2];
+            int nseg = 1;
+            azs[0] = azs[1] = 0.f, pks[0] = pks[1] = pi.z;
+            zc0[1] = zc1[1] = 0;
+            if (iz == 0 && b.per[2]) {  // cell nz-1 one period down, then cells 0, 1
+                zc0[0] = zc1[0] = nz - 1, azs[0] = b.L[2];
+                zc0[1] = 0, zc1[1] = 1, nseg = 2;
+            } else if (iz == 0) {
+                zc0[0] = 0, zc1[0] = 1;
+            } else if (iz == nz - 1) {  // cells nz-2, nz-1, then cell 0 with i moved down
+                zc0[0] = nz - 2, zc1[0] = nz - 1;
+                if (b.per[2]) zc0[1] = zc1[1] = 0, pks[1] = pi.z - b.L[2], nseg = 2;
+            } else {
+                zc0[0] = iz - 1, zc1[0] = iz + 1;
             }
-            if (h2 < 0.f) continue;
-            const float hz = sqrtf(h2);
-#pragma unroll
-            for (int g = 0; g < 2; g++) {
-                if (kb[g] >= ke[g]) continue;
-                const float3 a = make_float3(ax, ay, azs[g]);
-                const float3 pk = make_float3(px, py, pks[g]);
-                const bool sh = ax != 0.f || px != pi.x || ay != 0.f || py != pi.y ||
-                                azs[g] != 0.f || pks[g] != pi.z;
-                const bool hit =
-                    sh ? scan_run_group<G, true>(gr, pos, kb[g], ke[g], a, pk, pk.z + hz, (int)i,
-                                                 R2, row, p, lcap, gl, cap, cnt)
-                       : scan_run_group<G, false>(gr, pos, kb[g], ke[g], a, pk, pk.z + hz, (int)i,
-                                                  R2, row, p, lcap, gl, cap, cnt);
-                img |= hit && sh;
+            // run bounds: this lane fetches those of columns l, l + G, ...
+            int rb[NC][2], re[NC][2];
+    #pragma unroll
+            for (int m = 0; m < NC; m++) {
+                const int k = gr.l + m * G;
+                int cx = ix + k / 3 - 1, cy = iy + k % 3 - 1;
+                const bool ok = k < 9 && (b.per[0] || (cx >= 0 && cx < nx)) &&
+                                (b.per[1] || (cy >= 0 && cy < ny));
+                cx = cx < 0 ? cx + nx : (cx >= nx ? cx - nx : cx);
+                cy = cy < 0 ? cy + ny : (cy >= ny ? cy - ny : cy);
+                const int col = ok ? (cx * ny + cy) * nz : 0;
+    #pragma unroll
+                for (int g = 0; g < 2; g++) {
+                    const bool okg = ok && g < nseg;
+                    const int e0 = off[okg ? col + zc0[g] : 0], e1 = off[okg ? col + zc1[g] + 1 : 0];
+                    rb[m][g] = okg ? e0 : 0;
+                    re[m][g] = okg ? e1 : 0;
+                }
+            }
+            const float marg = 1e-5f * fmaxf(b.L[0], fmaxf(b.L[1], b.L[2]));
+            const float dxl = fmaxf(pi.x - (float)ix / b.inv[0] - marg, 0.f);
+            const float dxh = fmaxf((float)(ix + 1) / b.inv[0] - pi.x - marg, 0.f);
+            const float dyl = fmaxf(pi.y - (float)iy / b.inv[1] - marg, 0.f);
+            const float dyh = fmaxf((float)(iy + 1) / b.inv[1] - pi.y - marg, 0.f);
+            const float Rw2 = R2 * 1.0001f;
+            for (int k = 0; k < 9; k++) {
+                const int ox = k / 3 - 1, oy = k % 3 - 1;
+                const int cx = ix + ox, cy = iy + oy;
+                const float ax = cx < 0 ? b.L[0] : 0.f, px = cx >= nx ? pi.x - b.L[0] : pi.x;
+                const float ay = cy < 0 ? b.L[1] : 0.f, py = cy >= ny ? pi.y - b.L[1] : pi.y;
+                const float ddx = ox < 0 ? dxl : (ox > 0 ? dxh : 0.f);
+                const float ddy = oy < 0 ? dyl : (oy > 0 ? dyh : 0.f);
+                const float h2 = Rw2 - ddx * ddx - ddy * ddy;
+                // bounds of column k from lane k % G of the group (empty runs where
+                // the column lies across a closed face)
+                int kb[2], ke[2];
+    #pragma unroll
+                for (int g = 0; g < 2; g++) {
+                    int vb = rb[0][g], ve = re[0][g];
+    #pragma unroll
+                    for (int m = 1; m < NC; m++) {
+                        vb = k / G == m ? rb[m][g] : vb;
+                        ve = k / G == m ? re[m][g] : ve;
+                    }
+                    kb[g] = __shfl(vb, k % G, G);
+                    ke[g] = __shfl(ve, k % G, G);
+                }
+                if (h2 < 0.f) continue;
+                const float hz = sqrtf(h2);
+    #pragma unroll
+                for (int g = 0; g < 2; g++) {
+                    if (kb[g] >= ke[g]) continue;
+                    const float3 a = make_float3(ax, ay, azs[g]);
+                    const float3 pk = make_float3(px, py, pks[g]);
+                    const bool sh = ax != 0.f || px != pi.x || ay != 0.f || py != pi.y ||
+                                    azs[g] != 0.f || pks[g] != pi.z;
+                    const bool hit =
+                        sh ? scan_run_group<G, true>(gr, pos, kb[g], ke[g], a, pk, pk.z + hz, (int)i,
+                                                     R2, row, p, lcap, gl, cap, cnt)
+                           : scan_run_group<G, false>(gr, pos, kb[g], ke[g], a, pk, pk.z + hz, (int)i,
+                                                      R2, row, p, lcap, gl, cap, cnt);
+                    img |= hit && sh;
+                }
             }
         }
         const int c = min(cnt, cap);

@@ -54,12 +54,13 @@ def test_batch_matches_oracle_per_system(tuning):
     idx = list(range(10)) + [72, 130]  # 72 and 130 have boxes of 2 cells per axis
     systems = systems_of(idx)
     sim = make_batch(systems, tuning=tuning)
-    # two Verlet build paths occur: whole cells for grids below 3 cells per axis,
-    # and above lane groups (default, -2), column workgroups (path 2: z-cells
-    # per block) or particle-by-particle windows (path 3: -1)
+    # two Verlet build paths occur: whole cells for grids below 3 cells per axis
+    # (lane groups by default, -3; particle by particle otherwise, 0), and above
+    # lane groups (default, -2), column workgroups (path 2: z-cells per block)
+    # or particle-by-particle windows (path 3: -1)
     zb = [sim.system_info(k)["zblock"] for k in range(len(idx))]
     big = {None: lambda z: z == -2, (2, 0, 8): lambda z: z > 0, (3, 0, 8): lambda z: z == -1}
-    assert 0 in zb and any(big[tuning](z) for z in zb)
+    assert (-3 if tuning is None else 0) in zb and any(big[tuning](z) for z in zb)
     off, order = (np_(t) for t in sim.cell_list())
     for k, s in enumerate(systems):
         info = sim.system_info(k)
