@@ -71,6 +71,10 @@ def lib():
                                           f64p, _opt(i64p), C.c_int64, f64p, f64p, f64p]
             L.oracle_sph_kernel_w.restype = C.c_double
             L.oracle_sph_kernel_w.argtypes = [C.c_double, C.c_double]
+            L.oracle_sph_cubic_w.restype = C.c_double
+            L.oracle_sph_cubic_w.argtypes = [C.c_double, C.c_double]
+            L.oracle_sph_kernel_dwdr.restype = C.c_double
+            L.oracle_sph_kernel_dwdr.argtypes = [C.c_double, C.c_double, C.c_int]
         if hasattr(L, "oracle_lj_vjp"):
             L.oracle_lj_vjp.argtypes = [C.c_int64, f32p, _opt(i32p), f32p, i32p, C.c_float, f64p,
                                         f64p, f64p, f64p, f64p]
@@ -304,11 +308,25 @@ def sph_kernel_w(r: float, h: float) -> float:
     return float(lib().oracle_sph_kernel_w(float(r), float(h)))
 
 
-def sph_params_array(h, mass, rho0, c0, gamma=7.0, alpha=0.1, eta2=None, g=(0.0, 0.0, -9.81)):
-    """The oracle's SPH parameter vector {h, m, rho0, c0, gamma, alpha, eta2, gx, gy, gz}."""
+def sph_cubic_w(r: float, h: float) -> float:
+    """Cubic spline kernel value W(r) with support 2h (section 4.2's kernel)."""
+    return float(lib().oracle_sph_cubic_w(float(r), float(h)))
+
+
+def sph_kernel_dwdr(r: float, h: float, kernel: int) -> float:
+    """dW/dr of the Wendland C2 (kernel 0) or cubic spline (kernel 1) kernel."""
+    return float(lib().oracle_sph_kernel_dwdr(float(r), float(h), int(kernel)))
+
+
+def sph_params_array(h, mass, rho0, c0, gamma=7.0, alpha=0.1, eta2=None, g=(0.0, 0.0, -9.81),
+                     kernel=0, cbar=0.0):
+    """The oracle's SPH parameter vector {h, m, rho0, c0, gamma, alpha, eta2, gx, gy, gz,
+    kernel, cbar}: kernel 0 Wendland C2, 1 cubic spline; cbar the sound speed of
+    Eq. 5's viscosity (0: c0)."""
     if eta2 is None:
         eta2 = 0.01 * h * h
-    return np.array([h, mass, rho0, c0, gamma, alpha, eta2, g[0], g[1], g[2]], dtype=np.float64)
+    return np.array([h, mass, rho0, c0, gamma, alpha, eta2, g[0], g[1], g[2], kernel, cbar],
+                    dtype=np.float64)
 
 
 def sph_rates(pos, vel, rho, kind, L, per, R2, prm, rows=None):
@@ -370,6 +388,53 @@ def sph_kdk(pos, vel, rho, kind, L, per, R2, prm, cfl, nsteps):
         hist[k] = (t, dt)
         dt = sph_dt(a, kind, mu, prm, cfl)
     return x, v, r, hist
+
+
+def verlet_steps(x, v, rho, fluid, rates, dt_of, nsteps, every):
+    """The Verlet scheme of section 4.2 (ref. [46]) with a dynamic step, on FP64
+    state: at step n with rates (a, D) of the state n and time step dt,
+      x^{n+1} = x^n + dt v^n + dt^2/2 a^n                      (fluid only)
+      v^{n+1} = v^{n-1} + 2 dt a^n,  rho^{n+1} = rho^{n-1} + 2 dt D^n,
+    except on every `every`-th step counted from 0, which takes the Euler form
+      v^{n+1} = v^n + dt a^n,  rho^{n+1} = rho^n + dt D^n
+    (step 0 has no previous state).  Boundary particles (fluid False) keep x
+    and v; their density evolves.  `rates(x, v, rho)` returns (a, D, extra)
+    and `dt_of(a, extra)` the step for those rates.  Returns (x, v, rho,
+    hist (nsteps, 2) = [t, dt])."""
+    x, v, r = (np.asarray(q, np.float64).copy() for q in (x, v, rho))
+    fl = np.asarray(fluid, bool)
+    vp, rp = v.copy(), r.copy()
+    a, D, extra = rates(x, v, r)
+    t = 0.0
+    hist = np.empty((nsteps, 2), np.float64)
+    for n in range(nsteps):
+        dt = dt_of(a, extra)
+        euler = n % every == 0
+        bv, br, f = (v, r, dt) if euler else (vp, rp, 2.0 * dt)
+        xn = x.copy()
+        xn[fl] = x[fl] + dt * v[fl] + 0.5 * dt * dt * a[fl]
+        vn = v.copy()
+        vn[fl] = bv[fl] + f * a[fl]
+        rn = br + f * D
+        vp, rp = v, r
+        x, v, r = xn, vn, rn
+        a, D, extra = rates(x, v, r)
+        t += dt
+        hist[n] = (t, dt)
+    return x, v, r, hist
+
+
+def sph_verlet(pos, vel, rho, kind, L, per, R2, prm, cfl, nsteps, every):
+    """nsteps of the Verlet scheme (verlet_steps) with SPH rates (Eqs. 1-5) and
+    the CFL time step of the current rates.  Rates see the FP64 state rounded
+    to FP32 (the precision the particle arrays have)."""
+    def rates(x, v, r):
+        a, D, mu = sph_rates(x.astype(np.float32), v.astype(np.float32), r.astype(np.float32),
+                             kind, L, per, R2, prm)
+        return a, D, mu
+
+    return verlet_steps(pos, vel, rho, np.asarray(kind) == 0, rates,
+                        lambda a, mu: sph_dt(a, kind, mu, prm, cfl), nsteps, every)
 
 
 def num_threads() -> int:

@@ -3,13 +3,17 @@
  * 4.2 (Eqs. 1-5).  TEST INFRASTRUCTURE ONLY (see oracle.c).
  *
  * Readings taken where the paper is silent or garbled (listed in the design doc):
- *  - kernel: Wendland C2 with support 2h, W(r) = aD (1 - q/2)^4 (2q + 1),
- *    q = r/h, aD = 21 / (16 pi h^3) (the paper names the classic cubic kernel);
+ *  - kernel (prm[10]): 0 = Wendland C2 with support 2h,
+ *    W(r) = aD (1 - q/2)^4 (2q + 1), q = r/h, aD = 21 / (16 pi h^3);
+ *    1 = the classic cubic spline the paper names, support 2h,
+ *    W = aD (1 - 3q^2/2 + 3q^3/4) for q < 1, aD (2 - q)^3 / 4 for 1 <= q < 2,
+ *    aD = 1 / (pi h^3); the paper's cutoff 2 sqrt(3) dp is h = sqrt(3) dp;
  *  - gradient: grad_a W_ab = dW/dr (x_a - x_b) / r, so a compressed pair repels;
  *  - Eq. 4: B = c0^2 rho0 / gamma with c0 given directly;
- *  - Eq. 5: Pi_ab = -alpha c0 mu_ab / rhobar_ab for approaching pairs
+ *  - Eq. 5: Pi_ab = -alpha cbar mu_ab / rhobar_ab for approaching pairs
  *    (v_ab . x_ab < 0), zero otherwise; mu_ab = h v_ab.x_ab / (r^2 + eta^2);
- *    rhobar_ab = (rho_a + rho_b) / 2;
+ *    rhobar_ab = (rho_a + rho_b) / 2; cbar = prm[11] when positive (the
+ *    paper's sqrt(g h_swl)), else c0;
  *  - boundary particles (kind 1) enter every sum and get a density rate, but
  *    no acceleration.
  * The pair set is the FP32 predicate of oracle.c with R = 2h.
@@ -64,11 +68,28 @@ double oracle_sph_kernel_w(double r, double h)
     return aD * t * t * t * t * (2.0 * q + 1.0);
 }
 
-/* dW/dr of the same kernel. */
-static double kernel_dwdr(double r, double h)
+/* Cubic spline kernel value at distance r (3-D normalisation). */
+double oracle_sph_cubic_w(double r, double h)
+{
+    double q = r / h;
+    double aD = 1.0 / (PI * h * h * h);
+    if (q >= 2.0) return 0.0;
+    if (q < 1.0) return aD * (1.0 - 1.5 * q * q + 0.75 * q * q * q);
+    double t = 2.0 - q;
+    return aD * 0.25 * t * t * t;
+}
+
+/* dW/dr of the kernel selected by `kernel` (0 Wendland C2, 1 cubic spline). */
+double oracle_sph_kernel_dwdr(double r, double h, int kernel)
 {
     double q = r / h;
     if (q >= 2.0) return 0.0;
+    if (kernel == 1) {
+        double aD = 1.0 / (PI * h * h * h);
+        if (q < 1.0) return aD * (-3.0 * q + 2.25 * q * q) / h;
+        double t = 2.0 - q;
+        return aD * (-0.75 * t * t) / h;
+    }
     double aD = 21.0 / (16.0 * PI * h * h * h);
     double t = 1.0 - 0.5 * q;
     /* d/dq [t^4 (2q + 1)] = -2 t^3 (2q + 1) + 2 t^4 = -5 q t^3 */
@@ -82,7 +103,7 @@ static double pressure(double rho, double rho0, double c0, double gamma)
 }
 
 /*
- * prm = {h, m, rho0, c0, gamma, alpha, eta2, gx, gy, gz}.
+ * prm = {h, m, rho0, c0, gamma, alpha, eta2, gx, gy, gz, kernel, cbar}.
  * For each requested row a: acc (3), drho, mumax = max over its pairs of |mu_ab|.
  */
 void oracle_sph_rows(int64_t n, const float *pos, const float *vel, const float *rho,
@@ -92,6 +113,8 @@ void oracle_sph_rows(int64_t n, const float *pos, const float *vel, const float 
 {
     const double h = prm[0], m = prm[1], rho0 = prm[2], c0 = prm[3], gamma = prm[4];
     const double alpha = prm[5], eta2 = prm[6];
+    const int kernel = (int)prm[10];
+    const double cbar = prm[11] > 0.0 ? prm[11] : c0;
     int64_t nr = rows ? nrows : n;
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t r = 0; r < nr; r++) {
@@ -112,7 +135,7 @@ void oracle_sph_rows(int64_t n, const float *pos, const float *vel, const float 
             }
             double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
             double rr = sqrt(r2);
-            double gfac = kernel_dwdr(rr, h) / rr;   /* grad_a W_ab = gfac * x_ab */
+            double gfac = oracle_sph_kernel_dwdr(rr, h, kernel) / rr; /* grad_a W_ab = gfac x_ab */
             double v[3];
             for (int k = 0; k < 3; k++) v[k] = (double)vel[3 * a + k] - (double)vel[3 * b + k];
             double vx = v[0] * x[0] + v[1] * x[1] + v[2] * x[2];
@@ -121,7 +144,7 @@ void oracle_sph_rows(int64_t n, const float *pos, const float *vel, const float 
             double Pb = pressure(rb, rho0, c0, gamma);
             double mu = h * vx / (r2 + eta2);
             double Pi = 0.0;
-            if (vx < 0.0) Pi = -alpha * c0 * mu / (0.5 * (ra + rb));
+            if (vx < 0.0) Pi = -alpha * cbar * mu / (0.5 * (ra + rb));
             if (fabs(mu) > mu_max) mu_max = fabs(mu);
             double coef = -m * ((Pa + Pb) / (ra * rb) + Pi) * gfac;
             ax += coef * x[0];

@@ -19,6 +19,8 @@ section 4.2 starts SPH from a fluid column resting on boundary particles):
   chosen by a random permutation.
 * SPH column: a fluid lattice nf x nf x nz at spacing dx over a three-layer
   floor of boundary particles, periodic in x and y, hydrostatic density.
+* SPH dam break (section 4.2's benchmark, a water column released in one
+  corner of a tank onto a fixed obstacle): synthetic geometry, closed box.
 
 All generators use numpy.random.Generator(PCG64(seed)).
 """
@@ -31,7 +33,7 @@ import numpy as np
 
 __all__ = [
     "LJSystem", "lj_lattice", "lj_config", "batched_table", "batched_system",
-    "SPHSystem", "sph_column", "LJ_CONFIGS",
+    "SPHSystem", "sph_column", "sph_dambreak", "LJ_CONFIGS",
 ]
 
 
@@ -165,3 +167,49 @@ def sph_column(nf: int = 128, nz: int | None = None, dx: float = 0.01, *,
     L = np.array([nf * dx, nf * dx, (n_floor + nz + headroom) * dx], dtype=np.float32)
     return SPHSystem(pos=pos64.astype(np.float32), vel=np.zeros_like(pos64, dtype=np.float32),
                      rho=rho.astype(np.float32), kind=kind, L=L, dx=dx, H=H)
+
+
+def _lattice(lo, hi, dp):
+    """Sites (i + 1/2) dp of the box [lo, hi) (FP64), one per cell of side dp."""
+    axes = [lo[k] + (np.arange(int(round((hi[k] - lo[k]) / dp))) + 0.5) * dp for k in range(3)]
+    X, Y, Z = np.meshgrid(*axes, indexing="ij")
+    return np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+
+
+def sph_dambreak(dp: float = 0.01, *, tank=(1.6, 0.67, 0.4), column=(0.4, 0.67, 0.3),
+                 obstacle=((0.9, 0.24), (0.12, 0.12), 0.45), n_wall: int = 3,
+                 height: float = 1.0, rho0: float = 1000.0, g: float = 9.81,
+                 gamma: float = 7.0, c0_factor: float = 20.0) -> SPHSystem:
+    """Dam break in a closed tank (synthetic stand-in for section 4.2's case).
+
+    Tank interior [0, tank) (x, y, z; open top), walled by n_wall layers of
+    boundary particles at spacing dp on the floor and the four sides; a fluid
+    column [0, column) in the corner at x = 0; a solid obstacle block of
+    boundary particles with lower corner (x, y) = obstacle[0], footprint
+    obstacle[1] and height obstacle[2] standing on the floor.  Coordinates
+    are shifted by n_wall dp so that everything lies in the (closed) box
+    L = tank + 2 n_wall dp in x and y and `height` + n_wall dp in z.  The
+    fluid starts at rest with hydrostatic Tait density for the column height
+    H = column[2], c0 = c0_factor sqrt(g H); boundary particles at rho0.
+    With the defaults (dp = 0.01) N = 179,154 (80,400 fluid), near the paper's 171,496.
+    """
+    w = n_wall * dp
+    tx, ty, tz = tank
+    outer = _lattice((-w, -w, -w), (tx + w, ty + w, tz), dp)
+    inner = ((outer[:, 0] > 0) & (outer[:, 0] < tx) & (outer[:, 1] > 0) & (outer[:, 1] < ty)
+             & (outer[:, 2] > 0))
+    walls = outer[~inner]
+    (ox, oy), (fx, fy), oh = obstacle
+    block = _lattice((ox, oy, 0.0), (ox + fx, oy + fy, oh), dp)
+    fluid = _lattice((0.0, 0.0, 0.0), column, dp)
+    H = float(column[2])
+    c0 = c0_factor * math.sqrt(g * H)
+    b = c0 * c0 * rho0 / gamma
+    rho_f = rho0 * (1.0 + rho0 * g * (H - fluid[:, 2]) / b) ** (1.0 / gamma)
+    pos64 = np.concatenate([fluid, walls, block], axis=0) + w
+    kind = np.concatenate([np.zeros(len(fluid), np.int32),
+                           np.ones(len(walls) + len(block), np.int32)])
+    rho = np.concatenate([rho_f, np.full(len(walls) + len(block), rho0)])
+    L = np.array([tx + 2 * w, ty + 2 * w, height + w], dtype=np.float32)
+    return SPHSystem(pos=pos64.astype(np.float32), vel=np.zeros_like(pos64, dtype=np.float32),
+                     rho=rho.astype(np.float32), kind=kind, L=L, dx=dp, H=H)
