@@ -192,6 +192,66 @@ def bench_sph(dev, nsteps: int, quiet: bool):
                          "bytes_model": "N*(52 + 4*nbar): pos, vel 32, count 4, list, out 16"}}
 
 
+def bench_dambreak(dev, quiet: bool, t_end: float = 1.5, chunk: int = 2000,
+                   max_steps: int = 60000):
+    """Section 4.2's dam break with the paper's SPH choices (cubic spline kernel
+    with support 2 sqrt(3) dp, Eq. 5 viscosity with sqrt(g h_swl), Verlet time
+    stepping with an Euler-form step every 40 and the CFL step) on the
+    synthetic walled tank with obstacle (179,154 particles, dp = 0.01), run to
+    t_end of simulated time as the paper does."""
+    import math
+    import numpy as np
+    import torch
+    from paper_1804_07598_amd import _lib as F
+    from paper_1804_07598_amd import inputs
+    from paper_1804_07598_amd.sim import ParticleSim
+    s = inputs.sph_dambreak()
+    dx, H, g = s.dx, s.H, 9.81
+    h = math.sqrt(3.0) * dx
+    c0, cbar = 20.0 * math.sqrt(g * H), math.sqrt(g * H)
+    prm = F.sph_params(h, 1000.0 * dx ** 3, 1000.0, c0, 7.0, 0.1, 0.01 * h * h, (0, 0, -g), 0.2,
+                       kernel=1, cbar=cbar, scheme=1, verlet_every=40)
+    r_cut = float(np.float32(2 * h))
+    sim = ParticleSim(s.pos, s.L, (0, 0, 0), vel=s.vel, typ=s.kind, r_cut=r_cut, skin=0.1 * h,
+                      max_nbr=320, device=dev)
+    sim.set_density(s.rho)
+    hist = torch.zeros((chunk, 4), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    steps, t, dt = 0, 0.0, 0.0
+    while t < t_end and steps < max_steps:
+        # the last chunk is sized from the latest step to end just past t_end
+        k = chunk if dt == 0.0 else max(1, min(chunk, math.ceil((t_end - t) / dt)))
+        sim.sph_step(k, prm, hist)
+        steps += k
+        t, dt = (float(x) for x in hist[k - 1, :2].tolist())
+        log(f"dam break: {steps} steps, t = {t:.4f} s", quiet)
+    e1.record()
+    torch.cuda.synchronize()
+    sim.check()
+    ms = e0.elapsed_time(e1)
+    F.fpm_set_profiling(sim.ctx, True)
+    for _ in range(10):
+        sim.sph_rates(prm)
+    r_ms, _ = F.fpm_kernel_time(sim.ctx, "sph_rates")
+    F.fpm_set_profiling(sim.ctx, False)
+    reb, _, total = sim.counters()
+    sim.close()
+    n = len(s.pos)
+    log(f"dam break: {n} particles to t = {t:.3f} s in {steps} steps, {ms / 1e3:.2f} s "
+        f"({ms / steps * 1e3:.1f} us/step), rates kernel {r_ms * 1e3:.1f} us", quiet)
+    return {"workload": "SPH dam break, synthetic walled tank 1.6 x 0.67 x 0.4 with obstacle, "
+                        "water column 0.4 x 0.67 x 0.3, dp=0.01, N=179,154; cubic spline "
+                        "h=sqrt(3) dp, Verlet (Euler every 40), CFL 0.2, c0=20 sqrt(g h_swl), "
+                        "cbar=sqrt(g h_swl), alpha=0.1",
+            "particles": n, "steps": steps, "simulated_s": t, "wall_s": ms / 1e3,
+            "value": n * steps / (ms / 1e3), "unit": "particle-steps/s",
+            "ms_per_step": ms / steps, "rates_kernel_us": r_ms * 1e3,
+            "mean_list": total / n, "rebuilds": reb}
+
+
 def bench_adjoint(dev, quiet: bool):
     """Gradient of a force-matching loss through a 200-step trajectory of the
     N = 32768 binary mixture (checkpoints and loss frames every 20 steps), and
@@ -386,6 +446,7 @@ def main(argv=None) -> int:
     if not a.no_forms:
         result["batched"] = bench_batched(dev, 100, a.quiet)
         result["sph"] = bench_sph(dev, 500, a.quiet)
+        result["sph_dambreak"] = bench_dambreak(dev, a.quiet)
         result["adjoint"] = bench_adjoint(dev, a.quiet)
     if not a.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(s.pos, s.box, a.cpu_seconds, a.quiet)

@@ -70,9 +70,17 @@ typedef struct {
     float sig[3];
 } fpm_lj_params;
 
-/* Weakly compressible SPH of section 4.2 (Eqs. 1-5) with a Wendland C2
- * kernel of support 2h.  Boundary particles (kind 1) enter every sum and
- * evolve their density by Eq. 2, but do not move. */
+/* Weakly compressible SPH of section 4.2 (Eqs. 1-5).  Kernels of support
+ * 2h: 0 = Wendland C2, W = aD (1 - q/2)^4 (2q + 1), aD = 21 / (16 pi h^3);
+ * 1 = the classic cubic spline the paper names, W = aD (1 - 3q^2/2 + 3q^3/4)
+ * for q < 1, aD (2 - q)^3 / 4 for 1 <= q < 2, aD = 1 / (pi h^3) (the paper's
+ * cutoff 2 sqrt(3) dp is h = sqrt(3) dp); q = r/h.  Boundary particles
+ * (kind 1) enter every sum and evolve their density by Eq. 2, but do not
+ * move.  Time stepping (fpm_sph_step): scheme 0 kick-drift-kick; scheme 1
+ * the Verlet scheme with dynamic step (section 4.2, ref. [46]):
+ * x' = x + dt v + dt^2/2 a, v' = v_prev + 2 dt a, rho' = rho_prev + 2 dt D,
+ * where every verlet_every-th step (counted from the first step after the
+ * state was set) takes the Euler form v' = v + dt a, rho' = rho + dt D. */
 typedef struct {
     float h;        /* smoothing length; neighbours within 2h (r_cut = 2h) */
     float mass;     /* particle mass */
@@ -83,6 +91,11 @@ typedef struct {
     float eta2;     /* eta^2 of Eq. 5's mu (absolute, length^2) */
     float g[3];     /* body acceleration (gravity) */
     float cfl;      /* CFL factor of the dynamic time step */
+    int32_t kernel; /* 0 Wendland C2, 1 cubic spline */
+    float cbar;     /* sound speed of Eq. 5's viscosity (the paper's
+                       sqrt(g h_swl)); <= 0 takes c0 */
+    int32_t scheme; /* 0 kick-drift-kick, 1 Verlet */
+    int32_t verlet_every; /* scheme 1: period of the Euler-form steps (>= 1) */
 } fpm_sph_params;
 
 /* ---- context (the library-start/finish calls of the section 4.1 listing) ---- */
@@ -216,8 +229,10 @@ int fpm_step(fpm_ctx *ctx, const fpm_lj_params *prm, float dt, int32_t nsteps,
  * density rates; d_dt[1] (FP32, may be NULL) receives the CFL time step
  * dt = cfl * min(min_a sqrt(h/|f_a|), h / (c0 + max_ab |mu_ab|)). */
 int fpm_sph_rates(fpm_ctx *ctx, const fpm_sph_params *prm, float *d_dt);
-/* nsteps kick-drift-kick steps with the dynamic dt on the device;
- * d_hist (may be NULL) receives nsteps FP64 rows {t, dt, KE, max|v|}. */
+/* nsteps time steps of prm->scheme with the dynamic dt on the device (the
+ * dt of a step comes from the rates at its start); d_hist (may be NULL)
+ * receives nsteps FP64 rows {t, dt, KE, max|v|}.  FPM_EINVAL for an unknown
+ * kernel or scheme, or verlet_every < 1 with scheme 1. */
 int fpm_sph_step(fpm_ctx *ctx, const fpm_sph_params *prm, int32_t nsteps, double *d_hist);
 
 /* ---- status ---- */

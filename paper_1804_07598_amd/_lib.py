@@ -38,7 +38,8 @@ class fpm_lj_params(C.Structure):
 class fpm_sph_params(C.Structure):
     _fields_ = [("h", C.c_float), ("mass", C.c_float), ("rho0", C.c_float), ("c0", C.c_float),
                 ("gamma", C.c_float), ("alpha", C.c_float), ("eta2", C.c_float),
-                ("g", C.c_float * 3), ("cfl", C.c_float)]
+                ("g", C.c_float * 3), ("cfl", C.c_float), ("kernel", C.c_int32),
+                ("cbar", C.c_float), ("scheme", C.c_int32), ("verlet_every", C.c_int32)]
 
 
 _P = C.c_void_p
@@ -220,8 +221,10 @@ def lj_params(eps=(1.0, 1.0, 1.0), sig=(1.0, 1.0, 1.0), n_types: int = 1) -> fpm
 
 
 def sph_params(h, mass, rho0, c0, gamma=7.0, alpha=0.1, eta2=None, g=(0.0, 0.0, -9.81),
-               cfl=0.2) -> fpm_sph_params:
+               cfl=0.2, *, kernel=0, cbar=0.0, scheme=0, verlet_every=40) -> fpm_sph_params:
     p = fpm_sph_params()
+    p.kernel, p.cbar, p.scheme, p.verlet_every = int(kernel), float(cbar), int(scheme), \
+        int(verlet_every)
     p.h, p.mass, p.rho0, p.c0, p.gamma, p.alpha = (float(h), float(mass), float(rho0),
                                                     float(c0), float(gamma), float(alpha))
     p.eta2 = float(0.01 * h * h if eta2 is None else eta2)

@@ -142,6 +142,7 @@ size_t layout(const fpm_ctx *c, const Plan &P, char *base, State *st,
     s.nnb = (uint32_t *)take(ns * sizeof(uint32_t));
     s.part = (double *)take((size_t)P.nblk * kSlots * sizeof(double));
     s.aux = (float4 *)take(ns * sizeof(float4));
+    for (int k = 0; k < 2; k++) s.old[k] = (float4 *)take(ns * sizeof(float4));
     s.ctl = (Ctl *)take(sizeof(Ctl));
     s.sctl = (SysCtl *)take(nsys * sizeof(SysCtl));
     s.sys = (const SysDesc *)take(nsys * sizeof(SysDesc));
@@ -246,9 +247,12 @@ hipError_t lj_step_body(fpm_ctx *c, const fpm_lj_params &p, float dt, double *th
     return e;
 }
 
-// One SPH kick-drift-kick step with the device time step.
+// One SPH step with the device time step: kick-drift-kick (the closing half
+// kick of the previous step fused with this step's opening one) or Verlet.
 hipError_t sph_step_body(fpm_ctx *c, const fpm_sph_params &p, double *hist, bool first) {
-    hipError_t e = launch_sph_integrate(c, p, first ? kKickDriftFirst : kKickKickDrift);
+    hipError_t e = p.scheme == 1
+                       ? launch_sph_verlet(c, p)
+                       : launch_sph_integrate(c, p, first ? kKickDriftFirst : kKickKickDrift);
     if (e == hipSuccess) e = launch_finalize(c, kFinBuild | kFinDisp, nullptr, nullptr);
     if (e == hipSuccess) e = refresh_lists(c);
     if (e == hipSuccess) e = launch_sph_rates(c, p);
@@ -269,7 +273,9 @@ bool valid_sph(const fpm_sph_params *p) {
     for (float x : v)
         if (!(isfinite(x) && x > 0.f)) return false;
     return isfinite(p->alpha) && p->alpha >= 0.f && isfinite(p->eta2) && p->eta2 >= 0.f &&
-           isfinite(p->g[0]) && isfinite(p->g[1]) && isfinite(p->g[2]);
+           isfinite(p->g[0]) && isfinite(p->g[1]) && isfinite(p->g[2]) && isfinite(p->cbar) &&
+           (p->kernel == 0 || p->kernel == 1) && (p->scheme == 0 || p->scheme == 1) &&
+           (p->scheme == 0 || p->verlet_every >= 1);
 }
 
 }  // namespace
@@ -464,6 +470,7 @@ int fpm_set_particles(fpm_ctx *c, int64_t n, const float *pos, const float *vel,
     HIPCHK(c, refresh_and_account(c));
     c->have_particles = true;
     c->forces_valid = false;
+    c->sph_restart = true;
     return FPM_OK;
 }
 
@@ -488,6 +495,7 @@ int fpm_set_positions(fpm_ctx *c, const float *pos) {
     HIPCHK(c, launch_set_positions(c, pos));
     HIPCHK(c, launch_finalize(c, kFinDisp, nullptr, nullptr));
     c->forces_valid = false;
+    c->sph_restart = true;
     return FPM_OK;
 }
 
@@ -497,6 +505,7 @@ int fpm_set_density(fpm_ctx *c, const float *rho) {
     if (!rho) return fail(c, FPM_EINVAL, "null density");
     HIPCHK(c, launch_set_density(c, rho));
     c->forces_valid = false;
+    c->sph_restart = true;
     return FPM_OK;
 }
 
@@ -679,6 +688,20 @@ int fpm_sph_step(fpm_ctx *c, const fpm_sph_params *p, int32_t nsteps, double *hi
     if (c->nsys != 1) return fail(c, FPM_EINVAL, "SPH runs on a single system");
     if (nsteps < 0) return fail(c, FPM_EINVAL, "bad step count");
     if (nsteps == 0) return FPM_OK;
+    // the Verlet scheme keeps the previous step's (v, rho), which the cell
+    // sort must carry along; a switch of scheme restarts its step count
+    const int keep = p->scheme == 1;
+    if (c->st.keep_old != keep) {
+        c->st.keep_old = keep;
+        c->sph_restart = true;
+        drop_graphs(c);
+    }
+    if (!keep) {
+        c->sph_restart = true;
+    } else if (c->sph_restart) {
+        HIPCHK(c, launch_sph_restart(c));
+        c->sph_restart = false;
+    }
     if (!c->forces_valid || !c->sph || c->build_pending) {
         HIPCHK(c, refresh_and_account(c));
         HIPCHK(c, launch_sph_rates(c, *p));
@@ -711,7 +734,7 @@ int fpm_sph_step(fpm_ctx *c, const fpm_sph_params *p, int32_t nsteps, double *hi
     int left = nsteps - 1;
     for (; left >= kChunk; left -= kChunk) HIPCHK(c, hipGraphLaunch(c->s_chunk, c->stream));
     for (; left > 0; left--) HIPCHK(c, hipGraphLaunch(c->s_one, c->stream));
-    HIPCHK(c, launch_sph_integrate(c, *p, kKickOnly));
+    if (p->scheme == 0) HIPCHK(c, launch_sph_integrate(c, *p, kKickOnly));
     HIPCHK(c, launch_finalize(c, kFinBuild, nullptr, nullptr));
     return FPM_OK;
 }

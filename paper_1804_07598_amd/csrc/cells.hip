@@ -195,11 +195,13 @@ __global__ void k_rank_gather(State st) {
         st.vel[1][f] = st.vel[0][me.y];
         st.id[1][f] = me.x;
         st.xbuild[f] = p;
+        if (st.keep_old) st.old[1][f] = st.old[0][me.y];
     } else {
         st.pos[1][i] = st.pos[0][i];
         st.vel[1][i] = st.vel[0][i];
         st.id[1][i] = st.id[0][i];
         st.xbuild[i] = st.pos[0][i];
+        if (st.keep_old) st.old[1][i] = st.old[0][i];
     }
 }
 
@@ -210,6 +212,7 @@ __global__ void k_copy_back(State st) {
     st.pos[0][i] = st.pos[1][i];
     st.vel[0][i] = st.vel[1][i];
     st.id[0][i] = st.id[1][i];
+    if (st.keep_old) st.old[0][i] = st.old[1][i];
 }
 
 // Caller-order view of the cell lists: offsets renumbered into the packed

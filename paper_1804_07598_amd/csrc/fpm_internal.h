@@ -91,6 +91,8 @@ struct Ctl {
     float sph_dt;           // SPH time step of the next step (from the latest rates)
     float sph_dt_last;      // SPH time step of the last completed step
     double sph_time;        // simulated SPH time
+    int32_t sph_nstep;      // SPH steps since the state was set (Verlet/Euler choice)
+    int32_t sph_pad;
 };
 
 // Pointers into the workspace.  Buffer 0 holds the cell-sorted state between
@@ -110,6 +112,8 @@ struct State {
     uint32_t *nnb;          // list length | kWrapBit
     double *part;           // per-block partials, part[slot * pstride + block]
     float4 *aux;            // per-slot scratch (adjoint input, sorted)
+    float4 *old[2];         // SPH Verlet: previous step's (v, rho), double buffered like pos
+    int32_t keep_old;       // 1: the cell sort carries old[] along
     Ctl *ctl;
     SysCtl *sctl;           // per system
     const SysDesc *sys;     // per system
@@ -184,6 +188,7 @@ struct fpm_ctx {
     hipGraphExec_t s_first = nullptr, s_chunk = nullptr, s_one = nullptr;  // SPH graphs
     fpm_sph_params s_prm{};
     double *s_hist = nullptr;
+    bool sph_restart = true;           // the SPH step count restarts at the next step call
     // event timing of eager launches (fpm_set_profiling)
     struct Timed {
         std::string name;
@@ -230,6 +235,8 @@ hipError_t launch_neighbors_out(fpm_ctx *c, int32_t *counts, int32_t *cols);
 hipError_t launch_reset_step(fpm_ctx *c);
 hipError_t launch_sph_rates(fpm_ctx *c, const fpm_sph_params &p);
 hipError_t launch_sph_integrate(fpm_ctx *c, const fpm_sph_params &p, int mode);
+hipError_t launch_sph_verlet(fpm_ctx *c, const fpm_sph_params &p);
+hipError_t launch_sph_restart(fpm_ctx *c);  // the next SPH step counts as the first
 hipError_t launch_sph_finalize(fpm_ctx *c, const fpm_sph_params &p, int mode, float *dt_out,
                                double *hist);
 

@@ -4,18 +4,24 @@
 //   dv_a/dt   = -sum_b m ((P_a + P_b)/(rho_a rho_b) + Pi_ab) gradW_ab + g     (Eq. 1)
 //   drho_a/dt =  sum_b m v_ab . gradW_ab                                     (Eq. 2)
 //   P = B ((rho/rho0)^gamma - 1), B = c0^2 rho0 / gamma                      (Eqs. 3-4)
-//   Pi_ab = -alpha c0 mu_ab / rhobar_ab when v_ab . x_ab < 0, else 0,
+//   Pi_ab = -alpha cbar mu_ab / rhobar_ab when v_ab . x_ab < 0, else 0,
 //   mu_ab = h v_ab . x_ab / (|x_ab|^2 + eta^2), rhobar_ab = (rho_a + rho_b)/2 (Eq. 5)
-// with x_ab = x_a - x_b, v_ab = v_a - v_b and the Wendland C2 kernel
-// W(q) = a_D (1 - q/2)^4 (2q + 1), q = r/h, a_D = 21 / (16 pi h^3), whose
-// gradient is gradW_ab = -(5 a_D / h^2) (1 - q/2)^3 x_ab.
+// with x_ab = x_a - x_b, v_ab = v_a - v_b, cbar the viscosity's sound speed
+// (c0 unless given) and a kernel of support 2h, q = r/h:
+//   Wendland C2  W = a_D (1 - q/2)^4 (2q + 1), a_D = 21 / (16 pi h^3),
+//                gradW_ab = -(5 a_D / h^2) (1 - q/2)^3 x_ab;
+//   cubic spline W = a_D (1 - 3q^2/2 + 3q^3/4) (q < 1), a_D (2 - q)^3 / 4
+//                (1 <= q < 2), a_D = 1 / (pi h^3),
+//                gradW_ab = (a_D / h^2) (-3 + 9q/4) x_ab (q < 1),
+//                           -(3 a_D / (4 h)) (2 - q)^2 / r x_ab (1 <= q < 2).
 // Boundary particles (kind 1) take part in every sum and evolve their density
 // by Eq. 2, but carry no acceleration.  Pair terms are evaluated in FP64 from
 // exact FP32 separations (the pressure terms cancel to within a few percent of
 // gravity in a resting column, which FP32 pair terms cannot resolve to 1e-5).
 //
-// Time stepping is kick-drift-kick on (v, rho) with the time step chosen on
-// the device from the CFL terms of the latest rates:
+// Time stepping is kick-drift-kick on (v, rho), or the Verlet scheme (ref.
+// [46] of section 4.2) with periodic Euler-form steps, with the time step
+// chosen on the device from the CFL terms of the latest rates:
 //   dt = cfl * min(min_a sqrt(h / |a_a|), h / (c0 + max_ab |mu_ab|)).
 #include "geom.h"
 
@@ -23,8 +29,9 @@ namespace fpm {
 namespace {
 
 struct SphCoef {
-    double h, m, rho0, inv_rho0, B, gamma, alpha_c0, eta2, kgrad;  // kgrad = 5 a_D / h^2
+    double h, m, rho0, inv_rho0, B, gamma, alpha_c0, eta2, kgrad;  // alpha_c0 = alpha cbar
     double half_inv_h;  // 1 / (2 h)
+    double inv_h, cin, cout;  // cubic spline: 1/h, a_D / h^2, 3 a_D / (4 h)
     double rc2lo, rc2hi;
     float g[3];
     int gamma7;
@@ -60,7 +67,21 @@ struct SphAcc {
     double ax = 0.0, ay = 0.0, az = 0.0, dr = 0.0, mu = 0.0;
 };
 
-template <bool IMG>
+// gradW_ab / x_ab at distance r (KER 0 Wendland C2, 1 cubic spline).
+template <int KER>
+__device__ __forceinline__ double grad_factor(double r, const SphCoef &k) {
+    if (KER == 0) {
+        const double t = fma(-r, k.half_inv_h, 1.0);
+        return -k.kgrad * t * t * t;  // kgrad = 5 a_D / h^2
+    }
+    const double q = r * k.inv_h;
+    const double t = 2.0 - q;
+    const double outer = -k.cout * t * t * rcp64(r);
+    const double inner = k.cin * fma(2.25, q, -3.0);
+    return q < 1.0 ? inner : outer;
+}
+
+template <bool IMG, int KER>
 __device__ __forceinline__ void sph_pair(SphAcc &s, float3 pi, double xi, double yi, double zi,
                                          float4 vi, double Pa_over, float4 q, float4 w,
                                          const Box &b, float rc2, const SphCoef &k) {
@@ -79,9 +100,7 @@ __device__ __forceinline__ void sph_pair(SphAcc &s, float3 pi, double xi, double
     if (!in && r2 <= k.rc2hi)
         in = (IMG ? dist2_pred(pi, xyz(q), b) : dist2_direct(pi, xyz(q))) <= rc2;
     if (in) {
-        const double r = sqrt64(r2);
-        const double t = fma(-r, k.half_inv_h, 1.0);
-        const double gw = -k.kgrad * t * t * t;  // gradW = gw * x_ab
+        const double gw = grad_factor<KER>(sqrt64(r2), k);  // gradW = gw * x_ab
         const double rho_b = (double)w.w;
         const double vx = (double)vi.x - (double)w.x, vy = (double)vi.y - (double)w.y,
                      vz = (double)vi.z - (double)w.z;
@@ -102,7 +121,7 @@ __device__ __forceinline__ void sph_pair(SphAcc &s, float3 pi, double xi, double
     }
 }
 
-template <bool IMG>
+template <bool IMG, int KER>
 __device__ __forceinline__ void sph_walk(SphAcc &s, const float4 *__restrict__ pos,
                                          const float4 *__restrict__ vel,
                                          const int4 *__restrict__ lst, int cnt, int self,
@@ -126,10 +145,11 @@ __device__ __forceinline__ void sph_walk(SphAcc &s, const float4 *__restrict__ p
         }
 #pragma unroll
         for (int u = 0; u < 4; u++)
-            sph_pair<IMG>(s, pi, xi, yi, zi, vi, Pa, q[u], w[u], b, rc2, k);
+            sph_pair<IMG, KER>(s, pi, xi, yi, zi, vi, Pa, q[u], w[u], b, rc2, k);
     }
 }
 
+template <int KER>
 __global__ __launch_bounds__(kBlock) void k_sph_rates(State st, float rc2, SphCoef k,
                                                       int cap4) {
     const SysDesc &d = st.sys[block_system(st)];
@@ -152,9 +172,9 @@ __global__ __launch_bounds__(kBlock) void k_sph_rates(State st, float rc2, SphCo
     const double Pa = tait((double)vi.w, k);
     SphAcc s;
     if (img_wave)
-        sph_walk<true>(s, pos, vel, lst, cnt, (int)i, pi4, vi, Pa, b, rc2, k);
+        sph_walk<true, KER>(s, pos, vel, lst, cnt, (int)i, pi4, vi, Pa, b, rc2, k);
     else
-        sph_walk<false>(s, pos, vel, lst, cnt, (int)i, pi4, vi, Pa, b, rc2, k);
+        sph_walk<false, KER>(s, pos, vel, lst, cnt, (int)i, pi4, vi, Pa, b, rc2, k);
     const bool fluid = __float_as_int(pi4.w) == 0;
     double accmin = 1e300;
     if (active) {
@@ -220,6 +240,58 @@ __global__ __launch_bounds__(kBlock) void k_sph_integrate(State st) {
     block_partials<3>(v3, slot, op, st.part, st.pstride);
 }
 
+// One step of the Verlet scheme on (x, v, rho) with rates (a, D) of the
+// current state and the step dt of those rates:
+//   x' = x + dt v + dt^2/2 a (fluid), v' = v_prev + 2 dt a (fluid),
+//   rho' = rho_prev + 2 dt D,
+// or on every `every`-th step since the state was set (the first one
+// included) the Euler form v' = v + dt a, rho' = rho + dt D.  The state
+// before the step becomes the previous one.  Boundary particles keep x, v.
+__global__ __launch_bounds__(kBlock) void k_sph_verlet(State st, int every) {
+    const SysDesc &d = st.sys[block_system(st)];
+    const Box b = d.box;
+    const int64_t i = global_slot();
+    const Ctl *ctl = st.ctl;
+    const float dt = ctl->sph_dt;
+    const bool euler = ctl->sph_nstep % every == 0;
+    const float f2 = euler ? dt : 2.0f * dt;
+    const float hdt2 = 0.5f * dt * dt;
+    double ke = 0.0, vmax = 0.0, d2 = 0.0;
+    if (i - d.slot_base < d.n) {
+        const float4 v = st.vel[0][i];  // (v, rho) now
+        const float4 o = st.old[0][i];  // (v, rho) one step before
+        const float4 f = st.frc[i];     // (a, D)
+        const float4 base = euler ? v : o;
+        float4 p = st.pos[0][i];
+        float4 nv = v;
+        nv.w = base.w + f2 * f.w;
+        if (__float_as_int(p.w) == 0) {
+            nv.x = base.x + f2 * f.x;
+            nv.y = base.y + f2 * f.y;
+            nv.z = base.z + f2 * f.z;
+            p.x = (p.x + dt * v.x) + hdt2 * f.x;
+            p.y = (p.y + dt * v.y) + hdt2 * f.y;
+            p.z = (p.z + dt * v.z) + hdt2 * f.z;
+            st.pos[0][i] = p;
+            if (!isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z)) st.ctl->nonfinite = 1;
+        }
+        st.old[0][i] = v;
+        st.vel[0][i] = nv;
+        const double v2 = (double)nv.x * nv.x + (double)nv.y * nv.y + (double)nv.z * nv.z;
+        ke = 0.5 * v2;  // per unit mass; the finalize multiplies by m
+        vmax = sqrt(v2);
+        d2 = dist2_pred(xyz(st.xbuild[i]), xyz(p), b);
+    }
+    double v3[3] = {ke, vmax, d2};
+    const int slot[3] = {kSlotKE, kSlotVmax, kSlotDisp};
+    const int op[3] = {0, 1, 1};
+    block_partials<3>(v3, slot, op, st.part, st.pstride);
+}
+
+__global__ void k_sph_restart(Ctl *ctl) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) ctl->sph_nstep = 0;
+}
+
 // Reduces the CFL terms of the last rates into the next time step; with
 // `advance`, first moves the current step into the history (time, dt, kinetic
 // energy and largest speed of the last integrate).
@@ -275,6 +347,7 @@ __global__ __launch_bounds__(1024) void k_sph_finalize(State st, int nblk, SphCo
             hist[(int64_t)row * 4 + 3] = vmax;
         }
         st.sctl[0].step = row + 1;
+        ctl->sph_nstep += 1;
     }
     const double dt = (double)cfl * fmin(sqrt(acc), k.h / ((double)c0 + mu));
     ctl->sph_dt = (float)dt;
@@ -290,12 +363,16 @@ SphCoef make_coef(const fpm_ctx *c, const fpm_sph_params &p) {
     k.gamma = p.gamma;
     k.gamma7 = p.gamma == 7.0f;
     k.B = (double)p.c0 * (double)p.c0 * (double)p.rho0 / (double)p.gamma;
-    k.alpha_c0 = (double)p.alpha * (double)p.c0;
+    k.alpha_c0 = (double)p.alpha * (double)(p.cbar > 0.f ? p.cbar : p.c0);
     k.eta2 = p.eta2;
     const double h = p.h;
     const double aD = 21.0 / (16.0 * 3.14159265358979323846 * h * h * h);
     k.kgrad = 5.0 * aD / (h * h);
     k.half_inv_h = 0.5 / h;
+    const double aDc = 1.0 / (3.14159265358979323846 * h * h * h);
+    k.inv_h = 1.0 / h;
+    k.cin = aDc / (h * h);
+    k.cout = 0.75 * aDc / h;
     const double band = predicate_band(c);
     k.rc2lo = (double)c->rc2 * (1.0 - band);
     k.rc2hi = (double)c->rc2 * (1.0 + band);
@@ -307,8 +384,23 @@ SphCoef make_coef(const fpm_ctx *c, const fpm_sph_params &p) {
 
 hipError_t launch_sph_rates(fpm_ctx *c, const fpm_sph_params &p) {
     const SphCoef k = make_coef(c, p);
-    hipLaunchKernelGGL(k_sph_rates, dim3(c->nblk), dim3(kBlock), 0, c->stream, c->st, c->rc2, k,
-                       c->cap4);
+    if (p.kernel == 1)
+        hipLaunchKernelGGL(k_sph_rates<1>, dim3(c->nblk), dim3(kBlock), 0, c->stream, c->st,
+                           c->rc2, k, c->cap4);
+    else
+        hipLaunchKernelGGL(k_sph_rates<0>, dim3(c->nblk), dim3(kBlock), 0, c->stream, c->st,
+                           c->rc2, k, c->cap4);
+    return hipGetLastError();
+}
+
+hipError_t launch_sph_verlet(fpm_ctx *c, const fpm_sph_params &p) {
+    hipLaunchKernelGGL(k_sph_verlet, dim3(c->nblk), dim3(kBlock), 0, c->stream, c->st,
+                       p.verlet_every);
+    return hipGetLastError();
+}
+
+hipError_t launch_sph_restart(fpm_ctx *c) {
+    hipLaunchKernelGGL(k_sph_restart, dim3(1), dim3(64), 0, c->stream, c->st.ctl);
     return hipGetLastError();
 }
 

@@ -338,6 +338,7 @@ __device__ __forceinline__ void copy_back(const State &st, int64_t s) {
     st.pos[0][s] = st.pos[1][s];
     st.vel[0][s] = st.vel[1][s];
     st.id[0][s] = st.id[1][s];
+    if (st.keep_old) st.old[0][s] = st.old[1][s];
 }
 
 // ---------------------------------------------------------------------------

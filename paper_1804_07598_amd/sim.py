@@ -194,7 +194,8 @@ class ParticleSim(_Sim):
         return dt
 
     def sph_step(self, nsteps: int, prm, hist: torch.Tensor | None = None):
-        """nsteps KDK steps; returns the (nsteps, 4) FP64 history {t, dt, KE, max|v|}."""
+        """nsteps steps of prm's scheme (kick-drift-kick or Verlet); returns the
+        (nsteps, 4) FP64 history {t, dt, KE, max|v|}."""
         if hist is None:
             hist = torch.zeros((max(nsteps, 1), 4), dtype=torch.float64, device=self.device)
         F.fpm_sph_step(self.ctx, prm, nsteps, hist)
