@@ -461,9 +461,12 @@ __device__ __forceinline__ bool scan_cells_group(const Group<G> &gr, const float
     return img;
 }
 
+// Eight and sixteen lanes per particle: registers held to 64 per lane, so
+// that the LDS budget (four 512-lane workgroups per CU) sets the occupancy;
+// the few values this spills are reloaded between runs, not inside them.
 template <int G>
-__global__ __launch_bounds__(64 * G) void k_verlet_grp(State st, const int32_t *blocks, float R2,
-                                                      int cap, int cap4, int lcap4) {
+__global__ __launch_bounds__(64 * G) __attribute__((amdgpu_waves_per_eu(G == 4 ? 1 : 8)))
+void k_verlet_grp(State st, const int32_t *blocks, float R2, int cap, int cap4, int lcap4) {
     constexpr int NC = (9 + G - 1) / G;  // neighbour columns held per lane
     extern __shared__ int4 lrow[];       // lcap4 * 64 int4: the row's first lcap4 groups
     __shared__ int rowc8[64];            // padded list lengths of the row
