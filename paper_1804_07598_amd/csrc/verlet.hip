@@ -839,18 +839,29 @@ __global__ __launch_bounds__(kColThreads) void k_verlet_cols(State st, float R2,
             copy_back(st, q);
 }
 
-// Longest list and total entries of the current lists (on request only).
-__global__ void k_list_stats(State st, int64_t nslots) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int c = i < nslots ? (int)(st.nnb[i] & ~kWrapBit) : 0;
-    int mx = c;
-    unsigned long long sm = (unsigned long long)c;
+// Longest list and total entries of the current lists (on request only): a
+// grid-stride pass, reduced per workgroup, one pair of atomics per workgroup.
+__global__ __launch_bounds__(256) void k_list_stats(State st, int64_t nslots) {
+    __shared__ int smx[4];
+    __shared__ unsigned long long ssm[4];
+    int mx = 0;
+    unsigned long long sm = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nslots;
+         i += (int64_t)gridDim.x * 256) {
+        const int c = (int)(st.nnb[i] & ~kWrapBit);
+        mx = max(mx, c);
+        sm += (unsigned long long)c;
+    }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         mx = max(mx, __shfl_xor(mx, o, 64));
         sm += __shfl_xor(sm, o, 64);
     }
-    if ((threadIdx.x & 63) == 0) {
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) smx[w] = mx, ssm[w] = sm;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < 4; k++) mx = max(mx, smx[k]), sm += ssm[k];
         atomicMax(&st.ctl->max_count, mx);
         atomicAdd((unsigned long long *)&st.ctl->total_count, sm);
     }
@@ -911,8 +922,9 @@ hipError_t launch_verlet_build(fpm_ctx *c) {
 
 hipError_t launch_list_stats(fpm_ctx *c) {
     hipLaunchKernelGGL(k_zero_stats, dim3(1), dim3(64), 0, c->stream, c->st.ctl);
-    hipLaunchKernelGGL(k_list_stats, dim3(grid_for(c->n_slots, 256)), dim3(256), 0, c->stream,
-                       c->st, c->n_slots);
+    const unsigned g = grid_for(c->n_slots, 256);
+    hipLaunchKernelGGL(k_list_stats, dim3(g < 512 ? g : 512), dim3(256), 0, c->stream, c->st,
+                       c->n_slots);
     return hipGetLastError();
 }
 
