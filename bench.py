@@ -321,6 +321,8 @@ def main(argv=None) -> int:
                     help="keep the library's default launch shapes")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched and adjoint measurements")
+    ap.add_argument("--form", choices=["batched", "sph", "sph_dambreak", "adjoint"],
+                    help="run only this form's measurement and print its JSON (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer 5 times (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -348,6 +350,13 @@ def main(argv=None) -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}), flush=True)
+        return 0
+    if a.form:
+        legs = {"batched": lambda: bench_batched(dev, 100, a.quiet),
+                "sph": lambda: bench_sph(dev, 500, a.quiet),
+                "sph_dambreak": lambda: bench_dambreak(dev, a.quiet),
+                "adjoint": lambda: bench_adjoint(dev, a.quiet)}
+        print(json.dumps({a.form: legs[a.form]()}), flush=True)
         return 0
     s = inputs.lj_config("lj1m")
     log(f"workload lj1m: N={s.n} L={s.L:.5f}", a.quiet)

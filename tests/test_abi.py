@@ -65,5 +65,15 @@ def test_host_side_errors_without_device():
         # calls that need particles fail cleanly
         assert L.fpm_build_verlet(ctx) == F.FPM_EINVAL
         assert L.fpm_step(ctx, None, ctypes.c_float(0.005), 1, None) == F.FPM_EINVAL
+        # size limits: n at most 2^26 - 1, list capacity at most 4096
+        assert L.fpm_workspace_size(ctx, 1 << 26, ctypes.byref(sz)) == F.FPM_EINVAL
+        assert L.fpm_workspace_size(ctx, (1 << 26) - 1, ctypes.byref(sz)) == 0
+        assert L.fpm_set_neighbor_params(ctx, 2.5, 0.3, 4097) == F.FPM_EINVAL
+        # launch-shape knobs outside their ranges
+        assert L.fpm_set_tuning(ctx, 5, 0, 0) == F.FPM_EINVAL
+        assert L.fpm_set_tuning(ctx, 4, 5, 0) == F.FPM_EINVAL
+        assert L.fpm_set_tuning(ctx, 2, 65, 0) == F.FPM_EINVAL
+        assert L.fpm_set_tuning(ctx, 0, 0, 6) == F.FPM_EINVAL
+        assert L.fpm_set_tuning(ctx, 4, 16, 4) == 0
     finally:
         L.fpm_destroy(ctx)

@@ -219,6 +219,26 @@ def test_overflow_is_reported(tuning):
     compare_sets(sim2, s.pos, s.box, O.radius2(RC, SKIN))
 
 
+@pytest.mark.parametrize("n", [1, 2])
+def test_degenerate_systems(n):
+    # one particle, or two beyond the list radius: empty lists, zero forces and
+    # energy, and free flight under velocity Verlet
+    pos = np.array([[1.0, 2.0, 3.0], [7.0, 8.0, 9.0]], np.float32)[:n]
+    vel = np.array([[0.5, -0.25, 0.125], [-1.0, 0.0, 2.0]], np.float32)[:n]
+    s = inputs.LJSystem(pos, vel, np.zeros(n, np.int32), 12.0, 0, 0, 0)
+    sim = make_sim(s)
+    counts, _ = sim.neighbors()
+    assert np.all(np_(counts) == 0)
+    out = np_(sim.lj_forces())
+    _, _, f = sim.get()
+    assert np.all(np_(f) == 0) and np.all(out == 0)
+    sim.step(4, dt=0.25)
+    sim.check()
+    p, v, _ = (np_(t) for t in sim.get())
+    assert np.array_equal(v, vel)
+    assert np.allclose(p, pos + 4 * 0.25 * vel, rtol=0, atol=1e-6)
+
+
 def test_cutoff_error():
     from paper_1804_07598_amd._lib import FpmError, FPM_ECUTOFF
     s = inputs.lj_lattice(64, 0.8442, 1.0, seed=2)  # L = 4.2 < 2 * 2.8
