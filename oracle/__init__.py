@@ -75,6 +75,11 @@ def lib():
             L.oracle_sph_cubic_w.argtypes = [C.c_double, C.c_double]
             L.oracle_sph_kernel_dwdr.restype = C.c_double
             L.oracle_sph_kernel_dwdr.argtypes = [C.c_double, C.c_double, C.c_int]
+        if hasattr(L, "oracle_dem_forces"):
+            L.oracle_dem_forces.restype = C.c_int
+            L.oracle_dem_forces.argtypes = [C.c_int64, f64p, f64p, f64p, f32p, i32p, f64p, C.c_int,
+                                            i64p, f64p, f64p, f64p, i64p, f64p, i32p]
+            L.oracle_dem_leapfrog.argtypes = [C.c_int64, f64p, f64p, f64p, f64p, f64p, f64p]
         if hasattr(L, "oracle_lj_vjp"):
             L.oracle_lj_vjp.argtypes = [C.c_int64, f32p, _opt(i32p), f32p, i32p, C.c_float, f64p,
                                         f64p, f64p, f64p, f64p]
@@ -435,6 +440,42 @@ def sph_verlet(pos, vel, rho, kind, L, per, R2, prm, cfl, nsteps, every):
 
     return verlet_steps(pos, vel, rho, np.asarray(kind) == 0, rates,
                         lambda a, mu: sph_dt(a, kind, mu, prm, cfl), nsteps, every)
+
+
+def dem_params_array(R, m, I, kn, kt, gn, gt=0.0, mu=0.5, g=(0.0, 0.0, 0.0), dt=1e-4, walls=0):
+    """The oracle's DEM parameter vector {R, m, I, kn, kt, gn, gt, mu, gx, gy, gz, dt, walls}."""
+    return np.array([R, m, I, kn, kt, gn, gt, mu, g[0], g[1], g[2], dt, walls], np.float64)
+
+
+def dem_empty_history(n, C=16):
+    return np.full((n, C), -1, np.int64), np.zeros((n, C, 3), np.float64)
+
+
+def dem_forces(x, v, w, L, per, prm, hist=None, C=16):
+    """Forces and torques of the Silbert grain model (Eqs. 9-12) at (x, v, w)
+    with contact history `hist` = (ids (n, C), u_t (n, C, 3)); returns
+    (F, T, new history, contact counts)."""
+    x, v, w = (np.ascontiguousarray(q, np.float64) for q in (x, v, w))
+    n = len(x)
+    hid, hu = dem_empty_history(n, C) if hist is None else (np.ascontiguousarray(hist[0], np.int64),
+                                                           np.ascontiguousarray(hist[1], np.float64))
+    F = np.empty((n, 3)); T = np.empty((n, 3))
+    hid2, hu2 = dem_empty_history(n, C)
+    nc = np.empty(n, np.int32)
+    lib().oracle_dem_forces(n, x, v, w, _box(L), _per(per), _f64(prm), int(C), hid, hu, F, T,
+                            hid2, hu2, nc)
+    return F, T, (hid2, hu2), nc
+
+
+def dem_steps(x, v, w, L, per, prm, nsteps, hist=None, C=16):
+    """nsteps of forces (dem_forces) and the leapfrog of Eq. 13 on FP64 state.
+    Returns (x, v, w, history, F, T, contact counts) after the last step."""
+    x, v, w = (np.array(q, np.float64) for q in (x, v, w))
+    F = T = nc = None
+    for _ in range(nsteps):
+        F, T, hist, nc = dem_forces(x, v, w, L, per, prm, hist, C)
+        lib().oracle_dem_leapfrog(len(x), x, v, w, F, T, _f64(prm))
+    return x, v, w, hist, F, T, nc
 
 
 def num_threads() -> int:

@@ -6,7 +6,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["oracle.c", "oracle_sph.c", "oracle_adjoint.c"]
+SOURCES = ["oracle.c", "oracle_sph.c", "oracle_adjoint.c", "oracle_dem.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 
