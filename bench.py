@@ -252,6 +252,67 @@ def bench_dambreak(dev, quiet: bool, t_end: float = 1.5, chunk: int = 2000,
             "mean_list": total / n, "rebuilds": reb}
 
 
+def bench_dem(dev, quiet: bool, steps: int = 2000, warmup: int = 200, scale: float = 4.2):
+    """Section 4.5's granular avalanche: the Silbert grain model with Hertzian
+    contacts, tangential history and Coulomb cap, x walls, periodic y and a
+    floor, gravity tilted by 30 degrees; the block at scale 4.2 holds 688,380
+    grains (the paper's single-core figure is for 677,310)."""
+    import torch
+    from paper_1804_07598_amd import _lib as F
+    from paper_1804_07598_amd import inputs
+    from paper_1804_07598_amd.sim import ParticleSim
+    A = inputs.DEM_AVALANCHE
+    s = inputs.dem_avalanche(scale)
+    R = A["R"]
+    prm = F.dem_params(R, A["mass"], A["inertia"], A["kn"], A["kt"], A["gn"], A["gt"], A["mu"],
+                       inputs.dem_avalanche_gravity(), A["dt"], A["walls"])
+    sim = ParticleSim(s.pos, s.L, s.periodic, vel=s.vel, r_cut=2 * R, skin=0.1 * R, max_nbr=32,
+                      device=dev, dem_contacts=16)
+    sim.set_omega(s.omega)
+    sim.dem_step(warmup, prm)
+    torch.cuda.synchronize()
+    sim.check()
+    reb0, _, _ = sim.counters()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    sim.dem_step(steps, prm)
+    e1.record()
+    torch.cuda.synchronize()
+    sim.check()
+    ms = e0.elapsed_time(e1)
+    reb1, _, total = sim.counters()
+    _, _, nc = sim.get_dem()
+    cbar = float(nc.double().mean())
+    F.fpm_set_profiling(sim.ctx, True)
+    for _ in range(20):
+        sim.dem_forces(prm)
+    f_ms, _ = F.fpm_kernel_time(sim.ctx, "dem_forces")
+    F.fpm_set_profiling(sim.ctx, False)
+    sim.close()
+    n = len(s.pos)
+    nbar = total / n
+    # per grain: pos, vel, omega, id, list count 52 B; list 4 nbar; history
+    # rows read and written 2 x 16 x 4 B of ids; u_t of the contacts read and
+    # written 2 x 16 cbar; force, torque 32 B; contact count 4 B
+    bytes_f = n * (52.0 + 4.0 * nbar + 128.0 + 32.0 * cbar + 36.0)
+    achieved = bytes_f / (f_ms / 1e3) / 1e9
+    log(f"DEM avalanche: {n} grains, {steps} steps in {ms:.1f} ms ({ms / steps * 1e3:.1f} us/step), "
+        f"forces kernel {f_ms * 1e3:.1f} us, mean list {nbar:.2f}, mean contacts {cbar:.2f}, "
+        f"rebuilds {reb1 - reb0}", quiet)
+    return {"workload": "DEM avalanche (Silbert model), synthetic block 149 x 105 x 44 grains "
+                        "R=0.06 at spacing 2R in a 35.28 x 12.6 x 13.356 domain, x walls, "
+                        "periodic y, floor, |g|=5e-4 tilted 30 deg, dt=0.01, N=688,380",
+            "grains": n, "steps": steps, "value": n * steps / (ms / 1e3),
+            "unit": "grain-steps/s", "ms_per_step": ms / steps,
+            "paper_single_core_ms_per_step": 320.0,
+            "forces_kernel_us": f_ms * 1e3, "mean_list": nbar, "mean_contacts": cbar,
+            "rebuilds": reb1 - reb0,
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                         "bytes_per_launch": bytes_f}}
+
+
 def bench_adjoint(dev, quiet: bool):
     """Gradient of a force-matching loss through a 200-step trajectory of the
     N = 32768 binary mixture (checkpoints and loss frames every 20 steps), and
@@ -321,7 +382,7 @@ def main(argv=None) -> int:
                     help="keep the library's default launch shapes")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched and adjoint measurements")
-    ap.add_argument("--form", choices=["batched", "sph", "sph_dambreak", "adjoint"],
+    ap.add_argument("--form", choices=["batched", "sph", "sph_dambreak", "adjoint", "dem"],
                     help="run only this form's measurement and print its JSON (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer 5 times (reference for the "
@@ -355,7 +416,8 @@ def main(argv=None) -> int:
         legs = {"batched": lambda: bench_batched(dev, 100, a.quiet),
                 "sph": lambda: bench_sph(dev, 500, a.quiet),
                 "sph_dambreak": lambda: bench_dambreak(dev, a.quiet),
-                "adjoint": lambda: bench_adjoint(dev, a.quiet)}
+                "adjoint": lambda: bench_adjoint(dev, a.quiet),
+                "dem": lambda: bench_dem(dev, a.quiet)}
         print(json.dumps({a.form: legs[a.form]()}), flush=True)
         return 0
     s = inputs.lj_config("lj1m")
@@ -457,6 +519,7 @@ def main(argv=None) -> int:
         result["sph"] = bench_sph(dev, 500, a.quiet)
         result["sph_dambreak"] = bench_dambreak(dev, a.quiet)
         result["adjoint"] = bench_adjoint(dev, a.quiet)
+        result["dem"] = bench_dem(dev, a.quiet)
     if not a.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(s.pos, s.box, a.cpu_seconds, a.quiet)
     print(json.dumps(result), flush=True)

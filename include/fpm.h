@@ -98,6 +98,29 @@ typedef struct {
     int32_t verlet_every; /* scheme 1: period of the Euler-form steps (>= 1) */
 } fpm_sph_params;
 
+/* Discrete-element grains of section 4.5: the Silbert model with Hertzian
+ * contacts (Eqs. 9-12) and the leapfrog of Eq. 13.  All grains have radius R,
+ * mass m and moment of inertia I; (p, q) touch when |r_pq| < 2R (FP64 from the
+ * exact separation of the FP32 coordinates, minimum image).  With
+ * n = r_pq / |r_pq|, delta = 2R - |r_pq|, s = sqrt(delta / 2R), m_eff = m / 2
+ * and the contact point midway between the centres (arm a = |r_pq| / 2):
+ * v_pq = v_p - v_q - a (w_p + w_q) x n, v_n its normal part, v_t the rest;
+ * the tangential history u_t of the pair grows by v_t dt and loses its normal
+ * part (Eq. 10); F_n = s (kn delta n - gn m_eff v_n), F_t = s (-kt u_t -
+ * gt m_eff v_t), F_t capped at mu |F_n| with u_t reset to match (Coulomb);
+ * torque (-a n) x F_t.  Walls (bit 1: planes x = 0 and x = L_x; bit 2: floor
+ * z = 0) add Eq. 11's normal force with delta = R - distance and m_eff = m.
+ * Gravity m g.  A pair that separates forgets its history. */
+typedef struct {
+    float R, mass, inertia;
+    float kn, kt;   /* elastic constants */
+    float gn, gt;   /* damping constants */
+    float mu;       /* Coulomb friction coefficient */
+    float g[3];     /* gravity */
+    float dt;       /* time step */
+    int32_t walls;  /* bit mask, see above */
+} fpm_dem_params;
+
 /* ---- context (the library-start/finish calls of the section 4.1 listing) ---- */
 
 /* Creates a context bound to `stream` (a hipStream_t, or NULL). */
@@ -234,6 +257,32 @@ int fpm_sph_rates(fpm_ctx *ctx, const fpm_sph_params *prm, float *d_dt);
  * receives nsteps FP64 rows {t, dt, KE, max|v|}.  FPM_EINVAL for an unknown
  * kernel or scheme, or verlet_every < 1 with scheme 1. */
 int fpm_sph_step(fpm_ctx *ctx, const fpm_sph_params *prm, int32_t nsteps, double *d_hist);
+
+/* ---- DEM (section 4.5) ---- */
+
+/* Turns on DEM storage: a contact history of max_contacts (1..64) partners per
+ * grain and per-grain angular velocities.  Call before fpm_workspace_size and
+ * fpm_set_particles (single system; the Verlet list radius r_cut + skin must
+ * cover 2R).  The angular velocity shares storage with SPH's Verlet scheme:
+ * do not mix DEM and SPH on one context. */
+int fpm_set_dem(fpm_ctx *ctx, int32_t max_contacts);
+/* Angular velocities (device, caller order, n x 3; NULL = zero); clears the
+ * contact history.  fpm_set_particles starts from zero and no history. */
+int fpm_set_omega(fpm_ctx *ctx, const float *d_omega);
+/* Forces and torques at the current state, advancing the contact history by
+ * one step (Eq. 10 is part of the evaluation).  FPM_EOVERFLOW (from
+ * fpm_check) when a grain has more than max_contacts contacts. */
+int fpm_dem_forces(fpm_ctx *ctx, const fpm_dem_params *prm);
+/* nsteps of: forces (as fpm_dem_forces), then the leapfrog of Eq. 13,
+ * v += dt F / m, x += dt v, w += dt T / I; lists rebuilt on the device when
+ * some grain moved more than skin/2. */
+int fpm_dem_step(fpm_ctx *ctx, const fpm_dem_params *prm, int32_t nsteps);
+/* Caller-order outputs (any may be NULL): angular velocities and the last
+ * torques (n x 3), contact counts (n). */
+int fpm_get_dem(fpm_ctx *ctx, float *d_omega, float *d_torque, int32_t *d_ncontact);
+/* The contact history in caller order: d_ids (n x max_contacts partner caller
+ * indices, -1 = empty) and d_ut (n x max_contacts x 3). */
+int fpm_get_contacts(fpm_ctx *ctx, int32_t *d_ids, float *d_ut);
 
 /* ---- status ---- */
 

@@ -1,6 +1,6 @@
 /*
  * FP64 CPU oracle for the discrete-element grains of OpenFPM's DEM client
- * (the Silbert grain model with Hertzian contacts, Eqs. 9-13).
+ * (section 4.5: the Silbert grain model with Hertzian contacts, Eqs. 9-13).
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may call, link or
  * load this file; it shares no code with the HIP library.

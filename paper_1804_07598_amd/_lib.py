@@ -42,6 +42,12 @@ class fpm_sph_params(C.Structure):
                 ("cbar", C.c_float), ("scheme", C.c_int32), ("verlet_every", C.c_int32)]
 
 
+class fpm_dem_params(C.Structure):
+    _fields_ = [("R", C.c_float), ("mass", C.c_float), ("inertia", C.c_float),
+                ("kn", C.c_float), ("kt", C.c_float), ("gn", C.c_float), ("gt", C.c_float),
+                ("mu", C.c_float), ("g", C.c_float * 3), ("dt", C.c_float), ("walls", C.c_int32)]
+
+
 _P = C.c_void_p
 _SIGS = {
     "fpm_create": [C.POINTER(_P), _P],
@@ -71,6 +77,12 @@ _SIGS = {
     "fpm_step": [_P, C.POINTER(fpm_lj_params), C.c_float, C.c_int32, _P],
     "fpm_sph_rates": [_P, C.POINTER(fpm_sph_params), _P],
     "fpm_sph_step": [_P, C.POINTER(fpm_sph_params), C.c_int32, _P],
+    "fpm_set_dem": [_P, C.c_int32],
+    "fpm_set_omega": [_P, _P],
+    "fpm_dem_forces": [_P, C.POINTER(fpm_dem_params)],
+    "fpm_dem_step": [_P, C.POINTER(fpm_dem_params), C.c_int32],
+    "fpm_get_dem": [_P, _P, _P, _P],
+    "fpm_get_contacts": [_P, _P, _P],
     "fpm_check": [_P],
     "fpm_read_counters": [_P, C.POINTER(C.c_int64)],
     "fpm_set_profiling": [_P, C.c_int32],
@@ -232,6 +244,41 @@ def sph_params(h, mass, rho0, c0, gamma=7.0, alpha=0.1, eta2=None, g=(0.0, 0.0, 
         p.g[k] = float(g[k])
     p.cfl = float(cfl)
     return p
+
+
+def dem_params(R, mass, inertia, kn, kt, gn, gt=0.0, mu=0.5, g=(0.0, 0.0, 0.0), dt=1e-4,
+               walls=0) -> fpm_dem_params:
+    p = fpm_dem_params()
+    p.R, p.mass, p.inertia, p.kn, p.kt, p.gn, p.gt, p.mu = (float(x) for x in
+                                                          (R, mass, inertia, kn, kt, gn, gt, mu))
+    for k in range(3):
+        p.g[k] = float(g[k])
+    p.dt, p.walls = float(dt), int(walls)
+    return p
+
+
+def fpm_set_dem(ctx, max_contacts: int):
+    _call("fpm_set_dem", ctx, int(max_contacts))
+
+
+def fpm_set_omega(ctx, omega=None):
+    _call("fpm_set_omega", ctx, _ptr(omega))
+
+
+def fpm_dem_forces(ctx, prm: fpm_dem_params):
+    _call("fpm_dem_forces", ctx, C.byref(prm))
+
+
+def fpm_dem_step(ctx, prm: fpm_dem_params, nsteps: int):
+    _call("fpm_dem_step", ctx, C.byref(prm), int(nsteps))
+
+
+def fpm_get_dem(ctx, omega=None, torque=None, ncontact=None):
+    _call("fpm_get_dem", ctx, _ptr(omega), _ptr(torque), _ptr(ncontact))
+
+
+def fpm_get_contacts(ctx, ids=None, ut=None):
+    _call("fpm_get_contacts", ctx, _ptr(ids), _ptr(ut))
 
 
 def fpm_lj_forces(ctx, prm: fpm_lj_params, out=None):

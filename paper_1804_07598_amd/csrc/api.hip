@@ -143,6 +143,15 @@ size_t layout(const fpm_ctx *c, const Plan &P, char *base, State *st,
     s.part = (double *)take((size_t)P.nblk * kSlots * sizeof(double));
     s.aux = (float4 *)take(ns * sizeof(float4));
     for (int k = 0; k < 2; k++) s.old[k] = (float4 *)take(ns * sizeof(float4));
+    if (c->dem_cap > 0) {
+        int64_t ncall = 0;
+        for (const SysDesc &d : P.desc) ncall += d.n;
+        const size_t hslots = (size_t)ncall * c->dem_cap;
+        for (int k = 0; k < 2; k++) s.hid[k] = (int32_t *)take(hslots * sizeof(int32_t));
+        for (int k = 0; k < 2; k++) s.hu[k] = (float4 *)take(hslots * sizeof(float4));
+        s.ncon = (int32_t *)take((size_t)ncall * sizeof(int32_t));
+        s.keep_old = 1;
+    }
     s.ctl = (Ctl *)take(sizeof(Ctl));
     s.sctl = (SysCtl *)take(nsys * sizeof(SysCtl));
     s.sys = (const SysDesc *)take(nsys * sizeof(SysDesc));
@@ -276,6 +285,25 @@ bool valid_sph(const fpm_sph_params *p) {
            isfinite(p->g[0]) && isfinite(p->g[1]) && isfinite(p->g[2]) && isfinite(p->cbar) &&
            (p->kernel == 0 || p->kernel == 1) && (p->scheme == 0 || p->scheme == 1) &&
            (p->scheme == 0 || p->verlet_every >= 1);
+}
+
+int dem_ready(fpm_ctx *c, const fpm_dem_params *p) {
+    int r = ready(c);
+    if (r) return r;
+    if (c->dem_cap <= 0) return fail(c, FPM_EINVAL, "DEM storage not set (fpm_set_dem)");
+    if (!p) return fail(c, FPM_EINVAL, "null DEM params");
+    const float v[] = {p->R, p->mass, p->inertia, p->dt};
+    for (float x : v)
+        if (!(isfinite(x) && x > 0.f)) return fail(c, FPM_EINVAL, "bad DEM params");
+    const float w[] = {p->kn, p->kt, p->gn, p->gt, p->mu};
+    for (float x : w)
+        if (!(isfinite(x) && x >= 0.f)) return fail(c, FPM_EINVAL, "bad DEM params");
+    if (!(isfinite(p->g[0]) && isfinite(p->g[1]) && isfinite(p->g[2])) || p->walls < 0 ||
+        p->walls > 3)
+        return fail(c, FPM_EINVAL, "bad DEM params");
+    if ((double)c->r_cut + (double)c->skin < 2.0 * (double)p->R)
+        return fail(c, FPM_EINVAL, "the list radius must cover 2R");
+    return FPM_OK;
 }
 
 }  // namespace
@@ -468,6 +496,10 @@ int fpm_set_particles(fpm_ctx *c, int64_t n, const float *pos, const float *vel,
     HIPCHK(c, launch_init_state(c, pos, vel, type));
     HIPCHK(c, launch_force_rebuild(c));
     HIPCHK(c, refresh_and_account(c));
+    if (c->dem_cap > 0) {
+        c->dem_rb = 0;
+        HIPCHK(c, launch_dem_set_omega(c, nullptr));
+    }
     c->have_particles = true;
     c->forces_valid = false;
     c->sph_restart = true;
@@ -736,6 +768,69 @@ int fpm_sph_step(fpm_ctx *c, const fpm_sph_params *p, int32_t nsteps, double *hi
     for (; left > 0; left--) HIPCHK(c, hipGraphLaunch(c->s_one, c->stream));
     if (p->scheme == 0) HIPCHK(c, launch_sph_integrate(c, *p, kKickOnly));
     HIPCHK(c, launch_finalize(c, kFinBuild, nullptr, nullptr));
+    return FPM_OK;
+}
+
+int fpm_set_dem(fpm_ctx *c, int32_t max_contacts) {
+    if (!c) return FPM_EINVAL;
+    if (max_contacts < 1 || max_contacts > 64) return fail(c, FPM_EINVAL, "max_contacts is 1..64");
+    if (c->nsys > 1 || !c->counts.empty())
+        return fail(c, FPM_EINVAL, "DEM runs on a single system");
+    c->dem_cap = max_contacts;
+    c->have_particles = false;
+    drop_graphs(c);
+    return FPM_OK;
+}
+
+
+int fpm_set_omega(fpm_ctx *c, const float *w) {
+    int r = ready(c);
+    if (r) return r;
+    if (c->dem_cap <= 0) return fail(c, FPM_EINVAL, "DEM storage not set (fpm_set_dem)");
+    c->dem_rb = 0;
+    HIPCHK(c, launch_dem_set_omega(c, w));
+    return FPM_OK;
+}
+
+int fpm_dem_forces(fpm_ctx *c, const fpm_dem_params *p) {
+    int r = dem_ready(c, p);
+    if (r) return r;
+    HIPCHK(c, refresh_and_account(c));
+    HIPCHK(c, timed(c, "dem_forces", [&] { return launch_dem_forces(c, *p); }));
+    c->dem_rb ^= 1;
+    c->forces_valid = false;
+    return FPM_OK;
+}
+
+int fpm_dem_step(fpm_ctx *c, const fpm_dem_params *p, int32_t nsteps) {
+    int r = dem_ready(c, p);
+    if (r) return r;
+    if (nsteps < 0) return fail(c, FPM_EINVAL, "bad step count");
+    if (c->build_pending) HIPCHK(c, refresh_and_account(c));
+    for (int s = 0; s < nsteps; s++) {
+        HIPCHK(c, refresh_lists(c));  // gated on the device flag
+        HIPCHK(c, timed(c, "dem_forces", [&] { return launch_dem_forces(c, *p); }));
+        c->dem_rb ^= 1;
+        HIPCHK(c, launch_dem_integrate(c, *p));
+        HIPCHK(c, launch_finalize(c, kFinBuild | kFinDisp, nullptr, nullptr));
+    }
+    c->forces_valid = false;
+    return FPM_OK;
+}
+
+int fpm_get_dem(fpm_ctx *c, float *w, float *tq, int32_t *ncon) {
+    int r = ready(c);
+    if (r) return r;
+    if (c->dem_cap <= 0) return fail(c, FPM_EINVAL, "DEM storage not set (fpm_set_dem)");
+    HIPCHK(c, launch_dem_out(c, w, tq, nullptr, nullptr, ncon));
+    return FPM_OK;
+}
+
+int fpm_get_contacts(fpm_ctx *c, int32_t *ids, float *ut) {
+    int r = ready(c);
+    if (r) return r;
+    if (c->dem_cap <= 0) return fail(c, FPM_EINVAL, "DEM storage not set (fpm_set_dem)");
+    HIPCHK(c, launch_dem_out(c, nullptr, nullptr, ids, ut, nullptr));
     return FPM_OK;
 }
 

@@ -112,8 +112,12 @@ struct State {
     uint32_t *nnb;          // list length | kWrapBit
     double *part;           // per-block partials, part[slot * pstride + block]
     float4 *aux;            // per-slot scratch (adjoint input, sorted)
-    float4 *old[2];         // SPH Verlet: previous step's (v, rho), double buffered like pos
+    float4 *old[2];         // SPH Verlet: previous step's (v, rho); DEM: angular velocity;
+                            // double buffered like pos
     int32_t keep_old;       // 1: the cell sort carries old[] along
+    int32_t *hid[2];        // DEM: contact partners by caller index, two buffers
+    float4 *hu[2];          // DEM: their tangential histories
+    int32_t *ncon;          // DEM: contacts per grain (caller index)
     Ctl *ctl;
     SysCtl *sctl;           // per system
     const SysDesc *sys;     // per system
@@ -189,6 +193,8 @@ struct fpm_ctx {
     fpm_sph_params s_prm{};
     double *s_hist = nullptr;
     bool sph_restart = true;           // the SPH step count restarts at the next step call
+    int dem_cap = 0;                   // DEM contact slots per grain (0: DEM off)
+    int dem_rb = 0;                    // DEM history buffer holding the current contacts
     // event timing of eager launches (fpm_set_profiling)
     struct Timed {
         std::string name;
@@ -237,6 +243,11 @@ hipError_t launch_sph_rates(fpm_ctx *c, const fpm_sph_params &p);
 hipError_t launch_sph_integrate(fpm_ctx *c, const fpm_sph_params &p, int mode);
 hipError_t launch_sph_verlet(fpm_ctx *c, const fpm_sph_params &p);
 hipError_t launch_sph_restart(fpm_ctx *c);  // the next SPH step counts as the first
+hipError_t launch_dem_forces(fpm_ctx *c, const fpm_dem_params &p);
+hipError_t launch_dem_integrate(fpm_ctx *c, const fpm_dem_params &p);
+hipError_t launch_dem_set_omega(fpm_ctx *c, const float *w);  // also clears the history
+hipError_t launch_dem_out(fpm_ctx *c, float *w, float *tq, int32_t *ids, float *ut,
+                          int32_t *ncon);
 hipError_t launch_sph_finalize(fpm_ctx *c, const fpm_sph_params &p, int mode, float *dt_out,
                                double *hist);
 

@@ -33,7 +33,8 @@ def _as(t, dtype, device):
 class _Sim:
     """Context, workspace and the calls shared by single systems and batches."""
 
-    def _open(self, pos, vel, typ, r_cut, skin, max_nbr, device, set_boxes, tuning):
+    def _open(self, pos, vel, typ, r_cut, skin, max_nbr, device, set_boxes, tuning,
+              dem_contacts=0):
         self.device = torch.device(device)
         self.pos0 = _as(pos, torch.float32, self.device)
         self.n = int(self.pos0.shape[0])
@@ -43,6 +44,9 @@ class _Sim:
         self.ctx = F.fpm_create(_stream_handle())
         set_boxes()
         F.fpm_set_neighbor_params(self.ctx, self.r_cut, self.skin, self.max_nbr)
+        self.dem_contacts = int(dem_contacts)
+        if self.dem_contacts:
+            F.fpm_set_dem(self.ctx, self.dem_contacts)
         if tuning is not None:
             F.fpm_set_tuning(self.ctx, *tuning)
         self._load(self.pos0, self._vel)
@@ -162,7 +166,8 @@ class ParticleSim(_Sim):
     """One particle system on one device."""
 
     def __init__(self, pos, L, periodic=(1, 1, 1), *, vel=None, typ=None, r_cut: float = 2.5,
-                 skin: float = 0.3, max_nbr: int | None = None, device="cuda", tuning=None):
+                 skin: float = 0.3, max_nbr: int | None = None, device="cuda", tuning=None,
+                 dem_contacts: int = 0):
         self.L = [float(x) for x in (L if hasattr(L, "__len__") else (L, L, L))]
         self.periodic = tuple(int(p) for p in periodic)
         self.nsys = 1
@@ -170,7 +175,7 @@ class ParticleSim(_Sim):
         if max_nbr is None:
             max_nbr = default_max_nbr(n, self.L[0] * self.L[1] * self.L[2], r_cut + skin)
         self._open(pos, vel, typ, r_cut, skin, max_nbr, device,
-                   lambda: F.fpm_set_box(self.ctx, self.L, self.periodic), tuning)
+                   lambda: F.fpm_set_box(self.ctx, self.L, self.periodic), tuning, dem_contacts)
 
     def cell_list(self):
         """(ncell, offsets, order): grid, exclusive scan of counts, slot -> caller index."""
@@ -207,6 +212,34 @@ class ParticleSim(_Sim):
         dr = torch.empty_like(rho)
         F.fpm_get_sph(self.ctx, rho, dr)
         return rho, dr
+
+
+    # ---- DEM (dem_contacts > 0) ----
+    def set_omega(self, omega=None):
+        F.fpm_set_omega(self.ctx, None if omega is None else _as(omega, torch.float32, self.device))
+
+    def dem_forces(self, prm):
+        """Forces and torques of the grain model, advancing the contact history."""
+        F.fpm_dem_forces(self.ctx, prm)
+
+    def dem_step(self, nsteps: int, prm):
+        F.fpm_dem_step(self.ctx, prm, nsteps)
+
+    def get_dem(self):
+        """(omega (n, 3), torque (n, 3), contact counts (n,)) in caller order."""
+        w = torch.empty((self.n, 3), dtype=torch.float32, device=self.device)
+        t = torch.empty_like(w)
+        nc = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        F.fpm_get_dem(self.ctx, w, t, nc)
+        return w, t, nc
+
+    def contacts(self):
+        """(ids (n, C), u_t (n, C, 3)): partners by caller index (-1 empty)."""
+        C_ = self.dem_contacts
+        ids = torch.empty((self.n, C_), dtype=torch.int32, device=self.device)
+        ut = torch.empty((self.n, C_, 3), dtype=torch.float32, device=self.device)
+        F.fpm_get_contacts(self.ctx, ids, ut)
+        return ids, ut
 
 
 class BatchSim(_Sim):

@@ -1,0 +1,227 @@
+"""Parity of the DEM grains (section 4.5: Silbert model, Eqs. 9-13) with the
+FP64 oracle: forces, torques, contact counts and the tangential history of
+one evaluation; multi-step trajectories with list rebuilds, walls and
+gravity; and the avalanche at full size on properties."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1804_07598_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+R, M, INERTIA = 0.06, 1.0, 1.44e-3
+KN, KT, GN, GT = 7.849, 2.243, 3.401, 1.0
+C = 16
+TOL = 1e-5
+
+
+def np_(t):
+    return t.detach().cpu().numpy()
+
+
+def make(s, skin=0.02, **kw):
+    from paper_1804_07598_amd.sim import ParticleSim
+    sim = ParticleSim(s.pos, s.L, s.periodic, vel=s.vel, r_cut=2 * R, skin=skin, max_nbr=48,
+                      dem_contacts=C)
+    sim.set_omega(s.omega)
+    return sim
+
+
+def f32(x):
+    return float(np.float32(x))
+
+
+def params(dt=2e-4, g=(0.0, 0.0, 0.0), walls=0, mu=0.5):
+    """The library's parameter block and the oracle's, from the same FP32
+    values (the boundary carries FP32 parameters)."""
+    from paper_1804_07598_amd import _lib as F
+    v = [f32(x) for x in (R, M, INERTIA, KN, KT, GN, GT, mu)]
+    gg = [f32(x) for x in g]
+    return (F.dem_params(*v, gg, f32(dt), walls),
+            O.dem_params_array(*v, gg, f32(dt), walls))
+
+
+def contact_rms(Fo, g):
+    """RMS of the contact part of the oracle's forces (gravity m g removed)."""
+    return math.sqrt(((Fo - f32(M) * np.array([f32(x) for x in g])) ** 2).mean())
+
+
+def packing(shape=(10, 10, 10), seed=1, per=(1, 1, 1)):
+    L = [shape[k] * 1.9 * R for k in range(3)]
+    return inputs.dem_block(shape, R, 1.9 * R, L, per, seed=seed, jitter=0.005,
+                            vel_sigma=0.3, omega_sigma=3.0)
+
+
+def sorted_history(ids, ut):
+    """Per grain: partner ids ascending with their u_t (rows padded with -1)."""
+    out_i = np.full_like(ids, -1)
+    out_u = np.zeros_like(ut)
+    for p in range(len(ids)):
+        k = ids[p] >= 0
+        order = np.argsort(ids[p][k])
+        out_i[p, :k.sum()] = ids[p][k][order]
+        out_u[p, :k.sum()] = ut[p][k][order]
+    return out_i, out_u
+
+
+def test_forces_torques_history_match_oracle():
+    s = packing()
+    sim = make(s)
+    prm, oprm = params()
+    sim.dem_forces(prm)
+    sim.check()
+    _, _, F = sim.get()
+    _, T, nc = sim.get_dem()
+    ids, ut = sim.contacts()
+    F, T, nc, ids, ut = np_(F), np_(T), np_(nc), np_(ids), np_(ut)
+    Fo, To, (hid, hu), nco = O.dem_forces(s.pos.astype(np.float64), s.vel, s.omega, s.L,
+                                          s.periodic, oprm)
+    assert np.array_equal(nc, nco) and nco.max() >= 6  # a dense, overlapped packing
+    assert np.abs(F - Fo).max() <= TOL * math.sqrt((Fo ** 2).mean())
+    assert np.abs(T - To).max() <= TOL * math.sqrt((To ** 2).mean())
+    gi, gu = sorted_history(ids, ut)
+    assert np.array_equal(gi, hid.astype(np.int32))  # oracle rows are ascending already
+    scale = np.abs(hu).max()
+    assert np.abs(gu - hu).max() <= 1e-6 * scale + 1e-12
+
+
+def check_trajectory(s, prm, oprm, K, skin=0.02):
+    sim = make(s, skin=skin)
+    sim.dem_step(K, prm)
+    sim.check()
+    p, v, _ = (np_(t) for t in sim.get())
+    w, _, _ = (np_(t) for t in sim.get_dem())
+    x64, v64, w64, hist, _, _, _ = O.dem_steps(s.pos.astype(np.float64), s.vel, s.omega, s.L,
+                                               s.periodic, oprm, K)
+    d = p.astype(np.float64) - x64
+    for a in range(3):
+        if s.periodic[a]:
+            d[:, a] -= float(s.L[a]) * np.round(d[:, a] / float(s.L[a]))
+    # FP32 state: each step rounds x (|x| < 2), v (~0.3) and w (~3) to half an
+    # ulp (6e-8, 1.5e-8, 1.2e-7); tens of steps of soft contacts keep the
+    # accumulated difference within some hundred such roundings
+    print(f"trajectory K={K}: |dx| {np.abs(d).max():.3g} |dv| {np.abs(v - v64).max():.3g} "
+          f"|dw| {np.abs(w - w64).max():.3g}")
+    assert np.abs(d).max() <= 2e-5
+    assert np.abs(v - v64).max() <= 1e-5
+    assert np.abs(w - w64).max() <= 1e-4
+    return sim
+
+
+def test_steps_match_oracle_trajectory():
+    s = packing(seed=2)
+    prm, oprm = params(dt=5e-4)
+    sim = check_trajectory(s, prm, oprm, 60, skin=0.004)
+    assert sim.counters()[0] >= 2  # the lists were rebuilt on the way
+
+
+def test_walls_and_gravity_match_oracle():
+    # grains dropped onto the floor between the x walls, periodic in y
+    s = inputs.dem_block((8, 6, 4), R, 2.02 * R, (8 * 2.02 * R, 6 * 2.02 * R, 3.0), (0, 1, 0),
+                         origin=(0.0, 0.0, 0.001), seed=3, jitter=0.002, vel_sigma=0.2,
+                         omega_sigma=2.0)
+    prm, oprm = params(dt=5e-4, g=(0.0, 0.0, -9.81), walls=3)
+    check_trajectory(s, prm, oprm, 80)
+
+
+def test_avalanche_runs():
+    """The section 4.5 avalanche block (8750 grains) sliding down the tilted
+    plane for 400 steps: every grain stays in the domain above the floor, the
+    overlaps stay shallow and the block moves down the slope."""
+    from scipy.spatial import cKDTree
+    from paper_1804_07598_amd import _lib as F
+    A = inputs.DEM_AVALANCHE
+    s = inputs.dem_avalanche(1.0)
+    prm = F.dem_params(A["R"], A["mass"], A["inertia"], A["kn"], A["kt"], A["gn"], A["gt"],
+                       A["mu"], inputs.dem_avalanche_gravity(), A["dt"], A["walls"])
+    sim = make(s, skin=0.1 * R)
+    sim.dem_step(400, prm)
+    sim.check()
+    p, v, _ = (np_(t) for t in sim.get())
+    w, _, nc = (np_(t) for t in sim.get_dem())
+    assert np.isfinite(p).all() and np.isfinite(v).all() and np.isfinite(w).all()
+    assert p[:, 2].min() > 0.9 * R and p[:, 0].min() > 0.9 * R
+    assert p[:, 0].max() < s.L[0] - 0.9 * R
+    dmin = cKDTree(p.astype(np.float64)).query(p.astype(np.float64), k=2)[0][:, 1].min()
+    assert dmin > 0.9 * 2 * R
+    assert 4 <= nc.max() <= C
+    assert v[:, 0].mean() > 0  # the block slides down the slope
+
+
+def test_full_size_sampled_parity():
+    """One evaluation on a 688,380-grain overlapped packing (the avalanche's
+    size and boundaries: x walls, periodic y, floor, tilted gravity) against
+    the oracle at 600 sampled grains, each evaluated on the patch of grains
+    within its contact range."""
+    from scipy.spatial import cKDTree
+    shape = (149, 105, 44)
+    L = [shape[k] * 1.9 * R for k in range(3)]
+    s = inputs.dem_block(shape, R, 1.9 * R, L, (0, 1, 0), seed=21, jitter=0.005,
+                         vel_sigma=0.3, omega_sigma=3.0)
+    n = len(s.pos)
+    assert n == 688_380
+    g = inputs.dem_avalanche_gravity(9.81)
+    prm, oprm = params(g=g, walls=3)
+    sim = make(s, skin=0.01)
+    sim.dem_forces(prm)
+    sim.check()
+    _, _, F = sim.get()
+    _, T, nc = sim.get_dem()
+    F, T, nc = np_(F), np_(T), np_(nc)
+    rng = np.random.default_rng(5)
+    x = s.pos.astype(np.float64)
+    # samples spread over the block plus grains at every boundary
+    edge = np.flatnonzero((x[:, 0] < R) | (x[:, 0] > L[0] - R) | (x[:, 1] < R) |
+                          (x[:, 1] > L[1] - R) | (x[:, 2] < R))
+    sample = np.unique(np.concatenate([rng.choice(n, 400, replace=False),
+                                       rng.choice(edge, 200, replace=False)]))
+    box = np.array([3 * L[0], L[1], 3 * L[2]])  # only y wraps
+    tree = cKDTree(x, boxsize=box)
+    near = tree.query_ball_point(x[sample], r=2.05 * R)
+    patch = np.unique(np.concatenate([np.asarray(v, np.int64) for v in near]))
+    Fo, To, _, nco = O.dem_forces(x[patch], s.vel[patch], s.omega[patch], s.L, s.periodic,
+                                  oprm)
+    rows = np.searchsorted(patch, sample)
+    assert np.array_equal(nc[sample], nco[rows])
+    assert nco[rows].max() >= 4
+    ef = np.abs(F[sample] - Fo[rows]).max() / contact_rms(Fo[rows], g)
+    et = np.abs(T[sample] - To[rows]).max() / math.sqrt((To[rows] ** 2).mean())
+    print(f"full size: {len(sample)} samples on a patch of {len(patch)}: force {ef:.3g}, "
+          f"torque {et:.3g} of RMS")
+    assert ef <= TOL
+    assert np.abs(T[sample] - To[rows]).max() <= TOL * math.sqrt((To[rows] ** 2).mean())
+
+
+def test_full_size_history_antisymmetric():
+    """After 200 steps of the 688,380-grain avalanche the contact history is
+    a symmetric relation with u_t(q, p) = -u_t(p, q) exactly: both grains of a
+    pair evaluate it with negated operands in the same order."""
+    from paper_1804_07598_amd import _lib as F
+    A = inputs.DEM_AVALANCHE
+    s = inputs.dem_avalanche(4.2)
+    n = len(s.pos)
+    prm = F.dem_params(A["R"], A["mass"], A["inertia"], A["kn"], A["kt"], A["gn"], A["gt"],
+                       A["mu"], inputs.dem_avalanche_gravity(), A["dt"], A["walls"])
+    sim = make(s, skin=0.1 * R)
+    sim.dem_step(200, prm)
+    sim.check()
+    p, v, _ = (np_(t) for t in sim.get())
+    w, _, nc = (np_(t) for t in sim.get_dem())
+    ids, ut = (np_(t) for t in sim.contacts())
+    assert np.isfinite(p).all() and np.isfinite(v).all() and np.isfinite(w).all()
+    assert p[:, 2].min() > 0.9 * R
+    assert nc.max() <= C and nc.max() >= 4
+    assert np.array_equal((ids >= 0).sum(axis=1), nc)
+    pp, slot = np.nonzero(ids >= 0)
+    qq = ids[pp, slot].astype(np.int64)
+    key = pp.astype(np.int64) * n + qq
+    order = np.argsort(key)
+    rev = qq * n + pp.astype(np.int64)
+    at = np.searchsorted(key[order], rev)
+    assert (at < len(key)).all() and np.array_equal(key[order][at], rev)
+    u = ut[pp, slot]
+    assert np.array_equal(u[order][at], -u)
+    assert np.abs(u).max() > 0
