@@ -138,6 +138,7 @@ size_t layout(const fpm_ctx *c, const Plan &P, char *base, State *st,
     s.tmp = (int4 *)take(ns * sizeof(int4));
     s.cnt = (int32_t *)take(((size_t)P.ncells_total + 4) * sizeof(int32_t));
     s.off = (int32_t *)take(((size_t)P.noff_total + 4) * sizeof(int32_t));
+    s.tsum = (int32_t *)take(((size_t)P.ncells_total / 4096 + 4) * sizeof(int32_t));
     s.nbr = (int32_t *)take((size_t)ns * cap4_for(c->cap) * 4 * sizeof(int32_t));
     s.nnb = (uint32_t *)take(ns * sizeof(uint32_t));
     s.part = (double *)take((size_t)P.nblk * kSlots * sizeof(double));

@@ -100,60 +100,109 @@ __global__ __launch_bounds__(kBlock) void k_cell_assign(State st) {
     if (c >= 0) st.rnk[i] = base + (lane - hl);
 }
 
-// Exclusive prefix scan of one system's cell counts (one workgroup of 1024
-// threads per system), in tiles of 4096 cells: per-thread sums, wavefront
-// inclusive scan with shuffles, scan of the 16 wavefront totals, then the
-// carry to the next tile.  Offsets are global slots.  Counts are cleared on
-// the way for the next rebuild.
+// Exclusive scan of one tile of kScanTile values in[base ..) (n values in
+// all) into out[] with `carry` added, by a workgroup of 1024 threads:
+// per-thread sums of four, wavefront inclusive scan with shuffles, scan of the
+// 16 wavefront totals.  `in` may alias `out`; with `clear` the inputs are
+// zeroed.  Returns the tile's total to every thread.
+constexpr int kScanTile = 4096;
+
+__device__ __forceinline__ int32_t scan_tile(int32_t *in, int32_t *out, int64_t base, int64_t n,
+                                             int32_t carry, bool clear) {
+    __shared__ int32_t wsum[16];
+    __shared__ int32_t total;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t k0 = base + 4 * (int64_t)t;
+    int32_t v[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) v[q] = k0 + q < n ? in[k0 + q] : 0;
+    const int32_t sum = v[0] + v[1] + v[2] + v[3];
+    int32_t incl = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int32_t u = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += u;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    if (w == 0) {
+        int32_t x = lane < 16 ? wsum[lane] : 0;
+        int32_t y = x;
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+            int32_t u = __shfl_up(y, o, 64);
+            if (lane >= o) y += u;
+        }
+        if (lane < 16) wsum[lane] = y - x;
+        if (lane == 15) total = y;
+    }
+    __syncthreads();
+    int32_t e = carry + wsum[w] + incl - sum;
+#pragma unroll
+    for (int q = 0; q < 4; q++)
+        if (k0 + q < n) {
+            out[k0 + q] = e;
+            e += v[q];
+            if (clear) in[k0 + q] = 0;
+        }
+    const int32_t tot = total;
+    __syncthreads();  // wsum and total are reused by the next tile
+    return tot;
+}
+
+// Exclusive prefix scan of each system's cell counts, one workgroup per
+// system walking its tiles in order.  Offsets are global slots.  Counts are
+// cleared on the way for the next rebuild.
 __global__ __launch_bounds__(1024) void k_scan(State st) {
     const int s = blockIdx.x;
     if (!st.sctl[s].rebuild) return;
     const SysDesc &d = st.sys[s];
-    __shared__ int32_t wsum[16];
-    __shared__ int32_t carry_s;
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     int32_t *cnt = st.cnt + d.cell_base;
     int32_t *off = st.off + d.off_base;
     const int64_t ncells = d.ncells;
     int32_t carry = d.slot_base;
-    for (int64_t base = 0; base < ncells; base += 4096) {
-        const int64_t k0 = base + 4 * (int64_t)t;
-        int32_t v[4];
+    for (int64_t base = 0; base < ncells; base += kScanTile)
+        carry += scan_tile(cnt, off, base, ncells, carry, true);
+    if (threadIdx.x == 0) off[ncells] = carry;
+}
+
+// The same scan for a single system with many cells, over the whole device:
+// tile totals (one workgroup per tile), an exclusive scan of the totals (one
+// workgroup), then each tile's scan from its carry.
+__global__ __launch_bounds__(1024) void k_scan_sums(State st) {
+    if (!st.sctl[0].rebuild) return;
+    const SysDesc &d = st.sys[0];
+    const int32_t *cnt = st.cnt + d.cell_base;
+    const int64_t k0 = (int64_t)blockIdx.x * kScanTile + 4 * (int64_t)threadIdx.x;
+    int32_t v = 0;
 #pragma unroll
-        for (int q = 0; q < 4; q++) v[q] = k0 + q < ncells ? cnt[k0 + q] : 0;
-        const int32_t sum = v[0] + v[1] + v[2] + v[3];
-        int32_t incl = sum;
+    for (int q = 0; q < 4; q++) v += k0 + q < d.ncells ? cnt[k0 + q] : 0;
 #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            int32_t u = __shfl_up(incl, o, 64);
-            if (lane >= o) incl += u;
-        }
-        if (lane == 63) wsum[w] = incl;
-        __syncthreads();
-        if (w == 0) {
-            int32_t x = lane < 16 ? wsum[lane] : 0;
-            int32_t y = x;
-#pragma unroll
-            for (int o = 1; o < 16; o <<= 1) {
-                int32_t u = __shfl_up(y, o, 64);
-                if (lane >= o) y += u;
-            }
-            if (lane < 16) wsum[lane] = y - x;
-            if (lane == 15) carry_s = y;
-        }
-        __syncthreads();
-        int32_t e = carry + wsum[w] + incl - sum;
-#pragma unroll
-        for (int q = 0; q < 4; q++)
-            if (k0 + q < ncells) {
-                off[k0 + q] = e;
-                e += v[q];
-                cnt[k0 + q] = 0;
-            }
-        carry += carry_s;
-        __syncthreads();
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    __shared__ int32_t wsum[16];
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t t = 0;
+        for (int w = 0; w < 16; w++) t += wsum[w];
+        st.tsum[blockIdx.x] = t;
     }
-    if (t == 0) off[ncells] = carry;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_top(State st, int ntiles) {
+    if (!st.sctl[0].rebuild) return;
+    const SysDesc &d = st.sys[0];
+    int32_t carry = d.slot_base;
+    for (int64_t base = 0; base < ntiles; base += kScanTile)
+        carry += scan_tile(st.tsum, st.tsum, base, ntiles, carry, false);
+    if (threadIdx.x == 0) st.off[d.off_base + d.ncells] = carry;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_tiles(State st) {
+    if (!st.sctl[0].rebuild) return;
+    const SysDesc &d = st.sys[0];
+    scan_tile(st.cnt + d.cell_base, st.off + d.off_base, (int64_t)blockIdx.x * kScanTile,
+              d.ncells, st.tsum[blockIdx.x], true);
 }
 
 // Scatter (caller id, source slot, z) to the cell's offset + arrival rank.
@@ -263,7 +312,15 @@ hipError_t launch_force_rebuild(fpm_ctx *c) {
 hipError_t launch_cell_build(fpm_ctx *c) {
     const unsigned g = (unsigned)c->nblk;
     hipLaunchKernelGGL(k_cell_assign, dim3(g), dim3(kBlock), 0, c->stream, c->st);
-    hipLaunchKernelGGL(k_scan, dim3(c->nsys), dim3(1024), 0, c->stream, c->st);
+    const int64_t nc0 = c->sys[0].d.ncells;
+    if (c->nsys == 1 && nc0 > kScanDeviceCells) {
+        const unsigned nt = (unsigned)((nc0 + kScanTile - 1) / kScanTile);
+        hipLaunchKernelGGL(k_scan_sums, dim3(nt), dim3(1024), 0, c->stream, c->st);
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, c->stream, c->st, (int)nt);
+        hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(1024), 0, c->stream, c->st);
+    } else {
+        hipLaunchKernelGGL(k_scan, dim3(c->nsys), dim3(1024), 0, c->stream, c->st);
+    }
     hipLaunchKernelGGL(k_scatter, dim3(g), dim3(kBlock), 0, c->stream, c->st);
     hipLaunchKernelGGL(k_rank_gather, dim3(g), dim3(kBlock), 0, c->stream, c->st);
     return hipGetLastError();

@@ -26,7 +26,7 @@ namespace fpm {
 namespace {
 
 struct DemCoef {
-    double R, m, inv_m, inv_I, kn, kt, gn, gt, mu, dt, meff, inv_2R, d2max;
+    double R, m, inv_m, inv_I, kn, kt, gn, gt, mu, dt, meff, inv_2R, d2max, inv_kt;
     double g[3];
     float dtf, g32[3];
     int walls;
@@ -43,9 +43,68 @@ __device__ __forceinline__ double dot3(const double a[3], const double b[3]) {
     return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
+struct DemAcc {
+    double f[3], t[3];
+};
+
+// One contact at separation r (|r|^2 = rr2 < 4R^2) of a grain with velocity vi
+// and angular velocity wi and a partner with vj, wj; u holds the pair's
+// tangential history on entry and its update on exit.  Both grains of a pair
+// evaluate it with negated r, velocities and history, so their histories stay
+// exact negatives and their torques equal.
+__device__ __forceinline__ void contact(DemAcc &a, const DemCoef &k, const double r[3],
+                                        double rr2, const float4 vi, const float4 wi,
+                                        const float4 vj, const float4 wj, double u[3]) {
+    const double rr = sqrt(rr2);
+    const double inv = 1.0 / rr;
+    const double nv[3] = {r[0] * inv, r[1] * inv, r[2] * inv};
+    const double arm = 0.5 * rr;
+    const double delta = 2.0 * k.R - rr;
+    const double ws[3] = {(double)wi.x + (double)wj.x, (double)wi.y + (double)wj.y,
+                          (double)wi.z + (double)wj.z};
+    double rot[3];
+    cross3(ws, nv, rot);
+    const double vr[3] = {(double)vi.x - (double)vj.x - arm * rot[0],
+                          (double)vi.y - (double)vj.y - arm * rot[1],
+                          (double)vi.z - (double)vj.z - arm * rot[2]};
+    const double vn = dot3(vr, nv);
+    const double vt[3] = {vr[0] - vn * nv[0], vr[1] - vn * nv[1], vr[2] - vn * nv[2]};
+    for (int c = 0; c < 3; c++) u[c] += vt[c] * k.dt;
+    const double un = dot3(u, nv);
+    for (int c = 0; c < 3; c++) u[c] -= un * nv[c];
+    const double s = sqrt(delta * k.inv_2R);
+    const double fnm = s * (k.kn * delta - k.gn * k.meff * vn);  // F_n = fnm n
+    double ft[3];
+    for (int c = 0; c < 3; c++) ft[c] = s * (-k.kt * u[c] - k.gt * k.meff * vt[c]);
+    const double ft2 = dot3(ft, ft);
+    const double cap = k.mu * fabs(fnm);
+    if (ft2 > cap * cap) {  // Coulomb: |F_t| <= mu |F_n|
+        const double sc = cap / sqrt(ft2);
+        for (int c = 0; c < 3; c++) ft[c] *= sc;
+        if (k.kt > 0.0) {
+            const double is = 1.0 / s;
+            for (int c = 0; c < 3; c++) u[c] = -(ft[c] * is + k.gt * k.meff * vt[c]) * k.inv_kt;
+        }
+    }
+    const double am[3] = {-arm * nv[0], -arm * nv[1], -arm * nv[2]};
+    double tq[3];
+    cross3(am, ft, tq);
+    for (int c = 0; c < 3; c++) {
+        a.f[c] += fnm * nv[c] + ft[c];
+        a.t[c] += tq[c];
+    }
+}
+
 // Forces and torques of the grains; history read from buffer rb, the current
-// contacts written to buffer 1 - rb.
+// contacts written to buffer 1 - rb.  The list is walked four entries at a
+// time, and each dependent step is requested for the four together: the
+// neighbour positions, then the state of the partners in contact (a lane's
+// own slot stands in for the others), then their history slots.  CR > 0: the
+// history capacity is CR (a multiple of four, at most 16) and the grain's
+// partner ids are held in registers; CR = 0: any capacity, searched in memory.
+template <int CR>
 __global__ __launch_bounds__(kBlock) void k_dem_forces(State st, DemCoef k, int rb, int cap4) {
+    constexpr int NR = CR > 0 ? CR : 1;
     const SysDesc &d = st.sys[block_system(st)];
     const Box b = d.box;
     const int64_t i = global_slot();
@@ -54,75 +113,83 @@ __global__ __launch_bounds__(kBlock) void k_dem_forces(State st, DemCoef k, int 
     const float4 *__restrict__ vel = st.vel[0];
     const float4 *__restrict__ om = st.old[0];
     const int32_t *__restrict__ id = st.id[0];
-    const int C = k.C;
+    const int C = CR > 0 ? CR : k.C;
     const int64_t me = id[i];
     const int32_t *hid_in = st.hid[rb] + me * C;
     const float4 *hu_in = st.hu[rb] + me * C;
     int32_t *hid_out = st.hid[1 - rb] + me * C;
     float4 *hu_out = st.hu[1 - rb] + me * C;
-    const float4 pi4 = pos[i], vi4 = vel[i], wi4 = om[i];
+    int hrow[NR];
+    if (CR > 0) {
+        const int4 *h4 = reinterpret_cast<const int4 *>(hid_in);
+#pragma unroll
+        for (int g = 0; g < NR / 4; g++) {
+            const int4 t = h4[g];
+            hrow[4 * g] = t.x, hrow[4 * g + 1] = t.y, hrow[4 * g + 2] = t.z, hrow[4 * g + 3] = t.w;
+        }
+    }
+    const float4 pi4 = pos[i], vi = vel[i], wi = om[i];
     const float3 pi = xyz(pi4);
-    double f[3] = {k.m * k.g[0], k.m * k.g[1], k.m * k.g[2]}, t[3] = {0.0, 0.0, 0.0};
+    DemAcc a;
+    for (int c = 0; c < 3; c++) a.f[c] = k.m * k.g[c], a.t[c] = 0.0;
     int nc = 0;
     const int cnt = (int)(st.nnb[i] & ~kWrapBit);
-    for (int e = 0; e < cnt; e++) {
-        const int j = st.nbr[nbr_index(i, e, cap4)];
-        const float4 q4 = pos[j];
-        double r[3] = {sep_axis(pi.x, q4.x, b.L[0], b.half[0], b.per[0]),
-                       sep_axis(pi.y, q4.y, b.L[1], b.half[1], b.per[1]),
-                       sep_axis(pi.z, q4.z, b.L[2], b.half[2], b.per[2])};
-        const double rr2 = dot3(r, r);
-        if (!(rr2 < k.d2max)) continue;
-        const float4 vj4 = vel[j], wj4 = om[j];
-        const int64_t qid = id[j];
-        const double rr = sqrt(rr2);
-        const double nv[3] = {r[0] / rr, r[1] / rr, r[2] / rr};
-        const double a = 0.5 * rr;
-        const double delta = 2.0 * k.R - rr;
-        const double ws[3] = {(double)wi4.x + (double)wj4.x, (double)wi4.y + (double)wj4.y,
-                              (double)wi4.z + (double)wj4.z};
-        double rot[3];
-        cross3(ws, nv, rot);
-        const double vr[3] = {(double)vi4.x - (double)vj4.x - a * rot[0],
-                              (double)vi4.y - (double)vj4.y - a * rot[1],
-                              (double)vi4.z - (double)vj4.z - a * rot[2]};
-        const double vn = dot3(vr, nv);
-        const double vt[3] = {vr[0] - vn * nv[0], vr[1] - vn * nv[1], vr[2] - vn * nv[2]};
-        double u[3] = {0.0, 0.0, 0.0};
-        for (int c = 0; c < C; c++)
-            if (hid_in[c] == qid) {
-                const float4 h = hu_in[c];
-                u[0] = h.x, u[1] = h.y, u[2] = h.z;
-                break;
+    const int4 *lst = reinterpret_cast<const int4 *>(st.nbr) + ((i >> 6) * (int64_t)cap4) * 64 +
+                      (i & 63);
+    for (int k0 = 0; k0 < cnt; k0 += 4) {  // lists are padded to a multiple of eight
+        const int4 e = lst[(k0 >> 2) * 64];
+        const int j[4] = {e.x, e.y, e.z, e.w};
+        float4 q[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) q[u] = pos[j[u]];
+        bool in[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const double rx = sep_axis(pi.x, q[u].x, b.L[0], b.half[0], b.per[0]);
+            const double ry = sep_axis(pi.y, q[u].y, b.L[1], b.half[1], b.per[1]);
+            const double rz = sep_axis(pi.z, q[u].z, b.L[2], b.half[2], b.per[2]);
+            in[u] = k0 + u < cnt && rx * rx + ry * ry + rz * rz < k.d2max;
+        }
+        float4 vj[4], wj[4];
+        int qid[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int jj = in[u] ? j[u] : (int)i;
+            vj[u] = vel[jj];
+            wj[u] = om[jj];
+            qid[u] = id[jj];
+        }
+        float4 h[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            int m = -1;
+            if (CR > 0) {
+#pragma unroll
+                for (int c = 0; c < NR; c++) m = hrow[c] == qid[u] ? c : m;
+            } else {
+                for (int c = 0; c < C; c++)
+                    if (hid_in[c] == qid[u]) {
+                        m = c;
+                        break;
+                    }
             }
-        for (int c3 = 0; c3 < 3; c3++) u[c3] += vt[c3] * k.dt;
-        const double un = dot3(u, nv);
-        for (int c3 = 0; c3 < 3; c3++) u[c3] -= un * nv[c3];
-        const double s = sqrt(delta * k.inv_2R);
-        double fn[3], ft[3];
-        for (int c3 = 0; c3 < 3; c3++) {
-            fn[c3] = s * (k.kn * delta * nv[c3] - k.gn * k.meff * vn * nv[c3]);
-            ft[c3] = s * (-k.kt * u[c3] - k.gt * k.meff * vt[c3]);
+            h[u] = hu_in[m >= 0 ? m : 0];
+            if (!(in[u] && m >= 0)) h[u] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
-        const double fnm = sqrt(dot3(fn, fn)), ftm = sqrt(dot3(ft, ft));
-        if (ftm > k.mu * fnm) {
-            const double sc = k.mu * fnm / ftm;
-            for (int c3 = 0; c3 < 3; c3++) ft[c3] *= sc;
-            if (k.kt > 0.0)
-                for (int c3 = 0; c3 < 3; c3++) u[c3] = -(ft[c3] / s + k.gt * k.meff * vt[c3]) / k.kt;
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            if (!in[u]) continue;
+            const double r[3] = {sep_axis(pi.x, q[u].x, b.L[0], b.half[0], b.per[0]),
+                                 sep_axis(pi.y, q[u].y, b.L[1], b.half[1], b.per[1]),
+                                 sep_axis(pi.z, q[u].z, b.L[2], b.half[2], b.per[2])};
+            double uu[3] = {h[u].x, h[u].y, h[u].z};
+            contact(a, k, r, dot3(r, r), vi, wi, vj[u], wj[u], uu);
+            if (nc < C) {
+                hid_out[nc] = qid[u];
+                hu_out[nc] = make_float4((float)uu[0], (float)uu[1], (float)uu[2], 0.f);
+            }
+            nc++;
         }
-        const double arm[3] = {-a * nv[0], -a * nv[1], -a * nv[2]};
-        double tq[3];
-        cross3(arm, ft, tq);
-        for (int c3 = 0; c3 < 3; c3++) {
-            f[c3] += fn[c3] + ft[c3];
-            t[c3] += tq[c3];
-        }
-        if (nc < C) {
-            hid_out[nc] = (int32_t)qid;
-            hu_out[nc] = make_float4((float)u[0], (float)u[1], (float)u[2], 0.f);
-        }
-        nc++;
     }
     for (int c = nc; c < C; c++) hid_out[c] = -1;
     // walls: normal force only
@@ -144,15 +211,15 @@ __global__ __launch_bounds__(kBlock) void k_dem_forces(State st, DemCoef k, int 
         if (!(dist < k.R)) continue;
         const double delta = k.R - dist;
         const double s = sqrt(delta * k.inv_2R);
-        const double vv[3] = {vi4.x, vi4.y, vi4.z};
+        const double vv[3] = {vi.x, vi.y, vi.z};
         const double vn = dot3(vv, nw);
-        for (int c3 = 0; c3 < 3; c3++) f[c3] += s * (k.kn * delta * nw[c3] - k.gn * k.m * vn * nw[c3]);
+        for (int c = 0; c < 3; c++) a.f[c] += s * (k.kn * delta * nw[c] - k.gn * k.m * vn * nw[c]);
     }
-    st.frc[i] = make_float4((float)f[0], (float)f[1], (float)f[2], 0.f);
-    st.aux[i] = make_float4((float)t[0], (float)t[1], (float)t[2], 0.f);
+    st.frc[i] = make_float4((float)a.f[0], (float)a.f[1], (float)a.f[2], 0.f);
+    st.aux[i] = make_float4((float)a.t[0], (float)a.t[1], (float)a.t[2], 0.f);
     st.ncon[me] = nc;
     if (nc > C) st.ctl->overflow = nc;
-    if (!isfinite(f[0]) || !isfinite(f[1]) || !isfinite(f[2])) st.ctl->nonfinite = 1;
+    if (!isfinite(a.f[0]) || !isfinite(a.f[1]) || !isfinite(a.f[2])) st.ctl->nonfinite = 1;
 }
 
 // The leapfrog of Eq. 13 in FP32: v += dt F / m, x += dt v, w += dt T / I,
@@ -239,6 +306,7 @@ DemCoef make_coef(const fpm_ctx *c, const fpm_dem_params &p) {
     k.inv_I = 1.0 / (double)p.inertia;
     k.kn = p.kn;
     k.kt = p.kt;
+    k.inv_kt = p.kt > 0.f ? 1.0 / (double)p.kt : 0.0;
     k.gn = p.gn;
     k.gt = p.gt;
     k.mu = p.mu;
@@ -258,8 +326,15 @@ inline unsigned grid_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b);
 }  // namespace
 
 hipError_t launch_dem_forces(fpm_ctx *c, const fpm_dem_params &p) {
-    hipLaunchKernelGGL(k_dem_forces, dim3(c->nblk), dim3(kBlock), 0, c->stream, c->st,
-                       make_coef(c, p), c->dem_rb, c->cap4);
+    const DemCoef k = make_coef(c, p);
+    const dim3 g(c->nblk), blk(kBlock);
+    switch (c->dem_cap) {
+    case 4: hipLaunchKernelGGL(k_dem_forces<4>, g, blk, 0, c->stream, c->st, k, c->dem_rb, c->cap4); break;
+    case 8: hipLaunchKernelGGL(k_dem_forces<8>, g, blk, 0, c->stream, c->st, k, c->dem_rb, c->cap4); break;
+    case 12: hipLaunchKernelGGL(k_dem_forces<12>, g, blk, 0, c->stream, c->st, k, c->dem_rb, c->cap4); break;
+    case 16: hipLaunchKernelGGL(k_dem_forces<16>, g, blk, 0, c->stream, c->st, k, c->dem_rb, c->cap4); break;
+    default: hipLaunchKernelGGL(k_dem_forces<0>, g, blk, 0, c->stream, c->st, k, c->dem_rb, c->cap4); break;
+    }
     return hipGetLastError();
 }
 

@@ -19,6 +19,7 @@ namespace fpm {
 
 constexpr int kWave = 64;          // CDNA wavefront
 constexpr int kBlock = 256;        // threads per workgroup of the particle kernels
+constexpr int kScanDeviceCells = 65536;  // a single system with more cells scans device-wide
 constexpr int kMaxNbrCap = 4096;   // largest accepted Verlet-list capacity
 constexpr int64_t kMaxParticles = (int64_t(1) << 26) - 1;
 constexpr int kMaxSystems = 1 << 16;
@@ -108,6 +109,7 @@ struct State {
     int4 *tmp;              // (caller id, source slot, z bits, 0) after the scatter
     int32_t *cnt;           // per-cell counts (kept at zero between rebuilds)
     int32_t *off;           // per system: exclusive scan of counts (global slots), ncells + 1
+    int32_t *tsum;          // device-wide scan: totals of the 4096-cell tiles
     int32_t *nbr;           // Verlet lists, see nbr_index()
     uint32_t *nnb;          // list length | kWrapBit
     double *part;           // per-block partials, part[slot * pstride + block]

@@ -22,10 +22,10 @@ def np_(t):
     return t.detach().cpu().numpy()
 
 
-def make(s, skin=0.02, **kw):
+def make(s, skin=0.02, cap=C):
     from paper_1804_07598_amd.sim import ParticleSim
     sim = ParticleSim(s.pos, s.L, s.periodic, vel=s.vel, r_cut=2 * R, skin=skin, max_nbr=48,
-                      dem_contacts=C)
+                      dem_contacts=cap)
     sim.set_omega(s.omega)
     return sim
 
@@ -67,9 +67,10 @@ def sorted_history(ids, ut):
     return out_i, out_u
 
 
-def test_forces_torques_history_match_oracle():
+@pytest.mark.parametrize("cap", [16, 6])  # partner ids in registers / searched in memory
+def test_forces_torques_history_match_oracle(cap):
     s = packing()
-    sim = make(s)
+    sim = make(s, cap=cap)
     prm, oprm = params()
     sim.dem_forces(prm)
     sim.check()
@@ -78,8 +79,8 @@ def test_forces_torques_history_match_oracle():
     ids, ut = sim.contacts()
     F, T, nc, ids, ut = np_(F), np_(T), np_(nc), np_(ids), np_(ut)
     Fo, To, (hid, hu), nco = O.dem_forces(s.pos.astype(np.float64), s.vel, s.omega, s.L,
-                                          s.periodic, oprm)
-    assert np.array_equal(nc, nco) and nco.max() >= 6  # a dense, overlapped packing
+                                          s.periodic, oprm, C=cap)
+    assert np.array_equal(nc, nco) and nco.max() == 6  # a dense, overlapped packing
     assert np.abs(F - Fo).max() <= TOL * math.sqrt((Fo ** 2).mean())
     assert np.abs(T - To).max() <= TOL * math.sqrt((To ** 2).mean())
     gi, gu = sorted_history(ids, ut)
@@ -88,14 +89,14 @@ def test_forces_torques_history_match_oracle():
     assert np.abs(gu - hu).max() <= 1e-6 * scale + 1e-12
 
 
-def check_trajectory(s, prm, oprm, K, skin=0.02):
-    sim = make(s, skin=skin)
+def check_trajectory(s, prm, oprm, K, skin=0.02, cap=C):
+    sim = make(s, skin=skin, cap=cap)
     sim.dem_step(K, prm)
     sim.check()
     p, v, _ = (np_(t) for t in sim.get())
     w, _, _ = (np_(t) for t in sim.get_dem())
     x64, v64, w64, hist, _, _, _ = O.dem_steps(s.pos.astype(np.float64), s.vel, s.omega, s.L,
-                                               s.periodic, oprm, K)
+                                               s.periodic, oprm, K, C=cap)
     d = p.astype(np.float64) - x64
     for a in range(3):
         if s.periodic[a]:
@@ -111,10 +112,11 @@ def check_trajectory(s, prm, oprm, K, skin=0.02):
     return sim
 
 
-def test_steps_match_oracle_trajectory():
+@pytest.mark.parametrize("cap", [16, 6])
+def test_steps_match_oracle_trajectory(cap):
     s = packing(seed=2)
     prm, oprm = params(dt=5e-4)
-    sim = check_trajectory(s, prm, oprm, 60, skin=0.004)
+    sim = check_trajectory(s, prm, oprm, 60, skin=0.004, cap=cap)
     assert sim.counters()[0] >= 2  # the lists were rebuilt on the way
 
 

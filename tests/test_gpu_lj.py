@@ -53,7 +53,10 @@ def check_lj(sim, pos, L, eps=(1.0,) * 3, sig=(1.0,) * 3, typ=None, n_types=1, r
 
 # ---------------------------------------------------------------- cell list
 
-@pytest.mark.parametrize("n,rho,seed", [(4096, 0.8442, 1), (1000, 0.8442, 7), (256, 0.6, 4001)])
+# the two sparse cases have 85,184 and 17,373,979 cells: the scan then runs
+# over the whole device, in 21 and 4242 tiles of 4096 cells
+@pytest.mark.parametrize("n,rho,seed", [(4096, 0.8442, 1), (1000, 0.8442, 7), (256, 0.6, 4001),
+                                        (20000, 0.01, 12), (50000, 1.3e-4, 13)])
 def test_cell_list_bit_exact(n, rho, seed):
     s = inputs.lj_lattice(n, rho, 1.0, seed)
     sim = make_sim(s)
