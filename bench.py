@@ -292,10 +292,10 @@ def bench_dem(dev, quiet: bool, steps: int = 2000, warmup: int = 200, scale: flo
     sim.close()
     n = len(s.pos)
     nbar = total / n
-    # per grain: pos, vel, omega, id, list count 52 B; list 4 nbar; history
-    # rows read and written 2 x 16 x 4 B of ids; u_t of the contacts read and
-    # written 2 x 16 cbar; force, torque 32 B; contact count 4 B
-    bytes_f = n * (52.0 + 4.0 * nbar + 128.0 + 32.0 * cbar + 36.0)
+    # per grain: pos, vel, omega, id, list count 56 B; list 4 nbar; history
+    # entries read 16 nbar and written for the contacts 16 cbar; force, torque
+    # 32 B; contact count 4 B (neighbour state gathered from cache)
+    bytes_f = n * (92.0 + 20.0 * nbar + 16.0 * cbar)
     achieved = bytes_f / (f_ms / 1e3) / 1e9
     log(f"DEM avalanche: {n} grains, {steps} steps in {ms:.1f} ms ({ms / steps * 1e3:.1f} us/step), "
         f"forces kernel {f_ms * 1e3:.1f} us, mean list {nbar:.2f}, mean contacts {cbar:.2f}, "
@@ -310,7 +310,10 @@ def bench_dem(dev, quiet: bool, steps: int = 2000, warmup: int = 200, scale: flo
             "rebuilds": reb1 - reb0,
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                         "bytes_per_launch": bytes_f}}
+                         "bytes_per_launch": bytes_f,
+                         "bytes_model": "N*(92 + 20*nbar + 16*cbar): own state 56, list and "
+                                        "history entries 20 per entry, history of contacts "
+                                        "16, outputs 36"}}
 
 
 def bench_adjoint(dev, quiet: bool):

@@ -148,8 +148,9 @@ size_t layout(const fpm_ctx *c, const Plan &P, char *base, State *st,
         int64_t ncall = 0;
         for (const SysDesc &d : P.desc) ncall += d.n;
         const size_t hslots = (size_t)ncall * c->dem_cap;
-        for (int k = 0; k < 2; k++) s.hid[k] = (int32_t *)take(hslots * sizeof(int32_t));
-        for (int k = 0; k < 2; k++) s.hu[k] = (float4 *)take(hslots * sizeof(float4));
+        s.hl = (float4 *)take((size_t)ns * cap4_for(c->cap) * 4 * sizeof(float4));
+        s.hid = (int32_t *)take(hslots * sizeof(int32_t));
+        s.hu = (float4 *)take(hslots * sizeof(float4));
         s.ncon = (int32_t *)take((size_t)ncall * sizeof(int32_t));
         s.keep_old = 1;
     }
@@ -207,10 +208,18 @@ void drop_timers(fpm_ctx *c) {
 // Gated neighbour-structure refresh: every kernel returns at once unless the
 // device rebuild flag is set.  The flag is cleared (and the build accounted)
 // by the next finalize with kFinBuild.
+// With DEM on, the contact history follows the lists: exported to caller-keyed
+// rows before the cell sort, imported into the new lists after the build.
 hipError_t refresh_lists(fpm_ctx *c) {
-    hipError_t e = timed(c, "cell_build", [&] { return launch_cell_build(c); });
-    if (e != hipSuccess) return e;
-    return timed(c, "verlet_build", [&] { return launch_verlet_build(c); });
+    hipError_t e = hipSuccess;
+    if (c->dem_cap > 0 && !c->dem_exported) e = launch_dem_export(c);
+    if (e == hipSuccess) e = timed(c, "cell_build", [&] { return launch_cell_build(c); });
+    if (e == hipSuccess) e = timed(c, "verlet_build", [&] { return launch_verlet_build(c); });
+    if (e == hipSuccess && c->dem_cap > 0) {
+        e = launch_dem_import(c);
+        c->dem_exported = false;
+    }
+    return e;
 }
 
 // Eager refresh that leaves the flag clear.
@@ -496,11 +505,12 @@ int fpm_set_particles(fpm_ctx *c, int64_t n, const float *pos, const float *vel,
     HIPCHK(c, launch_fill_i32(c->stream, c->st.cnt, c->ncells_total, 0));
     HIPCHK(c, launch_init_state(c, pos, vel, type));
     HIPCHK(c, launch_force_rebuild(c));
-    HIPCHK(c, refresh_and_account(c));
-    if (c->dem_cap > 0) {
-        c->dem_rb = 0;
-        HIPCHK(c, launch_dem_set_omega(c, nullptr));
+    if (c->dem_cap > 0) {  // no history yet: nothing to export before the first build
+        HIPCHK(c, launch_dem_clear(c));
+        c->dem_exported = true;
     }
+    HIPCHK(c, refresh_and_account(c));
+    if (c->dem_cap > 0) HIPCHK(c, launch_dem_set_omega(c, nullptr));
     c->have_particles = true;
     c->forces_valid = false;
     c->sph_restart = true;
@@ -560,6 +570,10 @@ int fpm_build_cell_list(fpm_ctx *c) {
     int r = ready(c);
     if (r) return r;
     HIPCHK(c, launch_force_rebuild(c));
+    if (c->dem_cap > 0 && !c->dem_exported) {  // the sort below invalidates the list history
+        HIPCHK(c, launch_dem_export(c));
+        c->dem_exported = true;
+    }
     HIPCHK(c, timed(c, "cell_build", [&] { return launch_cell_build(c); }));
     HIPCHK(c, launch_copy_back(c));
     c->build_pending = true;  // flags stay set: the Verlet lists are rebuilt on next use
@@ -788,7 +802,6 @@ int fpm_set_omega(fpm_ctx *c, const float *w) {
     int r = ready(c);
     if (r) return r;
     if (c->dem_cap <= 0) return fail(c, FPM_EINVAL, "DEM storage not set (fpm_set_dem)");
-    c->dem_rb = 0;
     HIPCHK(c, launch_dem_set_omega(c, w));
     return FPM_OK;
 }
@@ -798,7 +811,6 @@ int fpm_dem_forces(fpm_ctx *c, const fpm_dem_params *p) {
     if (r) return r;
     HIPCHK(c, refresh_and_account(c));
     HIPCHK(c, timed(c, "dem_forces", [&] { return launch_dem_forces(c, *p); }));
-    c->dem_rb ^= 1;
     c->forces_valid = false;
     return FPM_OK;
 }
@@ -811,7 +823,6 @@ int fpm_dem_step(fpm_ctx *c, const fpm_dem_params *p, int32_t nsteps) {
     for (int s = 0; s < nsteps; s++) {
         HIPCHK(c, refresh_lists(c));  // gated on the device flag
         HIPCHK(c, timed(c, "dem_forces", [&] { return launch_dem_forces(c, *p); }));
-        c->dem_rb ^= 1;
         HIPCHK(c, launch_dem_integrate(c, *p));
         HIPCHK(c, launch_finalize(c, kFinBuild | kFinDisp, nullptr, nullptr));
     }

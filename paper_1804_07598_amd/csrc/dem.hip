@@ -14,12 +14,18 @@
 // Walls (bit 1: x = 0 and x = L_x, bit 2: z = 0) push with Eq. 11's normal
 // force (delta = R - distance, m_eff = m).  Gravity m g.
 //
-// Contact history: for each grain, by caller index, up to C (partner caller
-// index, u_t) slots; p and q each keep their own copy (u_t of (q, p) is minus
-// that of (p, q), and both update with exactly negated arithmetic).  A step
-// reads one buffer and writes the current contacts to the other, so grains
-// never share a write.  Angular velocity lives in the per-slot buffer the
-// cell sort carries along; torques in the per-slot scratch.
+// Contact history: the u_t of a grain's pairs sits beside its Verlet list,
+// one float4 (u_t, in-contact flag) per list entry, in the list's order and
+// slot blocking, so the step reads it with the list and each lane updates only
+// its own entries.  The lists and slots change only at a rebuild: the gated
+// export kernel then copies the history of the pairs in contact to rows keyed
+// by caller index (partner caller index, u_t; up to C per grain) before the
+// cell sort, and the gated import kernel moves it to the new list positions
+// after the build.  A pair keeps its history as long as it stays in contact;
+// p and q each keep their own copy (u_t of (q, p) is minus that of (p, q), and
+// both update with exactly negated arithmetic).  Angular velocity lives in the
+// per-slot buffer the cell sort carries along; torques in the per-slot
+// scratch.
 #include "geom.h"
 
 namespace fpm {
@@ -95,16 +101,17 @@ __device__ __forceinline__ void contact(DemAcc &a, const DemCoef &k, const doubl
     }
 }
 
-// Forces and torques of the grains; history read from buffer rb, the current
-// contacts written to buffer 1 - rb.  The list is walked four entries at a
-// time, and each dependent step is requested for the four together: the
-// neighbour positions, then the state of the partners in contact (a lane's
-// own slot stands in for the others), then their history slots.  CR > 0: the
-// history capacity is CR (a multiple of four, at most 16) and the grain's
-// partner ids are held in registers; CR = 0: any capacity, searched in memory.
-template <int CR>
-__global__ __launch_bounds__(kBlock) void k_dem_forces(State st, DemCoef k, int rb, int cap4) {
-    constexpr int NR = CR > 0 ? CR : 1;
+// History of list entry e of slot i: entry-major within each 64-slot block,
+// so one entry of a wavefront's 64 slots is one 1 KiB load.
+__device__ __forceinline__ int64_t hist_base(int64_t i, int cap4) {
+    return (i >> 6) * (int64_t)cap4 * 4 * 64 + (i & 63);
+}
+
+// Forces and torques of the grains, advancing the history in place.  The list
+// is walked four entries at a time: their list indices and history entries
+// with one request, then the four partners' position, velocity and angular
+// velocity with the next.
+__global__ __launch_bounds__(kBlock) void k_dem_forces(State st, DemCoef k, int cap4) {
     const SysDesc &d = st.sys[block_system(st)];
     const Box b = d.box;
     const int64_t i = global_slot();
@@ -112,22 +119,6 @@ __global__ __launch_bounds__(kBlock) void k_dem_forces(State st, DemCoef k, int 
     const float4 *__restrict__ pos = st.pos[0];
     const float4 *__restrict__ vel = st.vel[0];
     const float4 *__restrict__ om = st.old[0];
-    const int32_t *__restrict__ id = st.id[0];
-    const int C = CR > 0 ? CR : k.C;
-    const int64_t me = id[i];
-    const int32_t *hid_in = st.hid[rb] + me * C;
-    const float4 *hu_in = st.hu[rb] + me * C;
-    int32_t *hid_out = st.hid[1 - rb] + me * C;
-    float4 *hu_out = st.hu[1 - rb] + me * C;
-    int hrow[NR];
-    if (CR > 0) {
-        const int4 *h4 = reinterpret_cast<const int4 *>(hid_in);
-#pragma unroll
-        for (int g = 0; g < NR / 4; g++) {
-            const int4 t = h4[g];
-            hrow[4 * g] = t.x, hrow[4 * g + 1] = t.y, hrow[4 * g + 2] = t.z, hrow[4 * g + 3] = t.w;
-        }
-    }
     const float4 pi4 = pos[i], vi = vel[i], wi = om[i];
     const float3 pi = xyz(pi4);
     DemAcc a;
@@ -136,62 +127,39 @@ __global__ __launch_bounds__(kBlock) void k_dem_forces(State st, DemCoef k, int 
     const int cnt = (int)(st.nnb[i] & ~kWrapBit);
     const int4 *lst = reinterpret_cast<const int4 *>(st.nbr) + ((i >> 6) * (int64_t)cap4) * 64 +
                       (i & 63);
+    float4 *hrow = st.hl + hist_base(i, cap4);
     for (int k0 = 0; k0 < cnt; k0 += 4) {  // lists are padded to a multiple of eight
         const int4 e = lst[(k0 >> 2) * 64];
-        const int j[4] = {e.x, e.y, e.z, e.w};
-        float4 q[4];
-#pragma unroll
-        for (int u = 0; u < 4; u++) q[u] = pos[j[u]];
-        bool in[4];
-#pragma unroll
-        for (int u = 0; u < 4; u++) {
-            const double rx = sep_axis(pi.x, q[u].x, b.L[0], b.half[0], b.per[0]);
-            const double ry = sep_axis(pi.y, q[u].y, b.L[1], b.half[1], b.per[1]);
-            const double rz = sep_axis(pi.z, q[u].z, b.L[2], b.half[2], b.per[2]);
-            in[u] = k0 + u < cnt && rx * rx + ry * ry + rz * rz < k.d2max;
-        }
-        float4 vj[4], wj[4];
-        int qid[4];
-#pragma unroll
-        for (int u = 0; u < 4; u++) {
-            const int jj = in[u] ? j[u] : (int)i;
-            vj[u] = vel[jj];
-            wj[u] = om[jj];
-            qid[u] = id[jj];
-        }
         float4 h[4];
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
-            int m = -1;
-            if (CR > 0) {
+        for (int u = 0; u < 4; u++) h[u] = hrow[(k0 + u) * 64];
+        const int j[4] = {e.x, e.y, e.z, e.w};
+        float4 q[4], vj[4], wj[4];
 #pragma unroll
-                for (int c = 0; c < NR; c++) m = hrow[c] == qid[u] ? c : m;
-            } else {
-                for (int c = 0; c < C; c++)
-                    if (hid_in[c] == qid[u]) {
-                        m = c;
-                        break;
-                    }
-            }
-            h[u] = hu_in[m >= 0 ? m : 0];
-            if (!(in[u] && m >= 0)) h[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int u = 0; u < 4; u++) {
+            q[u] = pos[j[u]];
+            vj[u] = vel[j[u]];
+            wj[u] = om[j[u]];
         }
 #pragma unroll
         for (int u = 0; u < 4; u++) {
-            if (!in[u]) continue;
+            const bool live = k0 + u < cnt;
             const double r[3] = {sep_axis(pi.x, q[u].x, b.L[0], b.half[0], b.per[0]),
                                  sep_axis(pi.y, q[u].y, b.L[1], b.half[1], b.per[1]),
                                  sep_axis(pi.z, q[u].z, b.L[2], b.half[2], b.per[2])};
-            double uu[3] = {h[u].x, h[u].y, h[u].z};
-            contact(a, k, r, dot3(r, r), vi, wi, vj[u], wj[u], uu);
-            if (nc < C) {
-                hid_out[nc] = qid[u];
-                hu_out[nc] = make_float4((float)uu[0], (float)uu[1], (float)uu[2], 0.f);
+            const double rr2 = dot3(r, r);
+            if (live && rr2 < k.d2max) {
+                const bool had = h[u].w != 0.f;
+                double uu[3] = {had ? (double)h[u].x : 0.0, had ? (double)h[u].y : 0.0,
+                                had ? (double)h[u].z : 0.0};
+                contact(a, k, r, rr2, vi, wi, vj[u], wj[u], uu);
+                hrow[(k0 + u) * 64] = make_float4((float)uu[0], (float)uu[1], (float)uu[2], 1.f);
+                nc++;
+            } else if (live && h[u].w != 0.f) {
+                hrow[(k0 + u) * 64] = make_float4(0.f, 0.f, 0.f, 0.f);  // contact lost
             }
-            nc++;
         }
     }
-    for (int c = nc; c < C; c++) hid_out[c] = -1;
     // walls: normal force only
     for (int wall = 0; wall < 3; wall++) {
         double nw[3] = {0.0, 0.0, 0.0}, dist;
@@ -217,9 +185,71 @@ __global__ __launch_bounds__(kBlock) void k_dem_forces(State st, DemCoef k, int 
     }
     st.frc[i] = make_float4((float)a.f[0], (float)a.f[1], (float)a.f[2], 0.f);
     st.aux[i] = make_float4((float)a.t[0], (float)a.t[1], (float)a.t[2], 0.f);
-    st.ncon[me] = nc;
-    if (nc > C) st.ctl->overflow = nc;
+    st.ncon[st.id[0][i]] = nc;
+    if (nc > k.C) st.ctl->overflow = nc;
     if (!isfinite(a.f[0]) || !isfinite(a.f[1]) || !isfinite(a.f[2])) st.ctl->nonfinite = 1;
+}
+
+// Before a rebuild (gated on the flag): the pairs in contact with their u_t,
+// from list positions to rows keyed by caller index, in list order.
+__global__ __launch_bounds__(kBlock) void k_dem_export(State st, int cap4, int C, int64_t ns) {
+    const int s = block_system(st);
+    if (!st.sctl[s].rebuild) return;
+    const SysDesc &d = st.sys[s];
+    const int64_t i = global_slot();
+    if (i - d.slot_base >= d.n) return;
+    const int32_t *__restrict__ id = st.id[0];
+    const int64_t me = id[i];
+    int cnt = (int)(st.nnb[i] & ~kWrapBit);
+    if (cnt > 4 * cap4) cnt = 4 * cap4;
+    const float4 *hrow = st.hl + hist_base(i, cap4);
+    int32_t *hid = st.hid + me * C;
+    float4 *hu = st.hu + me * C;
+    int nc = 0;
+    for (int e = 0; e < cnt; e++) {
+        const float4 h = hrow[e * 64];
+        if (h.w == 0.f) continue;
+        const int j = st.nbr[nbr_index(i, e, cap4)];
+        if ((uint64_t)j >= (uint64_t)ns) continue;
+        if (nc < C) {
+            hid[nc] = id[j];
+            hu[nc] = h;
+        }
+        nc++;
+    }
+    for (int c = nc; c < C; c++) hid[c] = -1;
+    if (nc > C) st.ctl->overflow = nc;
+}
+
+// After a rebuild (gated on the flag): each entry of the new lists takes the
+// u_t its partner had in the exported row, or none.
+__global__ __launch_bounds__(kBlock) void k_dem_import(State st, int cap4, int C) {
+    const int s = block_system(st);
+    if (!st.sctl[s].rebuild) return;
+    const SysDesc &d = st.sys[s];
+    const int64_t i = global_slot();
+    if (i - d.slot_base >= d.n) return;
+    const int32_t *__restrict__ id = st.id[0];
+    const int64_t me = id[i];
+    const int cnt = (int)(st.nnb[i] & ~kWrapBit);
+    const int32_t *hid = st.hid + me * C;
+    const float4 *hu = st.hu + me * C;
+    int stored = 0;
+    while (stored < C && hid[stored] >= 0) stored++;
+    float4 *hrow = st.hl + hist_base(i, cap4);
+    for (int e = 0; e < cnt; e++) {
+        float4 h = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (stored > 0) {
+            const int pid = id[st.nbr[nbr_index(i, e, cap4)]];
+            for (int c = 0; c < stored; c++)
+                if (hid[c] == pid) {
+                    h = hu[c];
+                    h.w = 1.f;
+                    break;
+                }
+        }
+        hrow[e * 64] = h;
+    }
 }
 
 // The leapfrog of Eq. 13 in FP32: v += dt F / m, x += dt v, w += dt T / I,
@@ -266,13 +296,11 @@ __global__ void k_dem_set_omega(State st, const float *w) {
                      : make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
-__global__ void k_dem_clear(State st, int64_t n, int C) {
+__global__ void k_dem_clear(State st, int64_t n, int C, int64_t nh) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n * C) {
-        st.hid[0][t] = -1;
-        st.hid[1][t] = -1;
-    }
+    if (t < n * C) st.hid[t] = -1;
     if (t < n) st.ncon[t] = 0;
+    if (t < nh) st.hl[t] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
 __global__ void k_dem_out(State st, float *w, float *tq) {
@@ -285,17 +313,35 @@ __global__ void k_dem_out(State st, float *w, float *tq) {
     if (tq) tq[3 * r] = b.x, tq[3 * r + 1] = b.y, tq[3 * r + 2] = b.z;
 }
 
-__global__ void k_dem_contacts_out(State st, int rb, int64_t n, int C, int32_t *ids, float *ut,
-                                   int32_t *ncon) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n * C) {
-        if (ids) ids[t] = st.hid[rb][t];
-        if (ut) {
-            const float4 h = st.hu[rb][t];
-            ut[3 * t] = h.x, ut[3 * t + 1] = h.y, ut[3 * t + 2] = h.z;
-        }
+// The pairs in contact at the last evaluation, per grain in caller order (in
+// list order, up to C), with their u_t; the rest of each row -1 and zero.
+__global__ void k_dem_contacts_out(State st, int cap4, int C, int32_t *ids, float *ut) {
+    const SysDesc &d = st.sys[block_system(st)];
+    const int64_t i = global_slot();
+    if (i - d.slot_base >= d.n) return;
+    const int32_t *__restrict__ id = st.id[0];
+    const int64_t me = id[i];
+    const int cnt = (int)(st.nnb[i] & ~kWrapBit);
+    const float4 *hrow = st.hl + hist_base(i, cap4);
+    int nc = 0;
+    for (int e = 0; e < cnt && nc < C; e++) {
+        const float4 h = hrow[e * 64];
+        if (h.w == 0.f) continue;
+        const int64_t o = me * C + nc;
+        if (ids) ids[o] = id[st.nbr[nbr_index(i, e, cap4)]];
+        if (ut) ut[3 * o] = h.x, ut[3 * o + 1] = h.y, ut[3 * o + 2] = h.z;
+        nc++;
     }
-    if (ncon && t < n) ncon[t] = st.ncon[t];
+    for (int c = nc; c < C; c++) {
+        const int64_t o = me * C + c;
+        if (ids) ids[o] = -1;
+        if (ut) ut[3 * o] = 0.f, ut[3 * o + 1] = 0.f, ut[3 * o + 2] = 0.f;
+    }
+}
+
+__global__ void k_ncon_out(State st, int64_t n, int32_t *ncon) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) ncon[t] = st.ncon[t];
 }
 
 DemCoef make_coef(const fpm_ctx *c, const fpm_dem_params &p) {
@@ -326,15 +372,8 @@ inline unsigned grid_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b);
 }  // namespace
 
 hipError_t launch_dem_forces(fpm_ctx *c, const fpm_dem_params &p) {
-    const DemCoef k = make_coef(c, p);
-    const dim3 g(c->nblk), blk(kBlock);
-    switch (c->dem_cap) {
-    case 4: hipLaunchKernelGGL(k_dem_forces<4>, g, blk, 0, c->stream, c->st, k, c->dem_rb, c->cap4); break;
-    case 8: hipLaunchKernelGGL(k_dem_forces<8>, g, blk, 0, c->stream, c->st, k, c->dem_rb, c->cap4); break;
-    case 12: hipLaunchKernelGGL(k_dem_forces<12>, g, blk, 0, c->stream, c->st, k, c->dem_rb, c->cap4); break;
-    case 16: hipLaunchKernelGGL(k_dem_forces<16>, g, blk, 0, c->stream, c->st, k, c->dem_rb, c->cap4); break;
-    default: hipLaunchKernelGGL(k_dem_forces<0>, g, blk, 0, c->stream, c->st, k, c->dem_rb, c->cap4); break;
-    }
+    hipLaunchKernelGGL(k_dem_forces, dim3(c->nblk), dim3(kBlock), 0, c->stream, c->st,
+                       make_coef(c, p), c->cap4);
     return hipGetLastError();
 }
 
@@ -344,10 +383,29 @@ hipError_t launch_dem_integrate(fpm_ctx *c, const fpm_dem_params &p) {
     return hipGetLastError();
 }
 
+hipError_t launch_dem_export(fpm_ctx *c) {
+    hipLaunchKernelGGL(k_dem_export, dim3(c->nblk), dim3(kBlock), 0, c->stream, c->st, c->cap4,
+                       c->dem_cap, (int64_t)c->nblk * kBlock);
+    return hipGetLastError();
+}
+
+hipError_t launch_dem_import(fpm_ctx *c) {
+    hipLaunchKernelGGL(k_dem_import, dim3(c->nblk), dim3(kBlock), 0, c->stream, c->st, c->cap4,
+                       c->dem_cap);
+    return hipGetLastError();
+}
+
 hipError_t launch_dem_set_omega(fpm_ctx *c, const float *w) {
     hipLaunchKernelGGL(k_dem_set_omega, dim3(c->nblk), dim3(kBlock), 0, c->stream, c->st, w);
-    hipLaunchKernelGGL(k_dem_clear, dim3(grid_for(c->n * c->dem_cap, 256)), dim3(256), 0,
-                       c->stream, c->st, c->n, c->dem_cap);
+    return launch_dem_clear(c);
+}
+
+hipError_t launch_dem_clear(fpm_ctx *c) {
+    const int64_t nh = (int64_t)c->nblk * kBlock * c->cap4 * 4;
+    int64_t m = c->n * c->dem_cap;
+    if (nh > m) m = nh;
+    hipLaunchKernelGGL(k_dem_clear, dim3(grid_for(m, 256)), dim3(256), 0, c->stream, c->st, c->n,
+                       c->dem_cap, nh);
     return hipGetLastError();
 }
 
@@ -355,9 +413,12 @@ hipError_t launch_dem_out(fpm_ctx *c, float *w, float *tq, int32_t *ids, float *
                           int32_t *ncon) {
     if (w || tq)
         hipLaunchKernelGGL(k_dem_out, dim3(c->nblk), dim3(kBlock), 0, c->stream, c->st, w, tq);
-    if (ids || ut || ncon)
-        hipLaunchKernelGGL(k_dem_contacts_out, dim3(grid_for(c->n * c->dem_cap, 256)), dim3(256),
-                           0, c->stream, c->st, c->dem_rb, c->n, c->dem_cap, ids, ut, ncon);
+    if (ids || ut)
+        hipLaunchKernelGGL(k_dem_contacts_out, dim3(c->nblk), dim3(kBlock), 0, c->stream, c->st,
+                           c->cap4, c->dem_cap, ids, ut);
+    if (ncon)
+        hipLaunchKernelGGL(k_ncon_out, dim3(grid_for(c->n, 256)), dim3(256), 0, c->stream, c->st,
+                           c->n, ncon);
     return hipGetLastError();
 }
 

@@ -117,8 +117,9 @@ struct State {
     float4 *old[2];         // SPH Verlet: previous step's (v, rho); DEM: angular velocity;
                             // double buffered like pos
     int32_t keep_old;       // 1: the cell sort carries old[] along
-    int32_t *hid[2];        // DEM: contact partners by caller index, two buffers
-    float4 *hu[2];          // DEM: their tangential histories
+    float4 *hl;             // DEM: (u_t, in contact) per Verlet-list entry, entry-major per 64 slots
+    int32_t *hid;           // DEM: partners in contact by caller index, C per grain (at rebuilds)
+    float4 *hu;             // DEM: their u_t
     int32_t *ncon;          // DEM: contacts per grain (caller index)
     Ctl *ctl;
     SysCtl *sctl;           // per system
@@ -196,7 +197,7 @@ struct fpm_ctx {
     double *s_hist = nullptr;
     bool sph_restart = true;           // the SPH step count restarts at the next step call
     int dem_cap = 0;                   // DEM contact slots per grain (0: DEM off)
-    int dem_rb = 0;                    // DEM history buffer holding the current contacts
+    bool dem_exported = false;         // DEM: the caller-keyed rows already hold the history
     // event timing of eager launches (fpm_set_profiling)
     struct Timed {
         std::string name;
@@ -248,6 +249,9 @@ hipError_t launch_sph_restart(fpm_ctx *c);  // the next SPH step counts as the f
 hipError_t launch_dem_forces(fpm_ctx *c, const fpm_dem_params &p);
 hipError_t launch_dem_integrate(fpm_ctx *c, const fpm_dem_params &p);
 hipError_t launch_dem_set_omega(fpm_ctx *c, const float *w);  // also clears the history
+hipError_t launch_dem_clear(fpm_ctx *c);                      // empty history
+hipError_t launch_dem_export(fpm_ctx *c);  // gated: list history -> caller-keyed rows
+hipError_t launch_dem_import(fpm_ctx *c);  // gated: caller-keyed rows -> new list positions
 hipError_t launch_dem_out(fpm_ctx *c, float *w, float *tq, int32_t *ids, float *ut,
                           int32_t *ncon);
 hipError_t launch_sph_finalize(fpm_ctx *c, const fpm_sph_params &p, int mode, float *dt_out,

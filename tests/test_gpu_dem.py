@@ -89,9 +89,14 @@ def test_forces_torques_history_match_oracle(cap):
     assert np.abs(gu - hu).max() <= 1e-6 * scale + 1e-12
 
 
-def check_trajectory(s, prm, oprm, K, skin=0.02, cap=C):
+def check_trajectory(s, prm, oprm, K, skin=0.02, cap=C, resort_at=None):
     sim = make(s, skin=skin, cap=cap)
-    sim.dem_step(K, prm)
+    if resort_at is None:
+        sim.dem_step(K, prm)
+    else:  # an explicit cell sort mid-way: the history must follow the grains
+        sim.dem_step(resort_at, prm)
+        sim.build_cell_list()
+        sim.dem_step(K - resort_at, prm)
     sim.check()
     p, v, _ = (np_(t) for t in sim.get())
     w, _, _ = (np_(t) for t in sim.get_dem())
@@ -127,6 +132,12 @@ def test_walls_and_gravity_match_oracle():
                          omega_sigma=2.0)
     prm, oprm = params(dt=5e-4, g=(0.0, 0.0, -9.81), walls=3)
     check_trajectory(s, prm, oprm, 80)
+
+
+def test_history_survives_explicit_cell_sort():
+    s = packing(seed=4)
+    prm, oprm = params(dt=5e-4)
+    check_trajectory(s, prm, oprm, 40, skin=0.02, resort_at=17)
 
 
 def test_avalanche_runs():
