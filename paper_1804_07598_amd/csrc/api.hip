@@ -169,7 +169,8 @@ size_t layout(const fpm_ctx *c, const Plan &P, char *base, State *st,
 
 void drop_graphs(fpm_ctx *c) {
     for (hipGraphExec_t *g :
-         {&c->g_first, &c->g_chunk, &c->g_one, &c->s_first, &c->s_chunk, &c->s_one}) {
+         {&c->g_first, &c->g_chunk, &c->g_one, &c->s_first, &c->s_chunk, &c->s_one, &c->d_chunk,
+          &c->d_one}) {
         if (*g) (void)hipGraphExecDestroy(*g);
         *g = nullptr;
     }
@@ -815,18 +816,43 @@ int fpm_dem_forces(fpm_ctx *c, const fpm_dem_params *p) {
     return FPM_OK;
 }
 
+// One DEM step: gated rebuild (with the history export and import), forces
+// and torques, leapfrog, finalize (accounts a rebuild, decides the next).
+hipError_t dem_step_body(fpm_ctx *c, const fpm_dem_params &p) {
+    hipError_t e = refresh_lists(c);
+    if (e == hipSuccess) e = timed(c, "dem_forces", [&] { return launch_dem_forces(c, p); });
+    if (e == hipSuccess) e = launch_dem_integrate(c, p);
+    if (e == hipSuccess) e = launch_finalize(c, kFinBuild | kFinDisp, nullptr, nullptr);
+    return e;
+}
+
 int fpm_dem_step(fpm_ctx *c, const fpm_dem_params *p, int32_t nsteps) {
     int r = dem_ready(c, p);
     if (r) return r;
     if (nsteps < 0) return fail(c, FPM_EINVAL, "bad step count");
     if (c->build_pending) HIPCHK(c, refresh_and_account(c));
-    for (int s = 0; s < nsteps; s++) {
-        HIPCHK(c, refresh_lists(c));  // gated on the device flag
-        HIPCHK(c, timed(c, "dem_forces", [&] { return launch_dem_forces(c, *p); }));
-        HIPCHK(c, launch_dem_integrate(c, *p));
-        HIPCHK(c, launch_finalize(c, kFinBuild | kFinDisp, nullptr, nullptr));
-    }
     c->forces_valid = false;
+    if (nsteps == 0) return FPM_OK;
+    if (!(c->d_chunk && memcmp(&c->d_prm, p, sizeof(*p)) == 0)) {
+        drop_graphs(c);
+        const fpm_dem_params prm = *p;
+        c->dem_exported = false;  // the captured steps always carry the export
+        int e = capture(c,
+                        [&] {
+                            hipError_t x = hipSuccess;
+                            for (int s = 0; s < kChunk && x == hipSuccess; s++)
+                                x = dem_step_body(c, prm);
+                            return x;
+                        },
+                        &c->d_chunk);
+        if (e) return e;
+        e = capture(c, [&] { return dem_step_body(c, prm); }, &c->d_one);
+        if (e) return e;
+        c->d_prm = *p;
+    }
+    int left = nsteps;
+    for (; left >= kChunk; left -= kChunk) HIPCHK(c, hipGraphLaunch(c->d_chunk, c->stream));
+    for (; left > 0; left--) HIPCHK(c, hipGraphLaunch(c->d_one, c->stream));
     return FPM_OK;
 }
 

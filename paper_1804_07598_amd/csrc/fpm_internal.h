@@ -198,6 +198,8 @@ struct fpm_ctx {
     bool sph_restart = true;           // the SPH step count restarts at the next step call
     int dem_cap = 0;                   // DEM contact slots per grain (0: DEM off)
     bool dem_exported = false;         // DEM: the caller-keyed rows already hold the history
+    hipGraphExec_t d_chunk = nullptr, d_one = nullptr;  // DEM step graphs
+    fpm_dem_params d_prm{};
     // event timing of eager launches (fpm_set_profiling)
     struct Timed {
         std::string name;
