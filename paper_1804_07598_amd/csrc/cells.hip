@@ -106,6 +106,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_assign(State st) {
 // 16 wavefront totals.  `in` may alias `out`; with `clear` the inputs are
 // zeroed.  Returns the tile's total to every thread.
 constexpr int kScanTile = 4096;
+constexpr int64_t kScanDeviceCells = 16384;  // a single system with more cells scans device-wide
 
 __device__ __forceinline__ int32_t scan_tile(int32_t *in, int32_t *out, int64_t base, int64_t n,
                                              int32_t carry, bool clear) {

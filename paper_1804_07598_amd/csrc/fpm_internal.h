@@ -19,7 +19,6 @@ namespace fpm {
 
 constexpr int kWave = 64;          // CDNA wavefront
 constexpr int kBlock = 256;        // threads per workgroup of the particle kernels
-constexpr int kScanDeviceCells = 65536;  // a single system with more cells scans device-wide
 constexpr int kMaxNbrCap = 4096;   // largest accepted Verlet-list capacity
 constexpr int64_t kMaxParticles = (int64_t(1) << 26) - 1;
 constexpr int kMaxSystems = 1 << 16;
