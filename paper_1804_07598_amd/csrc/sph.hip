@@ -132,11 +132,15 @@ __device__ __forceinline__ void sph_walk(SphAcc &s, const float4 *__restrict__ p
     const char *pb = reinterpret_cast<const char *>(pos);
     const char *vb = reinterpret_cast<const char *>(vel);
     (void)self;
-    // lists are padded with a far-away slot to a multiple of eight entries
+    // lists are padded with a far-away slot to a multiple of eight entries;
+    // the entries of the next group are requested before this group's gathers
+    if (cnt <= 0) return;
+    int4 e = lst[0];
     for (int kk = 0; kk < cnt; kk += 4) {
-        const int4 e = lst[(kk >> 2) * 64];
+        const int4 en = lst[((kk + 4 < cnt ? kk + 4 : kk) >> 2) * 64];
         const uint32_t jj[4] = {(uint32_t)e.x << 4, (uint32_t)e.y << 4, (uint32_t)e.z << 4,
                                 (uint32_t)e.w << 4};
+        e = en;
         float4 q[4], w[4];
 #pragma unroll
         for (int u = 0; u < 4; u++) {
