@@ -128,12 +128,13 @@ __global__ __launch_bounds__(kBlock) void k_dem_forces(State st, DemCoef k, int 
     const int4 *lst = reinterpret_cast<const int4 *>(st.nbr) + ((i >> 6) * (int64_t)cap4) * 64 +
                       (i & 63);
     float4 *hrow = st.hl + hist_base(i, cap4);
+    int4 e = cnt > 0 ? lst[0] : make_int4(0, 0, 0, 0);
     for (int k0 = 0; k0 < cnt; k0 += 4) {  // lists are padded to a multiple of eight
-        const int4 e = lst[(k0 >> 2) * 64];
+        const int j[4] = {e.x, e.y, e.z, e.w};
+        e = lst[((k0 + 4 < cnt ? k0 + 4 : k0) >> 2) * 64];  // the next group, ahead of time
         float4 h[4];
 #pragma unroll
         for (int u = 0; u < 4; u++) h[u] = hrow[(k0 + u) * 64];
-        const int j[4] = {e.x, e.y, e.z, e.w};
         float4 q[4], vj[4], wj[4];
 #pragma unroll
         for (int u = 0; u < 4; u++) {

@@ -279,9 +279,11 @@ __device__ __forceinline__ void vjp_walk(VjpAcc &a, const float4 *__restrict__ p
     const float3 pi = xyz(pi4);
     const double xi = pi.x, yi = pi.y, zi = pi.z;
     const int ti = __float_as_int(pi4.w);
+    if (cnt <= 0) return;
+    int4 e = lst[0];  // the next group's entries are requested before this group's gathers
     for (int k = 0; k < cnt; k += 4) {
-        const int4 e = lst[(k >> 2) * 64];
         const int jj[4] = {e.x, e.y, e.z, e.w};
+        e = lst[((k + 4 < cnt ? k + 4 : k) >> 2) * 64];
         float4 q[4], l[4];
 #pragma unroll
         for (int u = 0; u < 4; u++) {
