@@ -238,3 +238,59 @@ def test_full_size_history_antisymmetric():
     u = ut[pp, slot]
     assert np.array_equal(u[order][at], -u)
     assert np.abs(u).max() > 0
+
+
+def test_contact_overflow_is_reported():
+    from paper_1804_07598_amd._lib import FpmError, FPM_EOVERFLOW
+    s = packing(seed=5)  # six contacts per grain
+    sim = make(s, cap=4)
+    prm, _ = params()
+    sim.dem_forces(prm)
+    with pytest.raises(FpmError) as e:
+        sim.check()
+    assert e.value.code == FPM_EOVERFLOW
+
+
+def test_history_kept_across_set_positions():
+    # positions handed back unchanged half-way: the contact history and the
+    # angular velocities carry on as if nothing happened
+    s = packing(seed=6)
+    prm, oprm = params(dt=5e-4)
+    sim = make(s, skin=0.02)
+    sim.dem_step(25, prm)
+    p, _, _ = sim.get()
+    sim.set_positions(p.clone())
+    sim.dem_step(25, prm)
+    sim.check()
+    p, v, _ = (np_(t) for t in sim.get())
+    w, _, _ = (np_(t) for t in sim.get_dem())
+    x64, v64, w64, _, _, _, _ = O.dem_steps(s.pos.astype(np.float64), s.vel, s.omega, s.L,
+                                            s.periodic, oprm, 50)
+    d = p.astype(np.float64) - x64
+    d -= np.asarray(s.L, np.float64) * np.round(d / np.asarray(s.L, np.float64))
+    assert np.abs(d).max() <= 2e-5
+    assert np.abs(v - v64).max() <= 1e-5
+    assert np.abs(w - w64).max() <= 1e-4
+
+
+def test_free_flight_without_contacts():
+    # grains 3R apart never touch: the leapfrog under gravity in closed form
+    # (v_k = v_0 + k dt g, x_k = x_0 + k dt v_0 + dt^2 g k (k + 1) / 2), omega kept
+    s = inputs.dem_block((6, 6, 6), R, 3 * R, (18 * R, 18 * R, 60.0), (1, 1, 0),
+                         origin=(0.0, 0.0, 30.0), seed=8, vel_sigma=0.01, omega_sigma=1.0)
+    g, dt, k = (0.0, 0.0, -9.81), 1e-3, 40
+    prm, _ = params(dt=dt, g=g)
+    sim = make(s)
+    sim.dem_step(k, prm)
+    sim.check()
+    p, v, _ = (np_(t) for t in sim.get())
+    w, T, nc = (np_(t) for t in sim.get_dem())
+    gv = np.array([f32(x) for x in g])
+    dt32 = f32(dt)
+    v_exp = s.vel.astype(np.float64) + k * dt32 * gv
+    x_exp = s.pos.astype(np.float64) + k * dt32 * s.vel + dt32 * dt32 * gv * k * (k + 1) / 2
+    dxy = (p - x_exp)[:, :2]
+    dxy -= 18 * R * np.round(dxy / (18 * R))
+    assert np.abs(dxy).max() <= 1e-5 and np.abs(p[:, 2] - x_exp[:, 2]).max() <= 2e-5
+    assert np.abs(v - v_exp).max() <= 1e-5
+    assert np.array_equal(w, s.omega) and np.all(T == 0) and np.all(nc == 0)
