@@ -61,8 +61,13 @@ __device__ __forceinline__ bool separation(float3 pi, double xi, double yi, doub
     }
     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
     bool in = r2 <= rc2lo;
-    if (!in && r2 <= rc2hi)
-        in = (IMG ? dist2_pred(pi, xyz(q), b) : dist2_direct(pi, xyz(q))) <= rc2;
+    // the band is narrow: a wavefront rarely has a lane in it, and only then
+    // is the FP32 predicate evaluated (otherwise the compiler computes it for
+    // every pair)
+    if (__builtin_expect(__ballot(!in && r2 <= rc2hi) != 0, 0)) {
+        if (!in && r2 <= rc2hi)
+            in = (IMG ? dist2_pred(pi, xyz(q), b) : dist2_direct(pi, xyz(q))) <= rc2;
+    }
     return in;
 }
 

@@ -97,8 +97,11 @@ __device__ __forceinline__ void sph_pair(SphAcc &s, float3 pi, double xi, double
     }
     const double r2 = dx * dx + dy * dy + dz * dz;
     bool in = r2 <= k.rc2lo;
-    if (!in && r2 <= k.rc2hi)
-        in = (IMG ? dist2_pred(pi, xyz(q), b) : dist2_direct(pi, xyz(q))) <= rc2;
+    // the band is narrow: the FP32 predicate only when some lane of the wavefront is in it
+    if (__builtin_expect(__ballot(!in && r2 <= k.rc2hi) != 0, 0)) {
+        if (!in && r2 <= k.rc2hi)
+            in = (IMG ? dist2_pred(pi, xyz(q), b) : dist2_direct(pi, xyz(q))) <= rc2;
+    }
     if (in) {
         const double gw = grad_factor<KER>(sqrt64(r2), k);  // gradW = gw * x_ab
         const double rho_b = (double)w.w;
