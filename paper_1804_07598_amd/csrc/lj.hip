@@ -62,8 +62,7 @@ __device__ __forceinline__ bool separation(float3 pi, double xi, double yi, doub
     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
     bool in = r2 <= rc2lo;
     // the band is narrow: a wavefront rarely has a lane in it, and only then
-    // is the FP32 predicate evaluated (otherwise the compiler computes it for
-    // every pair)
+    // is the FP32 predicate evaluated
     if (__builtin_expect(__ballot(!in && r2 <= rc2hi) != 0, 0)) {
         if (!in && r2 <= rc2hi)
             in = (IMG ? dist2_pred(pi, xyz(q), b) : dist2_direct(pi, xyz(q))) <= rc2;
