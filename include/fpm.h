@@ -260,11 +260,15 @@ int fpm_sph_step(fpm_ctx *ctx, const fpm_sph_params *prm, int32_t nsteps, double
 
 /* ---- DEM (section 4.5) ---- */
 
-/* Turns on DEM storage: a contact history of max_contacts (1..64) partners per
- * grain and per-grain angular velocities.  Call before fpm_workspace_size and
- * fpm_set_particles (single system; the Verlet list radius r_cut + skin must
- * cover 2R).  The angular velocity shares storage with SPH's Verlet scheme:
- * do not mix DEM and SPH on one context. */
+/* Turns on DEM storage: per-grain angular velocities and the contact
+ * history.  The history of a pair is kept beside its Verlet-list entry (one
+ * u_t per list entry, so the workspace grows by 16 B per list slot); across
+ * a list rebuild up to max_contacts (1..64) contacts per grain are carried
+ * over by partner, and max_contacts also sizes the rows of
+ * fpm_get_contacts.  Call before fpm_workspace_size and fpm_set_particles
+ * (single system; the Verlet list radius r_cut + skin must cover 2R).  The
+ * angular velocity shares storage with SPH's Verlet scheme: do not mix DEM
+ * and SPH on one context. */
 int fpm_set_dem(fpm_ctx *ctx, int32_t max_contacts);
 /* Angular velocities (device, caller order, n x 3; NULL = zero); clears the
  * contact history.  fpm_set_particles starts from zero and no history. */
@@ -280,8 +284,9 @@ int fpm_dem_step(fpm_ctx *ctx, const fpm_dem_params *prm, int32_t nsteps);
 /* Caller-order outputs (any may be NULL): angular velocities and the last
  * torques (n x 3), contact counts (n). */
 int fpm_get_dem(fpm_ctx *ctx, float *d_omega, float *d_torque, int32_t *d_ncontact);
-/* The contact history in caller order: d_ids (n x max_contacts partner caller
- * indices, -1 = empty) and d_ut (n x max_contacts x 3). */
+/* The contacts of the last evaluation with their history, in caller order:
+ * d_ids (n x max_contacts partner caller indices in list order, then -1) and
+ * d_ut (n x max_contacts x 3, zero after the last contact). */
 int fpm_get_contacts(fpm_ctx *ctx, int32_t *d_ids, float *d_ut);
 
 /* ---- status ---- */
