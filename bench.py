@@ -499,7 +499,8 @@ def main(argv=None) -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 state, f64 pair arithmetic",
+        "dtype": "f64",
+        "state_dtype": "f32 (positions, velocities, forces; pair arithmetic and sums in f64)",
         "data": "synthetic",
         "config": {"workload": "lj1m: LJ fluid N=1,000,000 (jittered 100^3 lattice), rho=0.8442, "
                                "T=1, r_cut=2.5, skin=0.3, dt=0.005, periodic",
