@@ -80,6 +80,8 @@ def lib():
             L.oracle_dem_forces.argtypes = [C.c_int64, f64p, f64p, f64p, f32p, i32p, f64p, C.c_int,
                                             i64p, f64p, f64p, f64p, i64p, f64p, i32p]
             L.oracle_dem_leapfrog.argtypes = [C.c_int64, f64p, f64p, f64p, f64p, f64p, f64p]
+            L.oracle_dem_forces_rows.argtypes = [C.c_int64, f64p, f64p, f64p, f32p, i32p, f64p,
+                                                 i64p, C.c_int64, f64p, f64p, i32p]
         if hasattr(L, "oracle_lj_vjp"):
             L.oracle_lj_vjp.argtypes = [C.c_int64, f32p, _opt(i32p), f32p, i32p, C.c_float, f64p,
                                         f64p, f64p, f64p, f64p]
@@ -465,6 +467,18 @@ def dem_forces(x, v, w, L, per, prm, hist=None, C=16):
     lib().oracle_dem_forces(n, x, v, w, _box(L), _per(per), _f64(prm), int(C), hid, hu, F, T,
                             hid2, hu2, nc)
     return F, T, (hid2, hu2), nc
+
+
+def dem_forces_rows(x, v, w, L, per, prm, rows):
+    """Forces and torques (dem_forces) of the grains `rows` only, against all
+    grains, with no contact history; returns (F, T, contact counts)."""
+    x, v, w = (np.ascontiguousarray(q, np.float64) for q in (x, v, w))
+    rows = np.ascontiguousarray(rows, np.int64)
+    F = np.empty((len(rows), 3)); T = np.empty((len(rows), 3))
+    nc = np.empty(len(rows), np.int32)
+    lib().oracle_dem_forces_rows(len(x), x, v, w, _box(L), _per(per), _f64(prm), rows,
+                                 len(rows), F, T, nc)
+    return F, T, nc
 
 
 def dem_steps(x, v, w, L, per, prm, nsteps, hist=None, C=16):

@@ -48,6 +48,109 @@ static double dot(const double a[3], const double b[3])
 }
 
 /*
+ * Force f and torque t on grain p at the state (x, v, w), its contact
+ * history (hid_p, hu_p: C slots of partner id, -1 empty, and u_t) and the
+ * updated history of its current contacts in ascending partner order
+ * (hid_o, hu_o); returns its number of contacts (only the first C stored).
+ */
+static int dem_grain(int64_t p, int64_t n, const double *x, const double *v, const double *w,
+                     const float L[3], const int32_t per[3], const double *prm, int C,
+                     const int64_t *hid_p, const double *hu_p, double f[3], double t[3],
+                     int64_t *hid_o, double *hu_o)
+{
+    const double R = prm[0], m = prm[1], kn = prm[3], kt = prm[4];
+    const double gn = prm[5], gt = prm[6], mu = prm[7], dt = prm[11];
+    const int walls = (int)prm[12];
+    const double meff = 0.5 * m, d2max = 4.0 * R * R;
+    f[0] = m * prm[8], f[1] = m * prm[9], f[2] = m * prm[10];
+    t[0] = t[1] = t[2] = 0.0;
+    int nc = 0;
+    for (int c = 0; c < C; c++) hid_o[c] = -1;
+    for (int64_t q = 0; q < n; q++) {
+        if (q == p) continue;
+        double r[3];
+        for (int k = 0; k < 3; k++) {
+            double d = x[3 * p + k] - x[3 * q + k];
+            if (per[k]) {
+                if (d > 0.5 * L[k]) d -= L[k];
+                else if (d < -0.5 * L[k]) d += L[k];
+            }
+            r[k] = d;
+        }
+        const double rr2 = dot(r, r);
+        if (!(rr2 < d2max)) continue;
+        const double rr = sqrt(rr2);
+        const double nv[3] = {r[0] / rr, r[1] / rr, r[2] / rr};
+        const double a = 0.5 * rr;
+        const double delta = 2.0 * R - rr;
+        double ws[3] = {w[3 * p] + w[3 * q], w[3 * p + 1] + w[3 * q + 1],
+                        w[3 * p + 2] + w[3 * q + 2]}, rot[3];
+        cross(ws, nv, rot);
+        double vr[3];
+        for (int k = 0; k < 3; k++) vr[k] = v[3 * p + k] - v[3 * q + k] - a * rot[k];
+        const double vn = dot(vr, nv);
+        double vt[3];
+        for (int k = 0; k < 3; k++) vt[k] = vr[k] - vn * nv[k];
+        double u[3] = {0, 0, 0};
+        for (int c = 0; c < C; c++)
+            if (hid_p[c] == q) {
+                for (int k = 0; k < 3; k++) u[k] = hu_p[c * 3 + k];
+                break;
+            }
+        for (int k = 0; k < 3; k++) u[k] += vt[k] * dt;
+        const double un = dot(u, nv);
+        for (int k = 0; k < 3; k++) u[k] -= un * nv[k];
+        const double s = sqrt(delta / (2.0 * R));
+        double fn[3], ft[3];
+        for (int k = 0; k < 3; k++) {
+            fn[k] = s * (kn * delta * nv[k] - gn * meff * vn * nv[k]);
+            ft[k] = s * (-kt * u[k] - gt * meff * vt[k]);
+        }
+        const double fnm = sqrt(dot(fn, fn)), ftm = sqrt(dot(ft, ft));
+        if (ftm > mu * fnm) {
+            const double sc = mu * fnm / ftm;
+            for (int k = 0; k < 3; k++) ft[k] *= sc;
+            if (kt > 0.0)
+                for (int k = 0; k < 3; k++) u[k] = -(ft[k] / s + gt * meff * vt[k]) / kt;
+        }
+        double arm[3] = {-a * nv[0], -a * nv[1], -a * nv[2]}, tq[3];
+        cross(arm, ft, tq);
+        for (int k = 0; k < 3; k++) {
+            f[k] += fn[k] + ft[k];
+            t[k] += tq[k];
+        }
+        if (nc < C) {
+            hid_o[nc] = q;
+            for (int k = 0; k < 3; k++) hu_o[nc * 3 + k] = u[k];
+        }
+        nc++;
+    }
+    /* walls: normal force only */
+    for (int wall = 0; wall < 3; wall++) {
+        double nw[3] = {0, 0, 0}, dist;
+        if (wall == 0) {
+            if (!(walls & 1)) continue;
+            dist = x[3 * p];
+            nw[0] = 1.0;
+        } else if (wall == 1) {
+            if (!(walls & 1)) continue;
+            dist = L[0] - x[3 * p];
+            nw[0] = -1.0;
+        } else {
+            if (!(walls & 2)) continue;
+            dist = x[3 * p + 2];
+            nw[2] = 1.0;
+        }
+        if (!(dist < R)) continue;
+        const double delta = R - dist;
+        const double s = sqrt(delta / (2.0 * R));
+        const double vn = dot(v + 3 * p, nw);
+        for (int k = 0; k < 3; k++) f[k] += s * (kn * delta * nw[k] - gn * m * vn * nw[k]);
+    }
+    return nc;
+}
+
+/*
  * Forces F (n x 3) and torques T (n x 3) at the state (x, v, w) with the
  * history (hid_in, hu_in): for grain p, slots c < C hold a partner id
  * (-1: empty) and its u_t.  The updated history of the current contacts goes
@@ -59,105 +162,35 @@ int oracle_dem_forces(int64_t n, const double *x, const double *v, const double 
                       const int64_t *hid_in, const double *hu_in, double *F, double *T,
                       int64_t *hid_out, double *hu_out, int32_t *ncontact)
 {
-    const double R = prm[0], m = prm[1], kn = prm[3], kt = prm[4];
-    const double gn = prm[5], gt = prm[6], mu = prm[7], dt = prm[11];
-    const int walls = (int)prm[12];
-    const double meff = 0.5 * m, d2max = 4.0 * R * R;
     int worst = 0;
 #pragma omp parallel for schedule(dynamic, 16) reduction(max : worst)
     for (int64_t p = 0; p < n; p++) {
-        double f[3] = {m * prm[8], m * prm[9], m * prm[10]}, t[3] = {0, 0, 0};
-        int nc = 0;
-        for (int c = 0; c < C; c++) hid_out[p * C + c] = -1;
-        for (int64_t q = 0; q < n; q++) {
-            if (q == p) continue;
-            double r[3];
-            for (int k = 0; k < 3; k++) {
-                double d = x[3 * p + k] - x[3 * q + k];
-                if (per[k]) {
-                    if (d > 0.5 * L[k]) d -= L[k];
-                    else if (d < -0.5 * L[k]) d += L[k];
-                }
-                r[k] = d;
-            }
-            const double rr2 = dot(r, r);
-            if (!(rr2 < d2max)) continue;
-            const double rr = sqrt(rr2);
-            const double nv[3] = {r[0] / rr, r[1] / rr, r[2] / rr};
-            const double a = 0.5 * rr;
-            const double delta = 2.0 * R - rr;
-            double ws[3] = {w[3 * p] + w[3 * q], w[3 * p + 1] + w[3 * q + 1],
-                            w[3 * p + 2] + w[3 * q + 2]}, rot[3];
-            cross(ws, nv, rot);
-            double vr[3];
-            for (int k = 0; k < 3; k++) vr[k] = v[3 * p + k] - v[3 * q + k] - a * rot[k];
-            const double vn = dot(vr, nv);
-            double vt[3];
-            for (int k = 0; k < 3; k++) vt[k] = vr[k] - vn * nv[k];
-            double u[3] = {0, 0, 0};
-            for (int c = 0; c < C; c++)
-                if (hid_in[p * C + c] == q) {
-                    for (int k = 0; k < 3; k++) u[k] = hu_in[(p * C + c) * 3 + k];
-                    break;
-                }
-            for (int k = 0; k < 3; k++) u[k] += vt[k] * dt;
-            const double un = dot(u, nv);
-            for (int k = 0; k < 3; k++) u[k] -= un * nv[k];
-            const double s = sqrt(delta / (2.0 * R));
-            double fn[3], ft[3];
-            for (int k = 0; k < 3; k++) {
-                fn[k] = s * (kn * delta * nv[k] - gn * meff * vn * nv[k]);
-                ft[k] = s * (-kt * u[k] - gt * meff * vt[k]);
-            }
-            const double fnm = sqrt(dot(fn, fn)), ftm = sqrt(dot(ft, ft));
-            if (ftm > mu * fnm) {
-                const double sc = mu * fnm / ftm;
-                for (int k = 0; k < 3; k++) ft[k] *= sc;
-                if (kt > 0.0)
-                    for (int k = 0; k < 3; k++) u[k] = -(ft[k] / s + gt * meff * vt[k]) / kt;
-            }
-            double arm[3] = {-a * nv[0], -a * nv[1], -a * nv[2]}, tq[3];
-            cross(arm, ft, tq);
-            for (int k = 0; k < 3; k++) {
-                f[k] += fn[k] + ft[k];
-                t[k] += tq[k];
-            }
-            if (nc < C) {
-                hid_out[p * C + nc] = q;
-                for (int k = 0; k < 3; k++) hu_out[(p * C + nc) * 3 + k] = u[k];
-            }
-            nc++;
-        }
-        /* walls: normal force only */
-        for (int wall = 0; wall < 3; wall++) {
-            double nw[3] = {0, 0, 0}, dist;
-            if (wall == 0) {
-                if (!(walls & 1)) continue;
-                dist = x[3 * p];
-                nw[0] = 1.0;
-            } else if (wall == 1) {
-                if (!(walls & 1)) continue;
-                dist = L[0] - x[3 * p];
-                nw[0] = -1.0;
-            } else {
-                if (!(walls & 2)) continue;
-                dist = x[3 * p + 2];
-                nw[2] = 1.0;
-            }
-            if (!(dist < R)) continue;
-            const double delta = R - dist;
-            const double s = sqrt(delta / (2.0 * R));
-            const double vn = dot(v + 3 * p, nw);
-            for (int k = 0; k < 3; k++) f[k] += s * (kn * delta * nw[k] - gn * m * vn * nw[k]);
-        }
-        for (int k = 0; k < 3; k++) {
-            F[3 * p + k] = f[k];
-            T[3 * p + k] = t[k];
-        }
+        const int nc = dem_grain(p, n, x, v, w, L, per, prm, C, hid_in + p * C,
+                                 hu_in + p * C * 3, F + 3 * p, T + 3 * p, hid_out + p * C,
+                                 hu_out + p * C * 3);
         ncontact[p] = nc;
         if (nc > worst) worst = nc;
     }
     return worst;
+}
+
+/*
+ * The same evaluation for the grains rows[0 .. nrows) only, with no contact
+ * history (every pair starts from u_t = 0): force and torque of row r in
+ * F[3 r], T[3 r], its contact count in ncontact[r].
+ */
+void oracle_dem_forces_rows(int64_t n, const double *x, const double *v, const double *w,
+                            const float L[3], const int32_t per[3], const double *prm,
+                            const int64_t *rows, int64_t nrows, double *F, double *T,
+                            int32_t *ncontact)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t r = 0; r < nrows; r++) {
+        int64_t hid_p[1] = {-1}, hid_o[1];
+        double hu_p[3] = {0, 0, 0}, hu_o[3];
+        ncontact[r] = dem_grain(rows[r], n, x, v, w, L, per, prm, 1, hid_p, hu_p, F + 3 * r,
+                                T + 3 * r, hid_o, hu_o);
+    }
 }
 
 /* One leapfrog step of Eq. 13 with the forces and torques given. */

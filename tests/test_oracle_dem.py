@@ -149,3 +149,16 @@ def test_floor_and_side_walls():
     # the floor only with bit 2, the x walls only with bit 1
     F2, _, _, _ = O.dem_forces(x, v, np.zeros((3, 3)), L, (0, 0, 0), prm(walls=1))
     assert F2[0, 2] == 0 and F2[1, 0] > 0
+
+
+def test_rows_evaluation_equals_full_evaluation():
+    # the sampled-rows entry (used to time the oracle on large systems) gives
+    # the full evaluation's rows bit for bit, walls and gravity included
+    x, v, w = cluster(125, 4)
+    x[:, 2] -= 3.97  # the bottom layer touches the floor
+    p = prm(gt=0.5, g=(0.3, 0.0, -9.81), walls=3)
+    F, T, _, nc = O.dem_forces(x, v, w, L, (0, 1, 0), p)
+    rows = np.array([0, 7, 31, 64, 99, 124])
+    Fr, Tr, ncr = O.dem_forces_rows(x, v, w, L, (0, 1, 0), p, rows)
+    assert np.array_equal(Fr, F[rows]) and np.array_equal(Tr, T[rows])
+    assert np.array_equal(ncr, nc[rows]) and nc.max() > 0
