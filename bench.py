@@ -90,6 +90,30 @@ def cpu_baseline(pos, box, target_s: float, quiet: bool):
                       f"FP64 physics) at the initial configuration; {dt:.1f} s"}
 
 
+def dem_cpu_baseline(s, oprm, target_s: float, quiet: bool):
+    """The FP64 O(N^2) DEM oracle on a bounded sample: forces and torques of R
+    random grains against all N grains (no contact history), on the host's
+    cores."""
+    import numpy as np
+    import oracle as O
+    rng = np.random.default_rng(1)
+    x, v, w = s.pos.astype(np.float64), s.vel, s.omega
+    R = 64
+    O.dem_forces_rows(x, v, w, s.L, s.periodic, oprm, rng.choice(len(x), R, replace=False))
+    while True:
+        rows = rng.choice(len(x), R, replace=False)
+        t0 = time.perf_counter()
+        O.dem_forces_rows(x, v, w, s.L, s.periodic, oprm, rows)
+        dt = time.perf_counter() - t0
+        if dt >= target_s or R >= len(x):
+            break
+        R = min(len(x), max(R * 2, int(R * target_s / max(dt, 1e-3) * 1.1)))
+        log(f"dem cpu baseline: trying {R} rows", quiet)
+    return {"value": R / dt, "unit": "grain-steps/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"{R} random grains' contact forces and torques against all {len(x)} "
+                      f"grains (FP64) at the initial configuration; {dt:.1f} s"}
+
+
 def timed_steps(sim, nsteps, dt, warmup, eps=(1.0,) * 3, sig=(1.0,) * 3, n_types=1):
     """Milliseconds of nsteps graph-launched steps after warmup steps (HIP events
     on the stream the library launches on)."""
@@ -252,7 +276,8 @@ def bench_dambreak(dev, quiet: bool, t_end: float = 1.5, chunk: int = 2000,
             "mean_list": total / n, "rebuilds": reb}
 
 
-def bench_dem(dev, quiet: bool, steps: int = 2000, warmup: int = 200, scale: float = 4.2):
+def bench_dem(dev, quiet: bool, steps: int = 2000, warmup: int = 200, scale: float = 4.2,
+              cpu_seconds: float = 0.0):
     """Section 4.5's granular avalanche: the Silbert grain model with Hertzian
     contacts, tangential history and Coulomb cap, x walls, periodic y and a
     floor, gravity tilted by 30 degrees; the block at scale 4.2 holds 688,380
@@ -297,6 +322,12 @@ def bench_dem(dev, quiet: bool, steps: int = 2000, warmup: int = 200, scale: flo
     # 32 B; contact count 4 B (neighbour state gathered from cache)
     bytes_f = n * (92.0 + 20.0 * nbar + 16.0 * cbar)
     achieved = bytes_f / (f_ms / 1e3) / 1e9
+    cpu = None
+    if cpu_seconds > 0:
+        import oracle as O
+        oprm = O.dem_params_array(R, A["mass"], A["inertia"], A["kn"], A["kt"], A["gn"], A["gt"],
+                                  A["mu"], inputs.dem_avalanche_gravity(), A["dt"], A["walls"])
+        cpu = dem_cpu_baseline(s, oprm, cpu_seconds, quiet)
     log(f"DEM avalanche: {n} grains, {steps} steps in {ms:.1f} ms ({ms / steps * 1e3:.1f} us/step), "
         f"forces kernel {f_ms * 1e3:.1f} us, mean list {nbar:.2f}, mean contacts {cbar:.2f}, "
         f"rebuilds {reb1 - reb0}", quiet)
@@ -308,6 +339,7 @@ def bench_dem(dev, quiet: bool, steps: int = 2000, warmup: int = 200, scale: flo
             "paper_single_core_ms_per_step": 320.0,
             "forces_kernel_us": f_ms * 1e3, "mean_list": nbar, "mean_contacts": cbar,
             "rebuilds": reb1 - reb0,
+            "cpu_baseline": cpu,
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                          "bytes_per_launch": bytes_f,
@@ -420,7 +452,8 @@ def main(argv=None) -> int:
                 "sph": lambda: bench_sph(dev, 500, a.quiet),
                 "sph_dambreak": lambda: bench_dambreak(dev, a.quiet),
                 "adjoint": lambda: bench_adjoint(dev, a.quiet),
-                "dem": lambda: bench_dem(dev, a.quiet)}
+                "dem": lambda: bench_dem(dev, a.quiet,
+                                         cpu_seconds=0.0 if a.no_cpu_baseline else a.cpu_seconds / 2)}
         print(json.dumps({a.form: legs[a.form]()}), flush=True)
         return 0
     s = inputs.lj_config("lj1m")
@@ -523,7 +556,8 @@ def main(argv=None) -> int:
         result["sph"] = bench_sph(dev, 500, a.quiet)
         result["sph_dambreak"] = bench_dambreak(dev, a.quiet)
         result["adjoint"] = bench_adjoint(dev, a.quiet)
-        result["dem"] = bench_dem(dev, a.quiet)
+        result["dem"] = bench_dem(dev, a.quiet,
+                                  cpu_seconds=0.0 if a.no_cpu_baseline else a.cpu_seconds / 2)
     if not a.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(s.pos, s.box, a.cpu_seconds, a.quiet)
     print(json.dumps(result), flush=True)
