@@ -162,3 +162,15 @@ def test_trajectory_adjoint_full_size_runs():
         res.append([np_(t.grad) for t in (x0, v0, th)])
     for a, b in zip(res[0], res[1]):
         assert np.isfinite(a).all() and np.array_equal(a, b)
+
+
+def test_force_vjp_without_neighbours():
+    # one atom, and two atoms beyond the cut-off: every gradient is zero
+    import torch
+    from paper_1804_07598_amd.sim import ParticleSim
+    for p in ([[1.0, 2.0, 3.0]], [[1.0, 1.0, 1.0], [7.0, 7.0, 7.0]]):
+        pos = np.asarray(p, np.float32)
+        sim = ParticleSim(pos, 12.0, (1, 1, 1), r_cut=2.5, skin=0.3)
+        lam = torch.ones((len(pos), 3), dtype=torch.float64, device="cuda")
+        gx, gth = sim.force_vjp(lam)
+        assert torch.all(gx == 0) and torch.all(gth == 0)

@@ -160,3 +160,30 @@ def test_autotuner_picks_a_candidate_and_caches_it(tmp_path):
     assert np.array_equal(c, c0)
     again, table2 = tune(sim, 0.75, cache=cache)
     assert again == knobs and table2 == []  # served from the cache
+
+
+def test_batch_with_tiny_systems():
+    # systems of one atom, of two atoms beyond the list radius and of one
+    # interacting pair, next to a regular system: empty lists give zero force
+    # and energy, the pair matches the oracle, and nothing leaks between boxes
+    L = 12.0
+    mk = lambda p: inputs.LJSystem(np.asarray(p, np.float32), np.zeros((len(p), 3), np.float32),
+                                   np.zeros(len(p), np.int32), L, 0, 0, 0)
+    tiny = [mk([[1.0, 2.0, 3.0]]), mk([[1.0, 1.0, 1.0], [7.0, 7.0, 7.0]]),
+            mk([[5.0, 5.0, 5.0], [6.2, 5.0, 5.0]])]
+    systems = tiny + systems_of([4])
+    sim = make_batch(systems)
+    out = np_(sim.lj_forces())
+    _, _, F = sim.get()
+    F = np_(F)
+    counts, _ = (np_(t) for t in sim.neighbors())
+    for k in range(2):
+        a, b = sim.offsets[k], sim.offsets[k + 1]
+        assert np.all(F[a:b] == 0) and np.all(counts[a:b] == 0) and np.all(out[k] == 0), k
+    a = sim.offsets[2]
+    F64, U64, W64, _, _ = O.lj(tiny[2].pos, L, PER, O.radius2(RC))
+    assert np.abs(F[a:a + 2] - F64).max() <= FORCE_TOL * np.abs(F64).max()
+    assert F[a, 0] == -F[a + 1, 0] and F[a, 0] > 0  # attraction at r = 1.2: atom 0 pulled to +x
+    assert abs(out[2, 0] - U64) <= ENERGY_TOL * abs(U64)
+    cnt, cols = (np_(t) for t in sim.neighbors())
+    check_system(sim, 3, systems[3], F, out, cnt, cols)

@@ -112,3 +112,30 @@ def test_full_column_sampled_rows():
     sim.sph_rates(prm)
     rows = np.random.default_rng(0).choice(len(s.pos), 96, replace=False)
     compare_rates(sim, s, s.pos, vel, rho, oprm, r_cut, rows=rows)
+
+
+def test_isolated_particles():
+    # no neighbours within 2h: a fluid particle feels gravity alone, its
+    # density does not change, and a boundary particle gets nothing
+    from paper_1804_07598_amd import _lib as F
+    from paper_1804_07598_amd.sim import ParticleSim
+    pos = np.array([[0.1, 0.1, 0.1], [0.5, 0.5, 0.5], [0.9, 0.2, 0.3], [0.3, 0.7, 0.05]],
+                   np.float32)
+    kind = np.array([0, 0, 0, 1], np.int32)
+    vel = np.array([[0.1, 0.0, 0.0], [0.0, -0.2, 0.0], [0.0, 0.0, 0.3], [0.0, 0.0, 0.0]],
+                   np.float32)
+    dx = 0.01
+    h = 1.3 * dx
+    r_cut = float(np.float32(2 * h))
+    sim = ParticleSim(pos, np.array([1.0, 1.0, 1.0], np.float32), (1, 1, 0), vel=vel, typ=kind,
+                      r_cut=r_cut, skin=0.1 * h, max_nbr=16)
+    sim.set_density(np.full(4, RHO0, np.float32))
+    prm = F.sph_params(h, RHO0 * dx ** 3, RHO0, 20.0 * math.sqrt(G * 0.3), 7.0, 0.1,
+                       0.01 * h * h, (0, 0, -G), 0.2)
+    sim.sph_rates(prm)
+    sim.check()
+    _, _, a = sim.get()
+    _, dr = sim.get_sph()
+    a, dr = np_(a), np_(dr)
+    assert np.array_equal(a[:3], np.tile(np.array([0, 0, -G], np.float32), (3, 1)))
+    assert np.all(a[3] == 0) and np.all(dr == 0)
