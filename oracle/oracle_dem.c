@@ -9,7 +9,7 @@
  * radius R, mass m, moment of inertia I.  prm = {R, m, I, kn, kt, gn, gt, mu,
  * gx, gy, gz, dt, walls}.  A pair (p, q) is in contact when the minimum-image
  * separation r_pq = x_p - x_q has |r_pq| < 2R (FP64).  Readings taken where
- * the paper is silent (listed in the design notes):
+ * the paper is silent:
  *  - n = r_pq / |r_pq|, delta = 2R - |r_pq| (Eq. 9), m_eff = m / 2;
  *  - the contact point lies midway between the centres, at arm a = |r_pq| / 2
  *    from each (so the pair's torques balance its tangential forces exactly

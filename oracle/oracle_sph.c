@@ -2,7 +2,7 @@
  * FP64 CPU oracle for the weakly compressible SPH sums of OpenFPM's section
  * 4.2 (Eqs. 1-5).  TEST INFRASTRUCTURE ONLY (see oracle.c).
  *
- * Readings taken where the paper is silent or garbled (listed in the design doc):
+ * Readings taken where the paper is silent or garbled:
  *  - kernel (prm[10]): 0 = Wendland C2 with support 2h,
  *    W(r) = aD (1 - q/2)^4 (2q + 1), q = r/h, aD = 21 / (16 pi h^3);
  *    1 = the classic cubic spline the paper names, support 2h,
