@@ -75,5 +75,19 @@ def test_host_side_errors_without_device():
         assert L.fpm_set_tuning(ctx, 2, 65, 0) == F.FPM_EINVAL
         assert L.fpm_set_tuning(ctx, 0, 0, 6) == F.FPM_EINVAL
         assert L.fpm_set_tuning(ctx, 4, 16, 4) == 0
+        # DEM: capacity range, and the DEM calls need DEM storage and particles
+        assert L.fpm_set_dem(ctx, 0) == F.FPM_EINVAL
+        assert L.fpm_set_dem(ctx, 65) == F.FPM_EINVAL
+        prm = F.dem_params(0.06, 1.0, 1.44e-3, 7.849, 2.243, 3.401)
+        assert L.fpm_dem_forces(ctx, ctypes.byref(prm)) == F.FPM_EINVAL
+        base = ctypes.c_size_t()
+        assert L.fpm_workspace_size(ctx, 1000, ctypes.byref(base)) == 0
+        assert L.fpm_set_dem(ctx, 16) == 0
+        dem_size = ctypes.c_size_t()
+        assert L.fpm_workspace_size(ctx, 1000, ctypes.byref(dem_size)) == 0
+        # the history: 16 B per list slot (capacity 128) plus 20 B per contact
+        # slot (16 per grain)
+        assert dem_size.value >= base.value + 1000 * (128 * 16 + 16 * 20)
+        assert L.fpm_dem_step(ctx, ctypes.byref(prm), 1) == F.FPM_EINVAL
     finally:
         L.fpm_destroy(ctx)
