@@ -11,6 +11,7 @@ from __future__ import annotations
 
 import torch
 
+from . import _lib as F
 from .sim import _Sim
 
 
@@ -64,6 +65,7 @@ class LJTrajFn(torch.autograd.Function):
     def forward(ctx, x0, v0, theta, sim: _Sim, dt: float, nsteps: int, frame_every: int,
                 ckpt_every: int, n_types: int = 1):
         eps, sig = _prm(theta)
+        prm = F.lj_params(eps, sig, n_types)
         frames = _frames(nsteps, frame_every)
         sim.set_particles(x0.detach().to(torch.float32), v0.detach().to(torch.float32))
         ckpts, out = [], []
@@ -76,7 +78,8 @@ class LJTrajFn(torch.autograd.Function):
             end = min(step + ckpt_every, nsteps)
             while step < end:
                 nxt = min(end, min((k for k in frames if k > step), default=end))
-                sim.step(nxt - step, dt, eps, sig, n_types)
+                # no thermo rows: the captured step graphs are reused across calls
+                F.fpm_step(sim.ctx, prm, dt, nxt - step, None)
                 step = nxt
                 if step in frames:
                     out.append(sim.get()[2].to(torch.float64))
@@ -101,17 +104,21 @@ class LJTrajFn(torch.autograd.Function):
         gt = torch.zeros((sim.nsys, 6), dtype=torch.float64, device=dev)
         bounds = [c[0] for c in ctx.ckpts] + [K]
         x_first = None
+        prm = F.lj_params(eps, sig, ctx.n_types)
         for q in range(len(ctx.ckpts) - 1, -1, -1):
             s0, p, v = ctx.ckpts[q]
             s1 = bounds[q + 1]
             sim.set_particles(p, v)
-            xs = [p]
-            for _ in range(s1 - s0):
-                sim.step(1, dt, eps, sig, ctx.n_types)
-                xs.append(sim.get()[0])
+            # the segment's positions, recomputed from its checkpoint
+            xs = torch.empty((s1 - s0 + 1, n, 3), dtype=torch.float32, device=dev)
+            xs[0] = p
+            for j in range(s1 - s0):
+                F.fpm_step(sim.ctx, prm, dt, 1, None)
+                F.fpm_get_particles(sim.ctx, xs[j + 1], None, None)
             for k in range(s1 - 1, s0 - 1, -1):
-                sim.set_positions(xs[k + 1 - s0])
-                sim.adjoint_step(dt, floss.get(k), xbar, vbar, fbar, gt, eps, sig, ctx.n_types)
+                F.fpm_set_positions(sim.ctx, xs[k + 1 - s0])
+                F.fpm_lj_adjoint_step(sim.ctx, prm, dt, floss.get(k), xbar, vbar, fbar, gt, 0)
+            sim._keep_pos = xs  # the last positions handed in stay alive with the context
             x_first = p
         if x_first is None:  # no steps: the loss sees F_0 only
             x_first = ctx.ckpts[0][1] if ctx.ckpts else None
