@@ -192,8 +192,12 @@ __global__ __launch_bounds__(kBlock) void k_dem_forces(State st, DemCoef k, int 
 }
 
 // Before a rebuild (gated on the flag): the pairs in contact with their u_t,
-// from list positions to rows keyed by caller index, in list order.
+// from list positions to rows keyed by caller index, in list order.  CR > 0:
+// the row capacity is CR (a multiple of four, at most 16) and the row of
+// partner ids is assembled in registers and stored 16 bytes at a time.
+template <int CR>
 __global__ __launch_bounds__(kBlock) void k_dem_export(State st, int cap4, int C, int64_t ns) {
+    constexpr int NR = CR > 0 ? CR : 1;
     const int s = block_system(st);
     if (!st.sctl[s].rebuild) return;
     const SysDesc &d = st.sys[s];
@@ -206,6 +210,9 @@ __global__ __launch_bounds__(kBlock) void k_dem_export(State st, int cap4, int C
     const float4 *hrow = st.hl + hist_base(i, cap4);
     int32_t *hid = st.hid + me * C;
     float4 *hu = st.hu + me * C;
+    int row[NR];
+#pragma unroll
+    for (int c = 0; c < NR; c++) row[c] = -1;
     int nc = 0;
     for (int e = 0; e < cnt; e++) {
         const float4 h = hrow[e * 64];
@@ -213,18 +220,35 @@ __global__ __launch_bounds__(kBlock) void k_dem_export(State st, int cap4, int C
         const int j = st.nbr[nbr_index(i, e, cap4)];
         if ((uint64_t)j >= (uint64_t)ns) continue;
         if (nc < C) {
-            hid[nc] = id[j];
+            const int pid = id[j];
+            if (CR > 0) {
+#pragma unroll
+                for (int c = 0; c < NR; c++) row[c] = c == nc ? pid : row[c];
+            } else {
+                hid[nc] = pid;
+            }
             hu[nc] = h;
         }
         nc++;
     }
-    for (int c = nc; c < C; c++) hid[c] = -1;
+    if (CR > 0) {
+        int4 *h4 = reinterpret_cast<int4 *>(hid);
+#pragma unroll
+        for (int g = 0; g < NR / 4; g++)
+            h4[g] = make_int4(row[4 * g], row[4 * g + 1], row[4 * g + 2], row[4 * g + 3]);
+    } else {
+        for (int c = nc; c < C; c++) hid[c] = -1;
+    }
     if (nc > C) st.ctl->overflow = nc;
 }
 
 // After a rebuild (gated on the flag): each entry of the new lists takes the
-// u_t its partner had in the exported row, or none.
+// u_t its partner had in the exported row, or none.  CR > 0: the row capacity
+// is CR (a multiple of four, at most 16) and its partner ids are loaded into
+// registers at once; CR = 0: any capacity, searched in memory.
+template <int CR>
 __global__ __launch_bounds__(kBlock) void k_dem_import(State st, int cap4, int C) {
+    constexpr int NR = CR > 0 ? CR : 1;
     const int s = block_system(st);
     if (!st.sctl[s].rebuild) return;
     const SysDesc &d = st.sys[s];
@@ -235,21 +259,42 @@ __global__ __launch_bounds__(kBlock) void k_dem_import(State st, int cap4, int C
     const int cnt = (int)(st.nnb[i] & ~kWrapBit);
     const int32_t *hid = st.hid + me * C;
     const float4 *hu = st.hu + me * C;
+    int hrow[NR];
     int stored = 0;
-    while (stored < C && hid[stored] >= 0) stored++;
-    float4 *hrow = st.hl + hist_base(i, cap4);
+    if (CR > 0) {
+        const int4 *h4 = reinterpret_cast<const int4 *>(hid);
+#pragma unroll
+        for (int g = 0; g < NR / 4; g++) {
+            const int4 t = h4[g];
+            hrow[4 * g] = t.x, hrow[4 * g + 1] = t.y, hrow[4 * g + 2] = t.z, hrow[4 * g + 3] = t.w;
+        }
+#pragma unroll
+        for (int c = 0; c < NR; c++) stored += hrow[c] >= 0;  // rows are filled from the front
+    } else {
+        while (stored < C && hid[stored] >= 0) stored++;
+    }
+    float4 *hrow_l = st.hl + hist_base(i, cap4);
     for (int e = 0; e < cnt; e++) {
         float4 h = make_float4(0.f, 0.f, 0.f, 0.f);
         if (stored > 0) {
             const int pid = id[st.nbr[nbr_index(i, e, cap4)]];
-            for (int c = 0; c < stored; c++)
-                if (hid[c] == pid) {
-                    h = hu[c];
-                    h.w = 1.f;
-                    break;
-                }
+            int m = -1;
+            if (CR > 0) {
+#pragma unroll
+                for (int c = 0; c < NR; c++) m = hrow[c] == pid ? c : m;
+            } else {
+                for (int c = 0; c < stored; c++)
+                    if (hid[c] == pid) {
+                        m = c;
+                        break;
+                    }
+            }
+            if (m >= 0) {
+                h = hu[m];
+                h.w = 1.f;
+            }
         }
-        hrow[e * 64] = h;
+        hrow_l[e * 64] = h;
     }
 }
 
@@ -385,14 +430,33 @@ hipError_t launch_dem_integrate(fpm_ctx *c, const fpm_dem_params &p) {
 }
 
 hipError_t launch_dem_export(fpm_ctx *c) {
-    hipLaunchKernelGGL(k_dem_export, dim3(c->nblk), dim3(kBlock), 0, c->stream, c->st, c->cap4,
-                       c->dem_cap, (int64_t)c->nblk * kBlock);
+    const dim3 g(c->nblk), blk(kBlock);
+    const int64_t ns = (int64_t)c->nblk * kBlock;
+    switch (c->dem_cap) {
+    case 4: hipLaunchKernelGGL(k_dem_export<4>, g, blk, 0, c->stream, c->st, c->cap4, 4, ns); break;
+    case 8: hipLaunchKernelGGL(k_dem_export<8>, g, blk, 0, c->stream, c->st, c->cap4, 8, ns); break;
+    case 12:
+        hipLaunchKernelGGL(k_dem_export<12>, g, blk, 0, c->stream, c->st, c->cap4, 12, ns);
+        break;
+    case 16:
+        hipLaunchKernelGGL(k_dem_export<16>, g, blk, 0, c->stream, c->st, c->cap4, 16, ns);
+        break;
+    default:
+        hipLaunchKernelGGL(k_dem_export<0>, g, blk, 0, c->stream, c->st, c->cap4, c->dem_cap, ns);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_dem_import(fpm_ctx *c) {
-    hipLaunchKernelGGL(k_dem_import, dim3(c->nblk), dim3(kBlock), 0, c->stream, c->st, c->cap4,
-                       c->dem_cap);
+    const dim3 g(c->nblk), blk(kBlock);
+    switch (c->dem_cap) {
+    case 4: hipLaunchKernelGGL(k_dem_import<4>, g, blk, 0, c->stream, c->st, c->cap4, 4); break;
+    case 8: hipLaunchKernelGGL(k_dem_import<8>, g, blk, 0, c->stream, c->st, c->cap4, 8); break;
+    case 12: hipLaunchKernelGGL(k_dem_import<12>, g, blk, 0, c->stream, c->st, c->cap4, 12); break;
+    case 16: hipLaunchKernelGGL(k_dem_import<16>, g, blk, 0, c->stream, c->st, c->cap4, 16); break;
+    default:
+        hipLaunchKernelGGL(k_dem_import<0>, g, blk, 0, c->stream, c->st, c->cap4, c->dem_cap);
+    }
     return hipGetLastError();
 }
 
