@@ -213,8 +213,8 @@ void drop_timers(fpm_ctx *c) {
 // rows before the cell sort, imported into the new lists after the build.
 hipError_t refresh_lists(fpm_ctx *c) {
     hipError_t e = hipSuccess;
-    if (c->dem_cap > 0 && !c->dem_exported) e = launch_dem_export(c);
-    if (e == hipSuccess) e = timed(c, "cell_build", [&] { return launch_cell_build(c); });
+    const bool exp = c->dem_cap > 0 && !c->dem_exported;
+    e = timed(c, "cell_build", [&] { return launch_cell_build(c, exp); });
     if (e == hipSuccess) e = timed(c, "verlet_build", [&] { return launch_verlet_build(c); });
     if (e == hipSuccess && c->dem_cap > 0) {
         e = launch_dem_import(c);
@@ -571,11 +571,9 @@ int fpm_build_cell_list(fpm_ctx *c) {
     int r = ready(c);
     if (r) return r;
     HIPCHK(c, launch_force_rebuild(c));
-    if (c->dem_cap > 0 && !c->dem_exported) {  // the sort below invalidates the list history
-        HIPCHK(c, launch_dem_export(c));
-        c->dem_exported = true;
-    }
-    HIPCHK(c, timed(c, "cell_build", [&] { return launch_cell_build(c); }));
+    const bool exp = c->dem_cap > 0 && !c->dem_exported;  // the sort invalidates the list history
+    HIPCHK(c, timed(c, "cell_build", [&] { return launch_cell_build(c, exp); }));
+    if (exp) c->dem_exported = true;
     HIPCHK(c, launch_copy_back(c));
     c->build_pending = true;  // flags stay set: the Verlet lists are rebuilt on next use
     c->forces_valid = false;

@@ -66,38 +66,11 @@ __global__ void k_set_density(State st, const float *rho) {
     if (i - d.slot_base < d.n) st.vel[0][i].w = rho[st.id[0][i]];
 }
 
-// Wrap, cell index and histogram, keeping each particle's arrival rank.
-// Particles are still nearly in cell order from the previous build, so
-// neighbouring lanes mostly share a cell: each run of equal cells inside a
-// wavefront issues one atomic add for the whole run.
+// Wrap, cell index and histogram (gated).
 __global__ __launch_bounds__(kBlock) void k_cell_assign(State st) {
     const int s = block_system(st);
     if (!st.sctl[s].rebuild) return;
-    const SysDesc &d = st.sys[s];
-    const Box b = d.box;
-    const int64_t i = global_slot();
-    const int lane = threadIdx.x & 63;
-    int c = -1;
-    if (i - d.slot_base < d.n) {
-        float4 p = st.pos[0][i];
-        if (b.per[0]) p.x = wrap_coord(p.x, b.L[0]);
-        if (b.per[1]) p.y = wrap_coord(p.y, b.L[1]);
-        if (b.per[2]) p.z = wrap_coord(p.z, b.L[2]);
-        st.pos[0][i] = p;
-        c = d.cell_base + cell_of(xyz(p), b);
-        st.cid[i] = c;
-    }
-    const int prev = __shfl_up(c, 1, 64);
-    const bool head = lane == 0 || c != prev;
-    const uint64_t heads = __ballot(head);
-    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);  // lanes 0..lane
-    const int hl = 63 - __clzll(heads & upto);                       // head of my run
-    const uint64_t after = heads & ~upto;
-    const int next = after ? __ffsll((long long)after) - 1 : 64;     // first head after me
-    int base = 0;
-    if (head && c >= 0) base = atomicAdd(&st.cnt[c], next - lane);
-    base = __shfl(base, hl, 64);
-    if (c >= 0) st.rnk[i] = base + (lane - hl);
+    cell_assign_slot(st, s, global_slot());
 }
 
 // Exclusive scan of one tile of kScanTile values in[base ..) (n values in
@@ -168,8 +141,7 @@ __global__ __launch_bounds__(1024) void k_scan(State st) {
 }
 
 // The same scan for a single system with many cells, over the whole device:
-// tile totals (one workgroup per tile), an exclusive scan of the totals (one
-// workgroup), then each tile's scan from its carry.
+// tile totals (one workgroup per tile), then each tile's scan from its carry.
 __global__ __launch_bounds__(1024) void k_scan_sums(State st) {
     if (!st.sctl[0].rebuild) return;
     const SysDesc &d = st.sys[0];
@@ -190,20 +162,26 @@ __global__ __launch_bounds__(1024) void k_scan_sums(State st) {
     }
 }
 
-__global__ __launch_bounds__(1024) void k_scan_top(State st, int ntiles) {
-    if (!st.sctl[0].rebuild) return;
-    const SysDesc &d = st.sys[0];
-    int32_t carry = d.slot_base;
-    for (int64_t base = 0; base < ntiles; base += kScanTile)
-        carry += scan_tile(st.tsum, st.tsum, base, ntiles, carry, false);
-    if (threadIdx.x == 0) st.off[d.off_base + d.ncells] = carry;
-}
-
+// Each tile's workgroup adds up the totals of the tiles before it for its
+// carry (integer sums, so the order does not matter); the last tile also
+// writes the end offset.
 __global__ __launch_bounds__(1024) void k_scan_tiles(State st) {
     if (!st.sctl[0].rebuild) return;
     const SysDesc &d = st.sys[0];
-    scan_tile(st.cnt + d.cell_base, st.off + d.off_base, (int64_t)blockIdx.x * kScanTile,
-              d.ncells, st.tsum[blockIdx.x], true);
+    const int b = blockIdx.x, t = threadIdx.x;
+    __shared__ int32_t part[16];
+    int32_t v = 0;
+    for (int k = t; k < b; k += 1024) v += st.tsum[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if ((t & 63) == 0) part[t >> 6] = v;
+    __syncthreads();
+    int32_t carry = d.slot_base;
+#pragma unroll
+    for (int w = 0; w < 16; w++) carry += part[w];
+    const int32_t tot = scan_tile(st.cnt + d.cell_base, st.off + d.off_base,
+                                  (int64_t)b * kScanTile, d.ncells, carry, true);
+    if (b == (int)gridDim.x - 1 && t == 0) st.off[d.off_base + d.ncells] = carry + tot;
 }
 
 // Scatter (caller id, source slot, z) to the cell's offset + arrival rank.
@@ -310,14 +288,18 @@ hipError_t launch_force_rebuild(fpm_ctx *c) {
     return hipGetLastError();
 }
 
-hipError_t launch_cell_build(fpm_ctx *c) {
+hipError_t launch_cell_build(fpm_ctx *c, bool dem_export) {
     const unsigned g = (unsigned)c->nblk;
-    hipLaunchKernelGGL(k_cell_assign, dim3(g), dim3(kBlock), 0, c->stream, c->st);
+    if (dem_export) {
+        const hipError_t e = launch_dem_export_assign(c);
+        if (e != hipSuccess) return e;
+    } else {
+        hipLaunchKernelGGL(k_cell_assign, dim3(g), dim3(kBlock), 0, c->stream, c->st);
+    }
     const int64_t nc0 = c->sys[0].d.ncells;
     if (c->nsys == 1 && nc0 > kScanDeviceCells) {
         const unsigned nt = (unsigned)((nc0 + kScanTile - 1) / kScanTile);
         hipLaunchKernelGGL(k_scan_sums, dim3(nt), dim3(1024), 0, c->stream, c->st);
-        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, c->stream, c->st, (int)nt);
         hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(1024), 0, c->stream, c->st);
     } else {
         hipLaunchKernelGGL(k_scan, dim3(c->nsys), dim3(1024), 0, c->stream, c->st);

@@ -191,17 +191,14 @@ __global__ __launch_bounds__(kBlock) void k_dem_forces(State st, DemCoef k, int 
     if (!isfinite(a.f[0]) || !isfinite(a.f[1]) || !isfinite(a.f[2])) st.ctl->nonfinite = 1;
 }
 
-// Before a rebuild (gated on the flag): the pairs in contact with their u_t,
-// from list positions to rows keyed by caller index, in list order.  CR > 0:
-// the row capacity is CR (a multiple of four, at most 16) and the row of
-// partner ids is assembled in registers and stored 16 bytes at a time.
+// Before a rebuild: the pairs in contact with their u_t, from list positions
+// to rows keyed by caller index, in list order.  CR > 0: the row capacity is
+// CR (a multiple of four, at most 16) and the row of partner ids is assembled
+// in registers and stored 16 bytes at a time.
 template <int CR>
-__global__ __launch_bounds__(kBlock) void k_dem_export(State st, int cap4, int C, int64_t ns) {
+__device__ __forceinline__ void export_slot(const State &st, const SysDesc &d, int64_t i, int cap4,
+                                            int C, int64_t ns) {
     constexpr int NR = CR > 0 ? CR : 1;
-    const int s = block_system(st);
-    if (!st.sctl[s].rebuild) return;
-    const SysDesc &d = st.sys[s];
-    const int64_t i = global_slot();
     if (i - d.slot_base >= d.n) return;
     const int32_t *__restrict__ id = st.id[0];
     const int64_t me = id[i];
@@ -240,6 +237,19 @@ __global__ __launch_bounds__(kBlock) void k_dem_export(State st, int cap4, int C
         for (int c = nc; c < C; c++) hid[c] = -1;
     }
     if (nc > C) st.ctl->overflow = nc;
+}
+
+// The export fused with the first kernel of the cell build (gated on the
+// flag): the export reads the old lists, ids and history, the cell
+// assignment the positions, so neither sees the other's writes.
+template <int CR>
+__global__ __launch_bounds__(kBlock) void k_dem_export_assign(State st, int cap4, int C,
+                                                              int64_t ns) {
+    const int s = block_system(st);
+    if (!st.sctl[s].rebuild) return;
+    const int64_t i = global_slot();
+    export_slot<CR>(st, st.sys[s], i, cap4, C, ns);
+    cell_assign_slot(st, s, i);
 }
 
 // After a rebuild (gated on the flag): each entry of the new lists takes the
@@ -429,20 +439,25 @@ hipError_t launch_dem_integrate(fpm_ctx *c, const fpm_dem_params &p) {
     return hipGetLastError();
 }
 
-hipError_t launch_dem_export(fpm_ctx *c) {
+hipError_t launch_dem_export_assign(fpm_ctx *c) {
     const dim3 g(c->nblk), blk(kBlock);
     const int64_t ns = (int64_t)c->nblk * kBlock;
     switch (c->dem_cap) {
-    case 4: hipLaunchKernelGGL(k_dem_export<4>, g, blk, 0, c->stream, c->st, c->cap4, 4, ns); break;
-    case 8: hipLaunchKernelGGL(k_dem_export<8>, g, blk, 0, c->stream, c->st, c->cap4, 8, ns); break;
+    case 4:
+        hipLaunchKernelGGL(k_dem_export_assign<4>, g, blk, 0, c->stream, c->st, c->cap4, 4, ns);
+        break;
+    case 8:
+        hipLaunchKernelGGL(k_dem_export_assign<8>, g, blk, 0, c->stream, c->st, c->cap4, 8, ns);
+        break;
     case 12:
-        hipLaunchKernelGGL(k_dem_export<12>, g, blk, 0, c->stream, c->st, c->cap4, 12, ns);
+        hipLaunchKernelGGL(k_dem_export_assign<12>, g, blk, 0, c->stream, c->st, c->cap4, 12, ns);
         break;
     case 16:
-        hipLaunchKernelGGL(k_dem_export<16>, g, blk, 0, c->stream, c->st, c->cap4, 16, ns);
+        hipLaunchKernelGGL(k_dem_export_assign<16>, g, blk, 0, c->stream, c->st, c->cap4, 16, ns);
         break;
     default:
-        hipLaunchKernelGGL(k_dem_export<0>, g, blk, 0, c->stream, c->st, c->cap4, c->dem_cap, ns);
+        hipLaunchKernelGGL(k_dem_export_assign<0>, g, blk, 0, c->stream, c->st, c->cap4,
+                           c->dem_cap, ns);
     }
     return hipGetLastError();
 }

@@ -215,7 +215,7 @@ hipError_t launch_fill_i32(hipStream_t s, int32_t *p, int64_t n, int32_t v);
 hipError_t launch_init_state(fpm_ctx *c, const float *pos, const float *vel, const int32_t *type);
 hipError_t launch_set_density(fpm_ctx *c, const float *rho);
 hipError_t launch_force_rebuild(fpm_ctx *c);
-hipError_t launch_cell_build(fpm_ctx *c);
+hipError_t launch_cell_build(fpm_ctx *c, bool dem_export);  // dem_export: history out first
 hipError_t launch_copy_back(fpm_ctx *c);
 hipError_t launch_verlet_build(fpm_ctx *c);
 hipError_t launch_list_stats(fpm_ctx *c);  // fills ctl->max_count and ctl->total_count
@@ -251,7 +251,7 @@ hipError_t launch_dem_forces(fpm_ctx *c, const fpm_dem_params &p);
 hipError_t launch_dem_integrate(fpm_ctx *c, const fpm_dem_params &p);
 hipError_t launch_dem_set_omega(fpm_ctx *c, const float *w);  // also clears the history
 hipError_t launch_dem_clear(fpm_ctx *c);                      // empty history
-hipError_t launch_dem_export(fpm_ctx *c);  // gated: list history -> caller-keyed rows
+hipError_t launch_dem_export_assign(fpm_ctx *c);  // gated: list history -> caller-keyed rows, then cell assign
 hipError_t launch_dem_import(fpm_ctx *c);  // gated: caller-keyed rows -> new list positions
 hipError_t launch_dem_out(fpm_ctx *c, float *w, float *tq, int32_t *ids, float *ut,
                           int32_t *ncon);

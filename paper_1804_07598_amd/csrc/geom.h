@@ -127,6 +127,38 @@ __device__ __forceinline__ int off_index(const SysDesc &d, int c) {
     return d.off_base + (c - d.cell_base);
 }
 
+// Wrap, cell index and histogram for slot i of system s, keeping each
+// particle's arrival rank.  Particles are still nearly in cell order from the
+// previous build, so neighbouring lanes mostly share a cell: each run of equal
+// cells inside a wavefront issues one atomic add for the whole run.  Every
+// lane of the wavefront takes part (shuffles and a ballot).
+__device__ __forceinline__ void cell_assign_slot(const State &st, int s, int64_t i) {
+    const SysDesc &d = st.sys[s];
+    const Box b = d.box;
+    const int lane = threadIdx.x & 63;
+    int c = -1;
+    if (i - d.slot_base < d.n) {
+        float4 p = st.pos[0][i];
+        if (b.per[0]) p.x = wrap_coord(p.x, b.L[0]);
+        if (b.per[1]) p.y = wrap_coord(p.y, b.L[1]);
+        if (b.per[2]) p.z = wrap_coord(p.z, b.L[2]);
+        st.pos[0][i] = p;
+        c = d.cell_base + cell_of(xyz(p), b);
+        st.cid[i] = c;
+    }
+    const int prev = __shfl_up(c, 1, 64);
+    const bool head = lane == 0 || c != prev;
+    const uint64_t heads = __ballot(head);
+    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);  // lanes 0..lane
+    const int hl = 63 - __clzll(heads & upto);                       // head of my run
+    const uint64_t after = heads & ~upto;
+    const int next = after ? __ffsll((long long)after) - 1 : 64;     // first head after me
+    int base = 0;
+    if (head && c >= 0) base = atomicAdd(&st.cnt[c], next - lane);
+    base = __shfl(base, hl, 64);
+    if (c >= 0) st.rnk[i] = base + (lane - hl);
+}
+
 // Wavefront reductions (64 lanes).
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
