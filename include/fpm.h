@@ -185,8 +185,11 @@ int fpm_get_sph(fpm_ctx *ctx, float *d_rho, float *d_drho);
 /* ---- neighbour structures (getCellListSym / updateCellListSym) ---- */
 
 /* Wraps positions into the box and rebuilds the cell list: cell index per
- * particle, per-cell counts, their exclusive prefix sum and a stable
- * reordering of particles by cell (ties in ascending caller index). */
+ * particle, per-cell counts, their exclusive prefix sum and a reordering of
+ * particles by cell (inside a cell by FP32 z, ties in ascending caller
+ * index).  Results of the last evaluation that live per particle (forces,
+ * SPH rates, DEM torques and contacts) are not carried through the
+ * reordering: read them before this call, or evaluate again after it. */
 int fpm_build_cell_list(fpm_ctx *ctx);
 /* Cell list in caller terms: d_offsets[ncells + 1] (exclusive scan of
  * counts) and d_order[n] (slot -> caller index).  h_ncell receives the grid.

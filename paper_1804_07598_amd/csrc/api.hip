@@ -211,13 +211,14 @@ void drop_timers(fpm_ctx *c) {
 // by the next finalize with kFinBuild.
 // With DEM on, the contact history follows the lists: exported to caller-keyed
 // rows before the cell sort, imported into the new lists after the build.
-hipError_t refresh_lists(fpm_ctx *c) {
+// defer_import: the DEM force kernel that follows imports the history.
+hipError_t refresh_lists(fpm_ctx *c, bool defer_import = false) {
     hipError_t e = hipSuccess;
     const bool exp = c->dem_cap > 0 && !c->dem_exported;
     e = timed(c, "cell_build", [&] { return launch_cell_build(c, exp); });
     if (e == hipSuccess) e = timed(c, "verlet_build", [&] { return launch_verlet_build(c); });
     if (e == hipSuccess && c->dem_cap > 0) {
-        e = launch_dem_import(c);
+        if (!defer_import) e = launch_dem_import(c);
         c->dem_exported = false;
     }
     return e;
@@ -817,8 +818,8 @@ int fpm_dem_forces(fpm_ctx *c, const fpm_dem_params *p) {
 // One DEM step: gated rebuild (with the history export and import), forces
 // and torques, leapfrog, finalize (accounts a rebuild, decides the next).
 hipError_t dem_step_body(fpm_ctx *c, const fpm_dem_params &p) {
-    hipError_t e = refresh_lists(c);
-    if (e == hipSuccess) e = timed(c, "dem_forces", [&] { return launch_dem_forces(c, p); });
+    hipError_t e = refresh_lists(c, true);
+    if (e == hipSuccess) e = timed(c, "dem_forces", [&] { return launch_dem_forces(c, p, true); });
     if (e == hipSuccess) e = launch_dem_integrate(c, p);
     if (e == hipSuccess) e = launch_finalize(c, kFinBuild | kFinDisp, nullptr, nullptr);
     return e;

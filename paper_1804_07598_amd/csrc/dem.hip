@@ -107,15 +107,145 @@ __device__ __forceinline__ int64_t hist_base(int64_t i, int cap4) {
     return (i >> 6) * (int64_t)cap4 * 4 * 64 + (i & 63);
 }
 
+
+// Before a rebuild: the pairs in contact with their u_t, from list positions
+// to rows keyed by caller index, in list order.  CR > 0: the row capacity is
+// CR (a multiple of four, at most 16) and the row of partner ids is assembled
+// in registers and stored 16 bytes at a time.
+template <int CR>
+__device__ __forceinline__ void export_slot(const State &st, const SysDesc &d, int64_t i, int cap4,
+                                            int C, int64_t ns) {
+    constexpr int NR = CR > 0 ? CR : 1;
+    if (i - d.slot_base >= d.n) return;
+    const int32_t *__restrict__ id = st.id[0];
+    const int64_t me = id[i];
+    int cnt = (int)(st.nnb[i] & ~kWrapBit);
+    if (cnt > 4 * cap4) cnt = 4 * cap4;
+    const float4 *hrow = st.hl + hist_base(i, cap4);
+    int32_t *hid = st.hid + me * C;
+    float4 *hu = st.hu + me * C;
+    int row[NR];
+#pragma unroll
+    for (int c = 0; c < NR; c++) row[c] = -1;
+    int nc = 0;
+    for (int e = 0; e < cnt; e++) {
+        const float4 h = hrow[e * 64];
+        if (h.w == 0.f) continue;
+        const int j = st.nbr[nbr_index(i, e, cap4)];
+        if ((uint64_t)j >= (uint64_t)ns) continue;
+        if (nc < C) {
+            const int pid = id[j];
+            if (CR > 0) {
+#pragma unroll
+                for (int c = 0; c < NR; c++) row[c] = c == nc ? pid : row[c];
+            } else {
+                hid[nc] = pid;
+            }
+            hu[nc] = h;
+        }
+        nc++;
+    }
+    if (CR > 0) {
+        int4 *h4 = reinterpret_cast<int4 *>(hid);
+#pragma unroll
+        for (int g = 0; g < NR / 4; g++)
+            h4[g] = make_int4(row[4 * g], row[4 * g + 1], row[4 * g + 2], row[4 * g + 3]);
+    } else {
+        for (int c = nc; c < C; c++) hid[c] = -1;
+    }
+    if (nc > C) st.ctl->overflow = nc;
+}
+
+// The export fused with the first kernel of the cell build (gated on the
+// flag): the export reads the old lists, ids and history, the cell
+// assignment the positions, so neither sees the other's writes.
+template <int CR>
+__global__ __launch_bounds__(kBlock) void k_dem_export_assign(State st, int cap4, int C,
+                                                              int64_t ns) {
+    const int s = block_system(st);
+    if (!st.sctl[s].rebuild) return;
+    const int64_t i = global_slot();
+    export_slot<CR>(st, st.sys[s], i, cap4, C, ns);
+    cell_assign_slot(st, s, i);
+}
+
+// After a rebuild: each entry of the new lists takes the u_t its partner had
+// in the exported row, or none.  Run by the gated import kernel after an eager
+// rebuild, and inside a captured step by the force kernel that follows the
+// rebuild.  CR > 0: the row capacity is CR (a multiple of four, at most 16)
+// and its partner ids are loaded into registers at once; CR = 0: any
+// capacity, searched in memory.
+template <int CR>
+__device__ __forceinline__ void import_slot(const State &st, int64_t i, int cap4, int C) {
+    constexpr int NR = CR > 0 ? CR : 1;
+    const int32_t *__restrict__ id = st.id[0];
+    const int64_t me = id[i];
+    const int cnt = (int)(st.nnb[i] & ~kWrapBit);
+    const int32_t *hid = st.hid + me * C;
+    const float4 *hu = st.hu + me * C;
+    int hrow[NR];
+    int stored = 0;
+    if (CR > 0) {
+        const int4 *h4 = reinterpret_cast<const int4 *>(hid);
+#pragma unroll
+        for (int g = 0; g < NR / 4; g++) {
+            const int4 t = h4[g];
+            hrow[4 * g] = t.x, hrow[4 * g + 1] = t.y, hrow[4 * g + 2] = t.z, hrow[4 * g + 3] = t.w;
+        }
+#pragma unroll
+        for (int c = 0; c < NR; c++) stored += hrow[c] >= 0;  // rows are filled from the front
+    } else {
+        while (stored < C && hid[stored] >= 0) stored++;
+    }
+    float4 *hrow_l = st.hl + hist_base(i, cap4);
+    for (int e = 0; e < cnt; e++) {
+        float4 h = make_float4(0.f, 0.f, 0.f, 0.f);
+        const int pid = stored > 0 ? id[st.nbr[nbr_index(i, e, cap4)]] : -1;
+        if (pid >= 0) {  // padding entries name a slot whose id is -1, like an empty row entry
+            int m = -1;
+            if (CR > 0) {
+#pragma unroll
+                for (int c = 0; c < NR; c++) m = hrow[c] == pid ? c : m;
+            } else {
+                for (int c = 0; c < stored; c++)
+                    if (hid[c] == pid) {
+                        m = c;
+                        break;
+                    }
+            }
+            if (m >= 0) {
+                h = hu[m];
+                h.w = 1.f;
+            }
+        }
+        hrow_l[e * 64] = h;
+    }
+}
+
+template <int CR>
+__global__ __launch_bounds__(kBlock) void k_dem_import(State st, int cap4, int C) {
+    const int s = block_system(st);
+    if (!st.sctl[s].rebuild) return;
+    const SysDesc &d = st.sys[s];
+    const int64_t i = global_slot();
+    if (i - d.slot_base >= d.n) return;
+    import_slot<CR>(st, i, cap4, C);
+}
+
 // Forces and torques of the grains, advancing the history in place.  The list
 // is walked four entries at a time: their list indices and history entries
 // with one request, then the four partners' position, velocity and angular
-// velocity with the next.
-__global__ __launch_bounds__(kBlock) void k_dem_forces(State st, DemCoef k, int cap4) {
-    const SysDesc &d = st.sys[block_system(st)];
+// velocity with the next.  With imp set, a grain whose system has just been
+// rebuilt (flag still set) first imports its history into the new list; the
+// same thread then reads it back.
+template <int CR>
+__global__ __launch_bounds__(kBlock) void k_dem_forces(State st, DemCoef k, int cap4, int imp) {
+    const int sy = block_system(st);
+    const SysDesc &d = st.sys[sy];
     const Box b = d.box;
     const int64_t i = global_slot();
     if (i - d.slot_base >= d.n) return;
+    if (imp && st.sctl[sy].rebuild) import_slot<CR>(st, i, cap4, k.C);  // lists just rebuilt
     const float4 *__restrict__ pos = st.pos[0];
     const float4 *__restrict__ vel = st.vel[0];
     const float4 *__restrict__ om = st.old[0];
@@ -189,123 +319,6 @@ __global__ __launch_bounds__(kBlock) void k_dem_forces(State st, DemCoef k, int 
     st.ncon[st.id[0][i]] = nc;
     if (nc > k.C) st.ctl->overflow = nc;
     if (!isfinite(a.f[0]) || !isfinite(a.f[1]) || !isfinite(a.f[2])) st.ctl->nonfinite = 1;
-}
-
-// Before a rebuild: the pairs in contact with their u_t, from list positions
-// to rows keyed by caller index, in list order.  CR > 0: the row capacity is
-// CR (a multiple of four, at most 16) and the row of partner ids is assembled
-// in registers and stored 16 bytes at a time.
-template <int CR>
-__device__ __forceinline__ void export_slot(const State &st, const SysDesc &d, int64_t i, int cap4,
-                                            int C, int64_t ns) {
-    constexpr int NR = CR > 0 ? CR : 1;
-    if (i - d.slot_base >= d.n) return;
-    const int32_t *__restrict__ id = st.id[0];
-    const int64_t me = id[i];
-    int cnt = (int)(st.nnb[i] & ~kWrapBit);
-    if (cnt > 4 * cap4) cnt = 4 * cap4;
-    const float4 *hrow = st.hl + hist_base(i, cap4);
-    int32_t *hid = st.hid + me * C;
-    float4 *hu = st.hu + me * C;
-    int row[NR];
-#pragma unroll
-    for (int c = 0; c < NR; c++) row[c] = -1;
-    int nc = 0;
-    for (int e = 0; e < cnt; e++) {
-        const float4 h = hrow[e * 64];
-        if (h.w == 0.f) continue;
-        const int j = st.nbr[nbr_index(i, e, cap4)];
-        if ((uint64_t)j >= (uint64_t)ns) continue;
-        if (nc < C) {
-            const int pid = id[j];
-            if (CR > 0) {
-#pragma unroll
-                for (int c = 0; c < NR; c++) row[c] = c == nc ? pid : row[c];
-            } else {
-                hid[nc] = pid;
-            }
-            hu[nc] = h;
-        }
-        nc++;
-    }
-    if (CR > 0) {
-        int4 *h4 = reinterpret_cast<int4 *>(hid);
-#pragma unroll
-        for (int g = 0; g < NR / 4; g++)
-            h4[g] = make_int4(row[4 * g], row[4 * g + 1], row[4 * g + 2], row[4 * g + 3]);
-    } else {
-        for (int c = nc; c < C; c++) hid[c] = -1;
-    }
-    if (nc > C) st.ctl->overflow = nc;
-}
-
-// The export fused with the first kernel of the cell build (gated on the
-// flag): the export reads the old lists, ids and history, the cell
-// assignment the positions, so neither sees the other's writes.
-template <int CR>
-__global__ __launch_bounds__(kBlock) void k_dem_export_assign(State st, int cap4, int C,
-                                                              int64_t ns) {
-    const int s = block_system(st);
-    if (!st.sctl[s].rebuild) return;
-    const int64_t i = global_slot();
-    export_slot<CR>(st, st.sys[s], i, cap4, C, ns);
-    cell_assign_slot(st, s, i);
-}
-
-// After a rebuild (gated on the flag): each entry of the new lists takes the
-// u_t its partner had in the exported row, or none.  CR > 0: the row capacity
-// is CR (a multiple of four, at most 16) and its partner ids are loaded into
-// registers at once; CR = 0: any capacity, searched in memory.
-template <int CR>
-__global__ __launch_bounds__(kBlock) void k_dem_import(State st, int cap4, int C) {
-    constexpr int NR = CR > 0 ? CR : 1;
-    const int s = block_system(st);
-    if (!st.sctl[s].rebuild) return;
-    const SysDesc &d = st.sys[s];
-    const int64_t i = global_slot();
-    if (i - d.slot_base >= d.n) return;
-    const int32_t *__restrict__ id = st.id[0];
-    const int64_t me = id[i];
-    const int cnt = (int)(st.nnb[i] & ~kWrapBit);
-    const int32_t *hid = st.hid + me * C;
-    const float4 *hu = st.hu + me * C;
-    int hrow[NR];
-    int stored = 0;
-    if (CR > 0) {
-        const int4 *h4 = reinterpret_cast<const int4 *>(hid);
-#pragma unroll
-        for (int g = 0; g < NR / 4; g++) {
-            const int4 t = h4[g];
-            hrow[4 * g] = t.x, hrow[4 * g + 1] = t.y, hrow[4 * g + 2] = t.z, hrow[4 * g + 3] = t.w;
-        }
-#pragma unroll
-        for (int c = 0; c < NR; c++) stored += hrow[c] >= 0;  // rows are filled from the front
-    } else {
-        while (stored < C && hid[stored] >= 0) stored++;
-    }
-    float4 *hrow_l = st.hl + hist_base(i, cap4);
-    for (int e = 0; e < cnt; e++) {
-        float4 h = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (stored > 0) {
-            const int pid = id[st.nbr[nbr_index(i, e, cap4)]];
-            int m = -1;
-            if (CR > 0) {
-#pragma unroll
-                for (int c = 0; c < NR; c++) m = hrow[c] == pid ? c : m;
-            } else {
-                for (int c = 0; c < stored; c++)
-                    if (hid[c] == pid) {
-                        m = c;
-                        break;
-                    }
-            }
-            if (m >= 0) {
-                h = hu[m];
-                h.w = 1.f;
-            }
-        }
-        hrow_l[e * 64] = h;
-    }
 }
 
 // The leapfrog of Eq. 13 in FP32: v += dt F / m, x += dt v, w += dt T / I,
@@ -427,9 +440,17 @@ inline unsigned grid_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b);
 
 }  // namespace
 
-hipError_t launch_dem_forces(fpm_ctx *c, const fpm_dem_params &p) {
-    hipLaunchKernelGGL(k_dem_forces, dim3(c->nblk), dim3(kBlock), 0, c->stream, c->st,
-                       make_coef(c, p), c->cap4);
+hipError_t launch_dem_forces(fpm_ctx *c, const fpm_dem_params &p, bool imp) {
+    const dim3 g(c->nblk), blk(kBlock);
+    const DemCoef k = make_coef(c, p);
+    const int m = imp ? 1 : 0;
+    switch (c->dem_cap) {
+    case 4: hipLaunchKernelGGL(k_dem_forces<4>, g, blk, 0, c->stream, c->st, k, c->cap4, m); break;
+    case 8: hipLaunchKernelGGL(k_dem_forces<8>, g, blk, 0, c->stream, c->st, k, c->cap4, m); break;
+    case 12: hipLaunchKernelGGL(k_dem_forces<12>, g, blk, 0, c->stream, c->st, k, c->cap4, m); break;
+    case 16: hipLaunchKernelGGL(k_dem_forces<16>, g, blk, 0, c->stream, c->st, k, c->cap4, m); break;
+    default: hipLaunchKernelGGL(k_dem_forces<0>, g, blk, 0, c->stream, c->st, k, c->cap4, m);
+    }
     return hipGetLastError();
 }
 

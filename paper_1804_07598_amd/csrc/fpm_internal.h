@@ -247,7 +247,7 @@ hipError_t launch_sph_rates(fpm_ctx *c, const fpm_sph_params &p);
 hipError_t launch_sph_integrate(fpm_ctx *c, const fpm_sph_params &p, int mode);
 hipError_t launch_sph_verlet(fpm_ctx *c, const fpm_sph_params &p);
 hipError_t launch_sph_restart(fpm_ctx *c);  // the next SPH step counts as the first
-hipError_t launch_dem_forces(fpm_ctx *c, const fpm_dem_params &p);
+hipError_t launch_dem_forces(fpm_ctx *c, const fpm_dem_params &p, bool imp = false);  // imp: import after a rebuild
 hipError_t launch_dem_integrate(fpm_ctx *c, const fpm_dem_params &p);
 hipError_t launch_dem_set_omega(fpm_ctx *c, const float *w);  // also clears the history
 hipError_t launch_dem_clear(fpm_ctx *c);                      // empty history

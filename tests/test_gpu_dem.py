@@ -273,6 +273,27 @@ def test_history_kept_across_set_positions():
     assert np.abs(w - w64).max() <= 1e-4
 
 
+@pytest.mark.parametrize("cap", [16, 6])
+def test_history_carried_by_explicit_verlet_build(cap):
+    # a rebuild outside a step carries each contact's u_t to the new lists by
+    # partner: the contacts read back are the same set, and no padding entry of
+    # the new lists (partner id -1) comes back flagged with a stale u_t
+    s = packing(seed=9)
+    prm, _ = params(dt=5e-4)
+    sim = make(s, skin=0.02, cap=cap)
+    sim.dem_step(60, prm)  # several rebuilds: rows of past exports hold stale entries
+    sim.check()
+    i0, u0 = (np_(t) for t in sim.contacts())
+    sim.build_verlet()
+    i1, u1 = (np_(t) for t in sim.contacts())
+    assert (i0 >= 0).sum() > 0
+    assert np.all(u1[i1 < 0] == 0.0) and np.all(u0[i0 < 0] == 0.0)
+    a0, b0 = sorted_history(i0, u0)
+    a1, b1 = sorted_history(i1, u1)
+    assert np.array_equal(a0, a1)
+    assert np.array_equal(b0, b1)
+
+
 def test_free_flight_without_contacts():
     # grains 3R apart never touch: the leapfrog under gravity in closed form
     # (v_k = v_0 + k dt g, x_k = x_0 + k dt v_0 + dt^2 g k (k + 1) / 2), omega kept
