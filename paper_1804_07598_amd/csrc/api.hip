@@ -56,6 +56,8 @@ bool system_counts(const fpm_ctx *c, int64_t n, std::vector<int64_t> &cnt) {
     return tot == n;
 }
 
+constexpr int kShortListCap = 48;
+
 Plan make_plan(const fpm_ctx *c, const std::vector<int64_t> &cnt) {
     Plan P;
     const int nsys = (int)cnt.size();
@@ -76,12 +78,18 @@ Plan make_plan(const fpm_ctx *c, const std::vector<int64_t> &cnt) {
         // whole cells, -1 particle by particle over candidate windows, -2 lane
         // groups over candidate windows, -3 lane groups over whole cells (the
         // lane-group builds stage rows of lists in LDS)
+        // lane groups (automatic for most lists), lane-per-particle windows when
+        // the list capacity is at most kShortListCap: such lists come from
+        // column runs of a few candidates, which would leave most lanes of a
+        // group idle (688,380 grains, capacity 32, about 6 entries: 89 us per
+        // build against 206 us; at 1M LJ atoms with 76 entries the groups win)
         const bool big = d.box.nc[0] >= 3 && d.box.nc[1] >= 3 && d.box.nc[2] >= 3;
+        const bool auto_groups = c->tune_verlet_path == 0 && c->cap > kShortListCap;
         if (c->tune_verlet_path == 1)
             d.zb = 0;
-        else if (c->tune_verlet_path == 4 || c->tune_verlet_path == 0)
+        else if (c->tune_verlet_path == 4 || auto_groups)
             d.zb = big ? -2 : -3;
-        else if (c->tune_verlet_path == 3)
+        else if (c->tune_verlet_path == 3 || c->tune_verlet_path == 0)
             d.zb = big ? -1 : 0;
         else
             d.zb = verlet_zblock(cnt[s], d.ncells, d.box.nc, c->tune_zb);

@@ -22,10 +22,10 @@ def np_(t):
     return t.detach().cpu().numpy()
 
 
-def make(s, skin=0.02, cap=C):
+def make(s, skin=0.02, cap=C, tuning=None):
     from paper_1804_07598_amd.sim import ParticleSim
     sim = ParticleSim(s.pos, s.L, s.periodic, vel=s.vel, r_cut=2 * R, skin=skin, max_nbr=48,
-                      dem_contacts=cap)
+                      dem_contacts=cap, tuning=tuning)
     sim.set_omega(s.omega)
     return sim
 
@@ -89,8 +89,8 @@ def test_forces_torques_history_match_oracle(cap):
     assert np.abs(gu - hu).max() <= 1e-6 * scale + 1e-12
 
 
-def check_trajectory(s, prm, oprm, K, skin=0.02, cap=C, resort_at=None):
-    sim = make(s, skin=skin, cap=cap)
+def check_trajectory(s, prm, oprm, K, skin=0.02, cap=C, resort_at=None, tuning=None):
+    sim = make(s, skin=skin, cap=cap, tuning=tuning)
     if resort_at is None:
         sim.dem_step(K, prm)
     else:  # an explicit cell sort mid-way: the history must follow the grains
@@ -117,11 +117,12 @@ def check_trajectory(s, prm, oprm, K, skin=0.02, cap=C, resort_at=None):
     return sim
 
 
-@pytest.mark.parametrize("cap", [16, 6])
-def test_steps_match_oracle_trajectory(cap):
+# short lists build lane by lane by default; (4, 8, 0) forces the lane groups
+@pytest.mark.parametrize("cap,tuning", [(16, None), (6, None), (16, (4, 8, 0))])
+def test_steps_match_oracle_trajectory(cap, tuning):
     s = packing(seed=2)
     prm, oprm = params(dt=5e-4)
-    sim = check_trajectory(s, prm, oprm, 60, skin=0.004, cap=cap)
+    sim = check_trajectory(s, prm, oprm, 60, skin=0.004, cap=cap, tuning=tuning)
     assert sim.counters()[0] >= 2  # the lists were rebuilt on the way
 
 
