@@ -314,3 +314,110 @@ def test_verlet_time_reversible_and_momentum():
     assert np.abs(d).max() < 1e-9
     # total momentum is conserved (the FP32 start is zero-mean only to rounding)
     assert np.abs(v1.sum(axis=0) - v0.sum(axis=0)).max() < 1e-10
+
+
+# ---------------------------------------------------------------- virial and rebuild criterion
+
+def pair_virial_closed_form(d):
+    """W_ab = r_a (s r_b) for one pair with separation d (each pair once),
+    s = 24 (2 u^-7 - u^-4), u = |d|^2 (sigma = eps = 1), i.e. the outer
+    product of the separation with the pair force; tr W = r F(r)."""
+    u = float(np.dot(d, d))
+    s = 24.0 * (2.0 * u ** -7 - u ** -4)
+    return np.array([s * d[0] * d[0], s * d[1] * d[1], s * d[2] * d[2],
+                     s * d[0] * d[1], s * d[0] * d[2], s * d[1] * d[2]])
+
+
+def test_virial_two_particles_closed_form():
+    # Along x: W_xx = r F(r) with F = -dV/dr from the section 4.1 potential,
+    # every other component 0.  A dropped factor 1/2 (the pair is seen from
+    # both rows) doubles it, a sign slip flips it.
+    L = np.full(3, 20.0, np.float32)
+    for r in [0.9, 1.0, 2.0 ** (1 / 6), 1.5, 2.4]:
+        pos = np.array([[4.0, 5.0, 5.0], [4.0 + r, 5.0, 5.0]], dtype=np.float32)
+        rr = float(pos[1, 0]) - float(pos[0, 0])
+        F, U, W, _, Wr = O.lj(pos, L, PER, O.radius2(2.5))
+        dVdr = -24.0 * (2.0 * rr ** -13 - rr ** -7)       # derivative of 4 (r^-12 - r^-6)
+        assert W[0] == pytest.approx(-rr * dVdr, rel=1e-12, abs=1e-12), r
+        assert np.abs(W[1:]).max() == 0.0
+        # each row carries half of the pair's virial
+        assert Wr[0, 0] == pytest.approx(Wr[1, 0], rel=1e-15)
+    # an oblique pair across the x and y faces (image separation) gets the
+    # full outer product, off-diagonal terms included
+    pos = np.array([[0.25, 19.5, 7.0], [19.5, 0.5, 7.75]], dtype=np.float32)
+    F, U, W, _, _ = O.lj(pos, L, PER, O.radius2(2.5))
+    d = np.array([0.25 - (19.5 - 20.0), (19.5 - 20.0) - 0.5, 7.0 - 7.75])  # x_0 - x_1 (image)
+    assert np.allclose(W, pair_virial_closed_form(d), rtol=1e-12, atol=1e-12)
+    # the pair force itself: F_0 = s d
+    u = float(np.dot(d, d))
+    s = 24.0 * (2.0 * u ** -7 - u ** -4)
+    assert np.allclose(F[0], s * d, rtol=1e-12, atol=1e-12)
+    assert np.allclose(F[1], -s * d, rtol=1e-12, atol=1e-12)
+
+
+def lattice_virial_trace(n_atoms, a, rc):
+    """tr W = sum over pairs of r F(r) = 1/2 N sum over lattice vectors
+    0 < |n| a <= rc of 24 (2 r^-12 - r^-6) (sigma = eps = 1)."""
+    m = int(math.ceil(rc / a)) + 1
+    tot = 0.0
+    for n in itertools.product(range(-m, m + 1), repeat=3):
+        r2 = (n[0] ** 2 + n[1] ** 2 + n[2] ** 2) * a * a
+        if 0 < r2 <= rc * rc:
+            tot += 24.0 * (2.0 * r2 ** -6 - r2 ** -3)
+    return 0.5 * n_atoms * tot
+
+
+def test_virial_trace_perfect_lattice():
+    s = inputs.lj_lattice(4096, 4096 / 17.0 ** 3, 1.0, seed=1, jitter=0.0)
+    F, U, W, _, _ = O.lj(s.pos, s.box, PER, O.radius2(2.5))
+    a = float(s.box[0]) / 16
+    tr = W[0] + W[1] + W[2]
+    assert tr == pytest.approx(lattice_virial_trace(s.n, a, 2.5), rel=1e-9)
+    # isotropy of a cubic lattice: each diagonal entry is a third of the trace
+    for k in range(3):
+        assert W[k] == pytest.approx(tr / 3, rel=1e-9)
+
+
+def test_max_disp2_hand_cases():
+    # minimum-image displacement in the predicate's FP32 arithmetic; all
+    # coordinates are exact binary fractions, so every value is exact
+    L = np.full(3, 16.0, np.float32)
+    ref = np.array([[0.25, 8.0, 8.0],     # crosses the x face downwards: 15.5 is 0.75 away
+                    [4.0, 4.0, 4.0],      # moves 0.5 in y
+                    [15.75, 15.75, 8.0],  # crosses the x and y faces upwards
+                    [8.0, 8.0, 8.0]], dtype=np.float32)
+    pos = np.array([[15.5, 8.0, 8.0],
+                    [4.0, 4.5, 4.0],
+                    [0.25, 0.125, 8.0],
+                    [8.0, 8.0, 8.0]], dtype=np.float32)
+    per_row = [0.5625, 0.25, 0.25 + 0.140625, 0.0]
+    for k in range(4):
+        assert float(O.max_disp2(pos[k:k + 1], ref[k:k + 1], L, PER)) == per_row[k]
+    assert float(O.max_disp2(pos, ref, L, PER)) == 0.5625
+    # a corner crossing on all three axes
+    r3 = np.array([[0.25, 0.25, 0.25]], np.float32)
+    p3 = np.array([[15.75, 15.75, 15.75]], np.float32)
+    assert float(O.max_disp2(p3, r3, L, PER)) == 0.75
+    # without periodic x the face crossing is a long move
+    assert float(O.max_disp2(pos[:1], ref[:1], L, (0, 1, 1))) == 15.25 ** 2
+
+
+def test_rebuild_criterion_is_strict():
+    # One free particle (no pairs) moves 1/32 per step: after two steps its
+    # squared displacement equals the threshold exactly and no rebuild is due
+    # (the rule is "exceeds"); the third step rebuilds, and the count restarts
+    # from the new reference.  A non-strict rule would rebuild at 2, 4, 6.
+    L = np.full(3, 16.0, np.float32)
+    x0 = np.array([[15.9375, 8.0, 8.0]], np.float32)
+    v0 = np.array([[0.25, 0.0, 0.0]], np.float32)
+    dt = np.float32(0.125)
+    thr = np.float32(0.0625 ** 2)
+    xs, vs, Fs, nb = O.lj_traj_f32(x0, v0, L, PER, O.radius2(2.5), dt, 7, thr)
+    assert nb == 1 + 2  # the initial build, then steps 3 and 6
+    assert np.all(Fs == 0.0) and np.all(vs[:, 0, 0] == 0.25)
+    # positions are wrapped into [0, L) at rebuilds only: the particle is at
+    # 16.0 after step 2 (not wrapped, no rebuild), back at 0.03125 after step 3
+    assert xs[2, 0, 0] == np.float32(16.0)
+    assert xs[3, 0, 0] == np.float32(0.03125)
+    assert xs[6, 0, 0] == np.float32(0.125)
+    assert float(O.max_disp2(xs[2], xs[0], L, PER)) == float(thr)
