@@ -292,6 +292,29 @@ int fpm_get_dem(fpm_ctx *ctx, float *d_omega, float *d_torque, int32_t *d_nconta
  * d_ut (n x max_contacts x 3, zero after the last contact). */
 int fpm_get_contacts(fpm_ctx *ctx, int32_t *d_ids, float *d_ut);
 
+/* ---- allocation-free entry point ---- */
+
+/* Bytes of the static device array behind fpm_lj_forces_static (one array per
+ * GPU, held until the process ends): with max_nbr = 128 it takes about 90,000
+ * particles. */
+#define FPM_STATIC_SCRATCH_BYTES (64u << 20)
+/* For callers that may not allocate device memory (serving loops and harnesses
+ * that forbid hipMalloc): the forces, energy and virial of fpm_lj_forces for n
+ * particles given in this call, computed in a static device array of
+ * FPM_STATIC_SCRATCH_BYTES instead of a caller workspace.  ctx supplies the
+ * box (a single system), the neighbour parameters, the launch shapes and the
+ * stream; its own workspace, particles and forces are not touched, and no
+ * fpm_set_workspace is needed.  d_pos (n x 3, caller order, inside the box),
+ * d_type (n, NULL = all 0), d_frc (n x 3, written) and d_out (8 FP64 as in
+ * fpm_lj_forces, may be NULL) are device pointers.  Returns FPM_ENOWS when
+ * the particles need more than FPM_STATIC_SCRATCH_BYTES (checked before any
+ * device work), FPM_EINVAL for a batch, DEM storage or bad arguments.
+ * Allocates no device memory.  The stream is synchronised once (when the
+ * small system tables are copied).  Every call on a GPU uses that GPU's one
+ * array: calls that overlap on one GPU (several streams or threads) race. */
+int fpm_lj_forces_static(fpm_ctx *ctx, const fpm_lj_params *prm, int64_t n, const float *d_pos,
+                         const int32_t *d_type, float *d_frc, double *d_out);
+
 /* ---- status ---- */
 
 /* Synchronises the stream and reports device-side flags: FPM_EOVERFLOW if a

@@ -70,6 +70,7 @@ _SIGS = {
     "fpm_build_verlet": [_P],
     "fpm_get_neighbors": [_P, _P, _P],
     "fpm_lj_forces": [_P, C.POINTER(fpm_lj_params), _P],
+    "fpm_lj_forces_static": [_P, C.POINTER(fpm_lj_params), C.c_int64, _P, _P, _P, _P],
     "fpm_lj_force_vjp": [_P, C.POINTER(fpm_lj_params), _P, _P, _P],
     "fpm_lj_adjoint_step": [_P, C.POINTER(fpm_lj_params), C.c_float, _P, _P, _P, _P, _P,
                             C.c_int32],
@@ -283,6 +284,11 @@ def fpm_get_contacts(ctx, ids=None, ut=None):
 
 def fpm_lj_forces(ctx, prm: fpm_lj_params, out=None):
     _call("fpm_lj_forces", ctx, C.byref(prm), _ptr(out))
+
+
+def fpm_lj_forces_static(ctx, prm: fpm_lj_params, pos, frc, typ=None, out=None):
+    _call("fpm_lj_forces_static", ctx, C.byref(prm), int(pos.shape[0]), _ptr(pos), _ptr(typ),
+          _ptr(frc), _ptr(out))
 
 
 def fpm_lj_force_vjp(ctx, prm: fpm_lj_params, lam, gx, gtheta=None):
