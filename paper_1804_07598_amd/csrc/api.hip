@@ -150,6 +150,7 @@ size_t layout(const fpm_ctx *c, const Plan &P, char *base, State *st,
     s.nbr = (int32_t *)take((size_t)ns * cap4_for(c->cap) * 4 * sizeof(int32_t));
     s.nnb = (uint32_t *)take(ns * sizeof(uint32_t));
     s.part = (double *)take((size_t)P.nblk * kSlots * sizeof(double));
+    s.ring = (double *)take((size_t)P.nblk * kRingRows * 8 * sizeof(double));
     s.aux = (float4 *)take(ns * sizeof(float4));
     for (int k = 0; k < 2; k++) s.old[k] = (float4 *)take(ns * sizeof(float4));
     if (c->dem_cap > 0) {
@@ -177,8 +178,8 @@ size_t layout(const fpm_ctx *c, const Plan &P, char *base, State *st,
 
 void drop_graphs(fpm_ctx *c) {
     for (hipGraphExec_t *g :
-         {&c->g_first, &c->g_chunk, &c->g_one, &c->s_first, &c->s_chunk, &c->s_one, &c->d_chunk,
-          &c->d_one}) {
+         {&c->g_pow[0], &c->g_pow[1], &c->g_pow[2], &c->g_pow[3], &c->g_one, &c->g_last[0],
+          &c->g_last[1], &c->s_first, &c->s_chunk, &c->s_one, &c->d_chunk, &c->d_one}) {
         if (*g) (void)hipGraphExecDestroy(*g);
         *g = nullptr;
     }
@@ -240,7 +241,9 @@ hipError_t refresh_and_account(fpm_ctx *c) {
     return e;
 }
 
-constexpr int kChunk = 25;  // steps per captured graph
+constexpr int kChunk = 25;  // steps per captured graph (SPH and DEM loops)
+constexpr int kPowSteps[4] = {16, 8, 4, 2};  // LJ loops: steps of the even graphs
+static_assert(kPowSteps[0] <= kRingRows, "a graph's steps must fit the partials ring");
 
 template <class F>
 int capture(fpm_ctx *c, F &&body, hipGraphExec_t *out) {
@@ -263,16 +266,39 @@ int capture(fpm_ctx *c, F &&body, hipGraphExec_t *out) {
     return FPM_OK;
 }
 
-// One LJ velocity-Verlet step: (fused) kicks and drift, finalize (accounts a
-// rebuild of the previous step, completes the previous step's thermo row,
-// decides this step's rebuild), gated rebuild, forces.
-hipError_t lj_step_body(fpm_ctx *c, const fpm_lj_params &p, float dt, double *thermo,
-                        bool first) {
-    hipError_t e = launch_integrate(c, dt, first ? kKickDriftFirst : kKickKickDrift);
-    const int fin = first ? kFinDisp : (kFinBuild | kFinForce | kFinKE | kFinRow | kFinDisp);
-    if (e == hipSuccess) e = launch_finalize(c, fin, nullptr, thermo);
-    if (e == hipSuccess) e = refresh_lists(c);
-    if (e == hipSuccess) e = launch_lj_forces(c, p);
+// Launches recorded by `body` see the state of step parity `par`: the rebuild
+// flag copy par, and for odd steps the two position buffers exchanged, so that
+// every step reads its positions from buffer 0 of its own view and writes the
+// drifted ones to buffer 1 (the caller-visible buffer 0 holds the positions of
+// even steps).
+template <class F>
+hipError_t with_parity(fpm_ctx *c, int par, F &&body) {
+    const State keep = c->st;
+    c->st.par = par;
+    if (par) {
+        c->st.pos[0] = keep.pos[1];
+        c->st.pos[1] = keep.pos[0];
+    }
+    hipError_t e = body();
+    c->st = keep;
+    return e;
+}
+
+// `count` LJ velocity-Verlet steps from a step of parity par0: per step the
+// gated rebuild, then the force kernel with the closing half kick and (but for
+// a last step) the next step's opening half kick and drift; then the thermo
+// rows of these steps.  The first opening half kick and drift of a loop run
+// before it (fpm_step).
+hipError_t lj_steps_body(fpm_ctx *c, const fpm_lj_params &p, float dt, double *thermo, int par0,
+                         int count, bool last) {
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < count && e == hipSuccess; k++)
+        e = with_parity(c, (par0 + k) & 1, [&] {
+            hipError_t x = refresh_lists(c);
+            if (x == hipSuccess) x = launch_lj_step(c, p, dt, last && k == count - 1, k);
+            return x;
+        });
+    if (e == hipSuccess) e = launch_finalize_rows(c, count, thermo);
     return e;
 }
 
@@ -689,37 +715,43 @@ int fpm_step(fpm_ctx *c, const fpm_lj_params *p, float dt, int32_t nsteps, doubl
         c->forces_valid = true;
     }
     c->sph = false;
-    const bool same = c->g_first && c->g_dt == dt && c->g_thermo == thermo &&
+    const bool same = c->g_one && c->g_dt == dt && c->g_thermo == thermo &&
                       memcmp(&c->g_prm, p, sizeof(*p)) == 0 && c->g_unroll == c->tune_unroll;
     if (!same) {
         drop_graphs(c);
         int e;
         const fpm_lj_params prm = *p;
-        e = capture(c, [&] { return lj_step_body(c, prm, dt, thermo, true); }, &c->g_first);
+        for (int g = 0; g < 4; g++) {
+            e = capture(c, [&] { return lj_steps_body(c, prm, dt, thermo, 0, kPowSteps[g], false); },
+                        &c->g_pow[g]);
+            if (e) return e;
+        }
+        e = capture(c, [&] { return lj_steps_body(c, prm, dt, thermo, 0, 1, false); }, &c->g_one);
         if (e) return e;
-        e = capture(c,
-                    [&] {
-                        hipError_t x = hipSuccess;
-                        for (int s = 0; s < kChunk && x == hipSuccess; s++)
-                            x = lj_step_body(c, prm, dt, thermo, false);
-                        return x;
-                    },
-                    &c->g_chunk);
-        if (e) return e;
-        e = capture(c, [&] { return lj_step_body(c, prm, dt, thermo, false); }, &c->g_one);
-        if (e) return e;
+        for (int par = 0; par < 2; par++) {
+            e = capture(c, [&] { return lj_steps_body(c, prm, dt, thermo, par, 1, true); },
+                        &c->g_last[par]);
+            if (e) return e;
+        }
         c->g_dt = dt;
         c->g_thermo = thermo;
         c->g_prm = *p;
         c->g_unroll = c->tune_unroll;
     }
     HIPCHK(c, launch_reset_step(c));
-    HIPCHK(c, hipGraphLaunch(c->g_first, c->stream));
-    int left = nsteps - 1;
-    for (; left >= kChunk; left -= kChunk) HIPCHK(c, hipGraphLaunch(c->g_chunk, c->stream));
-    for (; left > 0; left--) HIPCHK(c, hipGraphLaunch(c->g_one, c->stream));
-    HIPCHK(c, launch_integrate(c, dt, kKickOnly));
-    HIPCHK(c, launch_finalize(c, kFinBuild | kFinForce | kFinKE | kFinRow, nullptr, thermo));
+    // opening half kick and drift of the first step, its rebuild decision
+    HIPCHK(c, launch_integrate(c, dt, kKickDriftFirst));
+    HIPCHK(c, launch_finalize(c, kFinDisp, nullptr, nullptr));
+    // steps 0 .. nsteps-2 fused with the next step's opening, then the last step
+    int left = nsteps - 1, step = 0;
+    for (int g = 0; g < 4; g++)
+        for (; left >= kPowSteps[g]; left -= kPowSteps[g], step += kPowSteps[g])
+            HIPCHK(c, hipGraphLaunch(c->g_pow[g], c->stream));
+    if (left == 1) {
+        HIPCHK(c, hipGraphLaunch(c->g_one, c->stream));
+        step += 1;
+    }
+    HIPCHK(c, hipGraphLaunch(c->g_last[step & 1], c->stream));
     return FPM_OK;
 }
 

@@ -16,7 +16,7 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
 
 __global__ void k_force_rebuild(SysCtl *sctl, int nsys) {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < nsys) sctl[s].rebuild = 1;
+    if (s < nsys) sctl[s].rebuild[0] = 1;
 }
 
 __global__ void k_init_ctl(Ctl *ctl, SysCtl *sctl, int nsys) {
@@ -69,7 +69,7 @@ __global__ void k_set_density(State st, const float *rho) {
 // Wrap, cell index and histogram (gated).
 __global__ __launch_bounds__(kBlock) void k_cell_assign(State st) {
     const int s = block_system(st);
-    if (!st.sctl[s].rebuild) return;
+    if (!rebuilding(st, s)) return;
     cell_assign_slot(st, s, global_slot());
 }
 
@@ -129,7 +129,7 @@ __device__ __forceinline__ int32_t scan_tile(int32_t *in, int32_t *out, int64_t 
 // cleared on the way for the next rebuild.
 __global__ __launch_bounds__(1024) void k_scan(State st) {
     const int s = blockIdx.x;
-    if (!st.sctl[s].rebuild) return;
+    if (!rebuilding(st, s)) return;
     const SysDesc &d = st.sys[s];
     int32_t *cnt = st.cnt + d.cell_base;
     int32_t *off = st.off + d.off_base;
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(1024) void k_scan(State st) {
 // The same scan for a single system with many cells, over the whole device:
 // tile totals (one workgroup per tile), then each tile's scan from its carry.
 __global__ __launch_bounds__(1024) void k_scan_sums(State st) {
-    if (!st.sctl[0].rebuild) return;
+    if (!rebuilding(st, 0)) return;
     const SysDesc &d = st.sys[0];
     const int32_t *cnt = st.cnt + d.cell_base;
     const int64_t k0 = (int64_t)blockIdx.x * kScanTile + 4 * (int64_t)threadIdx.x;
@@ -166,7 +166,7 @@ __global__ __launch_bounds__(1024) void k_scan_sums(State st) {
 // carry (integer sums, so the order does not matter); the last tile also
 // writes the end offset.
 __global__ __launch_bounds__(1024) void k_scan_tiles(State st) {
-    if (!st.sctl[0].rebuild) return;
+    if (!rebuilding(st, 0)) return;
     const SysDesc &d = st.sys[0];
     const int b = blockIdx.x, t = threadIdx.x;
     __shared__ int32_t part[16];
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(State st) {
 // Scatter (caller id, source slot, z) to the cell's offset + arrival rank.
 __global__ void k_scatter(State st) {
     const int s = block_system(st);
-    if (!st.sctl[s].rebuild) return;
+    if (!rebuilding(st, s)) return;
     const SysDesc &d = st.sys[s];
     const int64_t i = global_slot();
     if (i - d.slot_base >= d.n) return;
@@ -203,7 +203,7 @@ __global__ void k_scatter(State st) {
 // positions.
 __global__ void k_rank_gather(State st) {
     const int s = block_system(st);
-    if (!st.sctl[s].rebuild) return;
+    if (!rebuilding(st, s)) return;
     const SysDesc &d = st.sys[s];
     const int64_t i = global_slot();
     if (i - d.slot_base < d.n) {
@@ -235,7 +235,7 @@ __global__ void k_rank_gather(State st) {
 
 // Buffer 1 -> buffer 0 (used when the cell list is rebuilt on its own).
 __global__ void k_copy_back(State st) {
-    if (!st.sctl[block_system(st)].rebuild) return;
+    if (!rebuilding(st, block_system(st))) return;
     const int64_t i = global_slot();
     st.pos[0][i] = st.pos[1][i];
     st.vel[0][i] = st.vel[1][i];

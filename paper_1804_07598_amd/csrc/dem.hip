@@ -163,7 +163,7 @@ template <int CR>
 __global__ __launch_bounds__(kBlock) void k_dem_export_assign(State st, int cap4, int C,
                                                               int64_t ns) {
     const int s = block_system(st);
-    if (!st.sctl[s].rebuild) return;
+    if (!rebuilding(st, s)) return;
     const int64_t i = global_slot();
     export_slot<CR>(st, st.sys[s], i, cap4, C, ns);
     cell_assign_slot(st, s, i);
@@ -225,7 +225,7 @@ __device__ __forceinline__ void import_slot(const State &st, int64_t i, int cap4
 template <int CR>
 __global__ __launch_bounds__(kBlock) void k_dem_import(State st, int cap4, int C) {
     const int s = block_system(st);
-    if (!st.sctl[s].rebuild) return;
+    if (!rebuilding(st, s)) return;
     const SysDesc &d = st.sys[s];
     const int64_t i = global_slot();
     if (i - d.slot_base >= d.n) return;
@@ -245,7 +245,7 @@ __global__ __launch_bounds__(kBlock) void k_dem_forces(State st, DemCoef k, int 
     const Box b = d.box;
     const int64_t i = global_slot();
     if (i - d.slot_base >= d.n) return;
-    if (imp && st.sctl[sy].rebuild) import_slot<CR>(st, i, cap4, k.C);  // lists just rebuilt
+    if (imp && rebuilding(st, sy)) import_slot<CR>(st, i, cap4, k.C);  // lists just rebuilt
     const float4 *__restrict__ pos = st.pos[0];
     const float4 *__restrict__ vel = st.vel[0];
     const float4 *__restrict__ om = st.old[0];

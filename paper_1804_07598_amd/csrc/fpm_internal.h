@@ -74,9 +74,14 @@ struct SysDesc {
 };
 
 // Per-system control words.
+// The rebuild flag comes in two copies so that a captured LJ step can consume
+// one (its force kernel accounts the rebuild and clears it) while its drift
+// raises the other for the next step: step t of a step loop reads copy t & 1
+// (State::par); every call outside a step loop uses copy 0.
 struct SysCtl {
-    int32_t rebuild;        // 1: this system's neighbour structures must be rebuilt
+    int32_t rebuild[2];     // 1: this system's neighbour structures must be rebuilt
     int32_t step;           // rows written in the current fpm_step call
+    int32_t pad;
     int64_t n_rebuilds;     // rebuilds since fpm_set_particles
     double thermo[8];       // last U, KE, W6
 };
@@ -125,9 +130,14 @@ struct State {
     const SysDesc *sys;     // per system
     const int32_t *blk2sys; // particle workgroup -> system
     const int32_t *item2sys;  // column-build work item -> system
+    double *ring;           // step loops: per-step partials U, W6, KE, ring[(row * 8 + k) * pstride + block]
     int32_t nsys;
     int32_t pstride;        // number of particle workgroups
+    int32_t par;            // rebuild flag copy this launch reads (see SysCtl)
 };
+
+// Rows of per-step partial sums kept by a step loop before they are reduced.
+constexpr int kRingRows = 16;
 
 // Position of the padding slots: far enough that no pair with them is ever in
 // range, small enough that squared FP32 distances stay finite.
@@ -186,7 +196,11 @@ struct fpm_ctx {
     int tune_zb = 0;            // z-cells per column workgroup (path 4: lanes per particle)
     int tune_unroll = 0;        // force kernel: entries in flight per lane (4 or 8)
     // graphs of fpm_step, keyed by their parameters
-    hipGraphExec_t g_first = nullptr, g_chunk = nullptr, g_one = nullptr;
+    // LJ step loops: 16, 8, 4 and 2 steps from an even step; one step from an
+    // even step; the last step from an even or an odd step
+    hipGraphExec_t g_pow[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipGraphExec_t g_one = nullptr;
+    hipGraphExec_t g_last[2] = {nullptr, nullptr};
     double *g_thermo = nullptr;
     float g_dt = 0.f;
     fpm_lj_params g_prm{};
@@ -223,6 +237,20 @@ hipError_t launch_list_stats(fpm_ctx *c);  // fills ctl->max_count and ctl->tota
 // grid is too small for it (fewer than three cells along an axis).
 int verlet_zblock(int64_t n, int64_t ncells, const int nc[3], int tune_zb);
 hipError_t launch_lj_forces(fpm_ctx *c, const fpm_lj_params &p);
+// Force kernel modes: forces only; forces fused with the closing half kick of
+// the step and the next step's opening half kick and drift; the same for the
+// last step of a loop (closing kick only).
+enum { kLjForce = 0, kLjStep = 1, kLjLast = 2 };
+struct StepArgs {
+    float dt;       // time step
+    float thr;      // (skin/2)^2 in FP32: a larger displacement since the build rebuilds
+    double *ring;   // this step's row of per-step partials (U, W6, KE)
+};
+// One step of a step loop (see kLjStep / kLjLast); its partials go to ring row `row`.
+hipError_t launch_lj_step(fpm_ctx *c, const fpm_lj_params &p, float dt, bool last, int row);
+// Reduces ring rows 0 .. nrows-1 of every system into thermo rows (rows may be
+// null) ending at the system's step counter.
+hipError_t launch_finalize_rows(fpm_ctx *c, int nrows, double *rows);
 // Output of the force VJP kernel.  kVjpPlain: gx = g.  kVjpLast: gx += g.
 // kVjpStep: one reverse velocity-Verlet step on caller-order FP64 arrays:
 // gx (= xbar) += g; vbar += dt xbar; fbar = dt/2 vbar + floss (floss may be null).

@@ -159,6 +159,11 @@ __device__ __forceinline__ void cell_assign_slot(const State &st, int s, int64_t
     if (c >= 0) st.rnk[i] = base + (lane - hl);
 }
 
+// True when system s must rebuild its neighbour structures in this launch.
+__device__ __forceinline__ bool rebuilding(const State &st, int s) {
+    return st.sctl[s].rebuild[st.par] != 0;
+}
+
 // Wavefront reductions (64 lanes).
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

@@ -117,9 +117,9 @@ __global__ __launch_bounds__(NT) void k_finalize(State st, int mode, float thr, 
     __syncthreads();
     if (t != 0) return;
     SysCtl *sc = st.sctl + s;
-    if ((mode & kFinBuild) && sc->rebuild) {
+    if ((mode & kFinBuild) && sc->rebuild[0]) {
         sc->n_rebuilds += 1;
-        sc->rebuild = 0;
+        sc->rebuild[0] = 0;
     }
     if (mode & kFinVjp) {
         if (out)
@@ -143,7 +143,61 @@ __global__ __launch_bounds__(NT) void k_finalize(State st, int mode, float thr, 
                 rows[((int64_t)row * st.nsys + s) * 8 + c] = sc->thermo[c];
         sc->step = row + 1;
     }
-    if (want_d && tot[8] > (double)thr) sc->rebuild = 1;
+    if (want_d && tot[8] > (double)thr) sc->rebuild[0] = 1;
+}
+
+// Thermo rows of a step loop: workgroup (r, s) reduces ring row r of system s
+// (U, W6, KE, per-workgroup partials in block order, then wavefront shuffles
+// and the wavefront results in order) into thermo row step - nrows + r, where
+// step is the system's step counter after the loop's force kernels (each
+// advanced it by one); the last row also becomes the system's thermo.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_finalize_rows(State st, int nrows, double *rows) {
+    constexpr int NS = 8;
+    constexpr int NW = NT / 64;
+    __shared__ double red[NW][NS];
+    const int r = blockIdx.x, s = blockIdx.y;
+    const SysDesc &d = st.sys[s];
+    const int b0 = d.blk_base, nb = d.n_pad / kBlock;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t S = st.pstride;
+    const double *P = st.ring + (int64_t)r * NS * S;
+    double acc[NS];
+#pragma unroll
+    for (int c = 0; c < NS; c++) acc[c] = 0.0;
+    for (int r0 = t; r0 < nb; r0 += NT * kFinRowsPerThread) {
+        double v[kFinRowsPerThread][NS];
+#pragma unroll
+        for (int q = 0; q < kFinRowsPerThread; q++) {
+            const int k = r0 + q * NT;
+#pragma unroll
+            for (int c = 0; c < NS; c++) v[q][c] = k < nb ? P[c * S + b0 + k] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < kFinRowsPerThread; q++)
+#pragma unroll
+            for (int c = 0; c < NS; c++) acc[c] += v[q][c];
+    }
+#pragma unroll
+    for (int c = 0; c < NS; c++) acc[c] = wave_sum(acc[c]);
+    if (lane == 0)
+#pragma unroll
+        for (int c = 0; c < NS; c++) red[w][c] = acc[c];
+    __syncthreads();
+    if (t != 0) return;
+    double tot[NS];
+    for (int c = 0; c < NS; c++) {
+        double x = red[0][c];
+        for (int k = 1; k < NW; k++) x += red[k][c];
+        tot[c] = x;
+    }
+    SysCtl *sc = st.sctl + s;
+    const double th[8] = {tot[0], 0.5 * tot[7], tot[1], tot[2], tot[3], tot[4], tot[5], tot[6]};
+    const int row = sc->step - nrows + r;
+    if (rows)
+        for (int c = 0; c < 8; c++) rows[((int64_t)row * st.nsys + s) * 8 + c] = th[c];
+    if (r == nrows - 1)
+        for (int c = 0; c < 8; c++) sc->thermo[c] = th[c];
 }
 
 __global__ void k_reset_step(SysCtl *sctl, int nsys) {
@@ -222,6 +276,16 @@ hipError_t launch_finalize(fpm_ctx *c, int mode, double *out, double *rows) {
     else
         hipLaunchKernelGGL(k_finalize<256>, dim3(c->nsys), dim3(256), 0, c->stream, c->st, mode,
                            c->disp2_thr, out, rows);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_rows(fpm_ctx *c, int nrows, double *rows) {
+    const dim3 g((unsigned)nrows, (unsigned)c->nsys);
+    if (c->max_sys_blocks > 1024)
+        hipLaunchKernelGGL(k_finalize_rows<1024>, g, dim3(1024), 0, c->stream, c->st, nrows,
+                           rows);
+    else
+        hipLaunchKernelGGL(k_finalize_rows<256>, g, dim3(256), 0, c->stream, c->st, nrows, rows);
     return hipGetLastError();
 }
 

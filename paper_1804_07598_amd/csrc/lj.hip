@@ -181,10 +181,48 @@ __device__ __forceinline__ void walk(Acc &a, const float4 *__restrict__ pos,
     }
 }
 
-template <int NT, int UNR>
+// The velocity-Verlet updates that follow the force evaluation of a step
+// (kLjStep, kLjLast): the closing half kick of this step with the new force
+// (rounded to FP32, as stored), the kinetic energy of the full-step velocity,
+// and for kLjStep the opening half kick and the drift of the next step, whose
+// positions go to the other position buffer (neighbour gathers of this launch
+// still read the current one), with the test of their displacement since the
+// last build against (skin/2)^2.  Every FP32 update rounds after each multiply
+// and add, as in the stand-alone integrate kernel, so trajectories do not
+// depend on whether the updates are fused.
+template <int MODE>
+__device__ __forceinline__ double kick_drift(const State &st, const SysDesc &d, int64_t i,
+                                             float4 f, float4 p, float dt, float thr,
+                                             bool &over) {
+#pragma clang fp contract(off)
+    const float h = 0.5f * dt;
+    float4 v = st.vel[0][i];
+    v.x += h * f.x;
+    v.y += h * f.y;
+    v.z += h * f.z;
+    const double ke = (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z;
+    if (MODE == kLjStep) {
+        v.x += h * f.x;
+        v.y += h * f.y;
+        v.z += h * f.z;
+        p.x += dt * v.x;
+        p.y += dt * v.y;
+        p.z += dt * v.z;
+        st.pos[1][i] = p;
+        over = dist2_pred(xyz(st.xbuild[i]), xyz(p), d.box) > thr;
+        if (!isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z)) st.ctl->nonfinite = 1;
+    } else if (st.par) {
+        st.pos[1][i] = p;  // odd step: buffer 1 of this launch is the caller-visible one
+    }
+    st.vel[0][i] = v;
+    return ke;
+}
+
+template <int NT, int UNR, int MODE>
 __global__ __launch_bounds__(kBlock) void k_lj(State st, float rc2, double rc2lo, double rc2hi,
-                                               LJCoef cf, int cap4) {
-    const SysDesc &d = st.sys[block_system(st)];
+                                               LJCoef cf, int cap4, StepArgs sa) {
+    const int sys = block_system(st);
+    const SysDesc &d = st.sys[sys];
     const Box b = d.box;
     const float4 *__restrict__ pos = st.pos[0];
     const int64_t i = global_slot();
@@ -204,22 +242,58 @@ __global__ __launch_bounds__(kBlock) void k_lj(State st, float rc2, double rc2lo
         walk<NT, true, UNR>(a, pos, lst, cnt, pi4, b, rc2, rc2lo, rc2hi, cf);
     else
         walk<NT, false, UNR>(a, pos, lst, cnt, pi4, b, rc2, rc2lo, rc2hi, cf);
+    double ke = 0.0;
+    bool over = false;
     if (active) {
-        st.frc[i] = make_float4((float)a.fx, (float)a.fy, (float)a.fz, (float)(0.5 * a.u));
+        const float4 f = make_float4((float)a.fx, (float)a.fy, (float)a.fz, (float)(0.5 * a.u));
+        st.frc[i] = f;
         if (!isfinite(a.fx) || !isfinite(a.fy) || !isfinite(a.fz)) st.ctl->nonfinite = 1;
+        if (MODE != kLjForce) ke = kick_drift<MODE>(st, d, i, f, pi4, sa.dt, sa.thr, over);
+    }
+    if (MODE != kLjForce) {
+        SysCtl *sc = st.sctl + sys;
+        if (MODE == kLjStep) {
+            // the next step's rebuild flag, raised by one lane of a wavefront that needs it
+            const uint64_t m = __ballot(over);
+            if (m && (int)(threadIdx.x & 63) == __ffsll((long long)m) - 1)
+                sc->rebuild[st.par ^ 1] = 1;
+        }
+        if (threadIdx.x == 0 && pblock() == d.blk_base) {
+            // this step's rebuild (if any) is complete: account it and clear its flag
+            if (sc->rebuild[st.par]) {
+                sc->n_rebuilds += 1;
+                sc->rebuild[st.par] = 0;
+            }
+            sc->step += 1;
+        }
     }
     const double xi = pi4.x, yi = pi4.y, zi = pi4.z;
-    double v[7] = {0.5 * a.u,
-                   fma(xi, a.fx, a.wxx),
-                   fma(yi, a.fy, a.wyy),
-                   fma(zi, a.fz, a.wzz),
-                   fma(xi, a.fy, a.wxy),
-                   fma(xi, a.fz, a.wxz),
-                   fma(yi, a.fz, a.wyz)};
-    const int slot[7] = {kSlotU, kSlotW, kSlotW + 1, kSlotW + 2, kSlotW + 3, kSlotW + 4,
-                         kSlotW + 5};
-    const int op[7] = {0, 0, 0, 0, 0, 0, 0};
-    block_partials<7>(v, slot, op, st.part, st.pstride);
+    if (MODE == kLjForce) {
+        double v[7] = {0.5 * a.u,
+                       fma(xi, a.fx, a.wxx),
+                       fma(yi, a.fy, a.wyy),
+                       fma(zi, a.fz, a.wzz),
+                       fma(xi, a.fy, a.wxy),
+                       fma(xi, a.fz, a.wxz),
+                       fma(yi, a.fz, a.wyz)};
+        const int slot[7] = {kSlotU, kSlotW, kSlotW + 1, kSlotW + 2, kSlotW + 3, kSlotW + 4,
+                             kSlotW + 5};
+        const int op[7] = {0, 0, 0, 0, 0, 0, 0};
+        block_partials<7>(v, slot, op, st.part, st.pstride);
+    } else {
+        // one row of the step loop's ring: U, W6, KE
+        double v[8] = {0.5 * a.u,
+                       fma(xi, a.fx, a.wxx),
+                       fma(yi, a.fy, a.wyy),
+                       fma(zi, a.fz, a.wzz),
+                       fma(xi, a.fy, a.wxy),
+                       fma(xi, a.fz, a.wxz),
+                       fma(yi, a.fz, a.wyz),
+                       ke};
+        const int slot[8] = {0, 1, 2, 3, 4, 5, 6, 7};
+        const int op[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        block_partials<8>(v, slot, op, sa.ring, st.pstride);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -385,7 +459,10 @@ LJCoef make_coef(const fpm_lj_params &p) {
 
 }  // namespace
 
-hipError_t launch_lj_forces(fpm_ctx *c, const fpm_lj_params &p) {
+namespace {
+
+template <int MODE>
+void launch_lj_mode(fpm_ctx *c, const fpm_lj_params &p, const StepArgs &sa) {
     const LJCoef cf = make_coef(p);
     const double band = predicate_band(c);
     const double rc2lo = (double)c->rc2 * (1.0 - band), rc2hi = (double)c->rc2 * (1.0 + band);
@@ -393,19 +470,34 @@ hipError_t launch_lj_forces(fpm_ctx *c, const fpm_lj_params &p) {
     const bool u4 = c->tune_unroll == 4;
     if (p.n_types == 2) {
         if (u4)
-            hipLaunchKernelGGL((k_lj<2, 4>), g, t, 0, c->stream, c->st, c->rc2, rc2lo, rc2hi, cf,
-                               c->cap4);
+            hipLaunchKernelGGL((k_lj<2, 4, MODE>), g, t, 0, c->stream, c->st, c->rc2, rc2lo,
+                               rc2hi, cf, c->cap4, sa);
         else
-            hipLaunchKernelGGL((k_lj<2, 8>), g, t, 0, c->stream, c->st, c->rc2, rc2lo, rc2hi, cf,
-                               c->cap4);
+            hipLaunchKernelGGL((k_lj<2, 8, MODE>), g, t, 0, c->stream, c->st, c->rc2, rc2lo,
+                               rc2hi, cf, c->cap4, sa);
     } else {
         if (u4)
-            hipLaunchKernelGGL((k_lj<1, 4>), g, t, 0, c->stream, c->st, c->rc2, rc2lo, rc2hi, cf,
-                               c->cap4);
+            hipLaunchKernelGGL((k_lj<1, 4, MODE>), g, t, 0, c->stream, c->st, c->rc2, rc2lo,
+                               rc2hi, cf, c->cap4, sa);
         else
-            hipLaunchKernelGGL((k_lj<1, 8>), g, t, 0, c->stream, c->st, c->rc2, rc2lo, rc2hi, cf,
-                               c->cap4);
+            hipLaunchKernelGGL((k_lj<1, 8, MODE>), g, t, 0, c->stream, c->st, c->rc2, rc2lo,
+                               rc2hi, cf, c->cap4, sa);
     }
+}
+
+}  // namespace
+
+hipError_t launch_lj_forces(fpm_ctx *c, const fpm_lj_params &p) {
+    launch_lj_mode<kLjForce>(c, p, StepArgs{0.f, 0.f, nullptr});
+    return hipGetLastError();
+}
+
+hipError_t launch_lj_step(fpm_ctx *c, const fpm_lj_params &p, float dt, bool last, int row) {
+    const StepArgs sa{dt, c->disp2_thr, c->st.ring + (size_t)row * 8 * c->st.pstride};
+    if (last)
+        launch_lj_mode<kLjLast>(c, p, sa);
+    else
+        launch_lj_mode<kLjStep>(c, p, sa);
     return hipGetLastError();
 }
 

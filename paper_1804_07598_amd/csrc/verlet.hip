@@ -473,7 +473,7 @@ void k_verlet_grp(State st, const int32_t *blocks, float R2, int cap, int cap4, 
     const int r = xcd_block((int)blockIdx.x, (int)gridDim.x);
     const int blk = blocks[r >> 2];
     const int s = st.blk2sys[blk];
-    if (!st.sctl[s].rebuild) return;
+    if (!rebuilding(st, s)) return;
     const SysDesc &d = st.sys[s];
     const Box &b = d.box;
     const Group<G> gr;
@@ -625,7 +625,7 @@ __global__ __launch_bounds__(kBlock) void k_verlet(State st, const int32_t *bloc
                                                    int cap, int cap4) {
     const int blk = blocks[blockIdx.x];
     const int s = st.blk2sys[blk];
-    if (!st.sctl[s].rebuild) return;
+    if (!rebuilding(st, s)) return;
     const SysDesc &d = st.sys[s];
     const Box b = d.box;
     const int64_t i = (int64_t)blk * kBlock + threadIdx.x;
@@ -658,7 +658,7 @@ __global__ __launch_bounds__(kColThreads) void k_verlet_cols(State st, float R2,
                                                              int cap4) {
     const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);  // consecutive columns per XCD
     const int s = st.item2sys[lb];
-    if (!st.sctl[s].rebuild) return;
+    if (!rebuilding(st, s)) return;
     const SysDesc &d = st.sys[s];
     const Box b = d.box;
     const int zb = d.zb, nzb = d.nzb;
