@@ -331,10 +331,12 @@ int fpm_read_counters(fpm_ctx *ctx, int64_t h_out[3]);
 /* Launch shapes (0 = automatic).  verlet_path: 1 builds Verlet lists particle
  * by particle over whole neighbour cells, 2 by column blocks staged in LDS,
  * 3 particle by particle over candidate windows, 4 over the same windows with
- * a group of lanes per particle and each 64-slot row of lists staged in LDS
- * (2, 3 and 4 where the grid has >= 3 cells per axis; elsewhere paths 2 and
- * 3 take path 1 and path 4 runs its lane groups over whole cells; automatic
- * takes 3 when max_nbr is at most 48, else 4).  zblock: z-cells per column workgroup (1..64);
+ * a group of lanes per particle and each 64-slot row of lists staged in LDS,
+ * 5 one lane per particle with the lanes of a wavefront walking their windows
+ * in step (2, 3, 4 and 5 where the grid has >= 3 cells per axis; elsewhere
+ * paths 2 and 3 take path 1 and paths 4 and 5 run lane groups over whole
+ * cells; automatic takes 3 when max_nbr is at most 48, else 5, and lane
+ * groups over whole cells for small grids).  zblock: z-cells per column workgroup (1..64);
  * for path 4, lanes per particle (0 = 8, 4, 8 or 16; other values are
  * FPM_EINVAL).  unroll: list entries in
  * flight per lane in the force kernel (4 or 8).  Results do not depend on

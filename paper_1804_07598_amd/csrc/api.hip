@@ -38,7 +38,7 @@ int cap4_for(int cap) { return (cap + 7) / 8 * 2; }
 struct Plan {
     std::vector<SysHost> sys;
     std::vector<SysDesc> desc;
-    std::vector<int32_t> blk2sys, item2sys, pa_blocks, grp_blocks;
+    std::vector<int32_t> blk2sys, item2sys, pa_blocks, grp_blocks, ls_blocks;
     int64_t n_slots = 0;
     int nblk = 0, ncells_total = 0, noff_total = 0, nitems = 0, max_ncells = 0;
     int max_sys_blocks = 0;
@@ -87,6 +87,8 @@ Plan make_plan(const fpm_ctx *c, const std::vector<int64_t> &cnt) {
         const bool auto_groups = c->tune_verlet_path == 0 && c->cap > kShortListCap;
         if (c->tune_verlet_path == 1)
             d.zb = 0;
+        else if (c->tune_verlet_path == 5 || (auto_groups && big))
+            d.zb = big ? -4 : -3;
         else if (c->tune_verlet_path == 4 || auto_groups)
             d.zb = big ? -2 : -3;
         else if (c->tune_verlet_path == 3 || c->tune_verlet_path == 0)
@@ -103,6 +105,7 @@ Plan make_plan(const fpm_ctx *c, const std::vector<int64_t> &cnt) {
             P.blk2sys.push_back(s);
             if (d.zb == 0 || d.zb == -1) P.pa_blocks.push_back(blk + b);
             if (d.zb == -2 || d.zb == -3) P.grp_blocks.push_back(blk + b);
+            if (d.zb == -4) P.ls_blocks.push_back(blk + b);
         }
         for (int q = 0; q < h.nitems; q++) P.item2sys.push_back(s);
         slot += d.n_pad;
@@ -146,6 +149,7 @@ size_t layout(const fpm_ctx *c, const Plan &P, char *base, State *st,
     s.tmp = (int4 *)take(ns * sizeof(int4));
     s.cnt = (int32_t *)take(((size_t)P.ncells_total + 4) * sizeof(int32_t));
     s.off = (int32_t *)take(((size_t)P.noff_total + 4) * sizeof(int32_t));
+    s.sub = (int32_t *)take(((size_t)P.ncells_total * 8 + 4) * sizeof(int32_t));
     s.tsum = (int32_t *)take(((size_t)P.ncells_total / 4096 + 4) * sizeof(int32_t));
     s.nbr = (int32_t *)take((size_t)ns * cap4_for(c->cap) * 4 * sizeof(int32_t));
     s.nnb = (uint32_t *)take(ns * sizeof(uint32_t));
@@ -168,7 +172,8 @@ size_t layout(const fpm_ctx *c, const Plan &P, char *base, State *st,
     s.sys = (const SysDesc *)take(nsys * sizeof(SysDesc));
     s.blk2sys = (const int32_t *)take(P.blk2sys.size() * sizeof(int32_t));
     s.item2sys = (const int32_t *)take((P.item2sys.size() + 1) * sizeof(int32_t));
-    char *pa = take((P.pa_blocks.size() + P.grp_blocks.size() + 1) * sizeof(int32_t));
+    char *pa = take((P.pa_blocks.size() + P.grp_blocks.size() + P.ls_blocks.size() + 1) *
+                    sizeof(int32_t));
     s.nsys = nsys;
     s.pstride = P.nblk;
     if (st) *st = s;
@@ -458,7 +463,7 @@ int fpm_set_neighbor_params(fpm_ctx *c, float r_cut, float skin, int32_t max_nbr
 
 int fpm_set_tuning(fpm_ctx *c, int32_t verlet_path, int32_t zblock, int32_t unroll) {
     if (!c) return FPM_EINVAL;
-    if (verlet_path < 0 || verlet_path > 4) return fail(c, FPM_EINVAL, "verlet_path is 0..4");
+    if (verlet_path < 0 || verlet_path > 5) return fail(c, FPM_EINVAL, "verlet_path is 0..5");
     if (zblock < 0 || zblock > 64) return fail(c, FPM_EINVAL, "zblock out of range");
     if (verlet_path == 4 && zblock != 0 && zblock != 4 && zblock != 8 && zblock != 16)
         return fail(c, FPM_EINVAL, "lanes per particle (zblock of path 4) is 0, 4, 8 or 16");
@@ -518,6 +523,7 @@ int fpm_set_particles(fpm_ctx *c, int64_t n, const float *pos, const float *vel,
     c->nitems = P.nitems;
     c->n_pa_blocks = (int)P.pa_blocks.size();
     c->n_grp_blocks = (int)P.grp_blocks.size();
+    c->n_ls_blocks = (int)P.ls_blocks.size();
     c->max_ncells = P.max_ncells;
     c->max_sys_blocks = P.max_sys_blocks;
     // the tables are small; the copies finish before the host vectors go away
@@ -537,6 +543,10 @@ int fpm_set_particles(fpm_ctx *c, int64_t n, const float *pos, const float *vel,
         HIPCHK(c, hipMemcpyAsync(c->pa_blocks + P.pa_blocks.size(), P.grp_blocks.data(),
                                  P.grp_blocks.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                                  c->stream));
+    if (!P.ls_blocks.empty())  // then the lockstep blocks
+        HIPCHK(c, hipMemcpyAsync(c->pa_blocks + P.pa_blocks.size() + P.grp_blocks.size(),
+                                 P.ls_blocks.data(), P.ls_blocks.size() * sizeof(int32_t),
+                                 hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, launch_fill_i32(c->stream, c->st.cnt, c->ncells_total, 0));
     HIPCHK(c, launch_init_state(c, pos, vel, type));

@@ -82,7 +82,7 @@ constexpr int kScanTile = 4096;
 constexpr int64_t kScanDeviceCells = 16384;  // a single system with more cells scans device-wide
 
 __device__ __forceinline__ int32_t scan_tile(int32_t *in, int32_t *out, int64_t base, int64_t n,
-                                             int32_t carry, bool clear) {
+                                             int32_t carry, bool clear, int32_t *sub) {
     __shared__ int32_t wsum[16];
     __shared__ int32_t total;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -116,6 +116,10 @@ __device__ __forceinline__ int32_t scan_tile(int32_t *in, int32_t *out, int64_t 
     for (int q = 0; q < 4; q++)
         if (k0 + q < n) {
             out[k0 + q] = e;
+            // an empty cell's eighths all start at its offset (the gather writes
+            // the table of every other cell)
+            if (v[q] == 0)
+                for (int h = 0; h < 8; h++) sub[(k0 + q) * 8 + h] = e;
             e += v[q];
             if (clear) in[k0 + q] = 0;
         }
@@ -136,7 +140,7 @@ __global__ __launch_bounds__(1024) void k_scan(State st) {
     const int64_t ncells = d.ncells;
     int32_t carry = d.slot_base;
     for (int64_t base = 0; base < ncells; base += kScanTile)
-        carry += scan_tile(cnt, off, base, ncells, carry, true);
+        carry += scan_tile(cnt, off, base, ncells, carry, true, st.sub + (int64_t)d.cell_base * 8);
     if (threadIdx.x == 0) off[ncells] = carry;
 }
 
@@ -180,7 +184,8 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(State st) {
 #pragma unroll
     for (int w = 0; w < 16; w++) carry += part[w];
     const int32_t tot = scan_tile(st.cnt + d.cell_base, st.off + d.off_base,
-                                  (int64_t)b * kScanTile, d.ncells, carry, true);
+                                  (int64_t)b * kScanTile, d.ncells, carry, true,
+                                  st.sub + (int64_t)d.cell_base * 8);
     if (b == (int)gridDim.x - 1 && t == 0) st.off[d.off_base + d.ncells] = carry + tot;
 }
 
@@ -200,7 +205,9 @@ __global__ void k_scatter(State st) {
 // before it in (z, caller index) order, which makes the order independent of
 // the atomics' arrival order and every column of cells one run sorted by z.
 // Gathers position, velocity and id into buffer 1 and records the build
-// positions.
+// positions.  Each member also writes the eighth-of-cell table entries that
+// start at its slot (the eighths after its predecessor's, up to its own; the
+// last member closes the cell).
 __global__ void k_rank_gather(State st) {
     const int s = block_system(st);
     if (!rebuilding(st, s)) return;
@@ -212,12 +219,26 @@ __global__ void k_rank_gather(State st) {
         const int c = st.cid[me.y];
         const int beg = st.off[off_index(d, c)], end = st.off[off_index(d, c) + 1];
         int r = 0;
+        float zprev = -INFINITY;
         for (int k = beg; k < end; k++) {
             const int4 o = st.tmp[k];
             const float oz = __int_as_float(o.z);
-            r += oz < mz || (oz == mz && o.x < me.x);
+            const bool before = oz < mz || (oz == mz && o.x < me.x);
+            r += before;
+            zprev = before ? fmaxf(zprev, oz) : zprev;
         }
         const int f = beg + r;
+        {
+            const int nz = d.box.nc[2];
+            const int iz = (c - d.cell_base) % nz;
+            const float inv = d.box.inv[2];
+            const int e = z_eighth(mz, inv, iz);
+            const int e0 = r == 0 ? 0 : z_eighth(zprev, inv, iz) + 1;
+            int32_t *sub = st.sub + (int64_t)c * 8;
+            for (int h = e0; h <= e; h++) sub[h] = f;
+            if (f == end - 1)
+                for (int h = e + 1; h < 8; h++) sub[h] = end;
+        }
         const float4 p = st.pos[0][me.y];
         st.pos[1][f] = p;
         st.vel[1][f] = st.vel[0][me.y];

@@ -113,6 +113,8 @@ struct State {
     int4 *tmp;              // (caller id, source slot, z bits, 0) after the scatter
     int32_t *cnt;           // per-cell counts (kept at zero between rebuilds)
     int32_t *off;           // per system: exclusive scan of counts (global slots), ncells + 1
+    int32_t *sub;           // per cell, 8 entries: first slot whose z lies in eighth q of the
+                            // cell or above (see z_eighth); entry 0 is the cell's offset
     int32_t *tsum;          // device-wide scan: totals of the 4096-cell tiles
     int32_t *nbr;           // Verlet lists, see nbr_index()
     uint32_t *nnb;          // list length | kWrapBit
@@ -188,11 +190,13 @@ struct fpm_ctx {
     int nitems = 0;          // column-build work items
     int n_pa_blocks = 0;     // workgroups of systems built particle by particle
     int n_grp_blocks = 0;    // workgroups of systems built by lane groups
+    int n_ls_blocks = 0;     // workgroups of systems built by the lockstep window build
     int32_t *pa_blocks = nullptr;  // device list of those workgroups, then of these
     int max_ncells = 0;
     int max_sys_blocks = 0;  // particle workgroups of the largest system
     // tuning (fpm_set_tuning); 0 = automatic
-    int tune_verlet_path = 0;   // 1: whole cells, 2: column blocks, 3: windows, 4: lane groups
+    int tune_verlet_path = 0;   // 1: whole cells, 2: column blocks, 3: windows, 4: lane groups,
+                                // 5: lockstep windows
     int tune_zb = 0;            // z-cells per column workgroup (path 4: lanes per particle)
     int tune_unroll = 0;        // force kernel: entries in flight per lane (4 or 8)
     // graphs of fpm_step, keyed by their parameters

@@ -91,6 +91,19 @@ __device__ __forceinline__ int cell_coord(float x, float inv, int n) {
     return i > n - 1 ? n - 1 : i;
 }
 
+// Eighth of cell iz (its cell_coord) in which coordinate z lies:
+// floor((z * inv - iz) * 8) clamped to [0, 7], in FP32.  z * inv - iz is exact
+// (Sterbenz) inside the cell, so (iz, eighth) never decreases as z grows; the
+// cell sort tabulates where each eighth of a cell starts, and the Verlet build
+// bounds its candidate windows with that table.
+__device__ __forceinline__ int z_eighth(float z, float inv, int iz) {
+#pragma clang fp contract(off)
+    const float f = z * inv;
+    const float t = (f - (float)iz) * 8.f;
+    if (!(t >= 0.f)) return 0;
+    return t >= 7.f ? 7 : (int)t;
+}
+
 __device__ __forceinline__ int cell_of(float3 p, const Box &b) {
     int ix = cell_coord(p.x, b.inv[0], b.nc[0]);
     int iy = cell_coord(p.y, b.inv[1], b.nc[1]);

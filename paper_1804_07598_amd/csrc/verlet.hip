@@ -839,6 +839,277 @@ __global__ __launch_bounds__(kColThreads) void k_verlet_cols(State st, float R2,
             copy_back(st, q);
 }
 
+// ---------------------------------------------------------------------------
+// Lockstep window build (grids of at least three cells per axis): one lane per
+// particle, and the lanes of a wavefront walk their candidate windows in step,
+// candidate m of every lane's window of the same neighbour column at a time,
+// so that the wavefront's loads fall on a few cache lines (the lanes are
+// consecutive slots of one column, and their windows in a neighbour column
+// are short z-shifted ranges of the same sorted run).  A particle's window in
+// column k holds the run of cells iz-1 .. iz+1 restricted to
+// |z - z_i| <= sqrt(R^2 - d_k^2), d_k its horizontal distance to the column
+// (as in verlet_atom_window: bounds widened so that rounding only adds
+// candidates); the window ends are found by bisection on the z-sorted run.
+// Opposite columns are walked as one sequence (window of column k, then of
+// column 8 - k): a particle close to one side of its cell has a long window on
+// that side and a short one on the other, so the pair's total varies much less
+// between the lanes than either window, and the wavefront waits less for its
+// longest lane.  Wavefronts with a particle in the first or last z-cell of a
+// periodic box take the general form (each window in up to two pieces, one of
+// them across the z face, walked piece by piece).  Hits are stored straight
+// into the list layout.  Lists are identical as sets to those of the other
+// builds; entries are in column order, z ascending within a column.
+
+// One window piece of one column: candidates [lo, lo + len) of the sorted
+// buffer, shifted by -a (candidates across the lower face) and tested against
+// the particle at pk (moved down one period across the upper face).
+struct Piece {
+    int lo, len;
+};
+
+// Slot bounds of the candidates of one window piece: cells zc0 .. zc1 of the
+// column starting at cell `col`, whose (unshifted) z lies in [zlo, zhi].
+// The bounds come from the eighth-of-cell table of the cell sort: a particle
+// with z >= zlo has (cell, eighth) >= those of zlo, so every such particle is
+// at or after lo, and likewise every particle with z <= zhi is before hi; the
+// piece holds at most an eighth of a cell of extra candidates at either end,
+// which the predicate rejects.
+__device__ __forceinline__ void window_bounds(const int32_t *__restrict__ off,
+                                              const int32_t *__restrict__ sub, const Box &b,
+                                              int col, int zc0, int zc1, float zlo, float zhi,
+                                              int &lo, int &hi) {
+    const int nz = b.nc[2];
+    const float inv = b.inv[2];
+    const int c0 = cell_coord(zlo, inv, nz), c1 = cell_coord(zhi, inv, nz);
+    const int e0 = z_eighth(zlo, inv, c0), e1 = z_eighth(zhi, inv, c1);
+    lo = c0 < zc0 ? off[col + zc0] : (c0 > zc1 ? off[col + zc1 + 1] : sub[(col + c0) * 8 + e0]);
+    hi = c1 > zc1 ? off[col + zc1 + 1]
+                  : (c1 < zc0 ? off[col + zc0]
+                              : (e1 == 7 ? off[col + c1 + 1] : sub[(col + c1) * 8 + e1 + 1]));
+}
+
+// Shifts of column k for a particle in cell (ix, iy): candidate shift (ax, ay)
+// for columns across the lower face, particle coordinate (px, py) moved down
+// across the upper face, and the column's first cell; false when the column
+// lies across a closed face.
+__device__ __forceinline__ bool column_of(const Box &b, int ix, int iy, float x, float y, int k,
+                                          float &ax, float &ay, float &px, float &py, int &col) {
+    const int nx = b.nc[0], ny = b.nc[1], nz = b.nc[2];
+    int cx = ix + k / 3 - 1, cy = iy + k % 3 - 1;
+    ax = ay = 0.f;
+    px = x;
+    py = y;
+    if (cx < 0 || cx >= nx) {
+        if (!b.per[0]) return false;
+        if (cx < 0) cx += nx, ax = b.L[0];
+        else cx -= nx, px = x - b.L[0];
+    }
+    if (cy < 0 || cy >= ny) {
+        if (!b.per[1]) return false;
+        if (cy < 0) cy += ny, ay = b.L[1];
+        else cy -= ny, py = y - b.L[1];
+    }
+    col = (cx * ny + cy) * nz;
+    return true;
+}
+
+// Hits of the lockstep build collect in a per-lane LDS ring of kRingEnt
+// entries.  A store inside the candidate loop makes the wavefront's next loads
+// wait for it (loads and stores share one completion counter), so stores are
+// issued at few, wavefront-uniform points: after a round of candidates in
+// which some lane reached kFlushAt unwritten entries, every lane writes its
+// complete groups of four (16-byte stores into the list layout).
+constexpr int kRingEnt = 32;
+constexpr int kRingStride = kRingEnt + 4;  // ints per lane (16-byte aligned rows)
+constexpr int kFlushAt = 16;               // at most kFlushAt - 1 + 4 entries wait
+
+// Writes list entries [from, upto) (multiples of four) of this lane from its
+// ring to global memory.
+__device__ __forceinline__ void flush_ring(const int *ring, int *gl, int from, int upto) {
+    for (int k = from; k < upto; k += 4)
+        *reinterpret_cast<int4 *>(gl + (k >> 2) * 256) =
+            *reinterpret_cast<const int4 *>(ring + (k & (kRingEnt - 1)));
+}
+
+// Appends slot j to the list of this lane (entries beyond the capacity are
+// counted, not kept).
+__device__ __forceinline__ void put(int *ring, int cap, int &cnt, int j) {
+    if (cnt < cap) ring[cnt & (kRingEnt - 1)] = j;
+    cnt++;
+}
+
+template <bool SH>
+__device__ __forceinline__ bool test_cand(float4 q, float3 a, float3 pk, float R2) {
+#pragma clang fp contract(off)
+    const float qx = SH ? q.x - a.x : q.x, qy = SH ? q.y - a.y : q.y, qz = SH ? q.z - a.z : q.z;
+    const float dx = qx - pk.x, dy = qy - pk.y, dz = qz - pk.z;
+    const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
+    const float sxy = xx + yy;
+    return sxy + zz <= R2;
+}
+
+__global__ __launch_bounds__(kBlock) void k_verlet_ls(State st, const int32_t *blocks, float R2,
+                                                      int cap, int cap4) {
+#pragma clang fp contract(off)
+    const int blk = blocks[xcd_block((int)blockIdx.x, (int)gridDim.x)];
+    const int s = st.blk2sys[blk];
+    if (!rebuilding(st, s)) return;
+    const SysDesc &d = st.sys[s];
+    const Box &b = d.box;
+    const int64_t i = (int64_t)blk * kBlock + threadIdx.x;
+    const bool active = i - d.slot_base < d.n;
+    const float4 *__restrict__ pos = st.pos[1];
+    const int32_t *__restrict__ off = st.off + d.off_base;
+    const int nx = b.nc[0], ny = b.nc[1], nz = b.nc[2];
+    float3 pi = make_float3(0.f, 0.f, 0.f);
+    int ix = 0, iy = 0, iz = 1;
+    if (active) {
+        pi = xyz(pos[i]);
+        ix = cell_coord(pi.x, b.inv[0], nx);
+        iy = cell_coord(pi.y, b.inv[1], ny);
+        iz = cell_coord(pi.z, b.inv[2], nz);
+    }
+    // z-pieces of the runs: cells zc0[g] .. zc1[g], candidate z shift azs[g],
+    // particle z pks[g] (as in the lane-group build)
+    int zc0[2] = {iz - 1, 0}, zc1[2] = {iz + 1, -1};
+    float azs[2] = {0.f, 0.f}, pks[2] = {pi.z, pi.z};
+    if (iz == 0) {
+        if (b.per[2]) zc0[0] = zc1[0] = nz - 1, azs[0] = b.L[2], zc0[1] = 0, zc1[1] = 1;
+        else zc0[0] = 0, zc1[0] = 1;
+    } else if (iz == nz - 1) {
+        zc0[0] = nz - 2, zc1[0] = nz - 1;
+        if (b.per[2]) zc0[1] = zc1[1] = 0, pks[1] = pi.z - b.L[2];
+    }
+    const bool zwrap = __ballot(active && zc1[1] >= zc0[1]) != 0;  // some lane has two pieces
+    // horizontal distances to the four sides of the particle's cell
+    const float marg = 1e-5f * fmaxf(b.L[0], fmaxf(b.L[1], b.L[2]));
+    const float dxl = fmaxf(pi.x - (float)ix / b.inv[0] - marg, 0.f);
+    const float dxh = fmaxf((float)(ix + 1) / b.inv[0] - pi.x - marg, 0.f);
+    const float dyl = fmaxf(pi.y - (float)iy / b.inv[1] - marg, 0.f);
+    const float dyh = fmaxf((float)(iy + 1) / b.inv[1] - pi.y - marg, 0.f);
+    const float Rw2 = R2 * 1.0001f;
+    // windows of every piece (independent table loads)
+    const int32_t *__restrict__ sub = st.sub;
+    Piece w[9][2];
+    bool shx[9];  // column k lies across an x or y face for this particle
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        const int ox = k / 3 - 1, oy = k % 3 - 1;
+        float ax, ay, px, py;
+        int col = 0;
+        bool ok = active && column_of(b, ix, iy, pi.x, pi.y, k, ax, ay, px, py, col);
+        shx[k] = ax != 0.f || ay != 0.f || px != pi.x || py != pi.y;
+        const float ddx = ox < 0 ? dxl : (ox > 0 ? dxh : 0.f);
+        const float ddy = oy < 0 ? dyl : (oy > 0 ? dyh : 0.f);
+        const float h2 = Rw2 - ddx * ddx - ddy * ddy;
+        ok = ok && h2 >= 0.f;
+        const float hz = ok ? sqrtf(h2) : 0.f;
+        col += d.cell_base;  // global cell numbering of the table
+#pragma unroll
+        for (int g = 0; g < 2; g++) {
+            int lo = 0, hi = 0;
+            if (ok && zc1[g] >= zc0[g])
+                window_bounds(off - d.cell_base, sub, b, col, zc0[g], zc1[g],
+                              pks[g] - hz + azs[g], pks[g] + hz + azs[g], lo, hi);
+            w[k][g].lo = lo;
+            w[k][g].len = hi > lo ? hi - lo : 0;
+        }
+    }
+    // shifts of a column for this particle
+    auto shifts = [&](int k, int g, float3 &a, float3 &pk) {
+        float ax, ay, px, py;
+        int col;
+        column_of(b, ix, iy, pi.x, pi.y, k, ax, ay, px, py, col);
+        a = make_float3(ax, ay, azs[g]);
+        pk = make_float3(px, py, pks[g]);
+    };
+    int *gl = st.nbr + (((i >> 6) * (int64_t)cap4 * 64 + (i & 63)) << 2);
+    __shared__ __align__(16) int rings[kBlock * kRingStride];
+    int *ring = rings + threadIdx.x * kRingStride;
+    int cnt = 0, done = 0;  // entries found, entries written to global memory
+    bool img = false;
+    // one walk over window A followed by window B, all lanes in step, four
+    // candidates per round (their loads issued together); indices past the
+    // end of a lane's walk re-read a valid slot and are not tested
+    const char *pbase = reinterpret_cast<const char *>(pos);  // slots < 2^26: 32-bit offsets
+    auto walk = [&](Piece A, Piece B, int ka, int kb, bool shA, bool shB, int gA, int gB) {
+        constexpr int U = 4;
+        const int tot = A.len + B.len;
+        const bool sh = __ballot(active && (shA || shB)) != 0;
+        float3 aA = make_float3(0.f, 0.f, 0.f), pA = pi, aB = aA, pB = pi;
+        if (sh) {
+            shifts(ka, gA, aA, pA);
+            shifts(kb, gB, aB, pB);
+        }
+        for (int m = 0; __ballot(m < tot) != 0; m += U) {
+            int jj[U];
+            float4 q[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int mu = m + u;
+                jj[u] = mu < A.len ? A.lo + mu : (mu < tot ? B.lo + (mu - A.len) : A.lo);
+            }
+#pragma unroll
+            for (int u = 0; u < U; u++)
+                q[u] = *reinterpret_cast<const float4 *>(pbase + ((uint32_t)jj[u] << 4));
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int mu = m + u;
+                if (sh) {
+                    const bool inA = mu < A.len;
+                    if (mu < tot && test_cand<true>(q[u], inA ? aA : aB, inA ? pA : pB, R2) &&
+                        jj[u] != (int)i) {
+                        put(ring, cap, cnt, jj[u]);
+                        img |= inA ? shA : shB;
+                    }
+                } else if (mu < tot && test_cand<false>(q[u], aA, pi, R2) && jj[u] != (int)i) {
+                    put(ring, cap, cnt, jj[u]);
+                }
+            }
+            if (__ballot(min(cnt, cap) - done >= kFlushAt) != 0) {
+                const int upto = min(cnt, cap) & ~3;
+                flush_ring(ring, gl, done, upto);
+                done = upto;
+            }
+        }
+    };
+    const Piece none{0, 0};
+    if (!zwrap) {
+        // pairs of opposite columns, then the particle's own column
+#pragma unroll
+        for (int pr = 0; pr < 4; pr++)
+            walk(w[pr][0], w[8 - pr][0], pr, 8 - pr, shx[pr], shx[8 - pr], 0, 0);
+        walk(w[4][0], none, 4, 4, shx[4], false, 0, 0);
+    } else {
+        // general form: every piece of every column on its own (one copy of
+        // the walk; the piece is picked from registers by a select chain)
+#pragma unroll 1
+        for (int kg = 0; kg < 18; kg++) {
+            Piece P = none;
+            bool shk = false;
+#pragma unroll
+            for (int t = 0; t < 18; t++) {
+                P = t == kg ? w[t / 2][t % 2] : P;
+                shk = t == kg ? shx[t / 2] : shk;
+            }
+            const int k = kg >> 1, g = kg & 1;
+            const float az = g ? azs[1] : azs[0], pz = g ? pks[1] : pks[0];
+            walk(P, none, k, k, shk || az != 0.f || pz != pi.z, false, g, g);
+        }
+    }
+    if (active) {
+        const int c = min(cnt, cap);
+        const int c8 = (c + 7) & ~7;
+        // the unwritten entries, padded with the far-away slot to a multiple of
+        // eight (a list that overflowed ends at the capacity)
+        for (int k = c; k < c8; k++) ring[k & (kRingEnt - 1)] = d.dummy;
+        flush_ring(ring, gl, done, c8);
+        st.nnb[i] = (uint32_t)c | (img ? kWrapBit : 0u);
+        note_overflow(st, cnt, cap);
+    }
+    copy_back(st, i);
+}
+
 // Longest list and total entries of the current lists (on request only): a
 // grid-stride pass, reduced per workgroup, one pair of atomics per workgroup.
 __global__ __launch_bounds__(256) void k_list_stats(State st, int64_t nslots) {
@@ -897,6 +1168,10 @@ hipError_t launch_verlet_build(fpm_ctx *c) {
     if (c->n_pa_blocks > 0)
         hipLaunchKernelGGL(k_verlet, dim3(c->n_pa_blocks), dim3(kBlock), 0, c->stream, c->st,
                            c->pa_blocks, c->R2, c->cap, c->cap4);
+    if (c->n_ls_blocks > 0)
+        hipLaunchKernelGGL(k_verlet_ls, dim3(c->n_ls_blocks), dim3(kBlock), 0, c->stream, c->st,
+                           c->pa_blocks + c->n_pa_blocks + c->n_grp_blocks, c->R2, c->cap,
+                           c->cap4);
     if (c->n_grp_blocks > 0) {
         // four 64-slot rows per particle workgroup
         const dim3 grid(4 * c->n_grp_blocks);

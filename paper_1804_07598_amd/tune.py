@@ -31,7 +31,8 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_1804_0759
 
 # (verlet_path, zblock, unroll); zblock 0 lets the library size the column blocks,
 # for path 4 it is the number of lanes per particle
-CANDIDATES = [(4, 8, 8), (4, 8, 4), (4, 4, 8), (3, 0, 8), (2, 0, 8), (1, 0, 8)]
+CANDIDATES = [(5, 0, 8), (5, 0, 4), (4, 8, 8), (4, 8, 4), (4, 4, 8), (3, 0, 8), (2, 0, 8),
+              (1, 0, 8)]
 
 
 def _device_key(device) -> str:

@@ -70,7 +70,8 @@ def test_host_side_errors_without_device():
         assert L.fpm_workspace_size(ctx, (1 << 26) - 1, ctypes.byref(sz)) == 0
         assert L.fpm_set_neighbor_params(ctx, 2.5, 0.3, 4097) == F.FPM_EINVAL
         # launch-shape knobs outside their ranges
-        assert L.fpm_set_tuning(ctx, 5, 0, 0) == F.FPM_EINVAL
+        assert L.fpm_set_tuning(ctx, 6, 0, 0) == F.FPM_EINVAL
+        assert L.fpm_set_tuning(ctx, 5, 0, 0) == 0
         assert L.fpm_set_tuning(ctx, 4, 5, 0) == F.FPM_EINVAL
         assert L.fpm_set_tuning(ctx, 2, 65, 0) == F.FPM_EINVAL
         assert L.fpm_set_tuning(ctx, 0, 0, 6) == F.FPM_EINVAL

@@ -49,18 +49,21 @@ def check_system(sim, k, s, F_all, out, counts, cols, sets=True):
     assert np.abs(out[k, 2:] - W64).max() <= ENERGY_TOL * scale, k
 
 
-@pytest.mark.parametrize("tuning", [None, (2, 0, 8), (3, 0, 8)])
+@pytest.mark.parametrize("tuning", [None, (2, 0, 8), (3, 0, 8), (4, 8, 8)])
 def test_batch_matches_oracle_per_system(tuning):
     idx = list(range(10)) + [72, 130]  # 72 and 130 have boxes of 2 cells per axis
     systems = systems_of(idx)
     sim = make_batch(systems, tuning=tuning)
     # two Verlet build paths occur: whole cells for grids below 3 cells per axis
-    # (lane groups by default, -3; particle by particle otherwise, 0), and above
-    # lane groups (default, -2), column workgroups (path 2: z-cells per block)
-    # or particle-by-particle windows (path 3: -1)
+    # (lane groups by default and for path 4, -3; particle by particle
+    # otherwise, 0), and above lockstep windows (default, -4), column
+    # workgroups (path 2: z-cells per block), particle-by-particle windows
+    # (path 3: -1) or lane groups (path 4: -2)
     zb = [sim.system_info(k)["zblock"] for k in range(len(idx))]
-    big = {None: lambda z: z == -2, (2, 0, 8): lambda z: z > 0, (3, 0, 8): lambda z: z == -1}
-    assert (-3 if tuning is None else 0) in zb and any(big[tuning](z) for z in zb)
+    big = {None: lambda z: z == -4, (2, 0, 8): lambda z: z > 0, (3, 0, 8): lambda z: z == -1,
+           (4, 8, 8): lambda z: z == -2}
+    small = -3 if tuning in (None, (4, 8, 8)) else 0
+    assert small in zb and any(big[tuning](z) for z in zb)
     off, order = (np_(t) for t in sim.cell_list())
     for k, s in enumerate(systems):
         info = sim.system_info(k)
@@ -128,7 +131,7 @@ def test_full_batch_sampled_systems():
 
 
 @pytest.mark.parametrize("tuning", [(1, 0, 4), (1, 0, 8), (2, 1, 8), (2, 3, 4), (2, 0, 8),
-                                    (3, 0, 4), (4, 4, 4), (4, 8, 8), (4, 16, 8)])
+                                    (3, 0, 4), (4, 4, 4), (4, 8, 8), (4, 16, 8), (5, 0, 4)])
 def test_tuning_knobs_change_nothing_but_speed(tuning):
     systems = systems_of([0, 5, 9, 72, 200, 300])
     ref = make_batch(systems)

@@ -207,7 +207,7 @@ def test_particles_on_faces_and_empty_cells():
     compare_sets(sim, s.pos, s.box, O.radius2(RC, SKIN))
 
 
-@pytest.mark.parametrize("tuning", [None, (3, 0, 8), (4, 8, 8)])
+@pytest.mark.parametrize("tuning", [None, (3, 0, 8), (4, 8, 8), (5, 0, 8)])
 def test_overflow_is_reported(tuning):
     from paper_1804_07598_amd._lib import FpmError, FPM_EOVERFLOW
     s = inputs.lj_lattice(1000, 0.8442, 1.0, seed=7)
