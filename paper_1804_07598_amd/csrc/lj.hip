@@ -60,11 +60,12 @@ __device__ __forceinline__ bool separation(float3 pi, double xi, double yi, doub
         dz += sz;
     }
     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-    bool in = r2 <= rc2lo;
+    bool in = r2 <= rc2hi;
+    const bool band = r2 > rc2lo;  // together with `in`: inside the band
     // the band is narrow: a wavefront rarely has a lane in it, and only then
     // is the FP32 predicate evaluated
-    if (__builtin_expect(__ballot(!in && r2 <= rc2hi) != 0, 0)) {
-        if (!in && r2 <= rc2hi)
+    if (__builtin_expect(__ballot(in && band) != 0, 0)) {
+        if (in && band)
             in = (IMG ? dist2_pred(pi, xyz(q), b) : dist2_direct(pi, xyz(q))) <= rc2;
     }
     return in;
@@ -166,18 +167,23 @@ __device__ __forceinline__ void walk(Acc &a, const float4 *__restrict__ pos,
     const float3 pi = xyz(pi4);
     const double xi = pi.x, yi = pi.y, zi = pi.z;
     const int ti = __float_as_int(pi4.w);
-    float4 q[UNR];
-    gather<UNR>(pos, list_group<UNR>(lst, 0), q);
+    // two register sets take turns (no copies between rounds); a round past
+    // the end of the list re-reads a group in range, which is harmless
+    float4 q0[UNR], q1[UNR];
+    gather<UNR>(pos, list_group<UNR>(lst, 0), q0);
     Entries<UNR> nxt = list_group<UNR>(lst, UNR < cnt ? UNR : 0);
-    for (int k = 0; k < cnt; k += UNR) {
-        float4 qn[UNR];
-        gather<UNR>(pos, nxt, qn);  // the last round re-reads a group in range: harmless
+    for (int k = 0; k < cnt; k += 2 * UNR) {
+        gather<UNR>(pos, nxt, q1);
         nxt = list_group<UNR>(lst, k + 2 * UNR < cnt ? k + 2 * UNR : k);
 #pragma unroll
         for (int u = 0; u < UNR; u++)
-            pair<NT, IMG>(a, pi, xi, yi, zi, ti, q[u], b, rc2, rc2lo, rc2hi, cf);
+            pair<NT, IMG>(a, pi, xi, yi, zi, ti, q0[u], b, rc2, rc2lo, rc2hi, cf);
+        if (k + UNR >= cnt) break;
+        gather<UNR>(pos, nxt, q0);
+        nxt = list_group<UNR>(lst, k + 3 * UNR < cnt ? k + 3 * UNR : k);
 #pragma unroll
-        for (int u = 0; u < UNR; u++) q[u] = qn[u];
+        for (int u = 0; u < UNR; u++)
+            pair<NT, IMG>(a, pi, xi, yi, zi, ti, q1[u], b, rc2, rc2lo, rc2hi, cf);
     }
 }
 
@@ -192,11 +198,10 @@ __device__ __forceinline__ void walk(Acc &a, const float4 *__restrict__ pos,
 // depend on whether the updates are fused.
 template <int MODE>
 __device__ __forceinline__ double kick_drift(const State &st, const SysDesc &d, int64_t i,
-                                             float4 f, float4 p, float dt, float thr,
-                                             bool &over) {
+                                             float4 f, float4 p, float4 v, float4 xb, float dt,
+                                             float thr, bool &over) {
 #pragma clang fp contract(off)
     const float h = 0.5f * dt;
-    float4 v = st.vel[0][i];
     v.x += h * f.x;
     v.y += h * f.y;
     v.z += h * f.z;
@@ -209,7 +214,7 @@ __device__ __forceinline__ double kick_drift(const State &st, const SysDesc &d, 
         p.y += dt * v.y;
         p.z += dt * v.z;
         st.pos[1][i] = p;
-        over = dist2_pred(xyz(st.xbuild[i]), xyz(p), d.box) > thr;
+        over = dist2_pred(xyz(xb), xyz(p), d.box) > thr;
         if (!isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z)) st.ctl->nonfinite = 1;
     } else if (st.par) {
         st.pos[1][i] = p;  // odd step: buffer 1 of this launch is the caller-visible one
@@ -229,9 +234,14 @@ __global__ __launch_bounds__(kBlock) void k_lj(State st, float rc2, double rc2lo
     const bool active = i - d.slot_base < d.n;
     uint32_t nn = 0;
     float4 pi4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    // the step modes read the velocity and build position at the start, so
+    // that their latency hides behind the pair loop
+    float4 v4 = pi4, xb4 = pi4;
     if (active) {
         nn = st.nnb[i];
         pi4 = pos[i];
+        if (MODE != kLjForce) v4 = st.vel[0][i];
+        if (MODE == kLjStep) xb4 = st.xbuild[i];
     }
     const bool img_wave = __ballot((nn & kWrapBit) != 0) != 0;
     const int cnt = (int)(nn & ~kWrapBit);
@@ -248,7 +258,8 @@ __global__ __launch_bounds__(kBlock) void k_lj(State st, float rc2, double rc2lo
         const float4 f = make_float4((float)a.fx, (float)a.fy, (float)a.fz, (float)(0.5 * a.u));
         st.frc[i] = f;
         if (!isfinite(a.fx) || !isfinite(a.fy) || !isfinite(a.fz)) st.ctl->nonfinite = 1;
-        if (MODE != kLjForce) ke = kick_drift<MODE>(st, d, i, f, pi4, sa.dt, sa.thr, over);
+        if (MODE != kLjForce)
+            ke = kick_drift<MODE>(st, d, i, f, pi4, v4, xb4, sa.dt, sa.thr, over);
     }
     if (MODE != kLjForce) {
         SysCtl *sc = st.sctl + sys;

@@ -1033,7 +1033,7 @@ __global__ __launch_bounds__(kBlock) void k_verlet_ls(State st, const int32_t *b
     // end of a lane's walk re-read a valid slot and are not tested
     const char *pbase = reinterpret_cast<const char *>(pos);  // slots < 2^26: 32-bit offsets
     auto walk = [&](Piece A, Piece B, int ka, int kb, bool shA, bool shB, int gA, int gB) {
-        constexpr int U = 4;
+        constexpr int U = 8;
         const int tot = A.len + B.len;
         const bool sh = __ballot(active && (shA || shB)) != 0;
         float3 aA = make_float3(0.f, 0.f, 0.f), pA = pi, aB = aA, pB = pi;

@@ -95,16 +95,10 @@ def tune(sim, density: float, *, rebuild_interval: float = 5.0, reps: int = 5,
         f_ms, b_ms = _measure(sim, 1, eps, sig, n_types)  # warm (graphs, caches)
         f_ms, b_ms = _measure(sim, reps, eps, sig, n_types)
         raw.append((knobs, f_ms, b_ms))
-    # the force kernel depends on the unroll knob only: pool its timings over
-    # the candidates sharing it, so that timing noise of the force launches
-    # does not decide between build paths
-    pooled = {}
-    for knobs, f_ms, _ in raw:
-        pooled.setdefault(knobs[2], []).append(f_ms)
-    table = []
-    for knobs, _, b_ms in raw:
-        f_ms = sum(pooled[knobs[2]]) / len(pooled[knobs[2]])
-        table.append((knobs, f_ms, b_ms, f_ms + b_ms / rebuild_interval))
+    # the force kernel's time depends on the build path too (the order of the
+    # entries it writes decides how many cache lines a gather touches), so each
+    # candidate keeps its own force timing
+    table = [(knobs, f_ms, b_ms, f_ms + b_ms / rebuild_interval) for knobs, f_ms, b_ms in raw]
     best = min(table, key=lambda r: r[3])
     sim.set_tuning(*best[0])
     if cache:
