@@ -252,18 +252,35 @@ def test_cutoff_error():
 
 # ---------------------------------------------------------------- 1M atoms, sampled
 
+def sampled_rows(pos, L, seed, n_face=1024, n_rand=3072):
+    """Rows for full-size checks: n_face particles within the list radius of a
+    periodic face (their lists hold image pairs) and n_rand random ones."""
+    rng = np.random.default_rng(seed)
+    near = np.nonzero(((pos < RC + SKIN) | (pos > L - (RC + SKIN))).any(axis=1))[0]
+    face = rng.choice(near, n_face, replace=False)
+    rest = rng.choice(np.setdiff1d(np.arange(len(pos)), face), n_rand, replace=False)
+    return np.sort(np.concatenate([face, rest]))
+
+
 def test_lj_1m_sampled_rows():
     s = inputs.lj_config("lj1m")
     sim = make_sim(s)
-    rows = np.random.default_rng(2).choice(s.n, 128, replace=False)
+    rows = sampled_rows(s.pos, s.box, 2)
     sim.lj_forces()
     compare_sets(sim, s.pos, s.box, O.radius2(RC, SKIN), rows=rows)
     check_lj(sim, s.pos, s.box, rows=rows)
-    # after steps with rebuilds the kept lists still cover the force set, and the
-    # total energy stays put (truncated LJ, 40 steps)
+    # after steps with rebuilds (the step loop's fused force kernels, the launch
+    # configuration the bench times) the kept lists still cover the force set,
+    # the forces at the reached positions match the oracle on sampled rows, and
+    # the total energy stays put (truncated LJ, 40 steps)
     th = np_(sim.step(40, dt=0.005))
     sim.check()
     assert sim.counters()[0] >= 2
     kept_lists_cover(sim, s.box, rows=np.random.default_rng(3).choice(s.n, 4096, replace=False))
+    p, _, f = (np_(t) for t in sim.get())
+    rows2 = sampled_rows(p, s.box, 4)
+    F64, _, _, _, _ = O.lj(p, s.box, PER, O.radius2(RC), rows=rows2)
+    err, _ = force_error(f[rows2], F64)
+    assert err <= FORCE_TOL
     E = th[:, 0] + th[:, 1]
     assert abs(E[-1] - E[0]) < 1e-3 * abs(E[0])
