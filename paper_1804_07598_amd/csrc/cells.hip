@@ -79,6 +79,12 @@ __global__ __launch_bounds__(kBlock) void k_cell_assign(State st) {
 // 16 wavefront totals.  `in` may alias `out`; with `clear` the inputs are
 // zeroed.  Returns the tile's total to every thread.
 constexpr int kScanTile = 4096;
+
+// The eighth-of-cell table of system d, which only the lockstep Verlet build
+// reads (null for systems built another way).
+__device__ __forceinline__ int32_t *eighths(const State &st, const SysDesc &d) {
+    return d.zb == -4 ? st.sub + (int64_t)d.cell_base * 8 : nullptr;
+}
 constexpr int64_t kScanDeviceCells = 16384;  // a single system with more cells scans device-wide
 
 __device__ __forceinline__ int32_t scan_tile(int32_t *in, int32_t *out, int64_t base, int64_t n,
@@ -118,7 +124,7 @@ __device__ __forceinline__ int32_t scan_tile(int32_t *in, int32_t *out, int64_t 
             out[k0 + q] = e;
             // an empty cell's eighths all start at its offset (the gather writes
             // the table of every other cell)
-            if (v[q] == 0)
+            if (sub && v[q] == 0)
                 for (int h = 0; h < 8; h++) sub[(k0 + q) * 8 + h] = e;
             e += v[q];
             if (clear) in[k0 + q] = 0;
@@ -140,7 +146,7 @@ __global__ __launch_bounds__(1024) void k_scan(State st) {
     const int64_t ncells = d.ncells;
     int32_t carry = d.slot_base;
     for (int64_t base = 0; base < ncells; base += kScanTile)
-        carry += scan_tile(cnt, off, base, ncells, carry, true, st.sub + (int64_t)d.cell_base * 8);
+        carry += scan_tile(cnt, off, base, ncells, carry, true, eighths(st, d));
     if (threadIdx.x == 0) off[ncells] = carry;
 }
 
@@ -184,8 +190,7 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(State st) {
 #pragma unroll
     for (int w = 0; w < 16; w++) carry += part[w];
     const int32_t tot = scan_tile(st.cnt + d.cell_base, st.off + d.off_base,
-                                  (int64_t)b * kScanTile, d.ncells, carry, true,
-                                  st.sub + (int64_t)d.cell_base * 8);
+                                  (int64_t)b * kScanTile, d.ncells, carry, true, eighths(st, d));
     if (b == (int)gridDim.x - 1 && t == 0) st.off[d.off_base + d.ncells] = carry + tot;
 }
 
@@ -228,7 +233,7 @@ __global__ void k_rank_gather(State st) {
             zprev = before ? fmaxf(zprev, oz) : zprev;
         }
         const int f = beg + r;
-        {
+        if (d.zb == -4) {
             const int nz = d.box.nc[2];
             const int iz = (c - d.cell_base) % nz;
             const float inv = d.box.inv[2];
