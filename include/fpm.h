@@ -261,6 +261,20 @@ int fpm_sph_rates(fpm_ctx *ctx, const fpm_sph_params *prm, float *d_dt);
  * kernel or scheme, or verlet_every < 1 with scheme 1. */
 int fpm_sph_step(fpm_ctx *ctx, const fpm_sph_params *prm, int32_t nsteps, double *d_hist);
 
+/* Symmetric half lists (the section 4.1 listing's getCellListSym and
+ * applyKernel_in_sym; the reaction step is section 3.4's ghost_put): with
+ * on = 1, fpm_lj_forces and fpm_step evaluate every pair once, at the pair's
+ * lower slot, and hand the reaction to the partner.  Lists are then kept in
+ * ascending slot order; each rebuild also records, for every pair, where it
+ * sits in the partner's list.  A first pass stores each pair's force factor
+ * and the particle's own sum, a second pass adds the partners' reactions in
+ * list order: no atomics, results repeat bit for bit.  Forces, energy and
+ * virial agree with the full-list path to rounding.  Call before
+ * fpm_workspace_size and fpm_set_particles (the workspace grows by 10 bytes
+ * per list entry and 28 per particle); not with DEM storage.  FPM_EOVERFLOW
+ * from fpm_check if a pair was missing from one side (lists overflowed). */
+int fpm_set_symmetric(fpm_ctx *ctx, int32_t on);
+
 /* ---- DEM (section 4.5) ---- */
 
 /* Turns on DEM storage: per-grain angular velocities and the contact

@@ -79,6 +79,7 @@ _SIGS = {
     "fpm_sph_rates": [_P, C.POINTER(fpm_sph_params), _P],
     "fpm_sph_step": [_P, C.POINTER(fpm_sph_params), C.c_int32, _P],
     "fpm_set_dem": [_P, C.c_int32],
+    "fpm_set_symmetric": [_P, C.c_int32],
     "fpm_set_omega": [_P, _P],
     "fpm_dem_forces": [_P, C.POINTER(fpm_dem_params)],
     "fpm_dem_step": [_P, C.POINTER(fpm_dem_params), C.c_int32],
@@ -256,6 +257,10 @@ def dem_params(R, mass, inertia, kn, kt, gn, gt=0.0, mu=0.5, g=(0.0, 0.0, 0.0), 
         p.g[k] = float(g[k])
     p.dt, p.walls = float(dt), int(walls)
     return p
+
+
+def fpm_set_symmetric(ctx, on: bool):
+    _call("fpm_set_symmetric", ctx, 1 if on else 0)
 
 
 def fpm_set_dem(ctx, max_contacts: int):

@@ -85,7 +85,9 @@ Plan make_plan(const fpm_ctx *c, const std::vector<int64_t> &cnt) {
         // build against 206 us; at 1M LJ atoms with 76 entries the groups win)
         const bool big = d.box.nc[0] >= 3 && d.box.nc[1] >= 3 && d.box.nc[2] >= 3;
         const bool auto_groups = c->tune_verlet_path == 0 && c->cap > kShortListCap;
-        if (c->tune_verlet_path == 1)
+        if (c->sym)  // symmetric half lists need lists in ascending slot order
+            d.zb = big ? -5 : 0;
+        else if (c->tune_verlet_path == 1)
             d.zb = 0;
         else if (c->tune_verlet_path == 5 || (auto_groups && big))
             d.zb = big ? -4 : -3;
@@ -105,7 +107,7 @@ Plan make_plan(const fpm_ctx *c, const std::vector<int64_t> &cnt) {
             P.blk2sys.push_back(s);
             if (d.zb == 0 || d.zb == -1) P.pa_blocks.push_back(blk + b);
             if (d.zb == -2 || d.zb == -3) P.grp_blocks.push_back(blk + b);
-            if (d.zb == -4) P.ls_blocks.push_back(blk + b);
+            if (d.zb == -4 || d.zb == -5) P.ls_blocks.push_back(blk + b);
         }
         for (int q = 0; q < h.nitems; q++) P.item2sys.push_back(s);
         slot += d.n_pad;
@@ -155,6 +157,13 @@ size_t layout(const fpm_ctx *c, const Plan &P, char *base, State *st,
     s.nnb = (uint32_t *)take(ns * sizeof(uint32_t));
     s.part = (double *)take((size_t)P.nblk * kSlots * sizeof(double));
     s.ring = (double *)take((size_t)P.nblk * kRingRows * 8 * sizeof(double));
+    if (c->sym) {
+        const size_t ent = (size_t)ns * cap4_for(c->cap) * 4;
+        s.sbuf = (double *)take(ent * sizeof(double));
+        s.tsym = (uint16_t *)take(ent * sizeof(uint16_t));
+        s.plo = (int32_t *)take(ns * sizeof(int32_t));
+        s.fown = (double *)take((size_t)ns * 3 * sizeof(double));
+    }
     s.aux = (float4 *)take(ns * sizeof(float4));
     for (int k = 0; k < 2; k++) s.old[k] = (float4 *)take(ns * sizeof(float4));
     if (c->dem_cap > 0) {
@@ -231,6 +240,7 @@ hipError_t refresh_lists(fpm_ctx *c, bool defer_import = false) {
     const bool exp = c->dem_cap > 0 && !c->dem_exported;
     e = timed(c, "cell_build", [&] { return launch_cell_build(c, exp); });
     if (e == hipSuccess) e = timed(c, "verlet_build", [&] { return launch_verlet_build(c); });
+    if (e == hipSuccess && c->sym) e = launch_sym_index(c);
     if (e == hipSuccess && c->dem_cap > 0) {
         if (!defer_import) e = launch_dem_import(c);
         c->dem_exported = false;
@@ -836,6 +846,17 @@ int fpm_sph_step(fpm_ctx *c, const fpm_sph_params *p, int32_t nsteps, double *hi
     return FPM_OK;
 }
 
+int fpm_set_symmetric(fpm_ctx *c, int32_t on) {
+    if (!c) return FPM_EINVAL;
+    if (on != 0 && on != 1) return fail(c, FPM_EINVAL, "on must be 0 or 1");
+    if (on && c->dem_cap > 0) return fail(c, FPM_EINVAL, "symmetric lists are for LJ, not DEM");
+    if (on && c->cap > 4096) return fail(c, FPM_EINVAL, "list capacity too large");
+    c->sym = on != 0;
+    c->have_particles = false;
+    drop_graphs(c);
+    return FPM_OK;
+}
+
 int fpm_set_dem(fpm_ctx *c, int32_t max_contacts) {
     if (!c) return FPM_EINVAL;
     if (max_contacts < 1 || max_contacts > 64) return fail(c, FPM_EINVAL, "max_contacts is 1..64");
@@ -928,6 +949,7 @@ int fpm_check(fpm_ctx *c) {
     HIPCHK(c, hipMemcpyAsync(&h, c->st.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (h.overflow) return fail(c, FPM_EOVERFLOW, "Verlet list exceeded max_nbr");
+    if (h.sym_miss) return fail(c, FPM_EOVERFLOW, "symmetric lists: a pair missing from one side");
     if (h.nonfinite) return fail(c, FPM_ENONFINITE, "non-finite position or force");
     return FPM_OK;
 }

@@ -83,7 +83,7 @@ constexpr int kScanTile = 4096;
 // The eighth-of-cell table of system d, which only the lockstep Verlet build
 // reads (null for systems built another way).
 __device__ __forceinline__ int32_t *eighths(const State &st, const SysDesc &d) {
-    return d.zb == -4 ? st.sub + (int64_t)d.cell_base * 8 : nullptr;
+    return d.zb == -4 || d.zb == -5 ? st.sub + (int64_t)d.cell_base * 8 : nullptr;
 }
 constexpr int64_t kScanDeviceCells = 16384;  // a single system with more cells scans device-wide
 
@@ -233,7 +233,7 @@ __global__ void k_rank_gather(State st) {
             zprev = before ? fmaxf(zprev, oz) : zprev;
         }
         const int f = beg + r;
-        if (d.zb == -4) {
+        if (d.zb == -4 || d.zb == -5) {
             const int nz = d.box.nc[2];
             const int iz = (c - d.cell_base) % nz;
             const float inv = d.box.inv[2];

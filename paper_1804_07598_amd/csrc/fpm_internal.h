@@ -91,7 +91,7 @@ struct Ctl {
     int32_t overflow;       // a list length above the capacity (sticky), else 0
     int32_t nonfinite;      // 1 once a non-finite value was seen (sticky)
     int32_t max_count;      // longest list (filled on request)
-    int32_t pad0;
+    int32_t sym_miss;       // symmetric lists: a partner's list lacked the pair (sticky)
     int64_t total_count;    // total list entries (filled on request)
     float sph_dt;           // SPH time step of the next step (from the latest rates)
     float sph_dt_last;      // SPH time step of the last completed step
@@ -133,6 +133,10 @@ struct State {
     const int32_t *blk2sys; // particle workgroup -> system
     const int32_t *item2sys;  // column-build work item -> system
     double *ring;           // step loops: per-step partials U, W6, KE, ring[(row * 8 + k) * pstride + block]
+    double *sbuf;           // symmetric lists: pair force factor per list entry
+    uint16_t *tsym;         // symmetric lists: per lower entry, the pair's position in the partner's list
+    int32_t *plo;           // symmetric lists: entries below the slot itself (lists ascend)
+    double *fown;           // symmetric lists: each slot's own pair sum (3 per slot)
     int32_t nsys;
     int32_t pstride;        // number of particle workgroups
     int32_t par;            // rebuild flag copy this launch reads (see SysCtl)
@@ -214,6 +218,7 @@ struct fpm_ctx {
     double *s_hist = nullptr;
     bool sph_restart = true;           // the SPH step count restarts at the next step call
     int dem_cap = 0;                   // DEM contact slots per grain (0: DEM off)
+    bool sym = false;                  // LJ forces from symmetric half lists (fpm_set_symmetric)
     bool dem_exported = false;         // DEM: the caller-keyed rows already hold the history
     hipGraphExec_t d_chunk = nullptr, d_one = nullptr;  // DEM step graphs
     fpm_dem_params d_prm{};
@@ -255,6 +260,8 @@ hipError_t launch_lj_step(fpm_ctx *c, const fpm_lj_params &p, float dt, bool las
 // Reduces ring rows 0 .. nrows-1 of every system into thermo rows (rows may be
 // null) ending at the system's step counter.
 hipError_t launch_finalize_rows(fpm_ctx *c, int nrows, double *rows);
+// Symmetric half lists: transpose positions at a rebuild (gated).
+hipError_t launch_sym_index(fpm_ctx *c);
 // Output of the force VJP kernel.  kVjpPlain: gx = g.  kVjpLast: gx += g.
 // kVjpStep: one reverse velocity-Verlet step on caller-order FP64 arrays:
 // gx (= xbar) += g; vbar += dt xbar; fbar = dt/2 vbar + floss (floss may be null).

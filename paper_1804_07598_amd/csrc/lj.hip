@@ -455,6 +455,240 @@ __global__ __launch_bounds__(kBlock) void k_lj_vjp(State st, float rc2, double r
     block_partials<6>(v, slot, op, st.part, st.pstride);
 }
 
+// ---------------------------------------------------------------------------
+// Symmetric half lists (the section 4.1 listing's getCellListSym and
+// applyKernel_in_sym: every pair evaluated once, its reaction given to the
+// partner, the ghost_put of section 3.4).  Lists hold every neighbour in
+// ascending slot order, so the partners above slot i are its entries from
+// plo[i] on and those below it the first plo[i].  At a rebuild k_sym_index
+// finds, for each lower entry m of slot j (partner i < j), the position of j
+// in i's list by bisection of that sorted list.  Pass 1 evaluates each pair
+// once, at its lower slot i: the force factor s (0 off the force set) goes to
+// i's list entry, s (x_i - x_j) into i's own sum, the pair energy and virial
+// into the partials.  Pass 2 adds to every slot j the reactions
+// s_ij (x_j - x_i) of its lower partners, read through the transpose
+// positions, in list order, and applies the step's velocity-Verlet updates.
+// There are no atomics and every sum has a fixed order, so results repeat
+// bit for bit.
+
+__global__ __launch_bounds__(kBlock) void k_sym_index(State st, int cap, int cap4) {
+    const int s = block_system(st);
+    if (!rebuilding(st, s)) return;
+    const SysDesc &d = st.sys[s];
+    const int64_t j = global_slot();
+    if (j - d.slot_base >= d.n) {
+        st.plo[j] = 0;
+        return;
+    }
+    const int cnt = min((int)(st.nnb[j] & ~kWrapBit), cap);
+    const int32_t *__restrict__ nbr = st.nbr;
+    int lo = 0, hi = cnt;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (nbr[nbr_index(j, mid, cap4)] < (int)j) lo = mid + 1;
+        else hi = mid;
+    }
+    st.plo[j] = lo;
+    bool miss = false;
+    for (int m = 0; m < lo; m++) {
+        const int i = nbr[nbr_index(j, m, cap4)];
+        const int ci = min((int)(st.nnb[i] & ~kWrapBit), cap);
+        int a = 0, b = ci;
+        while (a < b) {
+            const int mid = (a + b) >> 1;
+            if (nbr[nbr_index(i, mid, cap4)] < (int)j) a = mid + 1;
+            else b = mid;
+        }
+        miss |= a >= ci || nbr[nbr_index(i, a, cap4)] != (int)j;
+        st.tsym[nbr_index(j, m, cap4)] = (uint16_t)(a < ci ? a : 0);
+    }
+    if (miss) st.ctl->sym_miss = 1;
+}
+
+// Exact FP64 separation x_i - x_j for the image the FP32 predicate takes.
+template <bool IMG>
+__device__ __forceinline__ void pair_sep(float3 pi, double xi, double yi, double zi, float4 q,
+                                         const Box &b, double &dx, double &dy, double &dz) {
+    dx = xi - (double)q.x;
+    dy = yi - (double)q.y;
+    dz = zi - (double)q.z;
+    if (IMG) {
+        const float tx = q.x - pi.x, ty = q.y - pi.y, tz = q.z - pi.z;
+        const double Lx = b.per[0] ? (double)b.L[0] : 0.0, Ly = b.per[1] ? (double)b.L[1] : 0.0,
+                     Lz = b.per[2] ? (double)b.L[2] : 0.0;
+        dx += tx > b.half[0] ? Lx : (tx < -b.half[0] ? -Lx : 0.0);
+        dy += ty > b.half[1] ? Ly : (ty < -b.half[1] ? -Ly : 0.0);
+        dz += tz > b.half[2] ? Lz : (tz < -b.half[2] ? -Lz : 0.0);
+    }
+}
+
+template <int NT, bool IMG>
+__device__ __forceinline__ void sym_upper(const State &st, int64_t i, int p0, int cnt, float4 pi4,
+                                          const Box &b, float rc2, double rc2lo, double rc2hi,
+                                          const LJCoef &cf, int cap4, double (&f)[3], double &u,
+                                          double (&w)[6]) {
+    const float3 pi = xyz(pi4);
+    const double xi = pi.x, yi = pi.y, zi = pi.z;
+    const int ti = __float_as_int(pi4.w);
+    const float4 *__restrict__ pos = st.pos[0];
+    const int4 *lst = reinterpret_cast<const int4 *>(st.nbr) + ((i >> 6) * (int64_t)cap4) * 64 +
+                      (i & 63);
+    for (int g = p0 >> 2; g * 4 < cnt; g++) {
+        const int4 e = lst[g * 64];
+        const int jj[4] = {e.x, e.y, e.z, e.w};
+        float4 q[4];
+#pragma unroll
+        for (int t = 0; t < 4; t++) q[t] = pos[jj[t]];
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            const int k = 4 * g + t;
+            if (k < p0 || k >= cnt) continue;
+            double dx, dy, dz, sx, sy, sz, sv = 0.0;
+            if (separation<IMG>(pi, xi, yi, zi, q[t], b, rc2, rc2lo, rc2hi, dx, dy, dz, sx, sy,
+                                sz)) {
+                double c12, c6;
+                coef<NT>(cf, pair_type<NT>(ti, q[t]), c12, c6);
+                const double r2i = recip(fma(dx, dx, fma(dy, dy, dz * dz)));
+                const double r6i = r2i * r2i * r2i;
+                sv = r6i * r2i * fma(12.0 * c12, r6i, -6.0 * c6);
+                u = fma(r6i, fma(c12, r6i, -c6), u);
+                const double fx = sv * dx, fy = sv * dy, fz = sv * dz;
+                f[0] += fx;
+                f[1] += fy;
+                f[2] += fz;
+                w[0] = fma(dx, fx, w[0]);
+                w[1] = fma(dy, fy, w[1]);
+                w[2] = fma(dz, fz, w[2]);
+                w[3] = fma(dx, fy, w[3]);
+                w[4] = fma(dx, fz, w[4]);
+                w[5] = fma(dy, fz, w[5]);
+            }
+            st.sbuf[nbr_index(i, k, cap4)] = sv;
+        }
+    }
+}
+
+// Pass 1 (see above): each pair at its lower slot.
+template <int NT>
+__global__ __launch_bounds__(kBlock) void k_lj_sym1(State st, float rc2, double rc2lo,
+                                                    double rc2hi, LJCoef cf, int cap, int cap4,
+                                                    double *part) {
+    const SysDesc &d = st.sys[block_system(st)];
+    const Box b = d.box;
+    const int64_t i = global_slot();
+    const bool active = i - d.slot_base < d.n;
+    uint32_t nn = 0;
+    int p0 = 0;
+    float4 pi4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (active) {
+        nn = st.nnb[i];
+        p0 = st.plo[i];
+        pi4 = st.pos[0][i];
+    }
+    const bool img_wave = __ballot((nn & kWrapBit) != 0) != 0;
+    const int cnt = min((int)(nn & ~kWrapBit), cap);
+    double f[3] = {0.0, 0.0, 0.0}, u = 0.0, w[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (img_wave)
+        sym_upper<NT, true>(st, i, p0, cnt, pi4, b, rc2, rc2lo, rc2hi, cf, cap4, f, u, w);
+    else
+        sym_upper<NT, false>(st, i, p0, cnt, pi4, b, rc2, rc2lo, rc2hi, cf, cap4, f, u, w);
+    if (active)
+        for (int c = 0; c < 3; c++) st.fown[3 * i + c] = f[c];
+    double v[7] = {u, w[0], w[1], w[2], w[3], w[4], w[5]};
+    const int slot[7] = {0, 1, 2, 3, 4, 5, 6};
+    const int op[7] = {0, 0, 0, 0, 0, 0, 0};
+    block_partials<7>(v, slot, op, part, st.pstride);
+}
+
+template <bool IMG>
+__device__ __forceinline__ void sym_lower(const State &st, int64_t j, int p, float4 pj4,
+                                          const Box &b, int cap4, double (&f)[3]) {
+    const float3 pj = xyz(pj4);
+    const double xj = pj.x, yj = pj.y, zj = pj.z;
+    const float4 *__restrict__ pos = st.pos[0];
+    const int4 *lst = reinterpret_cast<const int4 *>(st.nbr) + ((j >> 6) * (int64_t)cap4) * 64 +
+                      (j & 63);
+    const ushort4 *tl = reinterpret_cast<const ushort4 *>(st.tsym) +
+                        ((j >> 6) * (int64_t)cap4) * 64 + (j & 63);
+    for (int g = 0; g * 4 < p; g++) {
+        const int4 e = lst[g * 64];
+        const ushort4 t4 = tl[g * 64];
+        const int ii[4] = {e.x, e.y, e.z, e.w};
+        const int kk[4] = {t4.x, t4.y, t4.z, t4.w};
+        float4 q[4];
+        double sv[4];
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            const bool ok = 4 * g + t < p;
+            q[t] = pos[ok ? ii[t] : j];
+            sv[t] = ok ? st.sbuf[nbr_index(ii[t], kk[t], cap4)] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            if (4 * g + t >= p) continue;
+            double dx, dy, dz;
+            pair_sep<IMG>(pj, xj, yj, zj, q[t], b, dx, dy, dz);
+            f[0] = fma(sv[t], dx, f[0]);
+            f[1] = fma(sv[t], dy, f[1]);
+            f[2] = fma(sv[t], dz, f[2]);
+        }
+    }
+}
+
+// Pass 2 (see above): reactions from the lower partners, then the forces and
+// (MODE kLjStep, kLjLast) the step's updates as in k_lj.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_lj_sym2(State st, int cap4, StepArgs sa) {
+    const int sys = block_system(st);
+    const SysDesc &d = st.sys[sys];
+    const Box b = d.box;
+    const int64_t i = global_slot();
+    const bool active = i - d.slot_base < d.n;
+    uint32_t nn = 0;
+    int p = 0;
+    float4 pi4 = make_float4(0.f, 0.f, 0.f, 0.f), v4 = pi4, xb4 = pi4;
+    double f[3] = {0.0, 0.0, 0.0};
+    if (active) {
+        nn = st.nnb[i];
+        p = st.plo[i];
+        pi4 = st.pos[0][i];
+        if (MODE != kLjForce) v4 = st.vel[0][i];
+        if (MODE == kLjStep) xb4 = st.xbuild[i];
+        for (int c = 0; c < 3; c++) f[c] = st.fown[3 * i + c];
+    }
+    if (__ballot((nn & kWrapBit) != 0) != 0)
+        sym_lower<true>(st, i, p, pi4, b, cap4, f);
+    else
+        sym_lower<false>(st, i, p, pi4, b, cap4, f);
+    double ke = 0.0;
+    bool over = false;
+    if (active) {
+        const float4 fo = make_float4((float)f[0], (float)f[1], (float)f[2], 0.f);
+        st.frc[i] = fo;
+        if (!isfinite(f[0]) || !isfinite(f[1]) || !isfinite(f[2])) st.ctl->nonfinite = 1;
+        if (MODE != kLjForce)
+            ke = kick_drift<MODE>(st, d, i, fo, pi4, v4, xb4, sa.dt, sa.thr, over);
+    }
+    if (MODE != kLjForce) {
+        SysCtl *sc = st.sctl + sys;
+        if (MODE == kLjStep) {
+            const uint64_t m = __ballot(over);
+            if (m && (int)(threadIdx.x & 63) == __ffsll((long long)m) - 1)
+                sc->rebuild[st.par ^ 1] = 1;
+        }
+        if (threadIdx.x == 0 && pblock() == d.blk_base) {
+            if (sc->rebuild[st.par]) {
+                sc->n_rebuilds += 1;
+                sc->rebuild[st.par] = 0;
+            }
+            sc->step += 1;
+        }
+        double v1[1] = {ke};
+        const int s1[1] = {7}, o1[1] = {0};
+        block_partials<1>(v1, s1, o1, sa.ring, st.pstride);
+    }
+}
+
 LJCoef make_coef(const fpm_lj_params &p) {
     LJCoef cf;
     for (int k = 0; k < 3; k++) {
@@ -498,17 +732,53 @@ void launch_lj_mode(fpm_ctx *c, const fpm_lj_params &p, const StepArgs &sa) {
 
 }  // namespace
 
+namespace {
+
+// The two passes over symmetric half lists; pass 1's partials go to `part`
+// (the force partials, or the step's ring row).
+template <int MODE>
+void launch_sym_mode(fpm_ctx *c, const fpm_lj_params &p, const StepArgs &sa, double *part) {
+    const LJCoef cf = make_coef(p);
+    const double band = predicate_band(c);
+    const double rc2lo = (double)c->rc2 * (1.0 - band), rc2hi = (double)c->rc2 * (1.0 + band);
+    const dim3 g((unsigned)c->nblk), t(kBlock);
+    if (p.n_types == 2)
+        hipLaunchKernelGGL(k_lj_sym1<2>, g, t, 0, c->stream, c->st, c->rc2, rc2lo, rc2hi, cf,
+                           c->cap, c->cap4, part);
+    else
+        hipLaunchKernelGGL(k_lj_sym1<1>, g, t, 0, c->stream, c->st, c->rc2, rc2lo, rc2hi, cf,
+                           c->cap, c->cap4, part);
+    hipLaunchKernelGGL(k_lj_sym2<MODE>, g, t, 0, c->stream, c->st, c->cap4, sa);
+}
+
+}  // namespace
+
 hipError_t launch_lj_forces(fpm_ctx *c, const fpm_lj_params &p) {
-    launch_lj_mode<kLjForce>(c, p, StepArgs{0.f, 0.f, nullptr});
+    if (c->sym)
+        launch_sym_mode<kLjForce>(c, p, StepArgs{0.f, 0.f, nullptr}, c->st.part);
+    else
+        launch_lj_mode<kLjForce>(c, p, StepArgs{0.f, 0.f, nullptr});
     return hipGetLastError();
 }
 
 hipError_t launch_lj_step(fpm_ctx *c, const fpm_lj_params &p, float dt, bool last, int row) {
     const StepArgs sa{dt, c->disp2_thr, c->st.ring + (size_t)row * 8 * c->st.pstride};
-    if (last)
+    if (c->sym) {
+        if (last)
+            launch_sym_mode<kLjLast>(c, p, sa, sa.ring);
+        else
+            launch_sym_mode<kLjStep>(c, p, sa, sa.ring);
+    } else if (last) {
         launch_lj_mode<kLjLast>(c, p, sa);
-    else
+    } else {
         launch_lj_mode<kLjStep>(c, p, sa);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sym_index(fpm_ctx *c) {
+    hipLaunchKernelGGL(k_sym_index, dim3(c->nblk), dim3(kBlock), 0, c->stream, c->st, c->cap,
+                       c->cap4);
     return hipGetLastError();
 }
 

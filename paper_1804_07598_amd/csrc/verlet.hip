@@ -1074,7 +1074,31 @@ __global__ __launch_bounds__(kBlock) void k_verlet_ls(State st, const int32_t *b
         }
     };
     const Piece none{0, 0};
-    if (!zwrap) {
+    // symmetric-list systems need every list in ascending slot order: each
+    // lane walks its pieces sorted by their first slot (a window is one
+    // ascending slot range and windows do not overlap)
+    const bool sorted = d.zb == -5;
+    int ord[18];
+#pragma unroll
+    for (int t = 0; t < 18; t++) ord[t] = t;
+    if (sorted) {
+        int key[18];
+#pragma unroll
+        for (int t = 0; t < 18; t++) key[t] = w[t / 2][t % 2].len > 0 ? w[t / 2][t % 2].lo : INT_MAX;
+        // odd-even transposition sort of (key, piece) pairs
+#pragma unroll
+        for (int r = 0; r < 18; r++)
+#pragma unroll
+            for (int t = r & 1; t + 1 < 18; t += 2) {
+                const bool sw = key[t + 1] < key[t];
+                const int k0 = key[t], o0 = ord[t];
+                key[t] = sw ? key[t + 1] : k0;
+                ord[t] = sw ? ord[t + 1] : o0;
+                key[t + 1] = sw ? k0 : key[t + 1];
+                ord[t + 1] = sw ? o0 : ord[t + 1];
+            }
+    }
+    if (!zwrap && !sorted) {
         // pairs of opposite columns, then the particle's own column
 #pragma unroll
         for (int pr = 0; pr < 4; pr++)
@@ -1084,7 +1108,10 @@ __global__ __launch_bounds__(kBlock) void k_verlet_ls(State st, const int32_t *b
         // general form: every piece of every column on its own (one copy of
         // the walk; the piece is picked from registers by a select chain)
 #pragma unroll 1
-        for (int kg = 0; kg < 18; kg++) {
+        for (int q = 0; q < 18; q++) {
+            int kg = 0;
+#pragma unroll
+            for (int t = 0; t < 18; t++) kg = t == q ? ord[t] : kg;
             Piece P = none;
             bool shk = false;
 #pragma unroll

@@ -34,7 +34,7 @@ class _Sim:
     """Context, workspace and the calls shared by single systems and batches."""
 
     def _open(self, pos, vel, typ, r_cut, skin, max_nbr, device, set_boxes, tuning,
-              dem_contacts=0):
+              dem_contacts=0, symmetric=False):
         self.device = torch.device(device)
         self.pos0 = _as(pos, torch.float32, self.device)
         self.n = int(self.pos0.shape[0])
@@ -47,6 +47,9 @@ class _Sim:
         self.dem_contacts = int(dem_contacts)
         if self.dem_contacts:
             F.fpm_set_dem(self.ctx, self.dem_contacts)
+        self.symmetric = bool(symmetric)
+        if self.symmetric:
+            F.fpm_set_symmetric(self.ctx, True)
         if tuning is not None:
             F.fpm_set_tuning(self.ctx, *tuning)
         self._load(self.pos0, self._vel)
@@ -167,7 +170,7 @@ class ParticleSim(_Sim):
 
     def __init__(self, pos, L, periodic=(1, 1, 1), *, vel=None, typ=None, r_cut: float = 2.5,
                  skin: float = 0.3, max_nbr: int | None = None, device="cuda", tuning=None,
-                 dem_contacts: int = 0):
+                 dem_contacts: int = 0, symmetric: bool = False):
         self.L = [float(x) for x in (L if hasattr(L, "__len__") else (L, L, L))]
         self.periodic = tuple(int(p) for p in periodic)
         self.nsys = 1
@@ -175,7 +178,8 @@ class ParticleSim(_Sim):
         if max_nbr is None:
             max_nbr = default_max_nbr(n, self.L[0] * self.L[1] * self.L[2], r_cut + skin)
         self._open(pos, vel, typ, r_cut, skin, max_nbr, device,
-                   lambda: F.fpm_set_box(self.ctx, self.L, self.periodic), tuning, dem_contacts)
+                   lambda: F.fpm_set_box(self.ctx, self.L, self.periodic), tuning, dem_contacts,
+                   symmetric)
 
     def cell_list(self):
         """(ncell, offsets, order): grid, exclusive scan of counts, slot -> caller index."""
@@ -251,7 +255,7 @@ class BatchSim(_Sim):
 
     def __init__(self, pos_list, L_list, periodic=(1, 1, 1), *, vel_list=None, typ_list=None,
                  r_cut: float = 2.5, skin: float = 0.3, max_nbr: int | None = None,
-                 device="cuda", tuning=None):
+                 device="cuda", tuning=None, symmetric: bool = False):
         self.nsys = len(pos_list)
         self.counts = [len(p) for p in pos_list]
         self.L = [[float(x) for x in (L if hasattr(L, "__len__") else (L, L, L))]
@@ -270,7 +274,7 @@ class BatchSim(_Sim):
                           for c, L in zip(self.counts, self.L))
         self._open(pos, vel, typ, r_cut, skin, max_nbr, device,
                    lambda: F.fpm_set_systems(self.ctx, self.L, self.periodic, self.counts),
-                   tuning)
+                   tuning, 0, symmetric)
 
     def system_info(self, s: int):
         """{n, first caller index, cells, first offsets entry, nc_x, nc_y, nc_z, zblock}."""
