@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "LJ atom-steps/s at 1M particles, %HBM roofline; batched & adjoint vs plain"
-PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "lj_force_lj1m_counters.txt")
+PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "lj_step_lj1m_counters.txt")
 # the sources the force kernel is compiled from
 LJ_SOURCES = [os.path.join(ROOT, "paper_1804_07598_amd", "csrc", f)
               for f in ("lj.hip", "geom.h", "fpm_internal.h")]
@@ -67,27 +67,65 @@ def stored_traffic(n_launch_atoms: int, unroll: int):
         return None
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(pos, box, target_s: float, quiet: bool):
     """The FP64 O(N^2) oracle on a bounded sample: forces of R random atoms
-    against all N atoms, timed on the host's cores."""
+    against all N atoms, timed on the host's cores (median of three timings of
+    the same sample), plus the small configurations in full: the 4096-atom
+    liquid's force evaluation and 10 velocity-Verlet steps, and one force
+    evaluation of the 32,768-atom mixture."""
     import numpy as np
     import oracle as O
+    from paper_1804_07598_amd import inputs
     rc2 = O.radius2(2.5)
     rng = np.random.default_rng(0)
     R = 64
     O.lj(pos, box, (1, 1, 1), rc2, rows=rng.choice(len(pos), R, replace=False))  # warm
+    per_run = target_s / 3.0
     while True:
         rows = rng.choice(len(pos), R, replace=False)
         t0 = time.perf_counter()
         O.lj(pos, box, (1, 1, 1), rc2, rows=rows)
         dt = time.perf_counter() - t0
-        if dt >= target_s or R >= len(pos):
+        if dt >= per_run or R >= len(pos):
             break
-        R = min(len(pos), max(R * 2, int(R * target_s / max(dt, 1e-3) * 1.1)))
+        R = min(len(pos), max(R * 2, int(R * per_run / max(dt, 1e-3) * 1.1)))
         log(f"cpu baseline: trying {R} rows", quiet)
-    return {"value": R / dt, "unit": "atom-steps/s", "cores": O.num_threads(), "kind": "oracle",
+    times = [dt]
+    for _ in range(2):
+        t0 = time.perf_counter()
+        O.lj(pos, box, (1, 1, 1), rc2, rows=rows)
+        times.append(time.perf_counter() - t0)
+    med = float(np.median(times))
+    # the 4096-atom case in full: one evaluation and 10 steps (11 evaluations)
+    s1 = inputs.lj_config("lj4096")
+    t0 = time.perf_counter()
+    O.lj_traj(s1.pos, s1.vel, s1.box, (1, 1, 1), 2.5, 0.005, 10)
+    t_cfg1 = time.perf_counter() - t0
+    s5 = inputs.lj_lattice(32768, 1.2, 1.0, 5, mixture=True)
+    M = inputs.LJ_MIXTURE
+    t0 = time.perf_counter()
+    O.lj(s5.pos, s5.box, (1, 1, 1), rc2, M["eps"], M["sig"], s5.typ)
+    t_cfg5 = time.perf_counter() - t0
+    return {"value": R / med, "unit": "atom-steps/s", "cores": O.num_threads(), "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"{R} random atoms' LJ forces against all {len(pos)} atoms (FP32 predicate, "
-                      f"FP64 physics) at the initial configuration; {dt:.1f} s"}
+                      f"FP64 physics) at the initial configuration; median of 3 timings "
+                      f"({', '.join(f'{t:.1f}' for t in times)} s)",
+            "full_cases": {
+                "lj4k_1_eval_10_steps_s": t_cfg1,
+                "lj4k_atom_steps_per_s": s1.n * 11 / t_cfg1,
+                "mix32k_1_eval_s": t_cfg5,
+                "mix32k_pair_tests_per_s": 32768.0 * 32768.0 / t_cfg5}}
 
 
 def dem_cpu_baseline(s, oprm, target_s: float, quiet: bool):
@@ -114,6 +152,27 @@ def dem_cpu_baseline(s, oprm, target_s: float, quiet: bool):
                       f"grains (FP64) at the initial configuration; {dt:.1f} s"}
 
 
+def copy_rate(dev, mib: int = 1024) -> float:
+    """Achievable HBM rate: GB/s (read + written bytes) of a device-to-device
+    copy of `mib` MiB, the best of five, HIP events."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(5):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del src, dst
+    return 2.0 * 4 * n / (best / 1e3) / 1e9
+
+
 def timed_steps(sim, nsteps, dt, warmup, eps=(1.0,) * 3, sig=(1.0,) * 3, n_types=1):
     """Milliseconds of nsteps graph-launched steps after warmup steps (HIP events
     on the stream the library launches on)."""
@@ -128,6 +187,34 @@ def timed_steps(sim, nsteps, dt, warmup, eps=(1.0,) * 3, sig=(1.0,) * 3, n_types
     torch.cuda.synchronize()
     sim.check()
     return e0.elapsed_time(e1)
+
+
+def bench_symmetric(dev, nsteps: int, quiet: bool, plain_value: float):
+    """The 1M-atom liquid with symmetric half lists (each pair evaluated once,
+    reactions gathered in a second pass): step rate and both passes' time."""
+    from paper_1804_07598_amd import _lib as F
+    from paper_1804_07598_amd import inputs
+    from paper_1804_07598_amd.sim import ParticleSim
+    s = inputs.lj_config("lj1m")
+    sim = ParticleSim(s.pos, s.box, (1, 1, 1), vel=s.vel, r_cut=2.5, skin=0.3, device=dev,
+                      symmetric=True)
+    ms = timed_steps(sim, nsteps, 0.005, 20)
+    F.fpm_set_profiling(sim.ctx, True)
+    for _ in range(20):
+        sim.lj_forces()
+    f_ms, _ = F.fpm_kernel_time(sim.ctx, "lj_force")
+    F.fpm_kernel_time(sim.ctx, "cell_build")
+    F.fpm_kernel_time(sim.ctx, "verlet_build")
+    F.fpm_set_profiling(sim.ctx, False)
+    sim.check()
+    sim.close()
+    value = s.n * nsteps / (ms / 1e3)
+    log(f"symmetric lists: {ms / nsteps * 1e3:.1f} us/step ({value:.3g} atom-steps/s), "
+        f"both passes {f_ms * 1e3:.1f} us", quiet)
+    return {"workload": "lj1m with symmetric half lists (each pair once, reactions gathered)",
+            "steps": nsteps, "value": value, "unit": "atom-steps/s",
+            "ms_per_step": ms / nsteps, "force_passes_us": f_ms * 1e3,
+            "vs_full_lists": value / plain_value}
 
 
 def bench_batched(dev, nsteps: int, quiet: bool):
@@ -417,7 +504,8 @@ def main(argv=None) -> int:
                     help="keep the library's default launch shapes")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched and adjoint measurements")
-    ap.add_argument("--form", choices=["batched", "sph", "sph_dambreak", "adjoint", "dem"],
+    ap.add_argument("--form", choices=["batched", "sph", "sph_dambreak", "adjoint", "dem",
+                                       "symmetric"],
                     help="run only this form's measurement and print its JSON (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer 5 times (reference for the "
@@ -449,6 +537,7 @@ def main(argv=None) -> int:
         return 0
     if a.form:
         legs = {"batched": lambda: bench_batched(dev, 100, a.quiet),
+                "symmetric": lambda: bench_symmetric(dev, 200, a.quiet, float("nan")),
                 "sph": lambda: bench_sph(dev, 500, a.quiet),
                 "sph_dambreak": lambda: bench_dambreak(dev, a.quiet),
                 "adjoint": lambda: bench_adjoint(dev, a.quiet),
@@ -516,9 +605,24 @@ def main(argv=None) -> int:
     nbar_k = total2 / s.n
     bytes_force = s.n * (36.0 + 4.0 * nbar_k)
     achieved = bytes_force / (f_ms / 1e3) / 1e9
-    traffic = stored_traffic(s.n, knobs[2] or 8)  # unroll 0 = automatic = 8
     log(f"force kernel {f_ms * 1e3:.1f} us over {f_n} launches -> {achieved:.0f} GB/s; "
         f"cell build {c_ms * 1e3:.1f} us, Verlet build {v_ms * 1e3:.1f} us", a.quiet)
+
+    # the step's own force kernel (forces fused with the kicks and the drift):
+    # the same steps issued without graphs, each launch timed with events
+    F.fpm_set_profiling(sim.ctx, True)
+    sim.step(a.kernel_reps, dt=dt, thermo=thermo)
+    s_ms, s_n = F.fpm_kernel_time(sim.ctx, "lj_step")
+    F.fpm_kernel_time(sim.ctx, "cell_build")
+    F.fpm_kernel_time(sim.ctx, "verlet_build")
+    F.fpm_set_profiling(sim.ctx, False)
+    sim.check()
+    bytes_step = s.n * (100.0 + 4.0 * nbar_k)
+    achieved_step = bytes_step / (s_ms / 1e3) / 1e9
+    traffic = stored_traffic(s.n, knobs[2] or 8)  # unroll 0 = automatic = 8
+    copy_gbs = copy_rate(dev)
+    log(f"step force kernel {s_ms * 1e3:.1f} us over {s_n} launches -> {achieved_step:.0f} GB/s; "
+        f"device copy {copy_gbs:.0f} GB/s", a.quiet)
 
     B = 132.0 + 4.0 * nbar + (164.0 + 4.0 * nbar) / kbar
     result = {
@@ -539,11 +643,20 @@ def main(argv=None) -> int:
                                "T=1, r_cut=2.5, skin=0.3, dt=0.005, periodic",
                    "n": s.n, "dt": dt, "r_cut": 2.5, "skin": 0.3,
                    "tuning": {"verlet_path": knobs[0], "zblock": knobs[1], "unroll": knobs[2]}},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "lj_force", "kernel_ms": f_ms,
-                     "bytes_per_launch": bytes_force,
-                     "bytes_model": "N*(36 + 4*nbar): pos_i 16, count 4, list 4*nbar, force 16"},
+        "roofline": {"bound": "hbm", "achieved": achieved_step, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved_step / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "lj_step (k_lj<1, 8, 1>: forces, closing kick, next opening "
+                               "kick and drift)", "kernel_ms": s_ms,
+                     "bytes_per_launch": bytes_step,
+                     "bytes_model": "N*(100 + 4*nbar): pos_i 16, count 4, list 4*nbar, force 16, "
+                                    "vel 16 + 16, build position 16, drifted position 16",
+                     "measured_copy_gbs": copy_gbs,
+                     "step_hbm_frac": B * value / (HBM_PEAK_GBS * 1e9)},
+        "force_kernel": {"kernel": "lj_force (k_lj<1, 8, 0>, forces only)", "ms": f_ms,
+                         "bytes_per_launch": bytes_force, "achieved_gbs": achieved,
+                         "frac": achieved / HBM_PEAK_GBS,
+                         "bytes_model": "N*(36 + 4*nbar): pos_i 16, count 4, list 4*nbar, "
+                                        "force 16"},
         "step_model": {"mean_list": nbar, "rebuilds": rebuilds, "rebuild_interval": kbar,
                        "bytes_per_atom_step": B,
                        "hbm_frac": B * value / (HBM_PEAK_GBS * 1e9),
@@ -552,6 +665,7 @@ def main(argv=None) -> int:
     }
     sim.close()
     if not a.no_forms:
+        result["symmetric"] = bench_symmetric(dev, 200, a.quiet, value)
         result["batched"] = bench_batched(dev, 100, a.quiet)
         result["sph"] = bench_sph(dev, 500, a.quiet)
         result["sph_dambreak"] = bench_dambreak(dev, a.quiet)

@@ -349,8 +349,10 @@ int fpm_read_counters(fpm_ctx *ctx, int64_t h_out[3]);
  * 5 one lane per particle with the lanes of a wavefront walking their windows
  * in step (2, 3, 4 and 5 where the grid has >= 3 cells per axis; elsewhere
  * paths 2 and 3 take path 1 and paths 4 and 5 run lane groups over whole
- * cells; automatic takes 3 when max_nbr is at most 48, else 5, and lane
- * groups over whole cells for small grids).  zblock: z-cells per column workgroup (1..64);
+ * cells; automatic takes 3 when max_nbr is at most 48, else 5 for systems of at
+ * least 131,072 particles and 4 for smaller ones, and lane groups over whole
+ * cells for small grids; max_nbr stands in for the list length here, since
+ * the lists are not known before the first build).  zblock: z-cells per column workgroup (1..64);
  * for path 4, lanes per particle (0 = 8, 4, 8 or 16; other values are
  * FPM_EINVAL).  unroll: list entries in
  * flight per lane in the force kernel (4 or 8).  Results do not depend on
@@ -360,8 +362,11 @@ int fpm_set_tuning(fpm_ctx *ctx, int32_t verlet_path, int32_t zblock, int32_t un
 
 /* With on = 1, every launch made outside a graph of the kernels named
  * "lj_force", "lj_vjp", "verlet_build", "cell_build", "integrate", "sph_rates" is
- * bracketed by two HIP events recorded on the context's stream; on = 0 stops
- * recording and drops pending records. */
+ * bracketed by two HIP events recorded on the context's stream, and fpm_step
+ * issues its steps without graphs so that each step's fused force kernel
+ * ("lj_step": forces, closing kick, next opening kick and drift) is timed the
+ * same way (identical results); on = 0 stops recording and drops pending
+ * records. */
 int fpm_set_profiling(fpm_ctx *ctx, int32_t on);
 /* Synchronises, then returns the mean duration in milliseconds (h_ms) and the
  * number (h_count) of the recorded launches of `kernel` since the last call

@@ -57,6 +57,7 @@ bool system_counts(const fpm_ctx *c, int64_t n, std::vector<int64_t> &cnt) {
 }
 
 constexpr int kShortListCap = 48;
+constexpr int64_t kLockstepMinSlots = 131072;  // 512 workgroups: two per CU
 
 Plan make_plan(const fpm_ctx *c, const std::vector<int64_t> &cnt) {
     Plan P;
@@ -74,22 +75,28 @@ Plan make_plan(const fpm_ctx *c, const std::vector<int64_t> &cnt) {
         d.ncells = d.box.nc[0] * d.box.nc[1] * d.box.nc[2];
         d.cell_base = cell;
         d.off_base = offb;
-        // Verlet build: zb > 0 column workgroups, 0 particle by particle over
-        // whole cells, -1 particle by particle over candidate windows, -2 lane
-        // groups over candidate windows, -3 lane groups over whole cells (the
-        // lane-group builds stage rows of lists in LDS)
-        // lane groups (automatic for most lists), lane-per-particle windows when
-        // the list capacity is at most kShortListCap: such lists come from
-        // column runs of a few candidates, which would leave most lanes of a
-        // group idle (688,380 grains, capacity 32, about 6 entries: 89 us per
-        // build against 206 us; at 1M LJ atoms with 76 entries the groups win)
+        // Verlet build of the system (zb): > 0 column workgroups, 0 particle by
+        // particle over whole cells, -1 particle by particle over candidate
+        // windows, -2 lane groups over candidate windows, -3 lane groups over
+        // whole cells, -4 lockstep windows, -5 lockstep windows in ascending
+        // slot order (symmetric half lists).  Automatic choice, with the list
+        // capacity standing in for the list length (unknown before the first
+        // build): capacities up to kShortListCap take -1 (short lists come
+        // from column runs of a few candidates, which would leave most lanes
+        // of a group idle: 688,380 grains, about 6 entries, 89 us against
+        // 206 us); longer lists take -4 for systems of at least
+        // kLockstepMinSlots particles (1M LJ atoms, 76 entries: 452 against
+        // 518 us) and -2 below that, where the lockstep build's one workgroup
+        // per 256 slots would leave the device short of workgroups; grids of
+        // fewer than three cells per axis take -3.
         const bool big = d.box.nc[0] >= 3 && d.box.nc[1] >= 3 && d.box.nc[2] >= 3;
         const bool auto_groups = c->tune_verlet_path == 0 && c->cap > kShortListCap;
+        const bool many = cnt[s] >= kLockstepMinSlots;
         if (c->sym)  // symmetric half lists need lists in ascending slot order
             d.zb = big ? -5 : 0;
         else if (c->tune_verlet_path == 1)
             d.zb = 0;
-        else if (c->tune_verlet_path == 5 || (auto_groups && big))
+        else if (c->tune_verlet_path == 5 || (auto_groups && big && many))
             d.zb = big ? -4 : -3;
         else if (c->tune_verlet_path == 4 || auto_groups)
             d.zb = big ? -2 : -3;
@@ -762,6 +769,22 @@ int fpm_step(fpm_ctx *c, const fpm_lj_params *p, float dt, int32_t nsteps, doubl
     // opening half kick and drift of the first step, its rebuild decision
     HIPCHK(c, launch_integrate(c, dt, kKickDriftFirst));
     HIPCHK(c, launch_finalize(c, kFinDisp, nullptr, nullptr));
+    if (c->profiling) {
+        // the same launches without graphs, each step's force kernel timed
+        // ("lj_step") and its rebuild kernels too ("cell_build", "verlet_build")
+        const fpm_lj_params prm = *p;
+        for (int k = 0; k < nsteps; k++) {
+            const bool last = k == nsteps - 1;
+            HIPCHK(c, with_parity(c, k & 1, [&] {
+                hipError_t x = refresh_lists(c);
+                if (x == hipSuccess)
+                    x = timed(c, "lj_step", [&] { return launch_lj_step(c, prm, dt, last, 0); });
+                return x;
+            }));
+            HIPCHK(c, launch_finalize_rows(c, 1, thermo));
+        }
+        return FPM_OK;
+    }
     // steps 0 .. nsteps-2 fused with the next step's opening, then the last step
     int left = nsteps - 1, step = 0;
     for (int g = 0; g < 4; g++)

@@ -49,20 +49,21 @@ def check_system(sim, k, s, F_all, out, counts, cols, sets=True):
     assert np.abs(out[k, 2:] - W64).max() <= ENERGY_TOL * scale, k
 
 
-@pytest.mark.parametrize("tuning", [None, (2, 0, 8), (3, 0, 8), (4, 8, 8)])
+@pytest.mark.parametrize("tuning", [None, (2, 0, 8), (3, 0, 8), (4, 8, 8), (5, 0, 8)])
 def test_batch_matches_oracle_per_system(tuning):
     idx = list(range(10)) + [72, 130]  # 72 and 130 have boxes of 2 cells per axis
     systems = systems_of(idx)
     sim = make_batch(systems, tuning=tuning)
     # two Verlet build paths occur: whole cells for grids below 3 cells per axis
-    # (lane groups by default and for path 4, -3; particle by particle
-    # otherwise, 0), and above lockstep windows (default, -4), column
-    # workgroups (path 2: z-cells per block), particle-by-particle windows
-    # (path 3: -1) or lane groups (path 4: -2)
+    # (lane groups, -3, by default and for paths 4 and 5; particle by particle,
+    # 0, otherwise), and above lane groups over windows (default for systems
+    # below 131,072 particles and path 4: -2), column workgroups (path 2:
+    # z-cells per block), particle-by-particle windows (path 3: -1) or
+    # lockstep windows (path 5: -4)
     zb = [sim.system_info(k)["zblock"] for k in range(len(idx))]
-    big = {None: lambda z: z == -4, (2, 0, 8): lambda z: z > 0, (3, 0, 8): lambda z: z == -1,
-           (4, 8, 8): lambda z: z == -2}
-    small = -3 if tuning in (None, (4, 8, 8)) else 0
+    big = {None: lambda z: z == -2, (2, 0, 8): lambda z: z > 0, (3, 0, 8): lambda z: z == -1,
+           (4, 8, 8): lambda z: z == -2, (5, 0, 8): lambda z: z == -4}
+    small = -3 if tuning in (None, (4, 8, 8), (5, 0, 8)) else 0
     assert small in zb and any(big[tuning](z) for z in zb)
     off, order = (np_(t) for t in sim.cell_list())
     for k, s in enumerate(systems):
