@@ -219,7 +219,11 @@ int fpm_lj_forces(fpm_ctx *ctx, const fpm_lj_params *prm, double *d_out);
  * overwritten) and ADDS dL/dtheta to d_gtheta[6 s + k] for system s, with
  * theta = (eps_AA, eps_AB, eps_BB, sig_AA, sig_AB, sig_BB) (n_types = 1: only
  * entries 0 and 3 are non-zero; d_gtheta may be NULL).  The pair set is the
- * force set; the cut-off is not differentiated.  Pair terms in FP64. */
+ * force set; the cut-off is not differentiated.  The cotangent is rounded to
+ * FP32 per particle before the pair loop (relative error at most 2^-24 per
+ * component; the neighbour gathers then move 16 bytes per pair, as for the
+ * positions); pair terms and all sums are FP64.  dL/deps is computed from the
+ * unit-depth pair force, so it is exact at eps = 0 too. */
 int fpm_lj_force_vjp(fpm_ctx *ctx, const fpm_lj_params *prm, const double *d_lam, double *d_gx,
                      double *d_gtheta);
 /* One step of the reverse velocity-Verlet recursion (unit mass) at the
@@ -233,6 +237,19 @@ int fpm_lj_force_vjp(fpm_ctx *ctx, const fpm_lj_params *prm, const double *d_lam
 int fpm_lj_adjoint_step(fpm_ctx *ctx, const fpm_lj_params *prm, float dt, const double *d_floss,
                         double *d_xbar, double *d_vbar, double *d_fbar, double *d_gtheta,
                         int32_t last);
+
+/* The reverse sweep over a recomputed segment of nsteps velocity-Verlet steps
+ * (section 4.1's step, differentiated): for k = nsteps - 1 down to 0, the
+ * positions become d_xs + 3 n k (device, caller order, n x 3 FP32 each: the
+ * positions after step k, as fpm_step_record writes them) and one
+ * fpm_lj_adjoint_step follows with d_floss = h_floss[k] (h_floss: host array
+ * of nsteps device pointers, NULL entries for steps without a loss term).
+ * Exactly the launches of the corresponding fpm_set_positions and
+ * fpm_lj_adjoint_step calls, queued without host synchronisation, so results
+ * are identical to those calls.  Velocities are left as they were. */
+int fpm_lj_adjoint_sweep(fpm_ctx *ctx, const fpm_lj_params *prm, float dt, int32_t nsteps,
+                         const float *d_xs, const double *const *h_floss, double *d_xbar,
+                         double *d_vbar, double *d_fbar, double *d_gtheta);
 
 /* ---- time stepping (the getV kick/drift expressions of the listing) ---- */
 
@@ -248,6 +265,13 @@ int fpm_integrate(fpm_ctx *ctx, float dt, int32_t half);
  * d_thermo[8 (t nsys + s)], for the state after step t + 1. */
 int fpm_step(fpm_ctx *ctx, const fpm_lj_params *prm, float dt, int32_t nsteps,
              double *d_thermo);
+/* nsteps steps as nsteps calls fpm_step(ctx, prm, dt, 1, NULL) make them
+ * (identical trajectory), with the caller-order positions after step k
+ * written to d_xs + 3 n k (device, n x 3 FP32 per step); no host
+ * synchronisation.  For the recomputation of a checkpointed segment before
+ * fpm_lj_adjoint_sweep. */
+int fpm_step_record(fpm_ctx *ctx, const fpm_lj_params *prm, float dt, int32_t nsteps,
+                    float *d_xs);
 
 /* ---- SPH (section 4.2) ---- */
 

@@ -9,7 +9,7 @@
  * image), u = |r|^2 and, with the pair's eps and sig,
  *     s(u)    = 24 eps (2 sig^12 u^-7 - sig^6 u^-4)        (section 4.1)
  *     ds/du   = 24 eps (-14 sig^12 u^-8 + 4 sig^6 u^-5)
- *     ds/deps = s / eps
+ *     ds/deps = 24 (2 sig^12 u^-7 - sig^6 u^-4)  (s is linear in eps: defined at eps = 0)
  *     ds/dsig = 24 eps (24 sig^11 u^-7 - 6 sig^5 u^-4).
  * The pair adds f = s r to F_i and -f to F_j.  For a scalar loss with
  * lam_i = dL/dF_i the pair contributes (lam_i - lam_j) . f, so with
@@ -46,10 +46,11 @@ static void pair_terms(const double r[3], const double dl[3], double eps, double
     double s2 = sig * sig, s6 = s2 * s2 * s2, s12 = s6 * s6;
     double s = 24.0 * eps * (2.0 * s12 / pow(u, 7.0) - s6 / pow(u, 4.0));
     double sp = 24.0 * eps * (-14.0 * s12 / pow(u, 8.0) + 4.0 * s6 / pow(u, 5.0));
+    double dsdeps = 24.0 * (2.0 * s12 / pow(u, 7.0) - s6 / pow(u, 4.0));
     double dsdsig = 24.0 * eps * (24.0 * s12 / sig / pow(u, 7.0) - 6.0 * s6 / sig / pow(u, 4.0));
     double rdl = r[0] * dl[0] + r[1] * dl[1] + r[2] * dl[2];
     for (int a = 0; a < 3; a++) g[a] += s * dl[a] + 2.0 * sp * rdl * r[a];
-    th[k] += 0.5 * (s / eps) * rdl;
+    th[k] += 0.5 * dsdeps * rdl;
     th[3 + k] += 0.5 * dsdsig * rdl;
 }
 

@@ -74,6 +74,9 @@ _SIGS = {
     "fpm_lj_force_vjp": [_P, C.POINTER(fpm_lj_params), _P, _P, _P],
     "fpm_lj_adjoint_step": [_P, C.POINTER(fpm_lj_params), C.c_float, _P, _P, _P, _P, _P,
                             C.c_int32],
+    "fpm_lj_adjoint_sweep": [_P, C.POINTER(fpm_lj_params), C.c_float, C.c_int32, _P, _P, _P,
+                             _P, _P, _P],
+    "fpm_step_record": [_P, C.POINTER(fpm_lj_params), C.c_float, C.c_int32, _P],
     "fpm_integrate": [_P, C.c_float, C.c_int32],
     "fpm_step": [_P, C.POINTER(fpm_lj_params), C.c_float, C.c_int32, _P],
     "fpm_sph_rates": [_P, C.POINTER(fpm_sph_params), _P],
@@ -304,6 +307,18 @@ def fpm_lj_adjoint_step(ctx, prm: fpm_lj_params, dt: float, floss, xbar, vbar, f
                         gtheta=None, last: int = 0):
     _call("fpm_lj_adjoint_step", ctx, C.byref(prm), float(dt), _ptr(floss), _ptr(xbar),
           _ptr(vbar), _ptr(fbar), _ptr(gtheta), int(last))
+
+
+def fpm_lj_adjoint_sweep(ctx, prm: fpm_lj_params, dt: float, nsteps: int, xs, floss, xbar,
+                         vbar, fbar, gtheta=None):
+    """floss: a sequence of nsteps device tensors or None (per step)."""
+    tab = (C.c_void_p * max(int(nsteps), 1))(*[_ptr(f) for f in floss])
+    _call("fpm_lj_adjoint_sweep", ctx, C.byref(prm), float(dt), int(nsteps), _ptr(xs), tab,
+          _ptr(xbar), _ptr(vbar), _ptr(fbar), _ptr(gtheta))
+
+
+def fpm_step_record(ctx, prm: fpm_lj_params, dt: float, nsteps: int, xs):
+    _call("fpm_step_record", ctx, C.byref(prm), float(dt), int(nsteps), _ptr(xs))
 
 
 def fpm_integrate(ctx, dt: float, half: int):

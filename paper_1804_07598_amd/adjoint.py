@@ -105,20 +105,21 @@ class LJTrajFn(torch.autograd.Function):
         bounds = [c[0] for c in ctx.ckpts] + [K]
         x_first = None
         prm = F.lj_params(eps, sig, ctx.n_types)
+        xs = None
         for q in range(len(ctx.ckpts) - 1, -1, -1):
             s0, p, v = ctx.ckpts[q]
             s1 = bounds[q + 1]
+            m = s1 - s0
             sim.set_particles(p, v)
-            # the segment's positions, recomputed from its checkpoint
-            xs = torch.empty((s1 - s0 + 1, n, 3), dtype=torch.float32, device=dev)
-            xs[0] = p
-            for j in range(s1 - s0):
-                F.fpm_step(sim.ctx, prm, dt, 1, None)
-                F.fpm_get_particles(sim.ctx, xs[j + 1], None, None)
-            for k in range(s1 - 1, s0 - 1, -1):
-                F.fpm_set_positions(sim.ctx, xs[k + 1 - s0])
-                F.fpm_lj_adjoint_step(sim.ctx, prm, dt, floss.get(k), xbar, vbar, fbar, gt, 0)
-            sim._keep_pos = xs  # the last positions handed in stay alive with the context
+            # the segment's positions after each of its steps, recomputed from
+            # its checkpoint, then its reverse sweep (both queued on the device
+            # without host round trips)
+            if xs is None or xs.shape[0] < m:
+                xs = torch.empty((m, n, 3), dtype=torch.float32, device=dev)
+            F.fpm_step_record(sim.ctx, prm, dt, m, xs)
+            F.fpm_lj_adjoint_sweep(sim.ctx, prm, dt, m, xs, [floss.get(k) for k in range(s0, s1)],
+                                   xbar, vbar, fbar, gt)
+            sim._keep_pos = xs  # the positions handed in stay alive with the context
             x_first = p
         if x_first is None:  # no steps: the loss sees F_0 only
             x_first = ctx.ckpts[0][1] if ctx.ckpts else None

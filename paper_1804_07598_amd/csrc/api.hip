@@ -715,6 +715,31 @@ int fpm_lj_adjoint_step(fpm_ctx *c, const fpm_lj_params *p, float dt, const doub
     return FPM_OK;
 }
 
+int fpm_lj_adjoint_sweep(fpm_ctx *c, const fpm_lj_params *p, float dt, int32_t nsteps,
+                         const float *xs, const double *const *floss, double *xbar,
+                         double *vbar, double *fbar, double *gtheta) {
+    int r = ready(c);
+    if (r) return r;
+    if (!valid_lj(p)) return fail(c, FPM_EINVAL, "bad LJ params");
+    if (!isfinite(dt) || nsteps < 0) return fail(c, FPM_EINVAL, "bad dt or step count");
+    if (nsteps > 0 && (!xs || !floss)) return fail(c, FPM_EINVAL, "null positions or loss table");
+    if (!xbar || !vbar || !fbar) return fail(c, FPM_EINVAL, "null adjoint array");
+    // step k (latest first) at the positions reached after it, x_{k+1}: the
+    // launches of fpm_set_positions followed by fpm_lj_adjoint_step, queued
+    // without host synchronisation
+    for (int32_t k = nsteps - 1; k >= 0; k--) {
+        HIPCHK(c, launch_set_positions(c, xs + (size_t)k * 3 * (size_t)c->n));
+        HIPCHK(c, launch_finalize(c, kFinDisp, nullptr, nullptr));
+        HIPCHK(c, refresh_and_account(c));
+        const AdjOut o{xbar, vbar, fbar, floss[k], (double)dt, kVjpStep};
+        HIPCHK(c, timed(c, "lj_vjp", [&] { return launch_lj_vjp(c, *p, fbar, vbar, o); }));
+        if (gtheta) HIPCHK(c, launch_finalize(c, kFinVjp, gtheta, nullptr));
+    }
+    c->forces_valid = false;
+    c->sph_restart = true;
+    return FPM_OK;
+}
+
 int fpm_integrate(fpm_ctx *c, float dt, int32_t half) {
     int r = ready(c);
     if (r) return r;
@@ -795,6 +820,19 @@ int fpm_step(fpm_ctx *c, const fpm_lj_params *p, float dt, int32_t nsteps, doubl
         step += 1;
     }
     HIPCHK(c, hipGraphLaunch(c->g_last[step & 1], c->stream));
+    return FPM_OK;
+}
+
+int fpm_step_record(fpm_ctx *c, const fpm_lj_params *p, float dt, int32_t nsteps, float *xs) {
+    int r = ready(c);
+    if (r) return r;
+    if (nsteps > 0 && !xs) return fail(c, FPM_EINVAL, "null position record");
+    for (int32_t k = 0; k < nsteps; k++) {
+        r = fpm_step(c, p, dt, 1, nullptr);
+        if (r) return r;
+        HIPCHK(c, launch_gather_out(c, xs + (size_t)k * 3 * (size_t)c->n, nullptr, nullptr,
+                                    nullptr, nullptr));
+    }
     return FPM_OK;
 }
 

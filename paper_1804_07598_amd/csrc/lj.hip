@@ -23,7 +23,9 @@ namespace {
 struct LJCoef {
     double c12[3];  // 4 eps sig^12
     double c6[3];   // 4 eps sig^6
-    double inv_eps[3], inv_sig[3];
+    double a12[3];  // 4 sig^12: c12 at unit eps (the pair force is linear in eps)
+    double a6[3];   // 4 sig^6
+    double inv_sig[3];
 };
 
 // 1/x in FP64: the hardware estimate (relative error up to 5e-8) refined by
@@ -314,7 +316,8 @@ __global__ __launch_bounds__(kBlock) void k_lj(State st, float rc2, double rc2lo
 //   dL/dtheta = 1/2 sum_i sum_j (ds/dtheta) r_ij . (lam_i - lam_j)
 // (each pair is visited from both sides, hence the 1/2), with
 // s = 12 c12 u^-7 - 6 c6 u^-4, s' = -84 c12 u^-8 + 24 c6 u^-5,
-// ds/deps = s / eps, ds/dsig = (144 c12 u^-7 - 36 c6 u^-4) / sig.
+// ds/deps = 12 a12 u^-7 - 6 a6 u^-4 (s at unit eps, a12 = 4 sig^12,
+// a6 = 4 sig^6; defined at eps = 0 too), ds/dsig = (144 c12 u^-7 - 36 c6 u^-4) / sig.
 // The pair set is the force set; the cut-off itself is not differentiated.
 
 struct VjpAcc {
@@ -343,7 +346,12 @@ __device__ __forceinline__ void vjp_pair(VjpAcc &a, float3 pi, double xi, double
         a.gx = fma(s, lx, fma(t, dx, a.gx));
         a.gy = fma(s, ly, fma(t, dy, a.gy));
         a.gz = fma(s, lz, fma(t, dz, a.gz));
-        const double de = 0.5 * s * rl;  // times 1/eps later
+        double a12 = cf.a12[0], a6 = cf.a6[0];
+        if (NT == 2) {
+            a12 = tp == 0 ? cf.a12[0] : (tp == 1 ? cf.a12[1] : cf.a12[2]);
+            a6 = tp == 0 ? cf.a6[0] : (tp == 1 ? cf.a6[1] : cf.a6[2]);
+        }
+        const double de = 0.5 * r6i * r2i * fma(12.0 * a12, r6i, -6.0 * a6) * rl;
         const double ds = 0.5 * r6i * r2i * fma(144.0 * c12, r6i, -36.0 * c6) * rl;  // / sig
         if (NT == 1) {
             a.ge[0] += de;
@@ -447,7 +455,7 @@ __global__ __launch_bounds__(kBlock) void k_lj_vjp(State st, float rc2, double r
     }
     double v[6];
     for (int p = 0; p < 3; p++) {
-        v[p] = a.ge[p] * cf.inv_eps[p];
+        v[p] = a.ge[p];
         v[3 + p] = a.gs[p] * cf.inv_sig[p];
     }
     const int slot[6] = {0, 1, 2, 3, 4, 5};
@@ -696,7 +704,8 @@ LJCoef make_coef(const fpm_lj_params &p) {
         const double s6 = s * s * s * s * s * s;
         cf.c12[k] = 4.0 * e * s6 * s6;
         cf.c6[k] = 4.0 * e * s6;
-        cf.inv_eps[k] = e != 0.0 ? 1.0 / e : 0.0;
+        cf.a12[k] = 4.0 * s6 * s6;
+        cf.a6[k] = 4.0 * s6;
         cf.inv_sig[k] = 1.0 / s;
     }
     return cf;

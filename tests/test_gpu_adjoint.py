@@ -56,6 +56,21 @@ def test_force_vjp_matches_oracle(n, mix):
         assert gt[0, [1, 2, 4, 5]].tolist() == [0, 0, 0, 0]
 
 
+def test_force_vjp_at_zero_well_depth():
+    """eps_AB = 0 switches the A-B pairs off; their dL/deps_AB (the unit-depth
+    pair forces against the cotangent) must still come out, as the oracle's."""
+    s = mixture(4096)
+    eps, sig = (1.0, 0.0, 0.5), MIX["sig"]
+    sim = make_sim(s)
+    lam = np.random.default_rng(2).normal(size=(s.n, 3))
+    gx, gt = (np_(t) for t in sim.force_vjp(lam, eps, sig, 2))
+    ox, ot = O.lj_vjp(s.pos, s.box, PER, O.radius2(RC), lam, eps, sig, s.typ)
+    assert ot[1] != 0.0
+    assert rel_max(gx, ox) <= TOL
+    assert np.all(np.abs(gt[0] - ot) <= TOL * np.abs(ot)), (gt[0], ot)
+    sim.close()
+
+
 def test_force_vjp_on_a_batch():
     from paper_1804_07598_amd.sim import BatchSim
     ns, rhos, Ts = inputs.batched_table()
@@ -174,3 +189,46 @@ def test_force_vjp_without_neighbours():
         lam = torch.ones((len(pos), 3), dtype=torch.float64, device="cuda")
         gx, gth = sim.force_vjp(lam)
         assert torch.all(gx == 0) and torch.all(gth == 0)
+
+
+def test_segment_record_and_sweep_equal_the_per_call_sequence():
+    """fpm_step_record and fpm_lj_adjoint_sweep (the device-side segment
+    recomputation and reverse sweep) against the per-call sequence they stand
+    for (fpm_step of one step + fpm_get_particles; fpm_set_positions +
+    fpm_lj_adjoint_step): positions and every cotangent equal bit for bit,
+    over a segment with list rebuilds and loss terms at some steps."""
+    import torch
+    from paper_1804_07598_amd import _lib as F
+    s = mixture(3000, seed=11)
+    eps, sig = MIX["eps"], MIX["sig"]
+    prm = F.lj_params(eps, sig, 2)
+    dt, K = 0.005, 30
+    rng = np.random.default_rng(12)
+    floss = [torch.tensor(rng.normal(size=(s.n, 3)), device="cuda") if k % 7 == 3 else None
+             for k in range(K)]
+    fbar0 = torch.tensor(rng.normal(size=(s.n, 3)), device="cuda")
+    out = []
+    for mode in ("device", "calls"):
+        sim = make_sim(s)
+        xs = torch.empty((K, s.n, 3), dtype=torch.float32, device="cuda")
+        if mode == "device":
+            F.fpm_step_record(sim.ctx, prm, dt, K, xs)
+        else:
+            for k in range(K):
+                F.fpm_step(sim.ctx, prm, dt, 1, None)
+                F.fpm_get_particles(sim.ctx, xs[k], None, None)
+        xbar = torch.zeros((s.n, 3), dtype=torch.float64, device="cuda")
+        vbar, fbar = torch.zeros_like(xbar), fbar0.clone()
+        gt = torch.zeros((1, 6), dtype=torch.float64, device="cuda")
+        if mode == "device":
+            F.fpm_lj_adjoint_sweep(sim.ctx, prm, dt, K, xs, floss, xbar, vbar, fbar, gt)
+        else:
+            for k in range(K - 1, -1, -1):
+                F.fpm_set_positions(sim.ctx, xs[k])
+                F.fpm_lj_adjoint_step(sim.ctx, prm, dt, floss[k], xbar, vbar, fbar, gt, 0)
+        sim.check()
+        out.append([np_(t) for t in (xs, xbar, vbar, fbar, gt)])
+        sim.close()
+    assert out[0][0].shape == (K, s.n, 3) and np.isfinite(out[0][1]).all()
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)

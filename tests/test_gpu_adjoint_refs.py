@@ -79,7 +79,8 @@ def gpu_case(n, K, frame_every, ckpt_every, seed=5):
     return s, theta, dt, frames, targets, grads, xs, fbar
 
 
-@pytest.mark.parametrize("n,K,fe,ce", [(2048, 40, 20, 20), (1500, 60, 20, 20)])
+@pytest.mark.parametrize("n,K,fe,ce", [(2048, 40, 20, 20), (1500, 60, 20, 20),
+                                      (1024, 200, 20, 20)])
 def test_fp64_adjoint_on_gpu_states(n, K, fe, ce):
     s, theta, dt, frames, targets, (gx, gv, gt), xs, fbar = gpu_case(n, K, fe, ce)
     # FP64 sweep on the FP32 pair set of each recorded state

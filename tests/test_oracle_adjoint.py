@@ -88,6 +88,23 @@ def test_vjp_eps_homogeneity():
     assert abs(lhs - rhs) <= 1e-12 * (abs(rhs) + np.abs(gt).max())
 
 
+@pytest.mark.parametrize("eps", [EPS, (1.0, 0.0, 0.5), (0.0, 0.0, 0.0)])
+def test_vjp_eps_derivative_is_the_unit_depth_force(eps):
+    # the force is linear in each well depth separately, so dL/deps_k is
+    # lam . F with only the type-k pairs on, at unit depth, whatever eps is
+    # (eps_k = 0 included, where the pair force itself vanishes)
+    x, L, typ = _system(seed=8)
+    per = (1, 1, 1)
+    lam = np.random.default_rng(9).normal(size=x.shape)
+    _, gt = oracle.lj_vjp_f64(x, L, per, RC, lam, eps, SIG, typ)
+    for k in range(3):
+        unit = tuple(1.0 if q == k else 0.0 for q in range(3))
+        ref = _lamF(x, L, per, lam, typ, unit, SIG)
+        assert abs(gt[k] - ref) <= 1e-12 * (abs(ref) + 1.0), (k, gt[k], ref)
+    if eps[1] == 0.0:
+        assert gt[1] != 0.0
+
+
 def test_vjp_joint_scaling_of_positions_and_sigma():
     # each pair force s(u) r is homogeneous of degree -1 in (r, sigma) jointly, so
     # in an open box sum_k x_k . dL/dx_k + sum_p sig_p dL/dsig_p = -lam . F
