@@ -73,19 +73,37 @@ __device__ __forceinline__ bool separation(float3 pi, double xi, double yi, doub
     return in;
 }
 
+// The coefficients a particle of type ti (0 or 1) can meet: pair type ti + tj
+// for a neighbour of type tj, so entry [tj] holds those of pair type ti + tj
+// (one type: both entries are pair type 0).  Selected once per lane, so a
+// pair needs a two-way select only.
+struct LaneCoef {
+    double c12[2], c6[2], a12[2], a6[2];
+};
+
 template <int NT>
-__device__ __forceinline__ int pair_type(int ti, float4 q) {
-    return NT == 2 ? ti + __float_as_int(q.w) : 0;
+__device__ __forceinline__ LaneCoef lane_coef(const LJCoef &cf, int ti) {
+    LaneCoef l;
+    for (int t = 0; t < 2; t++) {
+        const int k = NT == 2 ? ti + t : 0;
+        l.c12[t] = k == 0 ? cf.c12[0] : (k == 1 ? cf.c12[1] : cf.c12[2]);
+        l.c6[t] = k == 0 ? cf.c6[0] : (k == 1 ? cf.c6[1] : cf.c6[2]);
+        l.a12[t] = k == 0 ? cf.a12[0] : (k == 1 ? cf.a12[1] : cf.a12[2]);
+        l.a6[t] = k == 0 ? cf.a6[0] : (k == 1 ? cf.a6[1] : cf.a6[2]);
+    }
+    return l;
+}
+
+// Neighbour type (0 or 1; always 0 with one type).
+template <int NT>
+__device__ __forceinline__ int nbr_type(float4 q) {
+    return NT == 2 ? __float_as_int(q.w) : 0;
 }
 
 template <int NT>
-__device__ __forceinline__ void coef(const LJCoef &cf, int tp, double &c12, double &c6) {
-    c12 = cf.c12[0];
-    c6 = cf.c6[0];
-    if (NT == 2) {
-        c12 = tp == 0 ? cf.c12[0] : (tp == 1 ? cf.c12[1] : cf.c12[2]);
-        c6 = tp == 0 ? cf.c6[0] : (tp == 1 ? cf.c6[1] : cf.c6[2]);
-    }
+__device__ __forceinline__ void coef(const LaneCoef &lc, int tj, double &c12, double &c6) {
+    c12 = NT == 2 && tj ? lc.c12[1] : lc.c12[0];
+    c6 = NT == 2 && tj ? lc.c6[1] : lc.c6[0];
 }
 
 // Per-lane accumulators.  The virial needs no per-pair work: summed over all
@@ -99,13 +117,13 @@ struct Acc {
 };
 
 template <int NT, bool IMG>
-__device__ __forceinline__ void pair(Acc &a, float3 pi, double xi, double yi, double zi, int ti,
-                                     float4 q, const Box &b, float rc2, double rc2lo,
-                                     double rc2hi, const LJCoef &cf) {
+__device__ __forceinline__ void pair(Acc &a, float3 pi, double xi, double yi, double zi,
+                                     const LaneCoef &cf, float4 q, const Box &b, float rc2,
+                                     double rc2lo, double rc2hi) {
     double dx, dy, dz, sx, sy, sz;
     if (separation<IMG>(pi, xi, yi, zi, q, b, rc2, rc2lo, rc2hi, dx, dy, dz, sx, sy, sz)) {
         double c12, c6;
-        coef<NT>(cf, pair_type<NT>(ti, q), c12, c6);
+        coef<NT>(cf, nbr_type<NT>(q), c12, c6);
         const double r2i = recip(fma(dx, dx, fma(dy, dy, dz * dz)));
         const double r6i = r2i * r2i * r2i;
         const double s = r6i * r2i * fma(12.0 * c12, r6i, -6.0 * c6);
@@ -168,7 +186,7 @@ __device__ __forceinline__ void walk(Acc &a, const float4 *__restrict__ pos,
     if (cnt <= 0) return;
     const float3 pi = xyz(pi4);
     const double xi = pi.x, yi = pi.y, zi = pi.z;
-    const int ti = __float_as_int(pi4.w);
+    const LaneCoef lc = lane_coef<NT>(cf, __float_as_int(pi4.w));
     // two register sets take turns (no copies between rounds); a round past
     // the end of the list re-reads a group in range, which is harmless
     float4 q0[UNR], q1[UNR];
@@ -179,13 +197,13 @@ __device__ __forceinline__ void walk(Acc &a, const float4 *__restrict__ pos,
         nxt = list_group<UNR>(lst, k + 2 * UNR < cnt ? k + 2 * UNR : k);
 #pragma unroll
         for (int u = 0; u < UNR; u++)
-            pair<NT, IMG>(a, pi, xi, yi, zi, ti, q0[u], b, rc2, rc2lo, rc2hi, cf);
+            pair<NT, IMG>(a, pi, xi, yi, zi, lc, q0[u], b, rc2, rc2lo, rc2hi);
         if (k + UNR >= cnt) break;
         gather<UNR>(pos, nxt, q0);
         nxt = list_group<UNR>(lst, k + 3 * UNR < cnt ? k + 3 * UNR : k);
 #pragma unroll
         for (int u = 0; u < UNR; u++)
-            pair<NT, IMG>(a, pi, xi, yi, zi, ti, q1[u], b, rc2, rc2lo, rc2hi, cf);
+            pair<NT, IMG>(a, pi, xi, yi, zi, lc, q1[u], b, rc2, rc2lo, rc2hi);
     }
 }
 
@@ -320,21 +338,21 @@ __global__ __launch_bounds__(kBlock) void k_lj(State st, float rc2, double rc2lo
 // a6 = 4 sig^6; defined at eps = 0 too), ds/dsig = (144 c12 u^-7 - 36 c6 u^-4) / sig.
 // The pair set is the force set; the cut-off itself is not differentiated.
 
+// ge, gs: the eps and sig terms by neighbour type (pair type ti + index).
 struct VjpAcc {
     double gx = 0.0, gy = 0.0, gz = 0.0;
-    double ge[3] = {0.0, 0.0, 0.0}, gs[3] = {0.0, 0.0, 0.0};
+    double ge[2] = {0.0, 0.0}, gs[2] = {0.0, 0.0};
 };
 
 template <int NT, bool IMG>
 __device__ __forceinline__ void vjp_pair(VjpAcc &a, float3 pi, double xi, double yi, double zi,
-                                         int ti, float4 li, float4 q, float4 lj, const Box &b,
-                                         float rc2, double rc2lo, double rc2hi,
-                                         const LJCoef &cf) {
+                                         const LaneCoef &cf, float4 li, float4 q, float4 lj,
+                                         const Box &b, float rc2, double rc2lo, double rc2hi) {
     double dx, dy, dz, sx, sy, sz;
     if (separation<IMG>(pi, xi, yi, zi, q, b, rc2, rc2lo, rc2hi, dx, dy, dz, sx, sy, sz)) {
-        const int tp = pair_type<NT>(ti, q);
+        const int tj = nbr_type<NT>(q);
         double c12, c6;
-        coef<NT>(cf, tp, c12, c6);
+        coef<NT>(cf, tj, c12, c6);
         const double r2i = recip(fma(dx, dx, fma(dy, dy, dz * dz)));
         const double r6i = r2i * r2i * r2i;
         const double s = r6i * r2i * fma(12.0 * c12, r6i, -6.0 * c6);
@@ -346,23 +364,18 @@ __device__ __forceinline__ void vjp_pair(VjpAcc &a, float3 pi, double xi, double
         a.gx = fma(s, lx, fma(t, dx, a.gx));
         a.gy = fma(s, ly, fma(t, dy, a.gy));
         a.gz = fma(s, lz, fma(t, dz, a.gz));
-        double a12 = cf.a12[0], a6 = cf.a6[0];
-        if (NT == 2) {
-            a12 = tp == 0 ? cf.a12[0] : (tp == 1 ? cf.a12[1] : cf.a12[2]);
-            a6 = tp == 0 ? cf.a6[0] : (tp == 1 ? cf.a6[1] : cf.a6[2]);
-        }
+        const double a12 = NT == 2 && tj ? cf.a12[1] : cf.a12[0];
+        const double a6 = NT == 2 && tj ? cf.a6[1] : cf.a6[0];
         const double de = 0.5 * r6i * r2i * fma(12.0 * a12, r6i, -6.0 * a6) * rl;
         const double ds = 0.5 * r6i * r2i * fma(144.0 * c12, r6i, -36.0 * c6) * rl;  // / sig
         if (NT == 1) {
             a.ge[0] += de;
             a.gs[0] += ds;
         } else {
-            a.ge[0] += tp == 0 ? de : 0.0;
-            a.ge[1] += tp == 1 ? de : 0.0;
-            a.ge[2] += tp == 2 ? de : 0.0;
-            a.gs[0] += tp == 0 ? ds : 0.0;
-            a.gs[1] += tp == 1 ? ds : 0.0;
-            a.gs[2] += tp == 2 ? ds : 0.0;
+            a.ge[0] += tj ? 0.0 : de;
+            a.ge[1] += tj ? de : 0.0;
+            a.gs[0] += tj ? 0.0 : ds;
+            a.gs[1] += tj ? ds : 0.0;
         }
     }
 }
@@ -375,7 +388,7 @@ __device__ __forceinline__ void vjp_walk(VjpAcc &a, const float4 *__restrict__ p
                                          double rc2hi, const LJCoef &cf) {
     const float3 pi = xyz(pi4);
     const double xi = pi.x, yi = pi.y, zi = pi.z;
-    const int ti = __float_as_int(pi4.w);
+    const LaneCoef lc = lane_coef<NT>(cf, __float_as_int(pi4.w));
     if (cnt <= 0) return;
     int4 e = lst[0];  // the next group's entries are requested before this group's gathers
     for (int k = 0; k < cnt; k += 4) {
@@ -389,7 +402,7 @@ __device__ __forceinline__ void vjp_walk(VjpAcc &a, const float4 *__restrict__ p
         }
 #pragma unroll
         for (int u = 0; u < 4; u++)
-            vjp_pair<NT, IMG>(a, pi, xi, yi, zi, ti, li, q[u], l[u], b, rc2, rc2lo, rc2hi, cf);
+            vjp_pair<NT, IMG>(a, pi, xi, yi, zi, lc, li, q[u], l[u], b, rc2, rc2lo, rc2hi);
     }
 }
 
@@ -453,10 +466,21 @@ __global__ __launch_bounds__(kBlock) void k_lj_vjp(State st, float rc2, double r
             }
         }
     }
+    // by pair type: ti + neighbour type (one type: pair type 0 only)
+    const bool t1 = NT == 2 && __float_as_int(pi4.w) != 0;
+    double ge[3] = {a.ge[0], 0.0, 0.0}, gs[3] = {a.gs[0], 0.0, 0.0};
+    if (NT == 2) {
+        ge[0] = t1 ? 0.0 : a.ge[0];
+        ge[1] = t1 ? a.ge[0] : a.ge[1];
+        ge[2] = t1 ? a.ge[1] : 0.0;
+        gs[0] = t1 ? 0.0 : a.gs[0];
+        gs[1] = t1 ? a.gs[0] : a.gs[1];
+        gs[2] = t1 ? a.gs[1] : 0.0;
+    }
     double v[6];
     for (int p = 0; p < 3; p++) {
-        v[p] = a.ge[p];
-        v[3 + p] = a.gs[p] * cf.inv_sig[p];
+        v[p] = ge[p];
+        v[3 + p] = gs[p] * cf.inv_sig[p];
     }
     const int slot[6] = {0, 1, 2, 3, 4, 5};
     const int op[6] = {0, 0, 0, 0, 0, 0};
@@ -537,7 +561,7 @@ __device__ __forceinline__ void sym_upper(const State &st, int64_t i, int p0, in
                                           double (&w)[6]) {
     const float3 pi = xyz(pi4);
     const double xi = pi.x, yi = pi.y, zi = pi.z;
-    const int ti = __float_as_int(pi4.w);
+    const LaneCoef lc = lane_coef<NT>(cf, __float_as_int(pi4.w));
     const float4 *__restrict__ pos = st.pos[0];
     const int4 *lst = reinterpret_cast<const int4 *>(st.nbr) + ((i >> 6) * (int64_t)cap4) * 64 +
                       (i & 63);
@@ -555,7 +579,7 @@ __device__ __forceinline__ void sym_upper(const State &st, int64_t i, int p0, in
             if (separation<IMG>(pi, xi, yi, zi, q[t], b, rc2, rc2lo, rc2hi, dx, dy, dz, sx, sy,
                                 sz)) {
                 double c12, c6;
-                coef<NT>(cf, pair_type<NT>(ti, q[t]), c12, c6);
+                coef<NT>(lc, nbr_type<NT>(q[t]), c12, c6);
                 const double r2i = recip(fma(dx, dx, fma(dy, dy, dz * dz)));
                 const double r6i = r2i * r2i * r2i;
                 sv = r6i * r2i * fma(12.0 * c12, r6i, -6.0 * c6);
