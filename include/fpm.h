@@ -291,8 +291,9 @@ int fpm_sph_step(fpm_ctx *ctx, const fpm_sph_params *prm, int32_t nsteps, double
  * lower slot, and hand the reaction to the partner.  Lists are then kept in
  * ascending slot order; each rebuild also records, for every pair, where it
  * sits in the partner's list.  A first pass stores each pair's force factor
- * and the particle's own sum, a second pass adds the partners' reactions in
- * list order: no atomics, results repeat bit for bit.  Forces, energy and
+ * beside the pair's list entry and the particle's own sum, a second pass
+ * gathers the lower partners' factors and adds their reactions in list
+ * order: no atomics, results repeat bit for bit.  Forces, energy and
  * virial agree with the full-list path to rounding.  Call before
  * fpm_workspace_size and fpm_set_particles (the workspace grows by 10 bytes
  * per list entry and 28 per particle); not with DEM storage.  FPM_EOVERFLOW

@@ -494,45 +494,93 @@ __global__ __launch_bounds__(kBlock) void k_lj_vjp(State st, float rc2, double r
 // ascending slot order, so the partners above slot i are its entries from
 // plo[i] on and those below it the first plo[i].  At a rebuild k_sym_index
 // finds, for each lower entry m of slot j (partner i < j), the position of j
-// in i's list by bisection of that sorted list.  Pass 1 evaluates each pair
-// once, at its lower slot i: the force factor s (0 off the force set) goes to
-// i's list entry, s (x_i - x_j) into i's own sum, the pair energy and virial
-// into the partials.  Pass 2 adds to every slot j the reactions
-// s_ij (x_j - x_i) of its lower partners, read through the transpose
-// positions, in list order, and applies the step's velocity-Verlet updates.
-// There are no atomics and every sum has a fixed order, so results repeat
-// bit for bit.
+// in i's list, by bisection of that sorted list (the four entries of a group
+// searched together, so that their loads overlap).  Pass 1 evaluates each
+// pair once, at its lower slot i: s (x_i - x_j) goes into i's own sum, the
+// pair energy and virial into the partials, and the force factor s (0 off
+// the force set) beside i's own list entry.  Pass 2 adds to every slot j the
+// reactions s (x_j - x_i) of its lower partners in list order, the factors
+// gathered from the partners' entries through the recorded positions, and
+// applies the step's velocity-Verlet updates.  There are no atomics and every
+// sum has a fixed order, so results repeat bit for bit.  Both passes walk
+// whole groups of four entries in wavefront lockstep (from the first to the
+// last group any lane of the wavefront needs), so list and factor stores stay
+// coalesced; the factor gathers of pass 2 are the transposition the method
+// needs, one random 8-byte read per pair.
+
+__device__ __forceinline__ int wave_min(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
 
 __global__ __launch_bounds__(kBlock) void k_sym_index(State st, int cap, int cap4) {
     const int s = block_system(st);
     if (!rebuilding(st, s)) return;
     const SysDesc &d = st.sys[s];
-    const int64_t j = global_slot();
-    if (j - d.slot_base >= d.n) {
-        st.plo[j] = 0;
-        return;
-    }
-    const int cnt = min((int)(st.nnb[j] & ~kWrapBit), cap);
+    const int64_t i64 = global_slot();
+    const int i = (int)i64;
+    const bool active = i64 - d.slot_base < d.n;
     const int32_t *__restrict__ nbr = st.nbr;
+    const int cnt = active ? min((int)(st.nnb[i64] & ~kWrapBit), cap) : 0;
     int lo = 0, hi = cnt;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if (nbr[nbr_index(j, mid, cap4)] < (int)j) lo = mid + 1;
+        if (nbr[nbr_index(i64, mid, cap4)] < i) lo = mid + 1;
         else hi = mid;
     }
-    st.plo[j] = lo;
+    st.plo[i64] = lo;
+    const int4 *lst = reinterpret_cast<const int4 *>(nbr) + ((i64 >> 6) * (int64_t)cap4) * 64 +
+                      (i64 & 63);
+    ushort4 *tl = reinterpret_cast<ushort4 *>(st.tsym) + ((i64 >> 6) * (int64_t)cap4) * 64 +
+                  (i64 & 63);
     bool miss = false;
-    for (int m = 0; m < lo; m++) {
-        const int i = nbr[nbr_index(j, m, cap4)];
-        const int ci = min((int)(st.nnb[i] & ~kWrapBit), cap);
-        int a = 0, b = ci;
-        while (a < b) {
-            const int mid = (a + b) >> 1;
-            if (nbr[nbr_index(i, mid, cap4)] < (int)j) a = mid + 1;
-            else b = mid;
+    const int g1 = wave_max((lo + 3) >> 2);
+    for (int g = 0; g < g1; g++) {
+        const int4 e = lst[g * 64];
+        const int jj[4] = {e.x, e.y, e.z, e.w};
+        int j[4], a[4], b[4];
+        bool eq[4], on[4];
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            on[t] = 4 * g + t < lo;
+            j[t] = on[t] ? jj[t] : i;
+            a[t] = 0;
+            eq[t] = false;
         }
-        miss |= a >= ci || nbr[nbr_index(i, a, cap4)] != (int)j;
-        st.tsym[nbr_index(j, m, cap4)] = (uint16_t)(a < ci ? a : 0);
+#pragma unroll
+        for (int t = 0; t < 4; t++) b[t] = on[t] ? min((int)(st.nnb[j[t]] & ~kWrapBit), cap) : 0;
+        // lower-bound searches for i in the lower partners' lists; eq records
+        // whether the last probe that moved b found i itself
+        while (__ballot(a[0] < b[0] || a[1] < b[1] || a[2] < b[2] || a[3] < b[3]) != 0) {
+            int v[4];
+#pragma unroll
+            for (int t = 0; t < 4; t++)
+                v[t] = a[t] < b[t] ? nbr[nbr_index(j[t], (a[t] + b[t]) >> 1, cap4)] : 0;
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                if (a[t] >= b[t]) continue;
+                const int mid = (a[t] + b[t]) >> 1;
+                if (v[t] < i) {
+                    a[t] = mid + 1;
+                } else {
+                    b[t] = mid;
+                    eq[t] = v[t] == i;
+                }
+            }
+        }
+        ushort4 o;
+        o.x = (uint16_t)(on[0] ? a[0] : 0);
+        o.y = (uint16_t)(on[1] ? a[1] : 0);
+        o.z = (uint16_t)(on[2] ? a[2] : 0);
+        o.w = (uint16_t)(on[3] ? a[3] : 0);
+#pragma unroll
+        for (int t = 0; t < 4; t++) miss |= on[t] && !eq[t];
+        if (on[0] || on[1] || on[2] || on[3]) tl[g * 64] = o;
     }
     if (miss) st.ctl->sym_miss = 1;
 }
@@ -565,26 +613,36 @@ __device__ __forceinline__ void sym_upper(const State &st, int64_t i, int p0, in
     const float4 *__restrict__ pos = st.pos[0];
     const int4 *lst = reinterpret_cast<const int4 *>(st.nbr) + ((i >> 6) * (int64_t)cap4) * 64 +
                       (i & 63);
-    for (int g = p0 >> 2; g * 4 < cnt; g++) {
-        const int4 e = lst[g * 64];
+    double2 *fac = reinterpret_cast<double2 *>(st.sbuf) +
+                   (((i >> 6) * (int64_t)cap4) * 64 + (i & 63)) * 2;
+    const int g0 = wave_min(p0 >> 2), g1 = wave_max((cnt + 3) >> 2);
+    if (g0 >= g1) return;
+    int4 e = lst[g0 * 64];
+    for (int g = g0; g < g1; g++) {
         const int jj[4] = {e.x, e.y, e.z, e.w};
+        double sv[4] = {0.0, 0.0, 0.0, 0.0};
+        bool on[4];
         float4 q[4];
-#pragma unroll
-        for (int t = 0; t < 4; t++) q[t] = pos[jj[t]];
 #pragma unroll
         for (int t = 0; t < 4; t++) {
             const int k = 4 * g + t;
-            if (k < p0 || k >= cnt) continue;
-            double dx, dy, dz, sx, sy, sz, sv = 0.0;
+            on[t] = k >= p0 && k < cnt;
+            q[t] = pos[on[t] ? jj[t] : (int)i];
+        }
+        if (g + 1 < g1) e = lst[(g + 1) * 64];  // the next group's entries, requested early
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            if (!on[t]) continue;
+            double dx, dy, dz, sx, sy, sz;
             if (separation<IMG>(pi, xi, yi, zi, q[t], b, rc2, rc2lo, rc2hi, dx, dy, dz, sx, sy,
                                 sz)) {
                 double c12, c6;
                 coef<NT>(lc, nbr_type<NT>(q[t]), c12, c6);
                 const double r2i = recip(fma(dx, dx, fma(dy, dy, dz * dz)));
                 const double r6i = r2i * r2i * r2i;
-                sv = r6i * r2i * fma(12.0 * c12, r6i, -6.0 * c6);
+                sv[t] = r6i * r2i * fma(12.0 * c12, r6i, -6.0 * c6);
                 u = fma(r6i, fma(c12, r6i, -c6), u);
-                const double fx = sv * dx, fy = sv * dy, fz = sv * dz;
+                const double fx = sv[t] * dx, fy = sv[t] * dy, fz = sv[t] * dz;
                 f[0] += fx;
                 f[1] += fy;
                 f[2] += fz;
@@ -595,7 +653,11 @@ __device__ __forceinline__ void sym_upper(const State &st, int64_t i, int p0, in
                 w[4] = fma(dx, fz, w[4]);
                 w[5] = fma(dy, fz, w[5]);
             }
-            st.sbuf[nbr_index(i, k, cap4)] = sv;
+        }
+        // the group's factors, at the lane's own entries (lower entries: 0, unused)
+        if (on[0] || on[1] || on[2] || on[3]) {
+            fac[g * 128] = make_double2(sv[0], sv[1]);
+            fac[g * 128 + 1] = make_double2(sv[2], sv[3]);
         }
     }
 }
@@ -642,18 +704,24 @@ __device__ __forceinline__ void sym_lower(const State &st, int64_t j, int p, flo
                       (j & 63);
     const ushort4 *tl = reinterpret_cast<const ushort4 *>(st.tsym) +
                         ((j >> 6) * (int64_t)cap4) * 64 + (j & 63);
-    for (int g = 0; g * 4 < p; g++) {
-        const int4 e = lst[g * 64];
-        const ushort4 t4 = tl[g * 64];
+    const int g1 = wave_max((p + 3) >> 2);
+    if (g1 <= 0) return;
+    int4 e = lst[0];
+    ushort4 tm = tl[0];
+    for (int g = 0; g < g1; g++) {
         const int ii[4] = {e.x, e.y, e.z, e.w};
-        const int kk[4] = {t4.x, t4.y, t4.z, t4.w};
+        const int kk[4] = {tm.x, tm.y, tm.z, tm.w};
         float4 q[4];
         double sv[4];
 #pragma unroll
         for (int t = 0; t < 4; t++) {
             const bool ok = 4 * g + t < p;
-            q[t] = pos[ok ? ii[t] : j];
+            q[t] = pos[ok ? ii[t] : (int)j];
             sv[t] = ok ? st.sbuf[nbr_index(ii[t], kk[t], cap4)] : 0.0;
+        }
+        if (g + 1 < g1) {
+            e = lst[(g + 1) * 64];
+            tm = tl[(g + 1) * 64];
         }
 #pragma unroll
         for (int t = 0; t < 4; t++) {
