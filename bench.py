@@ -45,9 +45,10 @@ def source_hash(paths) -> str:
 
 
 def stored_traffic(n_launch_atoms: int, unroll: int):
-    """HBM bytes per force launch from the committed rocprofv3 counter summary,
-    or None when the summary is missing, was taken on another kernel variant or
-    the kernel source changed since."""
+    """HBM bytes per launch of the fused step kernel with `unroll` list entries
+    in flight, from the committed rocprofv3 counter summary, or None when the
+    summary is missing, holds no figure for that unroll or atom count, or the
+    kernel source changed since."""
     if not os.path.exists(PROFILE_COUNTERS):
         return None
     kv = {}
@@ -60,9 +61,7 @@ def stored_traffic(n_launch_atoms: int, unroll: int):
             return None
         if int(kv.get("atoms", "0")) != n_launch_atoms:
             return None
-        if int(kv.get("unroll", "0")) != unroll:
-            return None
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv[f"hbm_bytes_per_launch_unroll{unroll}"])
     except (KeyError, ValueError):
         return None
 
@@ -509,6 +508,8 @@ def main(argv=None) -> int:
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tuning", type=str, default="",
+                    help="fixed launch shapes 'path,zblock,unroll' instead of the tuner")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the library's default launch shapes")
     ap.add_argument("--no-forms", action="store_true",
@@ -558,7 +559,10 @@ def main(argv=None) -> int:
     log(f"workload lj1m: N={s.n} L={s.L:.5f}", a.quiet)
     sim = ParticleSim(s.pos, s.box, (1, 1, 1), vel=s.vel, r_cut=2.5, skin=0.3, device=dev)
     knobs = (0, 0, 0)
-    if not a.no_tune:
+    if a.tuning:
+        knobs = tuple(int(x) for x in a.tuning.split(","))
+        sim.set_tuning(*knobs)
+    elif not a.no_tune:
         from paper_1804_07598_amd.tune import tune
         knobs, table = tune(sim, s.rho, cache=None)
         for k, f_ms, b_ms, cost in table:
