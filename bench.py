@@ -632,7 +632,8 @@ def main(argv=None) -> int:
     sim.check()
     bytes_step = s.n * (100.0 + 4.0 * nbar_k)
     achieved_step = bytes_step / (s_ms / 1e3) / 1e9
-    traffic = stored_traffic(s.n, knobs[2] or 8)  # unroll 0 = automatic = 8
+    unroll = knobs[2] or 8  # 0 = automatic = 8
+    traffic = stored_traffic(s.n, unroll)
     copy_gbs = copy_rate(dev)
     log(f"step force kernel {s_ms * 1e3:.1f} us over {s_n} launches -> {achieved_step:.0f} GB/s; "
         f"device copy {copy_gbs:.0f} GB/s", a.quiet)
@@ -658,14 +659,14 @@ def main(argv=None) -> int:
                    "tuning": {"verlet_path": knobs[0], "zblock": knobs[1], "unroll": knobs[2]}},
         "roofline": {"bound": "hbm", "achieved": achieved_step, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved_step / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "lj_step (k_lj<1, 8, 1>: forces, closing kick, next opening "
-                               "kick and drift)", "kernel_ms": s_ms,
+                     "kernel": f"lj_step (k_lj<1, {unroll}, 1>: forces, closing kick, next "
+                               "opening kick and drift)", "kernel_ms": s_ms,
                      "bytes_per_launch": bytes_step,
                      "bytes_model": "N*(100 + 4*nbar): pos_i 16, count 4, list 4*nbar, force 16, "
                                     "vel 16 + 16, build position 16, drifted position 16",
                      "measured_copy_gbs": copy_gbs,
                      "step_hbm_frac": B * value / (HBM_PEAK_GBS * 1e9)},
-        "force_kernel": {"kernel": "lj_force (k_lj<1, 8, 0>, forces only)", "ms": f_ms,
+        "force_kernel": {"kernel": f"lj_force (k_lj<1, {unroll}, 0>, forces only)", "ms": f_ms,
                          "bytes_per_launch": bytes_force, "achieved_gbs": achieved,
                          "frac": achieved / HBM_PEAK_GBS,
                          "bytes_model": "N*(36 + 4*nbar): pos_i 16, count 4, list 4*nbar, "
