@@ -65,6 +65,11 @@ def test_host_side_errors_without_device():
         # calls that need particles fail cleanly
         assert L.fpm_build_verlet(ctx) == F.FPM_EINVAL
         assert L.fpm_step(ctx, None, ctypes.c_float(0.005), 1, None) == F.FPM_EINVAL
+        lj = F.lj_params((1.0,) * 3, (1.0,) * 3, 1)
+        assert L.fpm_step_record(ctx, ctypes.byref(lj), ctypes.c_float(0.005), 1,
+                                 None) == F.FPM_EINVAL
+        assert L.fpm_lj_adjoint_sweep(ctx, ctypes.byref(lj), ctypes.c_float(0.005), 1, None,
+                                      None, None, None, None, None) == F.FPM_EINVAL
         # size limits: n at most 2^26 - 1, list capacity at most 4096
         assert L.fpm_workspace_size(ctx, 1 << 26, ctypes.byref(sz)) == F.FPM_EINVAL
         assert L.fpm_workspace_size(ctx, (1 << 26) - 1, ctypes.byref(sz)) == 0

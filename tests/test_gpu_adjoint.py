@@ -232,3 +232,28 @@ def test_segment_record_and_sweep_equal_the_per_call_sequence():
     assert out[0][0].shape == (K, s.n, 3) and np.isfinite(out[0][1]).all()
     for a, b in zip(out[0], out[1]):
         assert np.array_equal(a, b)
+
+
+def test_segment_entry_points_reject_bad_arguments():
+    """Errors of the segment entry points with particles loaded: missing
+    record or loss table, negative step counts, and a zero-step call that
+    changes nothing."""
+    import torch
+    from paper_1804_07598_amd import _lib as F
+    s = mixture(1024, seed=13)
+    sim = make_sim(s)
+    prm = F.lj_params(MIX["eps"], MIX["sig"], 2)
+    z = torch.zeros((s.n, 3), dtype=torch.float64, device="cuda")
+    with pytest.raises(F.FpmError):
+        F.fpm_step_record(sim.ctx, prm, 0.005, 2, None)
+    with pytest.raises(F.FpmError):
+        F.fpm_lj_adjoint_sweep(sim.ctx, prm, 0.005, 2, None, [None, None], z, z, z)
+    xs = torch.zeros((1, s.n, 3), dtype=torch.float32, device="cuda")
+    with pytest.raises(F.FpmError):
+        F.fpm_lj_adjoint_sweep(sim.ctx, prm, 0.005, -1, xs, [], z, z, z)
+    p0 = np_(sim.get()[0])
+    F.fpm_step_record(sim.ctx, prm, 0.005, 0, None)
+    F.fpm_lj_adjoint_sweep(sim.ctx, prm, 0.005, 0, None, [], z, z, z)
+    assert np.array_equal(np_(sim.get()[0]), p0) and not torch.any(z != 0)
+    sim.check()
+    sim.close()
