@@ -276,7 +276,9 @@ __global__ __launch_bounds__(kBlock) void k_lj(State st, float rc2, double rc2lo
     bool over = false;
     if (active) {
         const float4 f = make_float4((float)a.fx, (float)a.fy, (float)a.fz, (float)(0.5 * a.u));
-        st.frc[i] = f;
+        // inside a step loop the stored force is read by nobody (the next
+        // step's kernel computes its own, and the last step of a loop stores it)
+        if (MODE != kLjStep) st.frc[i] = f;
         if (!isfinite(a.fx) || !isfinite(a.fy) || !isfinite(a.fz)) st.ctl->nonfinite = 1;
         if (MODE != kLjForce)
             ke = kick_drift<MODE>(st, d, i, f, pi4, v4, xb4, sa.dt, sa.thr, over);
@@ -764,7 +766,7 @@ __global__ __launch_bounds__(kBlock) void k_lj_sym2(State st, int cap4, StepArgs
     bool over = false;
     if (active) {
         const float4 fo = make_float4((float)f[0], (float)f[1], (float)f[2], 0.f);
-        st.frc[i] = fo;
+        if (MODE != kLjStep) st.frc[i] = fo;
         if (!isfinite(f[0]) || !isfinite(f[1]) || !isfinite(f[2])) st.ctl->nonfinite = 1;
         if (MODE != kLjForce)
             ke = kick_drift<MODE>(st, d, i, fo, pi4, v4, xb4, sa.dt, sa.thr, over);
