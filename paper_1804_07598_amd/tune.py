@@ -11,10 +11,11 @@ the one with the smallest cost per step,
 
     cost = t_force + t_build / k,
 
-k being the expected number of steps between list rebuilds.  Results are
-cached in a JSON file keyed by device, particle-count bucket (log2 of N) and
-density bucket (steps of 0.05), so later runs of similar systems skip the
-search.
+k being the number of steps between list rebuilds of a system, measured on
+the caller's own system by a short trajectory from its current state (which
+is restored afterwards), unless the caller gives it.  Results are cached in a
+JSON file keyed by device, particle-count bucket (log2 of N) and density
+bucket (steps of 0.05), so later runs of similar systems skip the search.
 """
 from __future__ import annotations
 
@@ -76,11 +77,24 @@ def _measure(sim, reps: int, eps, sig, n_types):
     return f_ms, v_ms + c_ms
 
 
-def tune(sim, density: float, *, rebuild_interval: float = 5.0, reps: int = 5,
-         eps=(1.0, 1.0, 1.0), sig=(1.0, 1.0, 1.0), n_types: int = 1,
+def measure_rebuild_interval(sim, steps: int = 100, dt: float = 0.005, eps=(1.0, 1.0, 1.0),
+                     sig=(1.0, 1.0, 1.0), n_types: int = 1) -> float:
+    """Mean number of steps between list rebuilds of a system of `sim` over
+    `steps` steps from its current state; the state is restored afterwards."""
+    p, v, _ = sim.get()
+    r0 = sim.counters()[0]
+    sim.step(steps, dt, eps, sig, n_types)
+    r = sim.counters()[0] - r0
+    sim.set_particles(p, v)
+    return steps * sim.nsys / max(r, 1)
+
+
+def tune(sim, density: float, *, rebuild_interval: float | None = None, dt: float = 0.005,
+         reps: int = 5, eps=(1.0, 1.0, 1.0), sig=(1.0, 1.0, 1.0), n_types: int = 1,
          cache: str | None = DEFAULT_CACHE, force: bool = False, candidates=None):
     """Pick and apply the fastest launch shapes for `sim` (a ParticleSim or
-    BatchSim).  Returns (knobs, table of (knobs, force ms, build ms, cost))."""
+    BatchSim).  rebuild_interval None measures it (100 steps of size dt).
+    Returns (knobs, table of (knobs, force ms, build ms, cost))."""
     key_dev = _device_key(sim.device)
     key = bucket(sim.n, density)
     data = _load(cache) if cache else {}
@@ -89,6 +103,9 @@ def tune(sim, density: float, *, rebuild_interval: float = 5.0, reps: int = 5,
         knobs = tuple(hit["knobs"])
         sim.set_tuning(*knobs)
         return knobs, []
+    k = rebuild_interval
+    if k is None:
+        k = measure_rebuild_interval(sim, dt=dt, eps=eps, sig=sig, n_types=n_types)
     raw = []
     for knobs in candidates or CANDIDATES:
         sim.set_tuning(*knobs)
@@ -98,13 +115,13 @@ def tune(sim, density: float, *, rebuild_interval: float = 5.0, reps: int = 5,
     # the force kernel's time depends on the build path too (the order of the
     # entries it writes decides how many cache lines a gather touches), so each
     # candidate keeps its own force timing
-    table = [(knobs, f_ms, b_ms, f_ms + b_ms / rebuild_interval) for knobs, f_ms, b_ms in raw]
+    table = [(knobs, f_ms, b_ms, f_ms + b_ms / k) for knobs, f_ms, b_ms in raw]
     best = min(table, key=lambda r: r[3])
     sim.set_tuning(*best[0])
     if cache:
         data = _load(cache)
         data.setdefault(key_dev, {})[key] = {"knobs": list(best[0]), "force_ms": best[1],
                                              "build_ms": best[2], "cost_ms": best[3],
-                                             "n": sim.n}
+                                             "rebuild_interval": k, "n": sim.n}
         _save(cache, data)
     return best[0], table

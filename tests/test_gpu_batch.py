@@ -156,12 +156,19 @@ def test_autotuner_picks_a_candidate_and_caches_it(tmp_path):
     systems = systems_of([1, 2, 72, 400])
     sim = make_batch(systems)
     c0, l0 = (np_(t) for t in sim.neighbors())
+    p0, v0, _ = (np_(t) for t in sim.get())
     cache = str(tmp_path / "tuning.json")
+    # the rebuild interval is measured on a short trajectory, then the state restored
     knobs, table = tune(sim, 0.75, cache=cache, reps=2)
     assert knobs in CANDIDATES and len(table) == len(CANDIDATES)
     assert all(f > 0 and b > 0 for _, f, b, _ in table)
+    p1, v1, _ = (np_(t) for t in sim.get())
+    assert np.array_equal(p0, p1) and np.array_equal(v0, v1)
     c, l = (np_(t) for t in sim.neighbors())
     assert np.array_equal(c, c0)
+    import json
+    hit = next(iter(json.load(open(cache)).values()))
+    assert all(e["rebuild_interval"] > 1.0 for e in hit.values())
     again, table2 = tune(sim, 0.75, cache=cache)
     assert again == knobs and table2 == []  # served from the cache
 
