@@ -38,7 +38,7 @@ def make_sim(s, **kw):
     return ParticleSim(s.pos, s.box, PER, vel=s.vel, typ=s.typ, r_cut=RC, skin=SKIN, **kw)
 
 
-@pytest.mark.parametrize("n,mix", [(4096, True), (4097, False), (300, True)])
+@pytest.mark.parametrize("n,mix", [(4096, True), (4097, False), (300, True), (32768, True)])
 def test_force_vjp_matches_oracle(n, mix):
     s = inputs.lj_lattice(n, 1.2 if mix else 0.8442, 1.0, 5, mixture=mix)
     eps, sig = (MIX["eps"], MIX["sig"]) if mix else ((1.0,) * 3, (1.0,) * 3)

@@ -36,11 +36,12 @@ def rel_max(g, ref):
     return float(np.abs(g - ref).max() / math.sqrt((ref ** 2).mean()))
 
 
-def gpu_case(n, K, frame_every, ckpt_every, seed=5):
+def gpu_case(n, K, frame_every, ckpt_every, seed=5, zero_targets=False):
     """GPU gradients of the frame-averaged force MSE (targets from the FP64
-    oracle trajectory at theta_tgt = 1.05 theta), the GPU's frame forces, and
-    the GPU's positions at every step of the same forward pass (recorded by
-    repeating it step by step with the same rebuilds at the checkpoints)."""
+    oracle trajectory at theta_tgt = 1.05 theta, or zero), the GPU's frame
+    forces, and the GPU's positions at every step of the same forward pass
+    (recorded by repeating it step by step with the same rebuilds at the
+    checkpoints)."""
     import torch
     from paper_1804_07598_amd.adjoint import LJTrajFn
     from paper_1804_07598_amd.sim import ParticleSim
@@ -49,9 +50,12 @@ def gpu_case(n, K, frame_every, ckpt_every, seed=5):
     theta = np.float32(np.array(MIX["eps"] + MIX["sig"])).astype(np.float64)
     theta_t = 1.05 * theta
     frames = list(range(frame_every, K + 1, frame_every))
-    _, Ft, _ = O.lj_traj(s.pos, s.vel, s.box, PER, RC, float(dt), K, theta_t[:3], theta_t[3:],
-                         s.typ)
-    targets = np.stack([Ft[k] for k in frames])
+    if zero_targets:
+        targets = np.zeros((len(frames), n, 3))
+    else:
+        _, Ft, _ = O.lj_traj(s.pos, s.vel, s.box, PER, RC, float(dt), K, theta_t[:3],
+                             theta_t[3:], s.typ)
+        targets = np.stack([Ft[k] for k in frames])
     sim = ParticleSim(s.pos, s.box, PER, vel=s.vel, typ=s.typ, r_cut=RC, skin=SKIN)
     x0 = torch.tensor(s.pos, dtype=torch.float64, device="cuda", requires_grad=True)
     v0 = torch.tensor(s.vel, dtype=torch.float64, device="cuda", requires_grad=True)
@@ -96,6 +100,21 @@ def test_fp64_adjoint_on_gpu_states(n, K, fe, ce):
           f"theta {np.max(np.abs(gt - pt) / np.abs(pt)):.2e}")
     assert rel_max(gx, px) <= TOL and rel_max(gv, pv) <= TOL
     assert np.all(np.abs(gt - pt) <= TOL * np.abs(pt)), (gt, pt)
+
+
+def test_fp64_adjoint_on_gpu_states_full_size_segment():
+    """The bench's configuration (32,768-atom mixture, checkpoints and loss
+    frames every 20 steps), one segment: the FP64 sweep on the FP32 pair sets
+    of the GPU's own states against the GPU gradients (loss: mean squared
+    frame force, so no FP64 trajectory is needed for targets)."""
+    s, theta, dt, frames, targets, (gx, gv, gt), xs, fbar = gpu_case(32768, 20, 20, 20,
+                                                                      zero_targets=True)
+    ox, ov, ot = O.lj_traj_adjoint_f32(xs, s.box, PER, O.radius2(RC), float(dt), fbar,
+                                       theta[:3], theta[3:], s.typ)
+    print(f"n=32768 K=20: x {rel_max(gx, ox):.2e} v {rel_max(gv, ov):.2e} "
+          f"theta {np.max(np.abs(gt - ot) / np.abs(ot)):.2e}")
+    assert rel_max(gx, ox) <= TOL and rel_max(gv, ov) <= TOL
+    assert np.all(np.abs(gt - ot) <= TOL * np.abs(ot)), (gt, ot)
 
 
 def test_report_fp64_end_to_end_error_vs_length():
