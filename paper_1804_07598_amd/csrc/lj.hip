@@ -26,6 +26,7 @@ struct LJCoef {
     double a12[3];  // 4 sig^12: c12 at unit eps (the pair force is linear in eps)
     double a6[3];   // 4 sig^6
     double inv_sig[3];
+    float side_margin;  // half the skin, widened: see Sided
 };
 
 // 1/x in FP64: the hardware estimate (relative error up to 5e-8) refined by
@@ -38,18 +39,64 @@ __device__ __forceinline__ double recip(double x) {
     return fma(y, e, y);
 }
 
+// Image handling of a lane whose particle lies more than half the skin
+// (widened) from the box's mid-plane on every periodic axis.  Every particle
+// is within half the skin of its build position, which lies in [0, L)
+// (larger displacements rebuild the lists first), so a partner of a particle
+// in the lower half of an axis can only have t = x_j - x_i > -L/2, and one of
+// a particle in the upper half only t < L/2: each lane meets images across
+// one face per axis.  The predicate's image test then takes one compare
+// (sg t > L/2) and the shifted separation (x_i +- L) - x_j, exact in FP64 like
+// the unshifted one, so the results are those of the general form bit for
+// bit.  sg is 0 on closed axes.
+struct Sided {
+    float sg[3];
+    double xs[3];  // x_i + sg L
+};
+
+__device__ __forceinline__ Sided make_sided(float3 pi, double xi, double yi, double zi,
+                                            const Box &b, float margin, bool &ok) {
+    Sided sd;
+    const float p[3] = {pi.x, pi.y, pi.z};
+    const double x[3] = {xi, yi, zi};
+    ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const bool lo = p[a] < b.half[a];
+        sd.sg[a] = b.per[a] ? (lo ? 1.f : -1.f) : 0.f;
+        sd.xs[a] = x[a] + (double)(sd.sg[a] * b.L[a]);
+        ok = ok && (!b.per[a] || fabsf(p[a] - b.half[a]) > margin + 4e-7f * b.L[a]);
+    }
+    return sd;
+}
+
 // Separation x_i - x_j (exact FP64, image as chosen by the predicate), its
-// periodic shift, and membership of the pair in the force set.
-template <bool IMG>
+// periodic shift, and membership of the pair in the force set.  IMG 0: no
+// lane of the wavefront has image partners; 1: the general form; 2: the
+// one-face form of Sided.
+template <int IMG>
 __device__ __forceinline__ bool separation(float3 pi, double xi, double yi, double zi, float4 q,
                                            const Box &b, float rc2, double rc2lo, double rc2hi,
                                            double &dx, double &dy, double &dz, double &sx,
-                                           double &sy, double &sz) {
-    dx = xi - (double)q.x;
-    dy = yi - (double)q.y;
-    dz = zi - (double)q.z;
-    sx = sy = sz = 0.0;
-    if (IMG) {
+                                           double &sy, double &sz, const Sided *sd = nullptr) {
+    if (IMG == 2) {
+        const float tx = q.x - pi.x, ty = q.y - pi.y, tz = q.z - pi.z;
+        const double bx = sd->sg[0] * tx > b.half[0] ? sd->xs[0] : xi;
+        const double by = sd->sg[1] * ty > b.half[1] ? sd->xs[1] : yi;
+        const double bz = sd->sg[2] * tz > b.half[2] ? sd->xs[2] : zi;
+        dx = bx - (double)q.x;
+        dy = by - (double)q.y;
+        dz = bz - (double)q.z;
+        sx = bx - xi;
+        sy = by - yi;
+        sz = bz - zi;
+    } else {
+        dx = xi - (double)q.x;
+        dy = yi - (double)q.y;
+        dz = zi - (double)q.z;
+        sx = sy = sz = 0.0;
+    }
+    if (IMG == 1) {
         // the image as chosen by the predicate, with selects rather than branches
         const float tx = q.x - pi.x, ty = q.y - pi.y, tz = q.z - pi.z;
         const double Lx = b.per[0] ? (double)b.L[0] : 0.0, Ly = b.per[1] ? (double)b.L[1] : 0.0,
@@ -116,12 +163,13 @@ struct Acc {
     double wxx = 0.0, wyy = 0.0, wzz = 0.0, wxy = 0.0, wxz = 0.0, wyz = 0.0;
 };
 
-template <int NT, bool IMG>
+template <int NT, int IMG>
 __device__ __forceinline__ void pair(Acc &a, float3 pi, double xi, double yi, double zi,
                                      const LaneCoef &cf, float4 q, const Box &b, float rc2,
-                                     double rc2lo, double rc2hi) {
+                                     double rc2lo, double rc2hi, const Sided &sd) {
     double dx, dy, dz, sx, sy, sz;
-    if (separation<IMG>(pi, xi, yi, zi, q, b, rc2, rc2lo, rc2hi, dx, dy, dz, sx, sy, sz)) {
+    if (separation<IMG>(pi, xi, yi, zi, q, b, rc2, rc2lo, rc2hi, dx, dy, dz, sx, sy, sz,
+                        &sd)) {
         double c12, c6;
         coef<NT>(cf, nbr_type<NT>(q), c12, c6);
         const double r2i = recip(fma(dx, dx, fma(dy, dy, dz * dz)));
@@ -178,11 +226,11 @@ __device__ __forceinline__ void gather(const float4 *__restrict__ pos, const Ent
 // software-pipelined: the neighbour positions of the next group and the list
 // entries of the one after are requested before the current group is
 // computed, so their latency overlaps the pair arithmetic.
-template <int NT, bool IMG, int UNR>
+template <int NT, int IMG, int UNR>
 __device__ __forceinline__ void walk(Acc &a, const float4 *__restrict__ pos,
                                      const int4 *__restrict__ lst, int cnt, float4 pi4,
                                      const Box &b, float rc2, double rc2lo, double rc2hi,
-                                     const LJCoef &cf) {
+                                     const LJCoef &cf, const Sided &sd) {
     if (cnt <= 0) return;
     const float3 pi = xyz(pi4);
     const double xi = pi.x, yi = pi.y, zi = pi.z;
@@ -197,13 +245,13 @@ __device__ __forceinline__ void walk(Acc &a, const float4 *__restrict__ pos,
         nxt = list_group<UNR>(lst, k + 2 * UNR < cnt ? k + 2 * UNR : k);
 #pragma unroll
         for (int u = 0; u < UNR; u++)
-            pair<NT, IMG>(a, pi, xi, yi, zi, lc, q0[u], b, rc2, rc2lo, rc2hi);
+            pair<NT, IMG>(a, pi, xi, yi, zi, lc, q0[u], b, rc2, rc2lo, rc2hi, sd);
         if (k + UNR >= cnt) break;
         gather<UNR>(pos, nxt, q0);
         nxt = list_group<UNR>(lst, k + 3 * UNR < cnt ? k + 3 * UNR : k);
 #pragma unroll
         for (int u = 0; u < UNR; u++)
-            pair<NT, IMG>(a, pi, xi, yi, zi, lc, q1[u], b, rc2, rc2lo, rc2hi);
+            pair<NT, IMG>(a, pi, xi, yi, zi, lc, q1[u], b, rc2, rc2lo, rc2hi, sd);
     }
 }
 
@@ -268,10 +316,14 @@ __global__ __launch_bounds__(kBlock) void k_lj(State st, float rc2, double rc2lo
     const int4 *lst = reinterpret_cast<const int4 *>(st.nbr) +
                       ((i >> 6) * (int64_t)cap4) * 64 + (i & 63);
     Acc a;
-    if (img_wave)
-        walk<NT, true, UNR>(a, pos, lst, cnt, pi4, b, rc2, rc2lo, rc2hi, cf);
+    bool side_ok = true;
+    const Sided sd = make_sided(xyz(pi4), pi4.x, pi4.y, pi4.z, b, cf.side_margin, side_ok);
+    if (img_wave && __ballot(active && !side_ok) == 0)
+        walk<NT, 2, UNR>(a, pos, lst, cnt, pi4, b, rc2, rc2lo, rc2hi, cf, sd);
+    else if (img_wave)
+        walk<NT, 1, UNR>(a, pos, lst, cnt, pi4, b, rc2, rc2lo, rc2hi, cf, sd);
     else
-        walk<NT, false, UNR>(a, pos, lst, cnt, pi4, b, rc2, rc2lo, rc2hi, cf);
+        walk<NT, 0, UNR>(a, pos, lst, cnt, pi4, b, rc2, rc2lo, rc2hi, cf, sd);
     double ke = 0.0;
     bool over = false;
     if (active) {
@@ -346,12 +398,14 @@ struct VjpAcc {
     double ge[2] = {0.0, 0.0}, gs[2] = {0.0, 0.0};
 };
 
-template <int NT, bool IMG>
+template <int NT, int IMG>
 __device__ __forceinline__ void vjp_pair(VjpAcc &a, float3 pi, double xi, double yi, double zi,
                                          const LaneCoef &cf, float4 li, float4 q, float4 lj,
-                                         const Box &b, float rc2, double rc2lo, double rc2hi) {
+                                         const Box &b, float rc2, double rc2lo, double rc2hi,
+                                         const Sided &sd) {
     double dx, dy, dz, sx, sy, sz;
-    if (separation<IMG>(pi, xi, yi, zi, q, b, rc2, rc2lo, rc2hi, dx, dy, dz, sx, sy, sz)) {
+    if (separation<IMG>(pi, xi, yi, zi, q, b, rc2, rc2lo, rc2hi, dx, dy, dz, sx, sy, sz,
+                        &sd)) {
         const int tj = nbr_type<NT>(q);
         double c12, c6;
         coef<NT>(cf, tj, c12, c6);
@@ -382,12 +436,12 @@ __device__ __forceinline__ void vjp_pair(VjpAcc &a, float3 pi, double xi, double
     }
 }
 
-template <int NT, bool IMG>
+template <int NT, int IMG>
 __device__ __forceinline__ void vjp_walk(VjpAcc &a, const float4 *__restrict__ pos,
                                          const float4 *__restrict__ lam,
                                          const int4 *__restrict__ lst, int cnt, float4 pi4,
                                          float4 li, const Box &b, float rc2, double rc2lo,
-                                         double rc2hi, const LJCoef &cf) {
+                                         double rc2hi, const LJCoef &cf, const Sided &sd) {
     const float3 pi = xyz(pi4);
     const double xi = pi.x, yi = pi.y, zi = pi.z;
     const LaneCoef lc = lane_coef<NT>(cf, __float_as_int(pi4.w));
@@ -404,7 +458,7 @@ __device__ __forceinline__ void vjp_walk(VjpAcc &a, const float4 *__restrict__ p
         }
 #pragma unroll
         for (int u = 0; u < 4; u++)
-            vjp_pair<NT, IMG>(a, pi, xi, yi, zi, lc, li, q[u], l[u], b, rc2, rc2lo, rc2hi);
+            vjp_pair<NT, IMG>(a, pi, xi, yi, zi, lc, li, q[u], l[u], b, rc2, rc2lo, rc2hi, sd);
     }
 }
 
@@ -445,10 +499,14 @@ __global__ __launch_bounds__(kBlock) void k_lj_vjp(State st, float rc2, double r
     const int4 *lst = reinterpret_cast<const int4 *>(st.nbr) +
                       ((i >> 6) * (int64_t)cap4) * 64 + (i & 63);
     VjpAcc a;
-    if (img_wave)
-        vjp_walk<NT, true>(a, pos, st.aux, lst, cnt, pi4, li, b, rc2, rc2lo, rc2hi, cf);
+    bool side_ok = true;
+    const Sided sd = make_sided(xyz(pi4), pi4.x, pi4.y, pi4.z, b, cf.side_margin, side_ok);
+    if (img_wave && __ballot(active && !side_ok) == 0)
+        vjp_walk<NT, 2>(a, pos, st.aux, lst, cnt, pi4, li, b, rc2, rc2lo, rc2hi, cf, sd);
+    else if (img_wave)
+        vjp_walk<NT, 1>(a, pos, st.aux, lst, cnt, pi4, li, b, rc2, rc2lo, rc2hi, cf, sd);
     else
-        vjp_walk<NT, false>(a, pos, st.aux, lst, cnt, pi4, li, b, rc2, rc2lo, rc2hi, cf);
+        vjp_walk<NT, 0>(a, pos, st.aux, lst, cnt, pi4, li, b, rc2, rc2lo, rc2hi, cf, sd);
     if (active) {
         const int64_t r = st.id[0][i];
         const double g[3] = {a.gx, a.gy, a.gz};
@@ -791,7 +849,7 @@ __global__ __launch_bounds__(kBlock) void k_lj_sym2(State st, int cap4, StepArgs
     }
 }
 
-LJCoef make_coef(const fpm_lj_params &p) {
+LJCoef make_coef(const fpm_ctx *c, const fpm_lj_params &p) {
     LJCoef cf;
     for (int k = 0; k < 3; k++) {
         const double e = (double)p.eps[k], s = (double)p.sig[k];
@@ -802,6 +860,8 @@ LJCoef make_coef(const fpm_lj_params &p) {
         cf.a6[k] = 4.0 * s6;
         cf.inv_sig[k] = 1.0 / s;
     }
+    // particles stay within half the skin of their build positions
+    cf.side_margin = 0.5f * c->skin * 1.001f + 1e-4f;
     return cf;
 }
 
@@ -811,7 +871,7 @@ namespace {
 
 template <int MODE>
 void launch_lj_mode(fpm_ctx *c, const fpm_lj_params &p, const StepArgs &sa) {
-    const LJCoef cf = make_coef(p);
+    const LJCoef cf = make_coef(c, p);
     const double band = predicate_band(c);
     const double rc2lo = (double)c->rc2 * (1.0 - band), rc2hi = (double)c->rc2 * (1.0 + band);
     const dim3 g((unsigned)c->nblk), t(kBlock);
@@ -841,7 +901,7 @@ namespace {
 // (the force partials, or the step's ring row).
 template <int MODE>
 void launch_sym_mode(fpm_ctx *c, const fpm_lj_params &p, const StepArgs &sa, double *part) {
-    const LJCoef cf = make_coef(p);
+    const LJCoef cf = make_coef(c, p);
     const double band = predicate_band(c);
     const double rc2lo = (double)c->rc2 * (1.0 - band), rc2hi = (double)c->rc2 * (1.0 + band);
     const dim3 g((unsigned)c->nblk), t(kBlock);
@@ -887,7 +947,7 @@ hipError_t launch_sym_index(fpm_ctx *c) {
 
 hipError_t launch_lj_vjp(fpm_ctx *c, const fpm_lj_params &p, const double *lam,
                          const double *vbar, const AdjOut &o) {
-    const LJCoef cf = make_coef(p);
+    const LJCoef cf = make_coef(c, p);
     const double band = predicate_band(c);
     const double rc2lo = (double)c->rc2 * (1.0 - band), rc2hi = (double)c->rc2 * (1.0 + band);
     const dim3 g((unsigned)c->nblk), t(kBlock);
