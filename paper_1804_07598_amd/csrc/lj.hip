@@ -645,14 +645,23 @@ __global__ __launch_bounds__(kBlock) void k_sym_index(State st, int cap, int cap
     if (miss) st.ctl->sym_miss = 1;
 }
 
-// Exact FP64 separation x_i - x_j for the image the FP32 predicate takes.
-template <bool IMG>
+// Exact FP64 separation x_i - x_j for the image the FP32 predicate takes
+// (IMG as in separation).
+template <int IMG>
 __device__ __forceinline__ void pair_sep(float3 pi, double xi, double yi, double zi, float4 q,
-                                         const Box &b, double &dx, double &dy, double &dz) {
+                                         const Box &b, double &dx, double &dy, double &dz,
+                                         const Sided &sd) {
+    if (IMG == 2) {
+        const float tx = q.x - pi.x, ty = q.y - pi.y, tz = q.z - pi.z;
+        dx = (sd.sg[0] * tx > b.half[0] ? sd.xs[0] : xi) - (double)q.x;
+        dy = (sd.sg[1] * ty > b.half[1] ? sd.xs[1] : yi) - (double)q.y;
+        dz = (sd.sg[2] * tz > b.half[2] ? sd.xs[2] : zi) - (double)q.z;
+        return;
+    }
     dx = xi - (double)q.x;
     dy = yi - (double)q.y;
     dz = zi - (double)q.z;
-    if (IMG) {
+    if (IMG == 1) {
         const float tx = q.x - pi.x, ty = q.y - pi.y, tz = q.z - pi.z;
         const double Lx = b.per[0] ? (double)b.L[0] : 0.0, Ly = b.per[1] ? (double)b.L[1] : 0.0,
                      Lz = b.per[2] ? (double)b.L[2] : 0.0;
@@ -662,11 +671,11 @@ __device__ __forceinline__ void pair_sep(float3 pi, double xi, double yi, double
     }
 }
 
-template <int NT, bool IMG>
+template <int NT, int IMG>
 __device__ __forceinline__ void sym_upper(const State &st, int64_t i, int p0, int cnt, float4 pi4,
                                           const Box &b, float rc2, double rc2lo, double rc2hi,
                                           const LJCoef &cf, int cap4, double (&f)[3], double &u,
-                                          double (&w)[6]) {
+                                          double (&w)[6], const Sided &sd) {
     const float3 pi = xyz(pi4);
     const double xi = pi.x, yi = pi.y, zi = pi.z;
     const LaneCoef lc = lane_coef<NT>(cf, __float_as_int(pi4.w));
@@ -695,7 +704,7 @@ __device__ __forceinline__ void sym_upper(const State &st, int64_t i, int p0, in
             if (!on[t]) continue;
             double dx, dy, dz, sx, sy, sz;
             if (separation<IMG>(pi, xi, yi, zi, q[t], b, rc2, rc2lo, rc2hi, dx, dy, dz, sx, sy,
-                                sz)) {
+                                sz, &sd)) {
                 double c12, c6;
                 coef<NT>(lc, nbr_type<NT>(q[t]), c12, c6);
                 const double r2i = recip(fma(dx, dx, fma(dy, dy, dz * dz)));
@@ -742,10 +751,14 @@ __global__ __launch_bounds__(kBlock) void k_lj_sym1(State st, float rc2, double 
     const bool img_wave = __ballot((nn & kWrapBit) != 0) != 0;
     const int cnt = min((int)(nn & ~kWrapBit), cap);
     double f[3] = {0.0, 0.0, 0.0}, u = 0.0, w[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (img_wave)
-        sym_upper<NT, true>(st, i, p0, cnt, pi4, b, rc2, rc2lo, rc2hi, cf, cap4, f, u, w);
+    bool side_ok = true;
+    const Sided sd = make_sided(xyz(pi4), pi4.x, pi4.y, pi4.z, b, cf.side_margin, side_ok);
+    if (img_wave && __ballot(active && !side_ok) == 0)
+        sym_upper<NT, 2>(st, i, p0, cnt, pi4, b, rc2, rc2lo, rc2hi, cf, cap4, f, u, w, sd);
+    else if (img_wave)
+        sym_upper<NT, 1>(st, i, p0, cnt, pi4, b, rc2, rc2lo, rc2hi, cf, cap4, f, u, w, sd);
     else
-        sym_upper<NT, false>(st, i, p0, cnt, pi4, b, rc2, rc2lo, rc2hi, cf, cap4, f, u, w);
+        sym_upper<NT, 0>(st, i, p0, cnt, pi4, b, rc2, rc2lo, rc2hi, cf, cap4, f, u, w, sd);
     if (active)
         for (int c = 0; c < 3; c++) st.fown[3 * i + c] = f[c];
     double v[7] = {u, w[0], w[1], w[2], w[3], w[4], w[5]};
@@ -754,9 +767,10 @@ __global__ __launch_bounds__(kBlock) void k_lj_sym1(State st, float rc2, double 
     block_partials<7>(v, slot, op, part, st.pstride);
 }
 
-template <bool IMG>
+template <int IMG>
 __device__ __forceinline__ void sym_lower(const State &st, int64_t j, int p, float4 pj4,
-                                          const Box &b, int cap4, double (&f)[3]) {
+                                          const Box &b, int cap4, double (&f)[3],
+                                          const Sided &sd) {
     const float3 pj = xyz(pj4);
     const double xj = pj.x, yj = pj.y, zj = pj.z;
     const float4 *__restrict__ pos = st.pos[0];
@@ -787,7 +801,7 @@ __device__ __forceinline__ void sym_lower(const State &st, int64_t j, int p, flo
         for (int t = 0; t < 4; t++) {
             if (4 * g + t >= p) continue;
             double dx, dy, dz;
-            pair_sep<IMG>(pj, xj, yj, zj, q[t], b, dx, dy, dz);
+            pair_sep<IMG>(pj, xj, yj, zj, q[t], b, dx, dy, dz, sd);
             f[0] = fma(sv[t], dx, f[0]);
             f[1] = fma(sv[t], dy, f[1]);
             f[2] = fma(sv[t], dz, f[2]);
@@ -798,7 +812,8 @@ __device__ __forceinline__ void sym_lower(const State &st, int64_t j, int p, flo
 // Pass 2 (see above): reactions from the lower partners, then the forces and
 // (MODE kLjStep, kLjLast) the step's updates as in k_lj.
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_lj_sym2(State st, int cap4, StepArgs sa) {
+__global__ __launch_bounds__(kBlock) void k_lj_sym2(State st, int cap4, StepArgs sa,
+                                                    float side_margin) {
     const int sys = block_system(st);
     const SysDesc &d = st.sys[sys];
     const Box b = d.box;
@@ -816,10 +831,15 @@ __global__ __launch_bounds__(kBlock) void k_lj_sym2(State st, int cap4, StepArgs
         if (MODE == kLjStep) xb4 = st.xbuild[i];
         for (int c = 0; c < 3; c++) f[c] = st.fown[3 * i + c];
     }
-    if (__ballot((nn & kWrapBit) != 0) != 0)
-        sym_lower<true>(st, i, p, pi4, b, cap4, f);
+    bool side_ok = true;
+    const Sided sd = make_sided(xyz(pi4), pi4.x, pi4.y, pi4.z, b, side_margin, side_ok);
+    const bool img_wave = __ballot((nn & kWrapBit) != 0) != 0;
+    if (img_wave && __ballot(active && !side_ok) == 0)
+        sym_lower<2>(st, i, p, pi4, b, cap4, f, sd);
+    else if (img_wave)
+        sym_lower<1>(st, i, p, pi4, b, cap4, f, sd);
     else
-        sym_lower<false>(st, i, p, pi4, b, cap4, f);
+        sym_lower<0>(st, i, p, pi4, b, cap4, f, sd);
     double ke = 0.0;
     bool over = false;
     if (active) {
@@ -849,6 +869,10 @@ __global__ __launch_bounds__(kBlock) void k_lj_sym2(State st, int cap4, StepArgs
     }
 }
 
+// Margin of the one-face image form (Sided): particles stay within half the
+// skin of their build positions.
+float side_margin(const fpm_ctx *c) { return 0.5f * c->skin * 1.001f + 1e-4f; }
+
 LJCoef make_coef(const fpm_ctx *c, const fpm_lj_params &p) {
     LJCoef cf;
     for (int k = 0; k < 3; k++) {
@@ -860,8 +884,7 @@ LJCoef make_coef(const fpm_ctx *c, const fpm_lj_params &p) {
         cf.a6[k] = 4.0 * s6;
         cf.inv_sig[k] = 1.0 / s;
     }
-    // particles stay within half the skin of their build positions
-    cf.side_margin = 0.5f * c->skin * 1.001f + 1e-4f;
+    cf.side_margin = side_margin(c);
     return cf;
 }
 
@@ -911,7 +934,8 @@ void launch_sym_mode(fpm_ctx *c, const fpm_lj_params &p, const StepArgs &sa, dou
     else
         hipLaunchKernelGGL(k_lj_sym1<1>, g, t, 0, c->stream, c->st, c->rc2, rc2lo, rc2hi, cf,
                            c->cap, c->cap4, part);
-    hipLaunchKernelGGL(k_lj_sym2<MODE>, g, t, 0, c->stream, c->st, c->cap4, sa);
+    hipLaunchKernelGGL(k_lj_sym2<MODE>, g, t, 0, c->stream, c->st, c->cap4, sa,
+                       side_margin(c));
 }
 
 }  // namespace
