@@ -128,7 +128,11 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 __device__ __forceinline__ int pblock() { return xcd_block((int)blockIdx.x, (int)gridDim.x); }
 
 // The system of the current particle workgroup (uniform over the workgroup).
-__device__ __forceinline__ int block_system(const State &st) { return st.blk2sys[pblock()]; }
+// (a single system needs no table load: kernels then start their loads of
+// the system's description at once)
+__device__ __forceinline__ int block_system(const State &st) {
+    return st.nsys == 1 ? 0 : st.blk2sys[pblock()];
+}
 
 // Global slot of this thread in a particle kernel (systems are block aligned).
 __device__ __forceinline__ int64_t global_slot() {

@@ -472,7 +472,7 @@ void k_verlet_grp(State st, const int32_t *blocks, float R2, int cap, int cap4, 
     __shared__ int rowc8[64];            // padded list lengths of the row
     const int r = xcd_block((int)blockIdx.x, (int)gridDim.x);
     const int blk = blocks[r >> 2];
-    const int s = st.blk2sys[blk];
+    const int s = st.nsys == 1 ? 0 : st.blk2sys[blk];
     if (!rebuilding(st, s)) return;
     const SysDesc &d = st.sys[s];
     const Box &b = d.box;
@@ -624,7 +624,7 @@ void k_verlet_grp(State st, const int32_t *blocks, float R2, int cap, int cap4, 
 __global__ __launch_bounds__(kBlock) void k_verlet(State st, const int32_t *blocks, float R2,
                                                    int cap, int cap4) {
     const int blk = blocks[blockIdx.x];
-    const int s = st.blk2sys[blk];
+    const int s = st.nsys == 1 ? 0 : st.blk2sys[blk];
     if (!rebuilding(st, s)) return;
     const SysDesc &d = st.sys[s];
     const Box b = d.box;
@@ -952,7 +952,7 @@ __global__ __launch_bounds__(kBlock) void k_verlet_ls(State st, const int32_t *b
                                                       int cap, int cap4) {
 #pragma clang fp contract(off)
     const int blk = blocks[xcd_block((int)blockIdx.x, (int)gridDim.x)];
-    const int s = st.blk2sys[blk];
+    const int s = st.nsys == 1 ? 0 : st.blk2sys[blk];
     if (!rebuilding(st, s)) return;
     const SysDesc &d = st.sys[s];
     const Box &b = d.box;
