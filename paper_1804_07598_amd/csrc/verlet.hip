@@ -470,6 +470,7 @@ void k_verlet_grp(State st, const int32_t *blocks, float R2, int cap, int cap4, 
     constexpr int NC = (9 + G - 1) / G;  // neighbour columns held per lane
     extern __shared__ int4 lrow[];       // lcap4 * 64 int4: the row's first lcap4 groups
     __shared__ int rowc8[64];            // padded list lengths of the row
+    if (st.nsys == 1 && !rebuilding(st, 0)) return;  // a single system: no table loads first
     const int r = xcd_block((int)blockIdx.x, (int)gridDim.x);
     const int blk = blocks[r >> 2];
     const int s = st.nsys == 1 ? 0 : st.blk2sys[blk];
@@ -623,6 +624,7 @@ void k_verlet_grp(State st, const int32_t *blocks, float R2, int cap, int cap4, 
 // runs over the list of particle workgroups of the systems built this way.
 __global__ __launch_bounds__(kBlock) void k_verlet(State st, const int32_t *blocks, float R2,
                                                    int cap, int cap4) {
+    if (st.nsys == 1 && !rebuilding(st, 0)) return;  // a single system: no table loads first
     const int blk = blocks[blockIdx.x];
     const int s = st.nsys == 1 ? 0 : st.blk2sys[blk];
     if (!rebuilding(st, s)) return;
@@ -951,6 +953,7 @@ __device__ __forceinline__ bool test_cand(float4 q, float3 a, float3 pk, float R
 __global__ __launch_bounds__(kBlock) void k_verlet_ls(State st, const int32_t *blocks, float R2,
                                                       int cap, int cap4) {
 #pragma clang fp contract(off)
+    if (st.nsys == 1 && !rebuilding(st, 0)) return;  // a single system: no table loads first
     const int blk = blocks[xcd_block((int)blockIdx.x, (int)gridDim.x)];
     const int s = st.nsys == 1 ? 0 : st.blk2sys[blk];
     if (!rebuilding(st, s)) return;
