@@ -102,7 +102,7 @@ def lib() -> C.CDLL:
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+            raise ImportError(f"{LIB_PATH} is not built; run "
                               "python paper_1804_07598_amd/build.py")
         L = C.CDLL(LIB_PATH)
         for name, args in _SIGS.items():
