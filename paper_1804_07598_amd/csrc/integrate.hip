@@ -219,7 +219,11 @@ __global__ __launch_bounds__(kBlock) void k_set_positions(State st, const float 
         p.y = pos[3 * r + 1];
         p.z = pos[3 * r + 2];
         st.pos[0][i] = p;
-        d2 = dist2_pred(xyz(st.xbuild[i]), xyz(p), d.box);
+        // measured without periodic images: a position moved by whole periods
+        // counts as far away, so the rebuild wraps it back into the box (the
+        // force kernels rely on every position lying within half the skin of
+        // [0, L) on periodic axes)
+        d2 = dist2_direct(xyz(st.xbuild[i]), xyz(p));
         if (!isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z)) st.ctl->nonfinite = 1;
     }
     double v1[1] = {d2};

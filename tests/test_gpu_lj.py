@@ -207,6 +207,29 @@ def test_particles_on_faces_and_empty_cells():
     compare_sets(sim, s.pos, s.box, O.radius2(RC, SKIN))
 
 
+def test_set_positions_moved_by_whole_periods():
+    # a small move plus a whole-period shift is a small move of the periodic
+    # system: the forces must be those of the wrapped positions
+    s = inputs.lj_lattice(4096, 0.8442, 1.0, seed=21)
+    sim = make_sim(s)
+    check_lj(sim, s.pos, s.box)
+    rng = np.random.default_rng(22)
+    moved = (s.pos + rng.uniform(-0.02, 0.02, s.pos.shape)).astype(np.float32)
+    moved = np.mod(moved, np.float32(s.box)).astype(np.float32)
+    shifted = moved.copy()
+    k = rng.choice(len(moved), 300, replace=False)
+    shifted[k] += (rng.integers(-1, 2, (300, 3)) * s.box).astype(np.float32)
+    sim.set_positions(shifted)
+    sim.lj_forces()
+    pg = np_(sim.get()[0])
+    # wrapped back into the box, up to the FP32 rounding of (x +- L) -+ L
+    assert pg.min() >= 0 and (pg < s.box).all()
+    d = pg - moved
+    d -= s.box * np.round(d / s.box)
+    assert np.abs(d).max() <= 4e-6 * s.box.max()
+    check_lj(sim, pg, s.box)
+
+
 @pytest.mark.parametrize("tuning", [None, (3, 0, 8), (4, 8, 8), (5, 0, 8)])
 def test_overflow_is_reported(tuning):
     from paper_1804_07598_amd._lib import FpmError, FPM_EOVERFLOW
