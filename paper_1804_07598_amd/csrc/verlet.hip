@@ -1107,9 +1107,26 @@ __global__ __launch_bounds__(kBlock) void k_verlet_ls(State st, const int32_t *b
         for (int pr = 0; pr < 4; pr++)
             walk(w[pr][0], w[8 - pr][0], pr, 8 - pr, shx[pr], shx[8 - pr], 0, 0);
         walk(w[4][0], none, 4, 4, shx[4], false, 0, 0);
+    } else if (!sorted) {
+        // some lane's column wraps in z: each column's two pieces in one walk
+        // (together they span the same z-range as an unwrapped window)
+        const bool sz0 = azs[0] != 0.f || pks[0] != pi.z, sz1 = azs[1] != 0.f || pks[1] != pi.z;
+#pragma unroll 1
+        for (int k = 0; k < 9; k++) {
+            Piece P0 = none, P1 = none;
+            bool shk = false;
+#pragma unroll
+            for (int t = 0; t < 9; t++) {
+                P0 = t == k ? w[t][0] : P0;
+                P1 = t == k ? w[t][1] : P1;
+                shk = t == k ? shx[t] : shk;
+            }
+            walk(P0, P1, k, k, shk || sz0, shk || sz1, 0, 1);
+        }
     } else {
-        // general form: every piece of every column on its own (one copy of
-        // the walk; the piece is picked from registers by a select chain)
+        // ascending slot order: every piece of every column on its own (one
+        // copy of the walk; the piece is picked from registers by a select
+        // chain)
 #pragma unroll 1
         for (int q = 0; q < 18; q++) {
             int kg = 0;
