@@ -950,8 +950,10 @@ __device__ __forceinline__ bool test_cand(float4 q, float3 a, float3 pk, float R
     return sxy + zz <= R2;
 }
 
-__global__ __launch_bounds__(kBlock) void k_verlet_ls(State st, const int32_t *blocks, float R2,
-                                                      int cap, int cap4) {
+// Registers held to 128 per lane: four waves per SIMD, as many as the LDS
+// rings (36 KB per workgroup) allow, without spills.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+void k_verlet_ls(State st, const int32_t *blocks, float R2, int cap, int cap4) {
 #pragma clang fp contract(off)
     if (st.nsys == 1 && !rebuilding(st, 0)) return;  // a single system: no table loads first
     const int blk = blocks[xcd_block((int)blockIdx.x, (int)gridDim.x)];
@@ -1076,6 +1078,48 @@ __global__ __launch_bounds__(kBlock) void k_verlet_ls(State st, const int32_t *b
             }
         }
     };
+    // the same over four pieces: both z-pieces of column ka, then both of
+    // column kb (lanes whose column wraps in z have two)
+    auto walk4 = [&](const Piece *P, int ka, int kb, bool sxa, bool sxb, bool sz0, bool sz1) {
+        constexpr int U = 8;
+        const int c1 = P[0].len, c2 = c1 + P[1].len, c3 = c2 + P[2].len, tot = c3 + P[3].len;
+        float axa, aya, pxa, pya, axb, ayb, pxb, pyb;
+        int col;
+        column_of(b, ix, iy, pi.x, pi.y, ka, axa, aya, pxa, pya, col);
+        column_of(b, ix, iy, pi.x, pi.y, kb, axb, ayb, pxb, pyb, col);
+        for (int m = 0; __ballot(m < tot) != 0; m += U) {
+            int jj[U];
+            float4 q[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int mu = m + u;
+                const int base = mu < c1 ? P[0].lo
+                                 : mu < c2 ? P[1].lo - c1
+                                 : mu < c3 ? P[2].lo - c2 : P[3].lo - c3;
+                jj[u] = mu < tot ? base + mu : P[0].lo;
+            }
+#pragma unroll
+            for (int u = 0; u < U; u++)
+                q[u] = *reinterpret_cast<const float4 *>(pbase + ((uint32_t)jj[u] << 4));
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int mu = m + u;
+                const bool inb = mu >= c2;
+                const bool g1 = inb ? mu >= c3 : mu >= c1;
+                const float3 a = make_float3(inb ? axb : axa, inb ? ayb : aya, g1 ? azs[1] : azs[0]);
+                const float3 pk = make_float3(inb ? pxb : pxa, inb ? pyb : pya, g1 ? pks[1] : pks[0]);
+                if (mu < tot && test_cand<true>(q[u], a, pk, R2) && jj[u] != (int)i) {
+                    put(ring, cap, cnt, jj[u]);
+                    img |= (inb ? sxb : sxa) || (g1 ? sz1 : sz0);
+                }
+            }
+            if (__ballot(min(cnt, cap) - done >= kFlushAt) != 0) {
+                const int upto = min(cnt, cap) & ~3;
+                flush_ring(ring, gl, done, upto);
+                done = upto;
+            }
+        }
+    };
     const Piece none{0, 0};
     // symmetric-list systems need every list in ascending slot order: each
     // lane walks its pieces sorted by their first slot (a window is one
@@ -1108,20 +1152,26 @@ __global__ __launch_bounds__(kBlock) void k_verlet_ls(State st, const int32_t *b
             walk(w[pr][0], w[8 - pr][0], pr, 8 - pr, shx[pr], shx[8 - pr], 0, 0);
         walk(w[4][0], none, 4, 4, shx[4], false, 0, 0);
     } else if (!sorted) {
-        // some lane's column wraps in z: each column's two pieces in one walk
-        // (together they span the same z-range as an unwrapped window)
+        // some lane's column wraps in z: pairs of opposite columns with both
+        // z-pieces of each (together a column's pieces span the z-range of an
+        // unwrapped window), then the particle's own column
         const bool sz0 = azs[0] != 0.f || pks[0] != pi.z, sz1 = azs[1] != 0.f || pks[1] != pi.z;
 #pragma unroll 1
-        for (int k = 0; k < 9; k++) {
-            Piece P0 = none, P1 = none;
-            bool shk = false;
+        for (int pr = 0; pr < 5; pr++) {
+            Piece P[4] = {none, none, none, none};
+            bool sxa = false, sxb = false;
 #pragma unroll
-            for (int t = 0; t < 9; t++) {
-                P0 = t == k ? w[t][0] : P0;
-                P1 = t == k ? w[t][1] : P1;
-                shk = t == k ? shx[t] : shk;
+            for (int t = 0; t < 5; t++) {
+                P[0] = t == pr ? w[t][0] : P[0];
+                P[1] = t == pr ? w[t][1] : P[1];
+                sxa = t == pr ? shx[t] : sxa;
+                if (t < 4) {
+                    P[2] = t == pr ? w[8 - t][0] : P[2];
+                    P[3] = t == pr ? w[8 - t][1] : P[3];
+                    sxb = t == pr ? shx[8 - t] : sxb;
+                }
             }
-            walk(P0, P1, k, k, shk || sz0, shk || sz1, 0, 1);
+            walk4(P, pr, 8 - pr, sxa, sxb, sz0, sz1);
         }
     } else {
         // ascending slot order: every piece of every column on its own (one
