@@ -377,8 +377,9 @@ int fpm_read_counters(fpm_ctx *ctx, int64_t h_out[3]);
  * 5 one lane per particle with the lanes of a wavefront walking their windows
  * in step (2, 3, 4 and 5 where the grid has >= 3 cells per axis; elsewhere
  * paths 2 and 3 take path 1 and paths 4 and 5 run lane groups over whole
- * cells; automatic takes 3 when max_nbr is at most 48, else 5 for systems of at
- * least 131,072 particles and 4 for smaller ones, and lane groups over whole
+ * cells; automatic takes 3 when max_nbr is at most 48, else 5 when the
+ * context holds at least 131,072 particles (all systems together) and 4
+ * below that, and lane groups over whole
  * cells for small grids; max_nbr stands in for the list length here, since
  * the lists are not known before the first build).  zblock: z-cells per column workgroup (1..64);
  * for path 4, lanes per particle (0 = 8, 4, 8 or 16; other values are

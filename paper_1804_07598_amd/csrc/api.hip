@@ -64,6 +64,8 @@ Plan make_plan(const fpm_ctx *c, const std::vector<int64_t> &cnt) {
     const int nsys = (int)cnt.size();
     int64_t slot = 0, caller = 0;
     int blk = 0, cell = 0, offb = 0, item = 0;
+    int64_t total = 0;
+    for (int64_t v : cnt) total += v;
     for (int s = 0; s < nsys; s++) {
         SysHost h{};
         SysDesc &d = h.d;
@@ -84,14 +86,16 @@ Plan make_plan(const fpm_ctx *c, const std::vector<int64_t> &cnt) {
         // build): capacities up to kShortListCap take -1 (short lists come
         // from column runs of a few candidates, which would leave most lanes
         // of a group idle: 688,380 grains, about 6 entries, 89 us against
-        // 206 us); longer lists take -4 for systems of at least
-        // kLockstepMinSlots particles (1M LJ atoms, 76 entries: 452 against
-        // 518 us) and -2 below that, where the lockstep build's one workgroup
-        // per 256 slots would leave the device short of workgroups; grids of
-        // fewer than three cells per axis take -3.
+        // 206 us); longer lists take -4 for contexts of at least
+        // kLockstepMinSlots particles, all systems together (1M LJ atoms, 76
+        // entries: 452 against 518 us; 512 boxes of 256..8192 atoms, 2.2M in
+        // all: 658 against 724 us per step) and -2 below that, where the
+        // lockstep build's one workgroup per 256 slots would leave the device
+        // short of workgroups; grids of fewer than three cells per axis take
+        // -3.
         const bool big = d.box.nc[0] >= 3 && d.box.nc[1] >= 3 && d.box.nc[2] >= 3;
         const bool auto_groups = c->tune_verlet_path == 0 && c->cap > kShortListCap;
-        const bool many = cnt[s] >= kLockstepMinSlots;
+        const bool many = total >= kLockstepMinSlots;
         if (c->sym)  // symmetric half lists need lists in ascending slot order
             d.zb = big ? -5 : 0;
         else if (c->tune_verlet_path == 1)
