@@ -66,6 +66,11 @@ Plan make_plan(const fpm_ctx *c, const std::vector<int64_t> &cnt) {
     int blk = 0, cell = 0, offb = 0, item = 0;
     int64_t total = 0;
     for (int64_t v : cnt) total += v;
+    // contexts built by lockstep windows build grids of at most two cells per
+    // axis in the same launch (every particle's candidates: the whole system)
+    const bool ls_ctx = !c->sym && (c->tune_verlet_path == 5 ||
+                                    (c->tune_verlet_path == 0 && c->cap > kShortListCap &&
+                                     total >= kLockstepMinSlots));
     for (int s = 0; s < nsys; s++) {
         SysHost h{};
         SysDesc &d = h.d;
@@ -92,7 +97,8 @@ Plan make_plan(const fpm_ctx *c, const std::vector<int64_t> &cnt) {
         // all: 658 against 724 us per step) and -2 below that, where the
         // lockstep build's one workgroup per 256 slots would leave the device
         // short of workgroups; grids of fewer than three cells per axis take
-        // -3.
+        // -3 (built in the lockstep launch when -4 is the context's choice and
+        // the grid has at most two cells per axis).
         const bool big = d.box.nc[0] >= 3 && d.box.nc[1] >= 3 && d.box.nc[2] >= 3;
         const bool auto_groups = c->tune_verlet_path == 0 && c->cap > kShortListCap;
         const bool many = total >= kLockstepMinSlots;
@@ -114,11 +120,13 @@ Plan make_plan(const fpm_ctx *c, const std::vector<int64_t> &cnt) {
         d.caller_base = (int32_t)caller;
         h.nblk = d.n_pad / kBlock;
         h.nitems = d.zb > 0 ? d.box.nc[0] * d.box.nc[1] * d.nzb : 0;
+        const bool tiny = d.box.nc[0] <= 2 && d.box.nc[1] <= 2 && d.box.nc[2] <= 2;
+        const bool ls = d.zb == -4 || d.zb == -5 || (d.zb == -3 && ls_ctx && tiny);
         for (int b = 0; b < h.nblk; b++) {
             P.blk2sys.push_back(s);
             if (d.zb == 0 || d.zb == -1) P.pa_blocks.push_back(blk + b);
-            if (d.zb == -2 || d.zb == -3) P.grp_blocks.push_back(blk + b);
-            if (d.zb == -4 || d.zb == -5) P.ls_blocks.push_back(blk + b);
+            if ((d.zb == -2 || d.zb == -3) && !ls) P.grp_blocks.push_back(blk + b);
+            if (ls) P.ls_blocks.push_back(blk + b);
         }
         for (int q = 0; q < h.nitems; q++) P.item2sys.push_back(s);
         slot += d.n_pad;

@@ -950,6 +950,53 @@ __device__ __forceinline__ bool test_cand(float4 q, float3 a, float3 pk, float R
     return sxy + zz <= R2;
 }
 
+// Lockstep build of a system whose grid has at most two cells per axis: the
+// stencil holds every cell, so the candidates of every particle are the whole
+// system, walked by all lanes together (each load serves the whole wavefront)
+// and tested with the whole-cell predicate (image chosen per axis).  The sets
+// are those of the other builds; hits come in slot order.
+__device__ __forceinline__ void lockstep_whole_system(const State &st, const SysDesc &d,
+                                                      int64_t i, bool active, float R2, int cap,
+                                                      int cap4, int *ring) {
+    const Box &b = d.box;
+    const float4 *__restrict__ pos = st.pos[1];
+    const float3 pi = active ? xyz(pos[i]) : make_float3(0.f, 0.f, 0.f);
+    int *gl = st.nbr + (((i >> 6) * (int64_t)cap4 * 64 + (i & 63)) << 2);
+    int cnt = 0, done = 0;
+    bool img = false;
+    const int end = d.slot_base + d.n;
+    const char *pbase = reinterpret_cast<const char *>(pos);
+    constexpr int U = 8;
+    for (int m = d.slot_base; m < end; m += U) {  // the same range for every lane
+        float4 q[U];
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            q[u] = *reinterpret_cast<const float4 *>(pbase + ((uint32_t)min(m + u, end - 1) << 4));
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int j = m + u;
+            if (active && j < end && j != (int)i && cand_d2<true>(pi, xyz(q[u]), b) <= R2) {
+                put(ring, cap, cnt, j);
+                img |= uses_image(pi, xyz(q[u]), b);
+            }
+        }
+        if (__ballot(min(cnt, cap) - done >= kFlushAt) != 0) {
+            const int upto = min(cnt, cap) & ~3;
+            flush_ring(ring, gl, done, upto);
+            done = upto;
+        }
+    }
+    if (active) {
+        const int c = min(cnt, cap);
+        const int c8 = (c + 7) & ~7;
+        for (int k = c; k < c8; k++) ring[k & (kRingEnt - 1)] = d.dummy;
+        flush_ring(ring, gl, done, c8);
+        st.nnb[i] = (uint32_t)c | (img ? kWrapBit : 0u);
+        note_overflow(st, cnt, cap);
+    }
+    copy_back(st, i);
+}
+
 // Registers held to 128 per lane: four waves per SIMD, as many as the LDS
 // rings (36 KB per workgroup) allow, without spills.
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
@@ -963,6 +1010,12 @@ void k_verlet_ls(State st, const int32_t *blocks, float R2, int cap, int cap4) {
     const Box &b = d.box;
     const int64_t i = (int64_t)blk * kBlock + threadIdx.x;
     const bool active = i - d.slot_base < d.n;
+    __shared__ __align__(16) int rings[kBlock * kRingStride];
+    int *ring = rings + threadIdx.x * kRingStride;
+    if (d.zb == -3) {  // the whole workgroup: a grid of at most two cells per axis
+        lockstep_whole_system(st, d, i, active, R2, cap, cap4, ring);
+        return;
+    }
     const float4 *__restrict__ pos = st.pos[1];
     const int32_t *__restrict__ off = st.off + d.off_base;
     const int nx = b.nc[0], ny = b.nc[1], nz = b.nc[2];
@@ -1029,8 +1082,6 @@ void k_verlet_ls(State st, const int32_t *blocks, float R2, int cap, int cap4) {
         pk = make_float3(px, py, pks[g]);
     };
     int *gl = st.nbr + (((i >> 6) * (int64_t)cap4 * 64 + (i & 63)) << 2);
-    __shared__ __align__(16) int rings[kBlock * kRingStride];
-    int *ring = rings + threadIdx.x * kRingStride;
     int cnt = 0, done = 0;  // entries found, entries written to global memory
     bool img = false;
     // one walk over window A followed by window B, all lanes in step, four
