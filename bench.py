@@ -216,9 +216,10 @@ def bench_symmetric(dev, nsteps: int, quiet: bool, plain_value: float):
             "vs_full_lists": value / plain_value}
 
 
-def bench_batched(dev, nsteps: int, quiet: bool):
+def bench_batched(dev, nsteps: int, quiet: bool, tuning=None):
     """512 independent boxes of 256..8192 atoms stepped together, against one
-    box holding the same total number of atoms."""
+    box holding the same total number of atoms (launch shapes from the
+    autotuner, or `tuning` for both)."""
     import numpy as np
     from paper_1804_07598_amd import inputs
     from paper_1804_07598_amd.sim import BatchSim, ParticleSim
@@ -228,7 +229,11 @@ def bench_batched(dev, nsteps: int, quiet: bool):
     sim = BatchSim([s.pos for s in systems], [s.box for s in systems], (1, 1, 1),
                    vel_list=[s.vel for s in systems], r_cut=2.5, skin=0.3, device=dev)
     from paper_1804_07598_amd.tune import tune
-    knobs, _ = tune(sim, float(np.mean(rhos)), cache=None)
+    if tuning:
+        knobs = tuning
+        sim.set_tuning(*knobs)
+    else:
+        knobs, _ = tune(sim, float(np.mean(rhos)), cache=None)
     sim.step(20, 0.005)  # warm-up
     reb0 = sim.counters()[0]
     ms_b = timed_steps(sim, nsteps, 0.005, 0)
@@ -237,7 +242,10 @@ def bench_batched(dev, nsteps: int, quiet: bool):
     one = inputs.lj_lattice(n, float(np.mean(rhos)), float(np.mean(Ts)), 6)
     sim = ParticleSim(one.pos, one.box, (1, 1, 1), vel=one.vel, r_cut=2.5, skin=0.3,
                       max_nbr=184, device=dev)
-    tune(sim, float(np.mean(rhos)), cache=None)
+    if tuning:
+        sim.set_tuning(*tuning)
+    else:
+        tune(sim, float(np.mean(rhos)), cache=None)
     ms_p = timed_steps(sim, nsteps, 0.005, 20)
     sim.close()
     vb, vp = n * nsteps / (ms_b / 1e3), n * nsteps / (ms_p / 1e3)
@@ -511,7 +519,7 @@ def main(argv=None) -> int:
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tuning", type=str, default="",
-                    help="fixed launch shapes 'path,zblock,unroll' instead of the tuner")
+                    help="fixed launch shapes 'path,zblock,unroll' instead of the tuner (headline and --form batched)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the library's default launch shapes")
     ap.add_argument("--no-forms", action="store_true",
@@ -548,7 +556,8 @@ def main(argv=None) -> int:
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}), flush=True)
         return 0
     if a.form:
-        legs = {"batched": lambda: bench_batched(dev, 100, a.quiet),
+        fixed = tuple(int(x) for x in a.tuning.split(",")) if a.tuning else None
+        legs = {"batched": lambda: bench_batched(dev, 100, a.quiet, fixed),
                 "symmetric": lambda: bench_symmetric(dev, 200, a.quiet, float("nan")),
                 "sph": lambda: bench_sph(dev, 500, a.quiet),
                 "sph_dambreak": lambda: bench_dambreak(dev, a.quiet),

@@ -166,9 +166,9 @@ int fpm_set_particles(fpm_ctx *ctx, int64_t n, const float *d_pos, const float *
 /* New positions (device, caller order, n x 3) for the current particles,
  * on periodic axes in [-L, 2L) (the box or one period either side of it);
  * types and velocities are kept.  The neighbour structures are rebuilt on
- * next use when some particle moved more than skin/2 since the last build,
- * measured without periodic images, so a position moved by a period is
- * wrapped back into the box by that rebuild. */
+ * next use when some particle moved more than skin/2 since the last build
+ * (nearest periodic image) or lies more than skin/2 outside [0, L) on a
+ * periodic axis; that rebuild wraps every position back into the box. */
 int fpm_set_positions(fpm_ctx *ctx, const float *d_pos);
 /* Host-side layout of system s: h_out = {n, first caller index, cells,
  * first entry of that system's cell offsets, cells along x, y, z, Verlet

@@ -207,8 +207,8 @@ __global__ void k_reset_step(SysCtl *sctl, int nsys) {
 
 // New positions in caller order for the current sorted state (type bits and
 // the neighbour structures are kept); the displacement since the last build
-// decides, as after a drift, whether they must be rebuilt.
-__global__ __launch_bounds__(kBlock) void k_set_positions(State st, const float *pos) {
+// decides, as after a drift, whether they must be rebuilt.  hs: half the skin.
+__global__ __launch_bounds__(kBlock) void k_set_positions(State st, const float *pos, float hs) {
     const SysDesc &d = st.sys[block_system(st)];
     const int64_t i = global_slot();
     double d2 = 0.0;
@@ -219,11 +219,15 @@ __global__ __launch_bounds__(kBlock) void k_set_positions(State st, const float 
         p.y = pos[3 * r + 1];
         p.z = pos[3 * r + 2];
         st.pos[0][i] = p;
-        // measured without periodic images: a position moved by whole periods
-        // counts as far away, so the rebuild wraps it back into the box (the
+        const Box &b = d.box;
+        d2 = dist2_pred(xyz(st.xbuild[i]), xyz(p), b);
+        // a position more than half the skin outside [0, L) on a periodic axis
+        // (moved by whole periods) forces the rebuild, which wraps it back: the
         // force kernels rely on every position lying within half the skin of
-        // [0, L) on periodic axes)
-        d2 = dist2_direct(xyz(st.xbuild[i]), xyz(p));
+        // [0, L)
+        const float c[3] = {p.x, p.y, p.z};
+        for (int a = 0; a < 3; a++)
+            if (b.per[a] && !(c[a] >= -hs && c[a] < b.L[a] + hs)) d2 = 1e30;
         if (!isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z)) st.ctl->nonfinite = 1;
     }
     double v1[1] = {d2};
@@ -300,7 +304,8 @@ hipError_t launch_reset_step(fpm_ctx *c) {
 }
 
 hipError_t launch_set_positions(fpm_ctx *c, const float *pos) {
-    hipLaunchKernelGGL(k_set_positions, dim3(c->nblk), dim3(kBlock), 0, c->stream, c->st, pos);
+    hipLaunchKernelGGL(k_set_positions, dim3(c->nblk), dim3(kBlock), 0, c->stream, c->st, pos,
+                       0.5f * c->skin);
     return hipGetLastError();
 }
 
