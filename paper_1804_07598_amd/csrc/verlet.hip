@@ -1003,7 +1003,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
 void k_verlet_ls(State st, const int32_t *blocks, float R2, int cap, int cap4) {
 #pragma clang fp contract(off)
     if (st.nsys == 1 && !rebuilding(st, 0)) return;  // a single system: no table loads first
-    const int blk = blocks[xcd_block((int)blockIdx.x, (int)gridDim.x)];
+    // one system: each XCD takes one contiguous range of its columns (shared
+    // candidates in one L2); a batch: workgroups in turn over the XCDs, so that
+    // the systems rebuilding in a step are spread evenly over them
+    const int blk = blocks[st.nsys == 1 ? xcd_block((int)blockIdx.x, (int)gridDim.x)
+                                        : (int)blockIdx.x];
     const int s = st.nsys == 1 ? 0 : st.blk2sys[blk];
     if (!rebuilding(st, s)) return;
     const SysDesc &d = st.sys[s];
