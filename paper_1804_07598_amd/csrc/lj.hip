@@ -27,6 +27,7 @@ struct LJCoef {
     double a6[3];   // 4 sig^6
     double inv_sig[3];
     float side_margin;  // half the skin, widened: see Sided
+    float side_wide;    // half box lengths above this take Sided on every lane
 };
 
 // 1/x in FP64: the hardware estimate (relative error up to 5e-8) refined by
@@ -48,14 +49,18 @@ __device__ __forceinline__ double recip(double x) {
 // one face per axis.  The predicate's image test then takes one compare
 // (sg t > L/2) and the shifted separation (x_i +- L) - x_j, exact in FP64 like
 // the unshifted one, so the results are those of the general form bit for
-// bit.  sg is 0 on closed axes.
+// bit.  sg is 0 on closed axes.  A lane nearer the mid-plane can meet a
+// partner across the other face too, but only at a separation along that axis
+// above L/2 - skin/2: where that exceeds r_cut (L/2 > r_cut + skin/2, widened:
+// every box of at least two cells per axis) such a pair lies outside the force
+// set under either image, so the one-face form holds for every lane.
 struct Sided {
     float sg[3];
     double xs[3];  // x_i + sg L
 };
 
 __device__ __forceinline__ Sided make_sided(float3 pi, double xi, double yi, double zi,
-                                            const Box &b, float margin, bool &ok) {
+                                            const Box &b, float margin, float wide, bool &ok) {
     Sided sd;
     const float p[3] = {pi.x, pi.y, pi.z};
     const double x[3] = {xi, yi, zi};
@@ -65,7 +70,8 @@ __device__ __forceinline__ Sided make_sided(float3 pi, double xi, double yi, dou
         const bool lo = p[a] < b.half[a];
         sd.sg[a] = b.per[a] ? (lo ? 1.f : -1.f) : 0.f;
         sd.xs[a] = x[a] + (double)(sd.sg[a] * b.L[a]);
-        ok = ok && (!b.per[a] || fabsf(p[a] - b.half[a]) > margin + 4e-7f * b.L[a]);
+        ok = ok && (!b.per[a] || b.half[a] > wide ||
+                    fabsf(p[a] - b.half[a]) > margin + 4e-7f * b.L[a]);
     }
     return sd;
 }
@@ -317,7 +323,8 @@ __global__ __launch_bounds__(kBlock) void k_lj(State st, float rc2, double rc2lo
                       ((i >> 6) * (int64_t)cap4) * 64 + (i & 63);
     Acc a;
     bool side_ok = true;
-    const Sided sd = make_sided(xyz(pi4), pi4.x, pi4.y, pi4.z, b, cf.side_margin, side_ok);
+    const Sided sd = make_sided(xyz(pi4), pi4.x, pi4.y, pi4.z, b, cf.side_margin, cf.side_wide,
+                                 side_ok);
     if (img_wave && __ballot(active && !side_ok) == 0)
         walk<NT, 2, UNR>(a, pos, lst, cnt, pi4, b, rc2, rc2lo, rc2hi, cf, sd);
     else if (img_wave)
@@ -500,7 +507,8 @@ __global__ __launch_bounds__(kBlock) void k_lj_vjp(State st, float rc2, double r
                       ((i >> 6) * (int64_t)cap4) * 64 + (i & 63);
     VjpAcc a;
     bool side_ok = true;
-    const Sided sd = make_sided(xyz(pi4), pi4.x, pi4.y, pi4.z, b, cf.side_margin, side_ok);
+    const Sided sd = make_sided(xyz(pi4), pi4.x, pi4.y, pi4.z, b, cf.side_margin, cf.side_wide,
+                                 side_ok);
     if (img_wave && __ballot(active && !side_ok) == 0)
         vjp_walk<NT, 2>(a, pos, st.aux, lst, cnt, pi4, li, b, rc2, rc2lo, rc2hi, cf, sd);
     else if (img_wave)
@@ -752,7 +760,8 @@ __global__ __launch_bounds__(kBlock) void k_lj_sym1(State st, float rc2, double 
     const int cnt = min((int)(nn & ~kWrapBit), cap);
     double f[3] = {0.0, 0.0, 0.0}, u = 0.0, w[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     bool side_ok = true;
-    const Sided sd = make_sided(xyz(pi4), pi4.x, pi4.y, pi4.z, b, cf.side_margin, side_ok);
+    const Sided sd = make_sided(xyz(pi4), pi4.x, pi4.y, pi4.z, b, cf.side_margin, cf.side_wide,
+                                 side_ok);
     if (img_wave && __ballot(active && !side_ok) == 0)
         sym_upper<NT, 2>(st, i, p0, cnt, pi4, b, rc2, rc2lo, rc2hi, cf, cap4, f, u, w, sd);
     else if (img_wave)
@@ -813,7 +822,7 @@ __device__ __forceinline__ void sym_lower(const State &st, int64_t j, int p, flo
 // (MODE kLjStep, kLjLast) the step's updates as in k_lj.
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_lj_sym2(State st, int cap4, StepArgs sa,
-                                                    float side_margin) {
+                                                    float side_margin, float side_wide) {
     const int sys = block_system(st);
     const SysDesc &d = st.sys[sys];
     const Box b = d.box;
@@ -832,7 +841,8 @@ __global__ __launch_bounds__(kBlock) void k_lj_sym2(State st, int cap4, StepArgs
         for (int c = 0; c < 3; c++) f[c] = st.fown[3 * i + c];
     }
     bool side_ok = true;
-    const Sided sd = make_sided(xyz(pi4), pi4.x, pi4.y, pi4.z, b, side_margin, side_ok);
+    const Sided sd =
+        make_sided(xyz(pi4), pi4.x, pi4.y, pi4.z, b, side_margin, side_wide, side_ok);
     const bool img_wave = __ballot((nn & kWrapBit) != 0) != 0;
     if (img_wave && __ballot(active && !side_ok) == 0)
         sym_lower<2>(st, i, p, pi4, b, cap4, f, sd);
@@ -870,8 +880,10 @@ __global__ __launch_bounds__(kBlock) void k_lj_sym2(State st, int cap4, StepArgs
 }
 
 // Margin of the one-face image form (Sided): particles stay within half the
-// skin of their build positions.
+// skin of their build positions; above half box lengths of side_wide every
+// lane takes the form.
 float side_margin(const fpm_ctx *c) { return 0.5f * c->skin * 1.001f + 1e-4f; }
+float side_wide(const fpm_ctx *c) { return c->r_cut * 1.00001f + side_margin(c); }
 
 LJCoef make_coef(const fpm_ctx *c, const fpm_lj_params &p) {
     LJCoef cf;
@@ -885,6 +897,7 @@ LJCoef make_coef(const fpm_ctx *c, const fpm_lj_params &p) {
         cf.inv_sig[k] = 1.0 / s;
     }
     cf.side_margin = side_margin(c);
+    cf.side_wide = side_wide(c);
     return cf;
 }
 
@@ -935,7 +948,7 @@ void launch_sym_mode(fpm_ctx *c, const fpm_lj_params &p, const StepArgs &sa, dou
         hipLaunchKernelGGL(k_lj_sym1<1>, g, t, 0, c->stream, c->st, c->rc2, rc2lo, rc2hi, cf,
                            c->cap, c->cap4, part);
     hipLaunchKernelGGL(k_lj_sym2<MODE>, g, t, 0, c->stream, c->st, c->cap4, sa,
-                       side_margin(c));
+                       side_margin(c), side_wide(c));
 }
 
 }  // namespace
