@@ -57,6 +57,7 @@ extern "C" {
 #define FPM_EOVERFLOW (-4)  /* a Verlet list exceeded max_nbr; lists invalid */
 #define FPM_ENOWS (-5)      /* workspace missing or too small */
 #define FPM_ENONFINITE (-6) /* a position or force became NaN/Inf */
+#define FPM_EBADINDEX (-7)  /* debug build only: a list or cell-list entry out of range */
 
 typedef struct fpm_ctx fpm_ctx;
 
@@ -360,7 +361,10 @@ int fpm_lj_forces_static(fpm_ctx *ctx, const fpm_lj_params *prm, int64_t n, cons
 /* ---- status ---- */
 
 /* Synchronises the stream and reports device-side flags: FPM_EOVERFLOW if a
- * list overflowed, FPM_ENONFINITE if a non-finite value was seen. */
+ * list overflowed, FPM_ENONFINITE if a non-finite value was seen, and in the
+ * debug build (libfpm_checked.so: cell list and Verlet lists validated after
+ * every rebuild, every list entry the LJ force and VJP kernels read checked
+ * against its system's slots) FPM_EBADINDEX if an entry was out of range. */
 int fpm_check(fpm_ctx *ctx);
 /* Synchronises and reads counters: h_out[0] = rebuilds so far (summed over
  * the systems of a batch),

@@ -20,9 +20,10 @@ FPM_ECUTOFF = -3
 FPM_EOVERFLOW = -4
 FPM_ENOWS = -5
 FPM_ENONFINITE = -6
+FPM_EBADINDEX = -7
 _NAMES = {FPM_EINVAL: "FPM_EINVAL", FPM_EHIP: "FPM_EHIP", FPM_ECUTOFF: "FPM_ECUTOFF",
           FPM_EOVERFLOW: "FPM_EOVERFLOW", FPM_ENOWS: "FPM_ENOWS",
-          FPM_ENONFINITE: "FPM_ENONFINITE"}
+          FPM_ENONFINITE: "FPM_ENONFINITE", FPM_EBADINDEX: "FPM_EBADINDEX"}
 
 
 class FpmError(RuntimeError):

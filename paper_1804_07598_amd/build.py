@@ -1,8 +1,10 @@
-"""Compile the HIP library libfpm.so for gfx950 in-tree.
+"""Compile the HIP library libfpm.so for gfx950 in-tree, and its debug build
+libfpm_checked.so (FPM_CHECKED=1: cell and Verlet lists validated after every
+rebuild, list entries range-checked where the LJ kernels read them).
 
 Every .hip file under csrc/ is compiled separately (in parallel) with hipcc and
-linked into paper_1804_07598_amd/libfpm.so.  Packed FP32 instructions are
-disabled for all device code.
+linked into the library.  Packed FP32 instructions are disabled for all device
+code.
 """
 from __future__ import annotations
 
@@ -16,6 +18,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfpm.so")
+OBJ_CHECKED = os.path.join(HERE, "_build", "checked")
+LIB_CHECKED = os.path.join(HERE, "libfpm_checked.so")
 ARCH = os.environ.get("FPM_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -27,9 +31,9 @@ FLAGS = [
 ]
 
 
-def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+def _compile(src: str, verbose: bool, checked: bool = False) -> str:
+    obj = os.path.join(OBJ_CHECKED if checked else OBJ, os.path.basename(src) + ".o")
+    cmd = [HIPCC, *FLAGS, *(["-DFPM_CHECKED=1"] if checked else []), "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -44,16 +48,19 @@ def _compile(src: str, verbose: bool) -> str:
 
 
 def build(verbose: bool = False) -> str:
-    os.makedirs(OBJ, exist_ok=True)
+    """Both libraries; returns the path of libfpm.so."""
+    os.makedirs(OBJ_CHECKED, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    jobs = [(src, checked) for checked in (False, True) for src in srcs]
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
+        objs = list(ex.map(lambda j: _compile(j[0], verbose, j[1]), jobs))
+    for lib, part in ((LIB, objs[:len(srcs)]), (LIB_CHECKED, objs[len(srcs):])):
+        tmp = lib + ".tmp"
+        cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *part]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, lib)
     return LIB
 
 

@@ -1024,6 +1024,7 @@ int fpm_check(fpm_ctx *c) {
     if (h.overflow) return fail(c, FPM_EOVERFLOW, "Verlet list exceeded max_nbr");
     if (h.sym_miss) return fail(c, FPM_EOVERFLOW, "symmetric lists: a pair missing from one side");
     if (h.nonfinite) return fail(c, FPM_ENONFINITE, "non-finite position or force");
+    if (h.bad_index) return fail(c, FPM_EBADINDEX, "a list or cell-list entry out of range");
     return FPM_OK;
 }
 

@@ -259,6 +259,24 @@ __global__ void k_rank_gather(State st) {
     }
 }
 
+// Debug builds: after a cell build every sorted slot of a system lies in the
+// offset range of the cell its position falls in, and the system's offsets
+// run from its first slot to its first slot plus its particle count.
+__global__ __launch_bounds__(kBlock) void k_check_cells(State st) {
+    const int s = block_system(st);
+    if (!rebuilding(st, s)) return;
+    const SysDesc &d = st.sys[s];
+    const int64_t f = global_slot();
+    if (f - d.slot_base >= d.n) return;
+    const int c = d.cell_base + cell_of(xyz(st.pos[1][f]), d.box);
+    const int lo = st.off[off_index(d, c)], hi = st.off[off_index(d, c) + 1];
+    bool bad = f < lo || f >= hi;
+    if (f == d.slot_base)
+        bad = bad || st.off[d.off_base] != d.slot_base ||
+              st.off[d.off_base + d.ncells] != d.slot_base + d.n;
+    if (bad) st.ctl->bad_index = 1;
+}
+
 // Buffer 1 -> buffer 0 (used when the cell list is rebuilt on its own).
 __global__ void k_copy_back(State st) {
     if (!rebuilding(st, block_system(st))) return;
@@ -332,6 +350,12 @@ hipError_t launch_cell_build(fpm_ctx *c, bool dem_export) {
     }
     hipLaunchKernelGGL(k_scatter, dim3(g), dim3(kBlock), 0, c->stream, c->st);
     hipLaunchKernelGGL(k_rank_gather, dim3(g), dim3(kBlock), 0, c->stream, c->st);
+    if (kChecked) return launch_check_cells(c);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_cells(fpm_ctx *c) {
+    hipLaunchKernelGGL(k_check_cells, dim3(c->nblk), dim3(kBlock), 0, c->stream, c->st);
     return hipGetLastError();
 }
 

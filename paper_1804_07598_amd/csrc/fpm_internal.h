@@ -15,7 +15,17 @@
 
 #include "../../include/fpm.h"
 
+#ifndef FPM_CHECKED
+#define FPM_CHECKED 0
+#endif
+
 namespace fpm {
+
+// Debug builds (compiled with FPM_CHECKED=1 as libfpm_checked.so): the cell
+// list and the Verlet lists are validated after every rebuild, and every list
+// entry the LJ force and VJP kernels read is range-checked; a violation sets
+// Ctl::bad_index, which fpm_check reports.
+constexpr bool kChecked = FPM_CHECKED != 0;
 
 constexpr int kWave = 64;          // CDNA wavefront
 constexpr int kBlock = 256;        // threads per workgroup of the particle kernels
@@ -97,7 +107,7 @@ struct Ctl {
     float sph_dt_last;      // SPH time step of the last completed step
     double sph_time;        // simulated SPH time
     int32_t sph_nstep;      // SPH steps since the state was set (Verlet/Euler choice)
-    int32_t sph_pad;
+    int32_t bad_index;      // debug builds: a list or cell-list entry out of range (sticky)
 };
 
 // Pointers into the workspace.  Buffer 0 holds the cell-sorted state between
@@ -242,6 +252,8 @@ hipError_t launch_cell_build(fpm_ctx *c, bool dem_export);  // dem_export: histo
 hipError_t launch_copy_back(fpm_ctx *c);
 hipError_t launch_verlet_build(fpm_ctx *c);
 hipError_t launch_list_stats(fpm_ctx *c);  // fills ctl->max_count and ctl->total_count
+hipError_t launch_check_cells(fpm_ctx *c);  // debug builds (gated): cell-list validation
+hipError_t launch_check_lists(fpm_ctx *c);  // debug builds (gated): Verlet-list validation
 // z-cells per workgroup of the column Verlet build for one system, 0 when the
 // grid is too small for it (fewer than three cells along an axis).
 int verlet_zblock(int64_t n, int64_t ncells, const int nc[3], int tune_zb);

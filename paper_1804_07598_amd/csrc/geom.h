@@ -176,6 +176,26 @@ __device__ __forceinline__ void cell_assign_slot(const State &st, int s, int64_t
     if (c >= 0) st.rnk[i] = base + (lane - hl);
 }
 
+// Slots of a system, for the entry checks of debug builds.
+struct SlotRange {
+    int base, n_pad, dummy;
+    int32_t *flag;  // Ctl::bad_index
+};
+
+__device__ __forceinline__ SlotRange slot_range(const State &st, const SysDesc &d) {
+    return SlotRange{d.slot_base, d.n_pad, d.dummy, &st.ctl->bad_index};
+}
+
+// A list entry as read by a kernel: in debug builds one outside the system's
+// slots is reported and replaced by the far-away slot; otherwise unchanged.
+__device__ __forceinline__ int checked(const SlotRange &r, int j) {
+    if (kChecked && (unsigned)(j - r.base) >= (unsigned)r.n_pad) {
+        *r.flag = 1;
+        return r.dummy;
+    }
+    return j;
+}
+
 // True when system s must rebuild its neighbour structures in this launch.
 __device__ __forceinline__ bool rebuilding(const State &st, int s) {
     return st.sctl[s].rebuild[st.par] != 0;

@@ -217,11 +217,12 @@ __device__ __forceinline__ Entries<UNR> list_group(const int4 *__restrict__ lst,
 // scalar base.
 template <int UNR>
 __device__ __forceinline__ void gather(const float4 *__restrict__ pos, const Entries<UNR> &en,
-                                       float4 (&q)[UNR]) {
+                                       float4 (&q)[UNR], const SlotRange &sr) {
     const char *base = reinterpret_cast<const char *>(pos);
 #pragma unroll
     for (int g = 0; g < UNR / 4; g++) {
-        const int j[4] = {en.e[g].x, en.e[g].y, en.e[g].z, en.e[g].w};
+        const int j[4] = {checked(sr, en.e[g].x), checked(sr, en.e[g].y),
+                          checked(sr, en.e[g].z), checked(sr, en.e[g].w)};
 #pragma unroll
         for (int u = 0; u < 4; u++)
             q[4 * g + u] = *reinterpret_cast<const float4 *>(base + ((uint32_t)j[u] << 4));
@@ -236,7 +237,7 @@ template <int NT, int IMG, int UNR>
 __device__ __forceinline__ void walk(Acc &a, const float4 *__restrict__ pos,
                                      const int4 *__restrict__ lst, int cnt, float4 pi4,
                                      const Box &b, float rc2, double rc2lo, double rc2hi,
-                                     const LJCoef &cf, const Sided &sd) {
+                                     const LJCoef &cf, const Sided &sd, const SlotRange &sr) {
     if (cnt <= 0) return;
     const float3 pi = xyz(pi4);
     const double xi = pi.x, yi = pi.y, zi = pi.z;
@@ -244,16 +245,16 @@ __device__ __forceinline__ void walk(Acc &a, const float4 *__restrict__ pos,
     // two register sets take turns (no copies between rounds); a round past
     // the end of the list re-reads a group in range, which is harmless
     float4 q0[UNR], q1[UNR];
-    gather<UNR>(pos, list_group<UNR>(lst, 0), q0);
+    gather<UNR>(pos, list_group<UNR>(lst, 0), q0, sr);
     Entries<UNR> nxt = list_group<UNR>(lst, UNR < cnt ? UNR : 0);
     for (int k = 0; k < cnt; k += 2 * UNR) {
-        gather<UNR>(pos, nxt, q1);
+        gather<UNR>(pos, nxt, q1, sr);
         nxt = list_group<UNR>(lst, k + 2 * UNR < cnt ? k + 2 * UNR : k);
 #pragma unroll
         for (int u = 0; u < UNR; u++)
             pair<NT, IMG>(a, pi, xi, yi, zi, lc, q0[u], b, rc2, rc2lo, rc2hi, sd);
         if (k + UNR >= cnt) break;
-        gather<UNR>(pos, nxt, q0);
+        gather<UNR>(pos, nxt, q0, sr);
         nxt = list_group<UNR>(lst, k + 3 * UNR < cnt ? k + 3 * UNR : k);
 #pragma unroll
         for (int u = 0; u < UNR; u++)
@@ -325,12 +326,13 @@ __global__ __launch_bounds__(kBlock) void k_lj(State st, float rc2, double rc2lo
     bool side_ok = true;
     const Sided sd = make_sided(xyz(pi4), pi4.x, pi4.y, pi4.z, b, cf.side_margin, cf.side_wide,
                                  side_ok);
+    const SlotRange sr = slot_range(st, d);
     if (img_wave && __ballot(active && !side_ok) == 0)
-        walk<NT, 2, UNR>(a, pos, lst, cnt, pi4, b, rc2, rc2lo, rc2hi, cf, sd);
+        walk<NT, 2, UNR>(a, pos, lst, cnt, pi4, b, rc2, rc2lo, rc2hi, cf, sd, sr);
     else if (img_wave)
-        walk<NT, 1, UNR>(a, pos, lst, cnt, pi4, b, rc2, rc2lo, rc2hi, cf, sd);
+        walk<NT, 1, UNR>(a, pos, lst, cnt, pi4, b, rc2, rc2lo, rc2hi, cf, sd, sr);
     else
-        walk<NT, 0, UNR>(a, pos, lst, cnt, pi4, b, rc2, rc2lo, rc2hi, cf, sd);
+        walk<NT, 0, UNR>(a, pos, lst, cnt, pi4, b, rc2, rc2lo, rc2hi, cf, sd, sr);
     double ke = 0.0;
     bool over = false;
     if (active) {
@@ -448,14 +450,16 @@ __device__ __forceinline__ void vjp_walk(VjpAcc &a, const float4 *__restrict__ p
                                          const float4 *__restrict__ lam,
                                          const int4 *__restrict__ lst, int cnt, float4 pi4,
                                          float4 li, const Box &b, float rc2, double rc2lo,
-                                         double rc2hi, const LJCoef &cf, const Sided &sd) {
+                                         double rc2hi, const LJCoef &cf, const Sided &sd,
+                                         const SlotRange &sr) {
     const float3 pi = xyz(pi4);
     const double xi = pi.x, yi = pi.y, zi = pi.z;
     const LaneCoef lc = lane_coef<NT>(cf, __float_as_int(pi4.w));
     if (cnt <= 0) return;
     int4 e = lst[0];  // the next group's entries are requested before this group's gathers
     for (int k = 0; k < cnt; k += 4) {
-        const int jj[4] = {e.x, e.y, e.z, e.w};
+        const int jj[4] = {checked(sr, e.x), checked(sr, e.y), checked(sr, e.z),
+                           checked(sr, e.w)};
         e = lst[((k + 4 < cnt ? k + 4 : k) >> 2) * 64];
         float4 q[4], l[4];
 #pragma unroll
@@ -509,12 +513,13 @@ __global__ __launch_bounds__(kBlock) void k_lj_vjp(State st, float rc2, double r
     bool side_ok = true;
     const Sided sd = make_sided(xyz(pi4), pi4.x, pi4.y, pi4.z, b, cf.side_margin, cf.side_wide,
                                  side_ok);
+    const SlotRange sr = slot_range(st, d);
     if (img_wave && __ballot(active && !side_ok) == 0)
-        vjp_walk<NT, 2>(a, pos, st.aux, lst, cnt, pi4, li, b, rc2, rc2lo, rc2hi, cf, sd);
+        vjp_walk<NT, 2>(a, pos, st.aux, lst, cnt, pi4, li, b, rc2, rc2lo, rc2hi, cf, sd, sr);
     else if (img_wave)
-        vjp_walk<NT, 1>(a, pos, st.aux, lst, cnt, pi4, li, b, rc2, rc2lo, rc2hi, cf, sd);
+        vjp_walk<NT, 1>(a, pos, st.aux, lst, cnt, pi4, li, b, rc2, rc2lo, rc2hi, cf, sd, sr);
     else
-        vjp_walk<NT, 0>(a, pos, st.aux, lst, cnt, pi4, li, b, rc2, rc2lo, rc2hi, cf, sd);
+        vjp_walk<NT, 0>(a, pos, st.aux, lst, cnt, pi4, li, b, rc2, rc2lo, rc2hi, cf, sd, sr);
     if (active) {
         const int64_t r = st.id[0][i];
         const double g[3] = {a.gx, a.gy, a.gz};

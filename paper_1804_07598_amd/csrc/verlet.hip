@@ -1262,6 +1262,30 @@ void k_verlet_ls(State st, const int32_t *blocks, float R2, int cap, int cap4) {
     copy_back(st, i);
 }
 
+// Debug builds: every list just built holds at most cap entries, all slots of
+// its own system, none of them the particle itself and none twice, followed
+// by the far-away slot up to a multiple of eight.
+__global__ __launch_bounds__(kBlock) void k_check_lists(State st, int cap, int cap4) {
+    const int s = block_system(st);
+    if (!rebuilding(st, s)) return;
+    const SysDesc &d = st.sys[s];
+    const int64_t i = global_slot();
+    if (i - d.slot_base >= d.n) return;
+    const int c = (int)(st.nnb[i] & ~kWrapBit);
+    bool bad = c < 0 || c > cap;
+    const int c8 = bad ? 0 : min((c + 7) & ~7, 4 * cap4);
+    for (int k = 0; k < c8 && !bad; k++) {
+        const int j = st.nbr[nbr_index(i, k, cap4)];
+        if (k < c) {
+            bad = (unsigned)(j - d.slot_base) >= (unsigned)d.n || j == (int)i;
+            for (int k2 = 0; k2 < k && !bad; k2++) bad = st.nbr[nbr_index(i, k2, cap4)] == j;
+        } else {
+            bad = j != d.dummy;
+        }
+    }
+    if (bad) st.ctl->bad_index = 1;
+}
+
 // Longest list and total entries of the current lists (on request only): a
 // grid-stride pass, reduced per workgroup, one pair of atomics per workgroup.
 __global__ __launch_bounds__(256) void k_list_stats(State st, int64_t nslots) {
@@ -1344,6 +1368,13 @@ hipError_t launch_verlet_build(fpm_ctx *c) {
                                c->R2, c->cap, c->cap4, lcap4);
         }
     }
+    if (kChecked) return launch_check_lists(c);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_lists(fpm_ctx *c) {
+    hipLaunchKernelGGL(k_check_lists, dim3(c->nblk), dim3(kBlock), 0, c->stream, c->st, c->cap,
+                       c->cap4);
     return hipGetLastError();
 }
 

@@ -35,6 +35,13 @@ def test_library_exports_every_declared_symbol():
     assert not missing, missing
 
 
+def test_debug_build_exports_the_same_symbols():
+    path = os.path.join(ROOT, "paper_1804_07598_amd", "libfpm_checked.so")
+    L = ctypes.CDLL(path)
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
 def test_binding_covers_every_symbol():
     from paper_1804_07598_amd import _lib
     bound = set(_lib._SIGS) | {"fpm_last_error"}
