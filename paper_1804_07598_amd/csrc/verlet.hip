@@ -997,24 +997,25 @@ __device__ __forceinline__ void lockstep_whole_system(const State &st, const Sys
     copy_back(st, i);
 }
 
-// Registers held to 128 per lane: four waves per SIMD, as many as the LDS
-// rings (36 KB per workgroup) allow, without spills.
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+// One wavefront per workgroup (a quarter of a particle workgroup's slots):
+// small systems spread over every CU.  Registers held to 128 per lane: four
+// waves per SIMD, without spills.
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4, 4)))
 void k_verlet_ls(State st, const int32_t *blocks, float R2, int cap, int cap4) {
 #pragma clang fp contract(off)
     if (st.nsys == 1 && !rebuilding(st, 0)) return;  // a single system: no table loads first
     // one system: each XCD takes one contiguous range of its columns (shared
     // candidates in one L2); a batch: workgroups in turn over the XCDs, so that
     // the systems rebuilding in a step are spread evenly over them
-    const int blk = blocks[st.nsys == 1 ? xcd_block((int)blockIdx.x, (int)gridDim.x)
-                                        : (int)blockIdx.x];
+    const int r = st.nsys == 1 ? xcd_block((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+    const int blk = blocks[r >> 2];
     const int s = st.nsys == 1 ? 0 : st.blk2sys[blk];
     if (!rebuilding(st, s)) return;
     const SysDesc &d = st.sys[s];
     const Box &b = d.box;
-    const int64_t i = (int64_t)blk * kBlock + threadIdx.x;
+    const int64_t i = (int64_t)blk * kBlock + (r & 3) * kWave + threadIdx.x;
     const bool active = i - d.slot_base < d.n;
-    __shared__ __align__(16) int rings[kBlock * kRingStride];
+    __shared__ __align__(16) int rings[kWave * kRingStride];
     int *ring = rings + threadIdx.x * kRingStride;
     if (d.zb == -3) {  // the whole workgroup: a grid of at most two cells per axis
         lockstep_whole_system(st, d, i, active, R2, cap, cap4, ring);
@@ -1344,9 +1345,9 @@ hipError_t launch_verlet_build(fpm_ctx *c) {
     if (c->n_pa_blocks > 0)
         hipLaunchKernelGGL(k_verlet, dim3(c->n_pa_blocks), dim3(kBlock), 0, c->stream, c->st,
                            c->pa_blocks, c->R2, c->cap, c->cap4);
-    if (c->n_ls_blocks > 0)
-        hipLaunchKernelGGL(k_verlet_ls, dim3(c->n_ls_blocks), dim3(kBlock), 0, c->stream, c->st,
-                           c->pa_blocks + c->n_pa_blocks + c->n_grp_blocks, c->R2, c->cap,
+    if (c->n_ls_blocks > 0)  // four one-wavefront workgroups per particle workgroup
+        hipLaunchKernelGGL(k_verlet_ls, dim3(4 * c->n_ls_blocks), dim3(kWave), 0, c->stream,
+                           c->st, c->pa_blocks + c->n_pa_blocks + c->n_grp_blocks, c->R2, c->cap,
                            c->cap4);
     if (c->n_grp_blocks > 0) {
         // four 64-slot rows per particle workgroup
