@@ -1,19 +1,23 @@
 // Verlet list build (section 2, ref [46]; section 4.1 uses Verlet lists for
 // the MD client).  A particle's list holds every j != i that passes the FP32
 // predicate at the list radius r_cut + skin; candidates are the particles of
-// the 27 (de-duplicated) cells around its cell.
+// the 27 (de-duplicated) cells around its cell.  Every build also moves the
+// freshly sorted state from buffer 1 back to buffer 0.
 //
-// Main path: a workgroup takes one (x, y) column of cells and a block of zb
-// consecutive z-cells.  The z-runs (z0 - 1 .. z1) of the 3 x 3 neighbouring
-// columns are staged in LDS, each column contiguous and in z order, with the
-// global slot kept in w, so that a particle's stencil is nine contiguous LDS
-// ranges.  Candidates are tested in chunks of 32; hits are collected in a bit
-// mask and written after the chunk, which takes far fewer store instructions
-// than storing inside the test loop.  The kernel also moves the freshly
-// sorted state from buffer 1 back to buffer 0.
-//
-// Fallback: grids with fewer than three cells along an axis (and workgroups
-// whose staged region would not fit) read candidates from global memory.
+// Four builds produce the same sets (the choice is a launch shape):
+//  - lockstep windows (k_verlet_ls, the default for contexts of at least
+//    131,072 particles): one lane per particle; each lane's candidates in a
+//    neighbour column are one z-window of slots, and the wavefront's lanes
+//    walk their windows in step, hits staged in LDS rings;
+//  - lane groups (k_verlet_grp, the default below that): G lanes per
+//    particle over the same windows (or over whole cells for grids of fewer
+//    than three cells along an axis), each 64-slot row of lists staged in
+//    LDS and stored whole;
+//  - one lane per particle without staging (k_verlet: windows, or whole
+//    cells read from global memory), the default for short lists;
+//  - column workgroups (k_verlet_cols): a workgroup stages the z-runs of the
+//    3 x 3 columns around a block of z-cells in LDS and tests candidates in
+//    chunks of 32.
 #include "geom.h"
 
 namespace fpm {
