@@ -937,11 +937,13 @@ __device__ __forceinline__ void flush_ring(const int *ring, int *gl, int from, i
             *reinterpret_cast<const int4 *>(ring + (k & (kRingEnt - 1)));
 }
 
-// Appends slot j to the list of this lane (entries beyond the capacity are
-// counted, not kept).
-__device__ __forceinline__ void put(int *ring, int cap, int &cnt, int j) {
-    if (cnt < cap) ring[cnt & (kRingEnt - 1)] = j;
-    cnt++;
+// Appends slot j to the list of this lane when `hit` (entries beyond the
+// capacity are counted, not kept).  Called for every candidate, without a
+// branch: a miss, or a hit beyond the capacity, writes the spare word after
+// the ring instead.
+__device__ __forceinline__ void put_if(int *ring, int cap, int &cnt, int j, bool hit) {
+    ring[hit & (cnt < cap) ? (cnt & (kRingEnt - 1)) : kRingEnt] = j;
+    cnt += hit;
 }
 
 template <bool SH>
@@ -979,10 +981,10 @@ __device__ __forceinline__ void lockstep_whole_system(const State &st, const Sys
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const int j = m + u;
-            if (active && j < end && j != (int)i && cand_d2<true>(pi, xyz(q[u]), b) <= R2) {
-                put(ring, cap, cnt, j);
-                img |= uses_image(pi, xyz(q[u]), b);
-            }
+            const bool hit = active & (j < end) & (j != (int)i) &
+                             (cand_d2<true>(pi, xyz(q[u]), b) <= R2);
+            put_if(ring, cap, cnt, j, hit);
+            img |= hit & uses_image(pi, xyz(q[u]), b);
         }
         if (__ballot(min(cnt, cap) - done >= kFlushAt) != 0) {
             const int upto = min(cnt, cap) & ~3;
@@ -1122,13 +1124,14 @@ void k_verlet_ls(State st, const int32_t *blocks, float R2, int cap, int cap4) {
                 const int mu = m + u;
                 if (sh) {
                     const bool inA = mu < A.len;
-                    if (mu < tot && test_cand<true>(q[u], inA ? aA : aB, inA ? pA : pB, R2) &&
-                        jj[u] != (int)i) {
-                        put(ring, cap, cnt, jj[u]);
-                        img |= inA ? shA : shB;
-                    }
-                } else if (mu < tot && test_cand<false>(q[u], aA, pi, R2) && jj[u] != (int)i) {
-                    put(ring, cap, cnt, jj[u]);
+                    const bool hit = (mu < tot) & (jj[u] != (int)i) &
+                                     test_cand<true>(q[u], inA ? aA : aB, inA ? pA : pB, R2);
+                    put_if(ring, cap, cnt, jj[u], hit);
+                    img |= hit & (inA ? shA : shB);
+                } else {
+                    const bool hit =
+                        (mu < tot) & (jj[u] != (int)i) & test_cand<false>(q[u], aA, pi, R2);
+                    put_if(ring, cap, cnt, jj[u], hit);
                 }
             }
             if (__ballot(min(cnt, cap) - done >= kFlushAt) != 0) {
@@ -1168,10 +1171,9 @@ void k_verlet_ls(State st, const int32_t *blocks, float R2, int cap, int cap4) {
                 const bool g1 = inb ? mu >= c3 : mu >= c1;
                 const float3 a = make_float3(inb ? axb : axa, inb ? ayb : aya, g1 ? azs[1] : azs[0]);
                 const float3 pk = make_float3(inb ? pxb : pxa, inb ? pyb : pya, g1 ? pks[1] : pks[0]);
-                if (mu < tot && test_cand<true>(q[u], a, pk, R2) && jj[u] != (int)i) {
-                    put(ring, cap, cnt, jj[u]);
-                    img |= (inb ? sxb : sxa) || (g1 ? sz1 : sz0);
-                }
+                const bool hit = (mu < tot) & (jj[u] != (int)i) & test_cand<true>(q[u], a, pk, R2);
+                put_if(ring, cap, cnt, jj[u], hit);
+                img |= hit & ((inb ? sxb : sxa) | (g1 ? sz1 : sz0));
             }
             if (__ballot(min(cnt, cap) - done >= kFlushAt) != 0) {
                 const int upto = min(cnt, cap) & ~3;
