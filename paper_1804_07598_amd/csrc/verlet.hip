@@ -1095,12 +1095,16 @@ void k_verlet_ls(State st, const int32_t *blocks, float R2, int cap, int cap4) {
     int *gl = st.nbr + (((i >> 6) * (int64_t)cap4 * 64 + (i & 63)) << 2);
     int cnt = 0, done = 0;  // entries found, entries written to global memory
     bool img = false;
-    // one walk over window A followed by window B, all lanes in step, four
+    // one walk over window A followed by window B, all lanes in step, eight
     // candidates per round (their loads issued together); indices past the
-    // end of a lane's walk re-read a valid slot and are not tested
+    // end of a lane's walk re-read a valid slot and are not tested.  `own`
+    // (std::true_type) when a window is the particle's own column, the only
+    // one that holds the particle itself.
     const char *pbase = reinterpret_cast<const char *>(pos);  // slots < 2^26: 32-bit offsets
-    auto walk = [&](Piece A, Piece B, int ka, int kb, bool shA, bool shB, int gA, int gB) {
+    auto walk = [&](Piece A, Piece B, int ka, int kb, bool shA, bool shB, int gA, int gB,
+                    auto own) {
         constexpr int U = 8;
+        constexpr bool kOwn = decltype(own)::value;
         const int tot = A.len + B.len;
         const bool sh = __ballot(active && (shA || shB)) != 0;
         float3 aA = make_float3(0.f, 0.f, 0.f), pA = pi, aB = aA, pB = pi;
@@ -1122,15 +1126,15 @@ void k_verlet_ls(State st, const int32_t *blocks, float R2, int cap, int cap4) {
 #pragma unroll
             for (int u = 0; u < U; u++) {
                 const int mu = m + u;
+                const bool other = !kOwn || jj[u] != (int)i;
                 if (sh) {
                     const bool inA = mu < A.len;
-                    const bool hit = (mu < tot) & (jj[u] != (int)i) &
+                    const bool hit = (mu < tot) & other &
                                      test_cand<true>(q[u], inA ? aA : aB, inA ? pA : pB, R2);
                     put_if(ring, cap, cnt, jj[u], hit);
                     img |= hit & (inA ? shA : shB);
                 } else {
-                    const bool hit =
-                        (mu < tot) & (jj[u] != (int)i) & test_cand<false>(q[u], aA, pi, R2);
+                    const bool hit = (mu < tot) & other & test_cand<false>(q[u], aA, pi, R2);
                     put_if(ring, cap, cnt, jj[u], hit);
                 }
             }
@@ -1211,8 +1215,9 @@ void k_verlet_ls(State st, const int32_t *blocks, float R2, int cap, int cap4) {
         // pairs of opposite columns, then the particle's own column
 #pragma unroll
         for (int pr = 0; pr < 4; pr++)
-            walk(w[pr][0], w[8 - pr][0], pr, 8 - pr, shx[pr], shx[8 - pr], 0, 0);
-        walk(w[4][0], none, 4, 4, shx[4], false, 0, 0);
+            walk(w[pr][0], w[8 - pr][0], pr, 8 - pr, shx[pr], shx[8 - pr], 0, 0,
+                 std::false_type{});
+        walk(w[4][0], none, 4, 4, shx[4], false, 0, 0, std::true_type{});
     } else if (!sorted) {
         // some lane's column wraps in z: pairs of opposite columns with both
         // z-pieces of each (together a column's pieces span the z-range of an
@@ -1253,7 +1258,7 @@ void k_verlet_ls(State st, const int32_t *blocks, float R2, int cap, int cap4) {
             }
             const int k = kg >> 1, g = kg & 1;
             const float az = g ? azs[1] : azs[0], pz = g ? pks[1] : pks[0];
-            walk(P, none, k, k, shk || az != 0.f || pz != pi.z, false, g, g);
+            walk(P, none, k, k, shk || az != 0.f || pz != pi.z, false, g, g, std::true_type{});
         }
     }
     if (active) {
