@@ -194,7 +194,7 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(State st) {
     if (b == (int)gridDim.x - 1 && t == 0) st.off[d.off_base + d.ncells] = carry + tot;
 }
 
-// Scatter (caller id, source slot, z) to the cell's offset + arrival rank.
+// Scatter (caller id, source slot, z, cell) to the cell's offset + arrival rank.
 __global__ void k_scatter(State st) {
     const int s = block_system(st);
     if (!rebuilding(st, s)) return;
@@ -203,7 +203,7 @@ __global__ void k_scatter(State st) {
     if (i - d.slot_base >= d.n) return;
     const int c = st.cid[i];
     const int slot = st.off[off_index(d, c)] + st.rnk[i];
-    st.tmp[slot] = make_int4(st.id[0][i], (int32_t)i, __float_as_int(st.pos[0][i].z), 0);
+    st.tmp[slot] = make_int4(st.id[0][i], (int32_t)i, __float_as_int(st.pos[0][i].z), c);
 }
 
 // The final slot inside the cell is the number of cell members that come
@@ -212,26 +212,36 @@ __global__ void k_scatter(State st) {
 // Gathers position, velocity and id into buffer 1 and records the build
 // positions.  Each member also writes the eighth-of-cell table entries that
 // start at its slot (the eighths after its predecessor's, up to its own; the
-// last member closes the cell).
-__global__ void k_rank_gather(State st) {
+// last member closes the cell).  The members that lie in the workgroup's
+// own slots are read from LDS.
+__global__ __launch_bounds__(kBlock) void k_rank_gather(State st) {
+    __shared__ int4 stage[kBlock];
     const int s = block_system(st);
-    if (!rebuilding(st, s)) return;
+    if (!rebuilding(st, s)) return;  // the whole workgroup
     const SysDesc &d = st.sys[s];
     const int64_t i = global_slot();
-    if (i - d.slot_base < d.n) {
-        const int4 me = st.tmp[i];
+    const int lo = (int)(i - threadIdx.x);  // the workgroup's first slot
+    const bool member = i - d.slot_base < d.n;
+    const int4 me = member ? st.tmp[i] : make_int4(0, 0, 0, 0);
+    stage[threadIdx.x] = me;
+    __syncthreads();
+    if (member) {
         const float mz = __int_as_float(me.z);
-        const int c = st.cid[me.y];
+        const int c = me.w;
         const int beg = st.off[off_index(d, c)], end = st.off[off_index(d, c) + 1];
         int r = 0;
         float zprev = -INFINITY;
-        for (int k = beg; k < end; k++) {
-            const int4 o = st.tmp[k];
+        auto count = [&](int4 o) {
             const float oz = __int_as_float(o.z);
             const bool before = oz < mz || (oz == mz && o.x < me.x);
             r += before;
             zprev = before ? fmaxf(zprev, oz) : zprev;
-        }
+        };
+        // [sb, se): the cell's members among this workgroup's slots (i is one)
+        const int sb = max(beg, lo), se = min(end, lo + kBlock);
+        for (int k = beg; k < sb; k++) count(st.tmp[k]);
+        for (int k = sb; k < se; k++) count(stage[k - lo]);
+        for (int k = se; k < end; k++) count(st.tmp[k]);
         const int f = beg + r;
         if (d.zb == -4 || d.zb == -5) {
             const int nz = d.box.nc[2];

@@ -120,7 +120,7 @@ struct State {
     float4 *xbuild;         // positions at the last rebuild
     int32_t *cid;           // global cell of each slot
     int32_t *rnk;           // arrival rank inside the cell
-    int4 *tmp;              // (caller id, source slot, z bits, 0) after the scatter
+    int4 *tmp;              // (caller id, source slot, z bits, cell) after the scatter
     int32_t *cnt;           // per-cell counts (kept at zero between rebuilds)
     int32_t *off;           // per system: exclusive scan of counts (global slots), ncells + 1
     int32_t *sub;           // per cell, 8 entries: first slot whose z lies in eighth q of the
