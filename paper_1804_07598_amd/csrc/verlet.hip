@@ -1112,38 +1112,47 @@ void k_verlet_ls(State st, const int32_t *blocks, float R2, int cap, int cap4) {
             shifts(ka, gA, aA, pA);
             shifts(kb, gB, aB, pB);
         }
-        for (int m = 0; __ballot(m < tot) != 0; m += U) {
-            int jj[U];
-            float4 q[U];
+        // one loop for wavefronts with shifted candidates, one without (the
+        // choice is uniform, so it is taken once per walk)
+        auto rounds = [&](auto shifted) {
+            constexpr bool kSh = decltype(shifted)::value;
+            for (int m = 0; __ballot(m < tot) != 0; m += U) {
+                int jj[U];
+                float4 q[U];
 #pragma unroll
-            for (int u = 0; u < U; u++) {
-                const int mu = m + u;
-                jj[u] = mu < A.len ? A.lo + mu : (mu < tot ? B.lo + (mu - A.len) : A.lo);
-            }
+                for (int u = 0; u < U; u++) {
+                    const int mu = m + u;
+                    jj[u] = mu < A.len ? A.lo + mu : (mu < tot ? B.lo + (mu - A.len) : A.lo);
+                }
 #pragma unroll
-            for (int u = 0; u < U; u++)
-                q[u] = *reinterpret_cast<const float4 *>(pbase + ((uint32_t)jj[u] << 4));
+                for (int u = 0; u < U; u++)
+                    q[u] = *reinterpret_cast<const float4 *>(pbase + ((uint32_t)jj[u] << 4));
 #pragma unroll
-            for (int u = 0; u < U; u++) {
-                const int mu = m + u;
-                const bool other = !kOwn || jj[u] != (int)i;
-                if (sh) {
-                    const bool inA = mu < A.len;
-                    const bool hit = (mu < tot) & other &
-                                     test_cand<true>(q[u], inA ? aA : aB, inA ? pA : pB, R2);
-                    put_if(ring, cap, cnt, jj[u], hit);
-                    img |= hit & (inA ? shA : shB);
-                } else {
-                    const bool hit = (mu < tot) & other & test_cand<false>(q[u], aA, pi, R2);
-                    put_if(ring, cap, cnt, jj[u], hit);
+                for (int u = 0; u < U; u++) {
+                    const int mu = m + u;
+                    const bool other = !kOwn || jj[u] != (int)i;
+                    if (kSh) {
+                        const bool inA = mu < A.len;
+                        const bool hit = (mu < tot) & other &
+                                         test_cand<true>(q[u], inA ? aA : aB, inA ? pA : pB, R2);
+                        put_if(ring, cap, cnt, jj[u], hit);
+                        img |= hit & (inA ? shA : shB);
+                    } else {
+                        const bool hit = (mu < tot) & other & test_cand<false>(q[u], aA, pi, R2);
+                        put_if(ring, cap, cnt, jj[u], hit);
+                    }
+                }
+                if (__ballot(min(cnt, cap) - done >= kFlushAt) != 0) {
+                    const int upto = min(cnt, cap) & ~3;
+                    flush_ring(ring, gl, done, upto);
+                    done = upto;
                 }
             }
-            if (__ballot(min(cnt, cap) - done >= kFlushAt) != 0) {
-                const int upto = min(cnt, cap) & ~3;
-                flush_ring(ring, gl, done, upto);
-                done = upto;
-            }
-        }
+        };
+        if (sh)
+            rounds(std::true_type{});
+        else
+            rounds(std::false_type{});
     };
     // the same over four pieces: both z-pieces of column ka, then both of
     // column kb (lanes whose column wraps in z have two)
