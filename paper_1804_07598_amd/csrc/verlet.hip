@@ -937,12 +937,14 @@ __device__ __forceinline__ void flush_ring(const int *ring, int *gl, int from, i
             *reinterpret_cast<const int4 *>(ring + (k & (kRingEnt - 1)));
 }
 
-// Appends slot j to the list of this lane when `hit` (entries beyond the
-// capacity are counted, not kept).  Called for every candidate, without a
-// branch: a miss, or a hit beyond the capacity, writes the spare word after
-// the ring instead.
-__device__ __forceinline__ void put_if(int *ring, int cap, int &cnt, int j, bool hit) {
-    ring[hit & (cnt < cap) ? (cnt & (kRingEnt - 1)) : kRingEnt] = j;
+// Appends slot j to the list of this lane when `hit`.  Called for every
+// candidate, without a branch: a miss writes the spare word after the ring.
+// Past the capacity the count goes on and hits may overwrite ring entries not
+// yet stored: such a list is reported as overflowed (FPM_EOVERFLOW, lists
+// invalid), its stored entries are still slots of the system, and nothing is
+// written beyond the capacity.
+__device__ __forceinline__ void put_if(int *ring, int &cnt, int j, bool hit) {
+    ring[hit ? (cnt & (kRingEnt - 1)) : kRingEnt] = j;
     cnt += hit;
 }
 
@@ -983,7 +985,7 @@ __device__ __forceinline__ void lockstep_whole_system(const State &st, const Sys
             const int j = m + u;
             const bool hit = active & (j < end) & (j != (int)i) &
                              (cand_d2<true>(pi, xyz(q[u]), b) <= R2);
-            put_if(ring, cap, cnt, j, hit);
+            put_if(ring, cnt, j, hit);
             img |= hit & uses_image(pi, xyz(q[u]), b);
         }
         if (__ballot(min(cnt, cap) - done >= kFlushAt) != 0) {
@@ -1135,11 +1137,11 @@ void k_verlet_ls(State st, const int32_t *blocks, float R2, int cap, int cap4) {
                         const bool inA = mu < A.len;
                         const bool hit = (mu < tot) & other &
                                          test_cand<true>(q[u], inA ? aA : aB, inA ? pA : pB, R2);
-                        put_if(ring, cap, cnt, jj[u], hit);
+                        put_if(ring, cnt, jj[u], hit);
                         img |= hit & (inA ? shA : shB);
                     } else {
                         const bool hit = (mu < tot) & other & test_cand<false>(q[u], aA, pi, R2);
-                        put_if(ring, cap, cnt, jj[u], hit);
+                        put_if(ring, cnt, jj[u], hit);
                     }
                 }
                 if (__ballot(min(cnt, cap) - done >= kFlushAt) != 0) {
@@ -1185,7 +1187,7 @@ void k_verlet_ls(State st, const int32_t *blocks, float R2, int cap, int cap4) {
                 const float3 a = make_float3(inb ? axb : axa, inb ? ayb : aya, g1 ? azs[1] : azs[0]);
                 const float3 pk = make_float3(inb ? pxb : pxa, inb ? pyb : pya, g1 ? pks[1] : pks[0]);
                 const bool hit = (mu < tot) & (jj[u] != (int)i) & test_cand<true>(q[u], a, pk, R2);
-                put_if(ring, cap, cnt, jj[u], hit);
+                put_if(ring, cnt, jj[u], hit);
                 img |= hit & ((inb ? sxb : sxa) | (g1 ? sz1 : sz0));
             }
             if (__ballot(min(cnt, cap) - done >= kFlushAt) != 0) {
