@@ -160,7 +160,9 @@ size_t layout(const fpm_ctx *c, const Plan &P, char *base, State *st,
         return p;
     };
     State s{};
-    for (int k = 0; k < 2; k++) s.pos[k] = (float4 *)take(ns * sizeof(float4));
+    // positions: kPosSlack slots past the end, which the lockstep build's
+    // walks may read (and never test) beyond a lane's last window
+    for (int k = 0; k < 2; k++) s.pos[k] = (float4 *)take((ns + kPosSlack) * sizeof(float4));
     for (int k = 0; k < 2; k++) s.vel[k] = (float4 *)take(ns * sizeof(float4));
     for (int k = 0; k < 2; k++) s.id[k] = (int32_t *)take(ns * sizeof(int32_t));
     s.frc = (float4 *)take(ns * sizeof(float4));

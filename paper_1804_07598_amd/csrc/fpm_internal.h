@@ -33,6 +33,7 @@ constexpr int kMaxNbrCap = 4096;   // largest accepted Verlet-list capacity
 constexpr int64_t kMaxParticles = (int64_t(1) << 26) - 1;
 constexpr int kMaxSystems = 1 << 16;
 constexpr uint32_t kWrapBit = 0x80000000u;  // "list holds periodic images" flag in counts
+constexpr int kPosSlack = 8;       // readable slots after each position buffer
 
 // Per-block partial results: for each slot one double per particle workgroup
 // (part[slot * pstride + block]), reduced per system in a fixed order by the

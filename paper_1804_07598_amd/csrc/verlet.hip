@@ -979,7 +979,7 @@ __device__ __forceinline__ void lockstep_whole_system(const State &st, const Sys
         float4 q[U];
 #pragma unroll
         for (int u = 0; u < U; u++)
-            q[u] = *reinterpret_cast<const float4 *>(pbase + ((uint32_t)min(m + u, end - 1) << 4));
+            q[u] = *reinterpret_cast<const float4 *>(pbase + ((uint32_t)(m + u) << 4));
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const int j = m + u;
@@ -1099,7 +1099,8 @@ void k_verlet_ls(State st, const int32_t *blocks, float R2, int cap, int cap4) {
     bool img = false;
     // one walk over window A followed by window B, all lanes in step, eight
     // candidates per round (their loads issued together); indices past the
-    // end of a lane's walk re-read a valid slot and are not tested.  `own`
+    // end of a lane's walk run up to seven slots past its last window (into
+    // the position buffer's slack at most) and are not tested.  `own`
     // (std::true_type) when a window is the particle's own column, the only
     // one that holds the particle itself.
     const char *pbase = reinterpret_cast<const char *>(pos);  // slots < 2^26: 32-bit offsets
@@ -1124,7 +1125,7 @@ void k_verlet_ls(State st, const int32_t *blocks, float R2, int cap, int cap4) {
 #pragma unroll
                 for (int u = 0; u < U; u++) {
                     const int mu = m + u;
-                    jj[u] = mu < A.len ? A.lo + mu : (mu < tot ? B.lo + (mu - A.len) : A.lo);
+                    jj[u] = (mu < A.len ? A.lo : B.lo - A.len) + mu;
                 }
 #pragma unroll
                 for (int u = 0; u < U; u++)
@@ -1174,7 +1175,7 @@ void k_verlet_ls(State st, const int32_t *blocks, float R2, int cap, int cap4) {
                 const int base = mu < c1 ? P[0].lo
                                  : mu < c2 ? P[1].lo - c1
                                  : mu < c3 ? P[2].lo - c2 : P[3].lo - c3;
-                jj[u] = mu < tot ? base + mu : P[0].lo;
+                jj[u] = base + mu;  // past the last piece: into the slack at most
             }
 #pragma unroll
             for (int u = 0; u < U; u++)

@@ -60,7 +60,8 @@ void audit(const char *cfg, int nsys, const float *L, const int32_t *per, const 
     expect(ncall == n, "caller indices cover n", cfg);
     const size_t lst = (size_t)ns * cap4_for(cap) * 4;  // list entries (nbr_index range)
     std::vector<Arr> arrs = {
-        {"pos0", s.pos[0], ns * sizeof(float4)},   {"pos1", s.pos[1], ns * sizeof(float4)},
+        {"pos0", s.pos[0], (ns + kPosSlack) * sizeof(float4)},
+        {"pos1", s.pos[1], (ns + kPosSlack) * sizeof(float4)},
         {"vel0", s.vel[0], ns * sizeof(float4)},   {"vel1", s.vel[1], ns * sizeof(float4)},
         {"id0", s.id[0], ns * sizeof(int32_t)},    {"id1", s.id[1], ns * sizeof(int32_t)},
         {"frc", s.frc, ns * sizeof(float4)},       {"xbuild", s.xbuild, ns * sizeof(float4)},
