@@ -57,7 +57,7 @@ bool system_counts(const fpm_ctx *c, int64_t n, std::vector<int64_t> &cnt) {
 }
 
 constexpr int kShortListCap = 48;
-constexpr int64_t kLockstepMinSlots = 131072;  // 512 workgroups: two per CU
+constexpr int64_t kLockstepMinSlots = 131072;  // 2048 wavefronts: two per SIMD
 
 Plan make_plan(const fpm_ctx *c, const std::vector<int64_t> &cnt) {
     Plan P;
@@ -95,8 +95,9 @@ Plan make_plan(const fpm_ctx *c, const std::vector<int64_t> &cnt) {
         // kLockstepMinSlots particles, all systems together (1M LJ atoms, 76
         // entries: 452 against 518 us; 512 boxes of 256..8192 atoms, 2.2M in
         // all: 658 against 724 us per step) and -2 below that, where the
-        // lockstep build's one workgroup per 256 slots would leave the device
-        // short of workgroups; grids of fewer than three cells per axis take
+        // lockstep build's one wavefront per 64 particles leaves the SIMDs
+        // short of waves (32,768-atom mixture: 130 against 55 us); grids of
+        // fewer than three cells per axis take
         // -3 (built in the lockstep launch when -4 is the context's choice and
         // the grid has at most two cells per axis).
         const bool big = d.box.nc[0] >= 3 && d.box.nc[1] >= 3 && d.box.nc[2] >= 3;
