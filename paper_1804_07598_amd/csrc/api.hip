@@ -531,19 +531,29 @@ int fpm_set_workspace(fpm_ctx *c, void *ws, size_t bytes) {
     return FPM_OK;
 }
 
-int fpm_set_particles(fpm_ctx *c, int64_t n, const float *pos, const float *vel,
-                      const int32_t *type) {
-    if (!c) return FPM_EINVAL;
-    if (!c->nbr_set) return fail(c, FPM_EINVAL, "set box and neighbour parameters first");
-    if (n < 1 || n > kMaxParticles) return fail(c, FPM_EINVAL, "particle count out of range");
-    if (!pos) return fail(c, FPM_EINVAL, "null positions");
-    std::vector<int64_t> cnt;
-    if (!system_counts(c, n, cnt)) return fail(c, FPM_EINVAL, "n differs from the batch total");
-    Plan P = make_plan(c, cnt);
-    const size_t need = layout(c, P, nullptr, nullptr);
-    if (!c->ws || c->ws_bytes < need) return fail(c, FPM_ENOWS, "workspace missing or too small");
-    c->have_particles = false;
-    drop_graphs(c);
+// The bytes that fix a plan's device tables and workspace layout.
+std::vector<char> plan_key(const fpm_ctx *c, const Plan &P) {
+    std::vector<char> k;
+    auto put = [&](const void *p, size_t bytes) {
+        const char *b = static_cast<const char *>(p);
+        k.insert(k.end(), b, b + bytes);
+    };
+    const void *ws = c->ws;
+    put(&ws, sizeof(ws));
+    put(&P.n_slots, sizeof(P.n_slots));
+    put(P.desc.data(), P.desc.size() * sizeof(SysDesc));
+    for (const std::vector<int32_t> *v :
+         {&P.blk2sys, &P.item2sys, &P.pa_blocks, &P.grp_blocks, &P.ls_blocks}) {
+        const size_t m = v->size();
+        put(&m, sizeof(m));
+        put(v->data(), m * sizeof(int32_t));
+    }
+    return k;
+}
+
+// Lays out the workspace for plan P (n particles) and uploads its tables;
+// waits for the copies.
+hipError_t upload_plan(fpm_ctx *c, const Plan &P, int64_t n) {
     layout(c, P, (char *)c->ws, &c->st, &c->pa_blocks);
     c->sys = P.sys;
     c->nsys = (int)P.sys.size();
@@ -559,27 +569,44 @@ int fpm_set_particles(fpm_ctx *c, int64_t n, const float *pos, const float *vel,
     c->max_ncells = P.max_ncells;
     c->max_sys_blocks = P.max_sys_blocks;
     // the tables are small; the copies finish before the host vectors go away
-    HIPCHK(c, hipMemcpyAsync((void *)c->st.sys, P.desc.data(), P.desc.size() * sizeof(SysDesc),
-                             hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync((void *)c->st.blk2sys, P.blk2sys.data(),
-                             P.blk2sys.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
-    if (!P.item2sys.empty())
-        HIPCHK(c, hipMemcpyAsync((void *)c->st.item2sys, P.item2sys.data(),
-                                 P.item2sys.size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                                 c->stream));
-    if (!P.pa_blocks.empty())
-        HIPCHK(c, hipMemcpyAsync(c->pa_blocks, P.pa_blocks.data(),
-                                 P.pa_blocks.size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                                 c->stream));
-    if (!P.grp_blocks.empty())  // after the particle-by-particle blocks
-        HIPCHK(c, hipMemcpyAsync(c->pa_blocks + P.pa_blocks.size(), P.grp_blocks.data(),
-                                 P.grp_blocks.size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                                 c->stream));
-    if (!P.ls_blocks.empty())  // then the lockstep blocks
-        HIPCHK(c, hipMemcpyAsync(c->pa_blocks + P.pa_blocks.size() + P.grp_blocks.size(),
-                                 P.ls_blocks.data(), P.ls_blocks.size() * sizeof(int32_t),
-                                 hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const struct {
+        void *dst;
+        const std::vector<int32_t> *src;
+    } tables[] = {{(void *)c->st.blk2sys, &P.blk2sys},
+                  {(void *)c->st.item2sys, &P.item2sys},
+                  {c->pa_blocks, &P.pa_blocks},  // then the lane-group and lockstep blocks
+                  {c->pa_blocks + P.pa_blocks.size(), &P.grp_blocks},
+                  {c->pa_blocks + P.pa_blocks.size() + P.grp_blocks.size(), &P.ls_blocks}};
+    hipError_t e = hipMemcpyAsync((void *)c->st.sys, P.desc.data(),
+                                  P.desc.size() * sizeof(SysDesc), hipMemcpyHostToDevice,
+                                  c->stream);
+    for (const auto &t : tables)
+        if (e == hipSuccess && !t.src->empty())
+            e = hipMemcpyAsync(t.dst, t.src->data(), t.src->size() * sizeof(int32_t),
+                               hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return e;
+}
+
+int fpm_set_particles(fpm_ctx *c, int64_t n, const float *pos, const float *vel,
+                      const int32_t *type) {
+    if (!c) return FPM_EINVAL;
+    if (!c->nbr_set) return fail(c, FPM_EINVAL, "set box and neighbour parameters first");
+    if (n < 1 || n > kMaxParticles) return fail(c, FPM_EINVAL, "particle count out of range");
+    if (!pos) return fail(c, FPM_EINVAL, "null positions");
+    std::vector<int64_t> cnt;
+    if (!system_counts(c, n, cnt)) return fail(c, FPM_EINVAL, "n differs from the batch total");
+    Plan P = make_plan(c, cnt);
+    const size_t need = layout(c, P, nullptr, nullptr);
+    if (!c->ws || c->ws_bytes < need) return fail(c, FPM_ENOWS, "workspace missing or too small");
+    std::vector<char> key = plan_key(c, P);
+    if (!(c->have_particles && key == c->plan_key)) {
+        // a new layout: tables uploaded, captured graphs dropped
+        c->have_particles = false;
+        drop_graphs(c);
+        HIPCHK(c, upload_plan(c, P, n));
+        c->plan_key = std::move(key);
+    }  // else the same layout and tables: the state is re-initialised in place
     HIPCHK(c, launch_fill_i32(c->stream, c->st.cnt, c->ncells_total, 0));
     HIPCHK(c, launch_init_state(c, pos, vel, type));
     HIPCHK(c, launch_force_rebuild(c));

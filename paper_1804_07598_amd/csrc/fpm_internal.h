@@ -198,6 +198,7 @@ struct fpm_ctx {
     size_t ws_bytes = 0;
     fpm::State st{};
     std::vector<fpm::SysHost> sys;
+    std::vector<char> plan_key;  // tables and layout of the last fpm_set_particles
     int nsys = 0;
     int nblk = 0;            // particle workgroups of the batch
     int ncells_total = 0;
