@@ -161,7 +161,11 @@ int fpm_set_workspace(fpm_ctx *ctx, void *d_ws, size_t bytes);
 
 /* Copies n particles in (device arrays, caller order): positions inside the
  * box, velocities (may be NULL = zero) and types (NULL = all 0; SPH: kind,
- * 0 fluid / 1 boundary).  Builds the cell list and Verlet list. */
+ * 0 fluid / 1 boundary).  Builds the cell list and Verlet list.  Called
+ * again with the same n and settings it keeps the workspace layout and the
+ * captured step graphs and does not synchronise the stream (a restart from a
+ * checkpoint); otherwise it lays the workspace out anew and waits for the
+ * upload of its tables. */
 int fpm_set_particles(fpm_ctx *ctx, int64_t n, const float *d_pos, const float *d_vel,
                       const int32_t *d_type);
 /* New positions (device, caller order, n x 3) for the current particles,
