@@ -230,6 +230,26 @@ def test_set_positions_moved_by_whole_periods():
     check_lj(sim, pg, s.box)
 
 
+@pytest.mark.parametrize("tuning", [None, (5, 0, 8)])
+def test_set_particles_again_equals_a_fresh_context(tuning):
+    # a second fpm_set_particles with the same count keeps the layout and the
+    # captured step graphs; the state must be that of a fresh context
+    import torch
+    a = inputs.lj_lattice(4096, 0.8442, 1.0, seed=31)
+    b = inputs.lj_lattice(4096, 0.8442, 1.2, seed=32)
+    sim = make_sim(a, tuning=tuning)
+    sim.step(30, dt=0.005)  # graphs captured, lists rebuilt on the way
+    sim.set_particles(b.pos, b.vel)
+    th = np_(sim.step(25, dt=0.005))
+    ref = make_sim(b, tuning=tuning)
+    th_ref = np_(ref.step(25, dt=0.005))
+    for x, y in zip(sim.get(), ref.get()):
+        assert torch.equal(x, y)
+    assert np.array_equal(th, th_ref)
+    assert sim.counters() == ref.counters()
+    sim.check()
+
+
 @pytest.mark.parametrize("tuning", [None, (3, 0, 8), (4, 8, 8), (5, 0, 8)])
 def test_overflow_is_reported(tuning):
     from paper_1804_07598_amd._lib import FpmError, FPM_EOVERFLOW
