@@ -51,10 +51,15 @@ __device__ __forceinline__ double sqrt64(double x) {
     return fma(0.5 * s, fma(-s, y, 1.0), s);   // one Newton step on sqrt
 }
 
+// Tait's equation of state.  G7: gamma is 7 (x^7 by multiplications);
+// otherwise k.gamma7 decides between that and pow(x, gamma).  The rates
+// kernels take G7 as a template argument, so that with gamma = 7 their pair
+// loop holds no pow.
+template <bool G7 = false>
 __device__ __forceinline__ double tait(double rho, const SphCoef &k) {
     const double x = rho * k.inv_rho0;
     double xg;
-    if (k.gamma7) {
+    if (G7 || k.gamma7) {
         const double x2 = x * x, x4 = x2 * x2;
         xg = x4 * x2 * x;
     } else {
@@ -81,7 +86,7 @@ __device__ __forceinline__ double grad_factor(double r, const SphCoef &k) {
     return q < 1.0 ? inner : outer;
 }
 
-template <bool IMG, int KER>
+template <bool IMG, int KER, bool G7>
 __device__ __forceinline__ void sph_pair(SphAcc &s, float3 pi, double xi, double yi, double zi,
                                          float4 vi, double Pa_over, float4 q, float4 w,
                                          const Box &b, float rc2, const SphCoef &k) {
@@ -111,7 +116,7 @@ __device__ __forceinline__ void sph_pair(SphAcc &s, float3 pi, double xi, double
         // continuity, Eq. 2
         s.dr += k.m * gw * vr;
         // momentum, Eq. 1 (pressure part uses (P_a + P_b) / (rho_a rho_b))
-        const double Pb = tait(rho_b, k);
+        const double Pb = tait<G7>(rho_b, k);
         const double rho_a = (double)vi.w;
         double term = (Pa_over + Pb) * rcp64(rho_a * rho_b);
         const double mu = k.h * vr * rcp64(r2 + k.eta2);
@@ -124,7 +129,7 @@ __device__ __forceinline__ void sph_pair(SphAcc &s, float3 pi, double xi, double
     }
 }
 
-template <bool IMG, int KER>
+template <bool IMG, int KER, bool G7>
 __device__ __forceinline__ void sph_walk(SphAcc &s, const float4 *__restrict__ pos,
                                          const float4 *__restrict__ vel,
                                          const int4 *__restrict__ lst, int cnt, int self,
@@ -152,11 +157,11 @@ __device__ __forceinline__ void sph_walk(SphAcc &s, const float4 *__restrict__ p
         }
 #pragma unroll
         for (int u = 0; u < 4; u++)
-            sph_pair<IMG, KER>(s, pi, xi, yi, zi, vi, Pa, q[u], w[u], b, rc2, k);
+            sph_pair<IMG, KER, G7>(s, pi, xi, yi, zi, vi, Pa, q[u], w[u], b, rc2, k);
     }
 }
 
-template <int KER>
+template <int KER, bool G7>
 __global__ __launch_bounds__(kBlock) void k_sph_rates(State st, float rc2, SphCoef k,
                                                       int cap4) {
     const SysDesc &d = st.sys[block_system(st)];
@@ -176,12 +181,12 @@ __global__ __launch_bounds__(kBlock) void k_sph_rates(State st, float rc2, SphCo
     const int cnt = (int)(nn & ~kWrapBit);
     const int4 *lst = reinterpret_cast<const int4 *>(st.nbr) +
                       ((i >> 6) * (int64_t)cap4) * 64 + (i & 63);
-    const double Pa = tait((double)vi.w, k);
+    const double Pa = tait<G7>((double)vi.w, k);
     SphAcc s;
     if (img_wave)
-        sph_walk<true, KER>(s, pos, vel, lst, cnt, (int)i, pi4, vi, Pa, b, rc2, k);
+        sph_walk<true, KER, G7>(s, pos, vel, lst, cnt, (int)i, pi4, vi, Pa, b, rc2, k);
     else
-        sph_walk<false, KER>(s, pos, vel, lst, cnt, (int)i, pi4, vi, Pa, b, rc2, k);
+        sph_walk<false, KER, G7>(s, pos, vel, lst, cnt, (int)i, pi4, vi, Pa, b, rc2, k);
     const bool fluid = __float_as_int(pi4.w) == 0;
     double accmin = 1e300;
     if (active) {
@@ -391,12 +396,15 @@ SphCoef make_coef(const fpm_ctx *c, const fpm_sph_params &p) {
 
 hipError_t launch_sph_rates(fpm_ctx *c, const fpm_sph_params &p) {
     const SphCoef k = make_coef(c, p);
-    if (p.kernel == 1)
-        hipLaunchKernelGGL(k_sph_rates<1>, dim3(c->nblk), dim3(kBlock), 0, c->stream, c->st,
-                           c->rc2, k, c->cap4);
+    const dim3 g((unsigned)c->nblk), t(kBlock);
+    if (p.kernel == 1 && k.gamma7)
+        hipLaunchKernelGGL((k_sph_rates<1, true>), g, t, 0, c->stream, c->st, c->rc2, k, c->cap4);
+    else if (p.kernel == 1)
+        hipLaunchKernelGGL((k_sph_rates<1, false>), g, t, 0, c->stream, c->st, c->rc2, k, c->cap4);
+    else if (k.gamma7)
+        hipLaunchKernelGGL((k_sph_rates<0, true>), g, t, 0, c->stream, c->st, c->rc2, k, c->cap4);
     else
-        hipLaunchKernelGGL(k_sph_rates<0>, dim3(c->nblk), dim3(kBlock), 0, c->stream, c->st,
-                           c->rc2, k, c->cap4);
+        hipLaunchKernelGGL((k_sph_rates<0, false>), g, t, 0, c->stream, c->st, c->rc2, k, c->cap4);
     return hipGetLastError();
 }
 
