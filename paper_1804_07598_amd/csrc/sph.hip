@@ -129,6 +129,22 @@ __device__ __forceinline__ void sph_pair(SphAcc &s, float3 pi, double xi, double
     }
 }
 
+// Positions and velocities of the four neighbours of one list group.
+__device__ __forceinline__ void sph_gather(const char *pb, const char *vb, int4 e, float4 (&q)[4],
+                                           float4 (&w)[4]) {
+    const uint32_t jj[4] = {(uint32_t)e.x << 4, (uint32_t)e.y << 4, (uint32_t)e.z << 4,
+                            (uint32_t)e.w << 4};
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        q[u] = *reinterpret_cast<const float4 *>(pb + jj[u]);
+        w[u] = *reinterpret_cast<const float4 *>(vb + jj[u]);
+    }
+}
+
+// Walks a list padded to a multiple of eight entries four at a time,
+// software-pipelined: the neighbours of the next group are requested before
+// the current group's pairs are evaluated (two register sets take turns; a
+// group past the end of the list re-reads one in range, which is harmless).
 template <bool IMG, int KER, bool G7>
 __device__ __forceinline__ void sph_walk(SphAcc &s, const float4 *__restrict__ pos,
                                          const float4 *__restrict__ vel,
@@ -140,24 +156,22 @@ __device__ __forceinline__ void sph_walk(SphAcc &s, const float4 *__restrict__ p
     const char *pb = reinterpret_cast<const char *>(pos);
     const char *vb = reinterpret_cast<const char *>(vel);
     (void)self;
-    // lists are padded with a far-away slot to a multiple of eight entries;
-    // the entries of the next group are requested before this group's gathers
     if (cnt <= 0) return;
-    int4 e = lst[0];
-    for (int kk = 0; kk < cnt; kk += 4) {
-        const int4 en = lst[((kk + 4 < cnt ? kk + 4 : kk) >> 2) * 64];
-        const uint32_t jj[4] = {(uint32_t)e.x << 4, (uint32_t)e.y << 4, (uint32_t)e.z << 4,
-                                (uint32_t)e.w << 4};
-        e = en;
-        float4 q[4], w[4];
-#pragma unroll
-        for (int u = 0; u < 4; u++) {
-            q[u] = *reinterpret_cast<const float4 *>(pb + jj[u]);
-            w[u] = *reinterpret_cast<const float4 *>(vb + jj[u]);
-        }
+    float4 q0[4], w0[4], q1[4], w1[4];
+    sph_gather(pb, vb, lst[0], q0, w0);
+    int4 nxt = lst[(4 < cnt ? 4 : 0) >> 2 << 6];
+    for (int kk = 0; kk < cnt; kk += 8) {
+        sph_gather(pb, vb, nxt, q1, w1);
+        nxt = lst[((kk + 8 < cnt ? kk + 8 : kk) >> 2) * 64];
 #pragma unroll
         for (int u = 0; u < 4; u++)
-            sph_pair<IMG, KER, G7>(s, pi, xi, yi, zi, vi, Pa, q[u], w[u], b, rc2, k);
+            sph_pair<IMG, KER, G7>(s, pi, xi, yi, zi, vi, Pa, q0[u], w0[u], b, rc2, k);
+        if (kk + 4 >= cnt) break;
+        sph_gather(pb, vb, nxt, q0, w0);
+        nxt = lst[((kk + 12 < cnt ? kk + 12 : kk) >> 2) * 64];
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            sph_pair<IMG, KER, G7>(s, pi, xi, yi, zi, vi, Pa, q1[u], w1[u], b, rc2, k);
     }
 }
 
