@@ -327,10 +327,14 @@ __global__ __launch_bounds__(kBlock) void k_lj(State st, float rc2, double rc2lo
     const Sided sd = make_sided(xyz(pi4), pi4.x, pi4.y, pi4.z, b, cf.side_margin, cf.side_wide,
                                  side_ok);
     const SlotRange sr = slot_range(st, d);
+    // wavefronts with image partners (a minority) keep at most four entries in
+    // flight: their walks need more registers per entry, and the kernel's
+    // register count, hence every wavefront's occupancy, is set by the largest
+    constexpr int UI = UNR < 4 ? UNR : 4;
     if (img_wave && __ballot(active && !side_ok) == 0)
-        walk<NT, 2, UNR>(a, pos, lst, cnt, pi4, b, rc2, rc2lo, rc2hi, cf, sd, sr);
+        walk<NT, 2, UI>(a, pos, lst, cnt, pi4, b, rc2, rc2lo, rc2hi, cf, sd, sr);
     else if (img_wave)
-        walk<NT, 1, UNR>(a, pos, lst, cnt, pi4, b, rc2, rc2lo, rc2hi, cf, sd, sr);
+        walk<NT, 1, UI>(a, pos, lst, cnt, pi4, b, rc2, rc2lo, rc2hi, cf, sd, sr);
     else
         walk<NT, 0, UNR>(a, pos, lst, cnt, pi4, b, rc2, rc2lo, rc2hi, cf, sd, sr);
     double ke = 0.0;
