@@ -8,7 +8,7 @@
 //  - lockstep windows (k_verlet_ls, the default for contexts of at least
 //    131,072 particles): one lane per particle; each lane's candidates in a
 //    neighbour column are one z-window of slots, and the wavefront's lanes
-//    walk their windows in step, hits staged in LDS rings;
+//    walk their windows in step, hits staged in LDS rows;
 //  - lane groups (k_verlet_grp, the default below that): G lanes per
 //    particle over the same windows (or over whole cells for grids of fewer
 //    than three cells along an axis), each 64-slot row of lists staged in
@@ -919,34 +919,77 @@ __device__ __forceinline__ bool column_of(const Box &b, int ix, int iy, float x,
     return true;
 }
 
-// Hits of the lockstep build collect in a per-lane LDS ring of kRingEnt
-// entries.  A store inside the candidate loop makes the wavefront's next loads
-// wait for it (loads and stores share one completion counter), so stores are
-// issued at few, wavefront-uniform points: after a round of candidates in
-// which some lane reached kFlushAt unwritten entries, every lane writes its
-// complete groups of four (16-byte stores into the list layout).
-constexpr int kRingEnt = 32;
-constexpr int kRingStride = kRingEnt + 4;  // ints per lane (16-byte aligned rows)
-constexpr int kFlushAt = 16;               // at most kFlushAt - 1 + 4 entries wait
+// Hits of the lockstep build collect in a per-lane LDS row, unwritten ones
+// at its front.  A store inside the candidate loop makes the wavefront's next
+// loads wait for it (loads and stores share one completion counter), so
+// stores are issued at few, wavefront-uniform points: after a round of
+// candidates in which some lane holds kFlushAt unwritten entries, every lane
+// writes its complete groups of four (16-byte stores into the list layout)
+// and moves the rest, at most three, to the front of its row.  A round adds
+// at most eight entries, so a row never holds more than kFlushAt + 7 and the
+// final padding to eight fits as well.
+constexpr int kRowInts = 36;  // ints per lane (16-byte aligned rows)
+constexpr int kFlushAt = 16;
+static_assert(kFlushAt + 7 + 4 <= kRowInts, "a lane's row must hold a round and a group read");
 
-// Writes list entries [from, upto) (multiples of four) of this lane from its
-// ring to global memory.
-__device__ __forceinline__ void flush_ring(const int *ring, int *gl, int from, int upto) {
-    for (int k = from; k < upto; k += 4)
-        *reinterpret_cast<int4 *>(gl + (k >> 2) * 256) =
-            *reinterpret_cast<const int4 *>(ring + (k & (kRingEnt - 1)));
+// Entries are held as byte offsets into the position buffer (slot * 16, the
+// form the candidate loads use) and written to the list as slots.
+__device__ __forceinline__ int4 slots_of(int4 o) {
+    return make_int4(o.x >> 4, o.y >> 4, o.z >> 4, o.w >> 4);
 }
 
-// Appends slot j to the list of this lane when `hit`.  Called for every
-// candidate, without a branch: a miss writes the spare word after the ring.
-// Past the capacity the count goes on and hits may overwrite ring entries not
-// yet stored: such a list is reported as overflowed (FPM_EOVERFLOW, lists
-// invalid), its stored entries are still slots of the system, and nothing is
-// written beyond the capacity.
-__device__ __forceinline__ void put_if(int *ring, int &cnt, int j, bool hit) {
-    ring[hit ? (cnt & (kRingEnt - 1)) : kRingEnt] = j;
-    cnt += hit;
-}
+struct HitRow {
+    int *r;         // this lane's row
+    int loc = 0;    // unwritten entries, at r[0, loc)
+    int done = 0;   // entries written to the list
+    int lost = 0;   // hits dropped past the capacity
+
+    // Appends the slot at byte offset o when `hit`.  Called for every
+    // candidate, without a branch: a miss writes the first free word, which
+    // the next hit reuses.
+    __device__ __forceinline__ void put(int o, bool hit) {
+        r[loc] = o;
+        loc += hit;
+    }
+
+    // Writes the complete groups of four below the capacity to the list (gl:
+    // this lane's list, groups 256 ints apart) and keeps the rest.  Hits past
+    // the capacity are dropped and counted, so that the list is reported as
+    // overflowed (FPM_EOVERFLOW, lists invalid); nothing is written beyond
+    // the capacity.
+    __device__ __forceinline__ void flush(int *gl, int cap) {
+        const int keep = min(done + loc, cap);
+        const int upto = keep & ~3;
+        for (int k = done; k < upto; k += 4)
+            *reinterpret_cast<int4 *>(gl + (k >> 2) * 256) =
+                slots_of(*reinterpret_cast<const int4 *>(r + (k - done)));
+        // the remaining 0 to 3 entries to the front (upto - done is a
+        // multiple of four, at most kFlushAt + 7 - 3)
+        *reinterpret_cast<int4 *>(r) = *reinterpret_cast<const int4 *>(r + (upto - done));
+        lost += done + loc - keep;
+        loc = keep - upto;
+        done = upto;
+    }
+
+    __device__ __forceinline__ void flush_if_due(int *gl, int cap) {
+        if (__ballot(loc >= kFlushAt) != 0) flush(gl, cap);
+    }
+
+    // Hits found, including any dropped.
+    __device__ __forceinline__ int found() const { return done + loc + lost; }
+
+    // Writes the remaining entries, padded with slot `pad` to a multiple of
+    // eight, and returns the list length (at most cap).
+    __device__ __forceinline__ int finish(int *gl, int cap, int pad) {
+        const int keep = min(done + loc, cap);
+        const int c8 = (keep + 7) & ~7;
+        for (int k = keep; k < c8; k++) r[k - done] = pad << 4;
+        for (int k = done; k < c8; k += 4)
+            *reinterpret_cast<int4 *>(gl + (k >> 2) * 256) =
+                slots_of(*reinterpret_cast<const int4 *>(r + (k - done)));
+        return keep;
+    }
+};
 
 template <bool SH>
 __device__ __forceinline__ bool test_cand(float4 q, float3 a, float3 pk, float R2) {
@@ -965,12 +1008,12 @@ __device__ __forceinline__ bool test_cand(float4 q, float3 a, float3 pk, float R
 // are those of the other builds; hits come in slot order.
 __device__ __forceinline__ void lockstep_whole_system(const State &st, const SysDesc &d,
                                                       int64_t i, bool active, float R2, int cap,
-                                                      int cap4, int *ring) {
+                                                      int cap4, int *row) {
     const Box &b = d.box;
     const float4 *__restrict__ pos = st.pos[1];
     const float3 pi = active ? xyz(pos[i]) : make_float3(0.f, 0.f, 0.f);
     int *gl = st.nbr + (((i >> 6) * (int64_t)cap4 * 64 + (i & 63)) << 2);
-    int cnt = 0, done = 0;
+    HitRow hr{row};
     bool img = false;
     const int end = d.slot_base + d.n;
     const char *pbase = reinterpret_cast<const char *>(pos);
@@ -985,22 +1028,15 @@ __device__ __forceinline__ void lockstep_whole_system(const State &st, const Sys
             const int j = m + u;
             const bool hit = active & (j < end) & (j != (int)i) &
                              (cand_d2<true>(pi, xyz(q[u]), b) <= R2);
-            put_if(ring, cnt, j, hit);
+            hr.put(j << 4, hit);
             img |= hit & uses_image(pi, xyz(q[u]), b);
         }
-        if (__ballot(min(cnt, cap) - done >= kFlushAt) != 0) {
-            const int upto = min(cnt, cap) & ~3;
-            flush_ring(ring, gl, done, upto);
-            done = upto;
-        }
+        hr.flush_if_due(gl, cap);
     }
     if (active) {
-        const int c = min(cnt, cap);
-        const int c8 = (c + 7) & ~7;
-        for (int k = c; k < c8; k++) ring[k & (kRingEnt - 1)] = d.dummy;
-        flush_ring(ring, gl, done, c8);
+        const int c = hr.finish(gl, cap, d.dummy);
         st.nnb[i] = (uint32_t)c | (img ? kWrapBit : 0u);
-        note_overflow(st, cnt, cap);
+        note_overflow(st, hr.found(), cap);
     }
     copy_back(st, i);
 }
@@ -1023,10 +1059,10 @@ void k_verlet_ls(State st, const int32_t *blocks, float R2, int cap, int cap4) {
     const Box &b = d.box;
     const int64_t i = (int64_t)blk * kBlock + (r & 3) * kWave + threadIdx.x;
     const bool active = i - d.slot_base < d.n;
-    __shared__ __align__(16) int rings[kWave * kRingStride];
-    int *ring = rings + threadIdx.x * kRingStride;
+    __shared__ __align__(16) int rows[kWave * kRowInts];
+    int *row = rows + threadIdx.x * kRowInts;
     if (d.zb == -3) {  // the whole workgroup: a grid of at most two cells per axis
-        lockstep_whole_system(st, d, i, active, R2, cap, cap4, ring);
+        lockstep_whole_system(st, d, i, active, R2, cap, cap4, row);
         return;
     }
     const float4 *__restrict__ pos = st.pos[1];
@@ -1095,7 +1131,7 @@ void k_verlet_ls(State st, const int32_t *blocks, float R2, int cap, int cap4) {
         pk = make_float3(px, py, pks[g]);
     };
     int *gl = st.nbr + (((i >> 6) * (int64_t)cap4 * 64 + (i & 63)) << 2);
-    int cnt = 0, done = 0;  // entries found, entries written to global memory
+    HitRow hr{row};
     bool img = false;
     // one walk over window A followed by window B, all lanes in step, eight
     // candidates per round (their loads issued together); indices past the
@@ -1104,6 +1140,7 @@ void k_verlet_ls(State st, const int32_t *blocks, float R2, int cap, int cap4) {
     // (std::true_type) when a window is the particle's own column, the only
     // one that holds the particle itself.
     const char *pbase = reinterpret_cast<const char *>(pos);  // slots < 2^26: 32-bit offsets
+    const int io = (int)i << 4;  // this particle's byte offset
     auto walk = [&](Piece A, Piece B, int ka, int kb, bool shA, bool shB, int gA, int gB,
                     auto own) {
         constexpr int U = 8;
@@ -1120,36 +1157,31 @@ void k_verlet_ls(State st, const int32_t *blocks, float R2, int cap, int cap4) {
         auto rounds = [&](auto shifted) {
             constexpr bool kSh = decltype(shifted)::value;
             for (int m = 0; __ballot(m < tot) != 0; m += U) {
-                int jj[U];
+                // byte offsets of the round's first candidate in A and in B
+                const int oA = (A.lo + m) << 4, oB = (B.lo - A.len + m) << 4;
+                int jj[U];  // byte offsets of the candidates (slot * 16)
                 float4 q[U];
 #pragma unroll
-                for (int u = 0; u < U; u++) {
-                    const int mu = m + u;
-                    jj[u] = (mu < A.len ? A.lo : B.lo - A.len) + mu;
-                }
+                for (int u = 0; u < U; u++) jj[u] = (m + u < A.len ? oA : oB) + 16 * u;
 #pragma unroll
                 for (int u = 0; u < U; u++)
-                    q[u] = *reinterpret_cast<const float4 *>(pbase + ((uint32_t)jj[u] << 4));
+                    q[u] = *reinterpret_cast<const float4 *>(pbase + (uint32_t)jj[u]);
 #pragma unroll
                 for (int u = 0; u < U; u++) {
                     const int mu = m + u;
-                    const bool other = !kOwn || jj[u] != (int)i;
+                    const bool other = !kOwn || jj[u] != io;
                     if (kSh) {
                         const bool inA = mu < A.len;
                         const bool hit = (mu < tot) & other &
                                          test_cand<true>(q[u], inA ? aA : aB, inA ? pA : pB, R2);
-                        put_if(ring, cnt, jj[u], hit);
+                        hr.put(jj[u], hit);
                         img |= hit & (inA ? shA : shB);
                     } else {
                         const bool hit = (mu < tot) & other & test_cand<false>(q[u], aA, pi, R2);
-                        put_if(ring, cnt, jj[u], hit);
+                        hr.put(jj[u], hit);
                     }
                 }
-                if (__ballot(min(cnt, cap) - done >= kFlushAt) != 0) {
-                    const int upto = min(cnt, cap) & ~3;
-                    flush_ring(ring, gl, done, upto);
-                    done = upto;
-                }
+                hr.flush_if_due(gl, cap);
             }
         };
         if (sh)
@@ -1167,19 +1199,18 @@ void k_verlet_ls(State st, const int32_t *blocks, float R2, int cap, int cap4) {
         column_of(b, ix, iy, pi.x, pi.y, ka, axa, aya, pxa, pya, col);
         column_of(b, ix, iy, pi.x, pi.y, kb, axb, ayb, pxb, pyb, col);
         for (int m = 0; __ballot(m < tot) != 0; m += U) {
-            int jj[U];
+            const int o0 = (P[0].lo + m) << 4, o1 = (P[1].lo - c1 + m) << 4,
+                      o2 = (P[2].lo - c2 + m) << 4, o3 = (P[3].lo - c3 + m) << 4;
+            int jj[U];  // byte offsets; past the last piece: into the slack at most
             float4 q[U];
 #pragma unroll
             for (int u = 0; u < U; u++) {
                 const int mu = m + u;
-                const int base = mu < c1 ? P[0].lo
-                                 : mu < c2 ? P[1].lo - c1
-                                 : mu < c3 ? P[2].lo - c2 : P[3].lo - c3;
-                jj[u] = base + mu;  // past the last piece: into the slack at most
+                jj[u] = (mu < c1 ? o0 : mu < c2 ? o1 : mu < c3 ? o2 : o3) + 16 * u;
             }
 #pragma unroll
             for (int u = 0; u < U; u++)
-                q[u] = *reinterpret_cast<const float4 *>(pbase + ((uint32_t)jj[u] << 4));
+                q[u] = *reinterpret_cast<const float4 *>(pbase + (uint32_t)jj[u]);
 #pragma unroll
             for (int u = 0; u < U; u++) {
                 const int mu = m + u;
@@ -1187,15 +1218,11 @@ void k_verlet_ls(State st, const int32_t *blocks, float R2, int cap, int cap4) {
                 const bool g1 = inb ? mu >= c3 : mu >= c1;
                 const float3 a = make_float3(inb ? axb : axa, inb ? ayb : aya, g1 ? azs[1] : azs[0]);
                 const float3 pk = make_float3(inb ? pxb : pxa, inb ? pyb : pya, g1 ? pks[1] : pks[0]);
-                const bool hit = (mu < tot) & (jj[u] != (int)i) & test_cand<true>(q[u], a, pk, R2);
-                put_if(ring, cnt, jj[u], hit);
+                const bool hit = (mu < tot) & (jj[u] != io) & test_cand<true>(q[u], a, pk, R2);
+                hr.put(jj[u], hit);
                 img |= hit & ((inb ? sxb : sxa) | (g1 ? sz1 : sz0));
             }
-            if (__ballot(min(cnt, cap) - done >= kFlushAt) != 0) {
-                const int upto = min(cnt, cap) & ~3;
-                flush_ring(ring, gl, done, upto);
-                done = upto;
-            }
+            hr.flush_if_due(gl, cap);
         }
     };
     const Piece none{0, 0};
@@ -1274,14 +1301,11 @@ void k_verlet_ls(State st, const int32_t *blocks, float R2, int cap, int cap4) {
         }
     }
     if (active) {
-        const int c = min(cnt, cap);
-        const int c8 = (c + 7) & ~7;
         // the unwritten entries, padded with the far-away slot to a multiple of
         // eight (a list that overflowed ends at the capacity)
-        for (int k = c; k < c8; k++) ring[k & (kRingEnt - 1)] = d.dummy;
-        flush_ring(ring, gl, done, c8);
+        const int c = hr.finish(gl, cap, d.dummy);
         st.nnb[i] = (uint32_t)c | (img ? kWrapBit : 0u);
-        note_overflow(st, cnt, cap);
+        note_overflow(st, hr.found(), cap);
     }
     copy_back(st, i);
 }
