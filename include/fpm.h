@@ -252,9 +252,10 @@ int fpm_lj_adjoint_step(fpm_ctx *ctx, const fpm_lj_params *prm, float dt, const 
  * positions after step k, as fpm_step_record writes them) and one
  * fpm_lj_adjoint_step follows with d_floss = h_floss[k] (h_floss: host array
  * of nsteps device pointers, NULL entries for steps without a loss term).
- * Exactly the launches of the corresponding fpm_set_positions and
- * fpm_lj_adjoint_step calls, queued without host synchronisation, so results
- * are identical to those calls.  Velocities are left as they were. */
+ * Results, rebuild decisions and rebuild counts are identical to those
+ * calls; the launches are queued without host synchronisation, and the
+ * rebuild a step needs is accounted by its VJP launch instead of a separate
+ * reduction.  Velocities are left as they were. */
 int fpm_lj_adjoint_sweep(fpm_ctx *ctx, const fpm_lj_params *prm, float dt, int32_t nsteps,
                          const float *d_xs, const double *const *h_floss, double *d_xbar,
                          double *d_vbar, double *d_fbar, double *d_gtheta);

@@ -325,13 +325,17 @@ hipError_t with_parity(fpm_ctx *c, int par, F &&body) {
 // gated rebuild, then the force kernel with the closing half kick and (but for
 // a last step) the next step's opening half kick and drift; then the thermo
 // rows of these steps.  The first opening half kick and drift of a loop run
-// before it (fpm_step).
+// before it (fpm_step).  With `rec`, step k's positions (those its force
+// kernel reads: the positions after step k) go to rec + 3 n k in caller order.
 hipError_t lj_steps_body(fpm_ctx *c, const fpm_lj_params &p, float dt, double *thermo, int par0,
-                         int count, bool last) {
+                         int count, bool last, float *rec = nullptr) {
     hipError_t e = hipSuccess;
     for (int k = 0; k < count && e == hipSuccess; k++)
         e = with_parity(c, (par0 + k) & 1, [&] {
             hipError_t x = refresh_lists(c);
+            if (x == hipSuccess && rec)
+                x = launch_gather_out(c, rec + (size_t)k * 3 * (size_t)c->n, nullptr, nullptr,
+                                      nullptr, nullptr);
             if (x == hipSuccess) x = launch_lj_step(c, p, dt, last && k == count - 1, k);
             return x;
         });
@@ -640,8 +644,7 @@ int fpm_set_positions(fpm_ctx *c, const float *pos) {
     int r = ready(c);
     if (r) return r;
     if (!pos) return fail(c, FPM_EINVAL, "null positions");
-    HIPCHK(c, launch_set_positions(c, pos));
-    HIPCHK(c, launch_finalize(c, kFinDisp, nullptr, nullptr));
+    HIPCHK(c, launch_set_positions(c, pos));  // raises the rebuild flag if needed
     c->forces_valid = false;
     c->sph_restart = true;
     return FPM_OK;
@@ -768,11 +771,12 @@ int fpm_lj_adjoint_sweep(fpm_ctx *c, const fpm_lj_params *p, float dt, int32_t n
     if (!xbar || !vbar || !fbar) return fail(c, FPM_EINVAL, "null adjoint array");
     // step k (latest first) at the positions reached after it, x_{k+1}: the
     // launches of fpm_set_positions followed by fpm_lj_adjoint_step, queued
-    // without host synchronisation
+    // without host synchronisation (the VJP kernel accounts a rebuild and
+    // clears its flag)
     for (int32_t k = nsteps - 1; k >= 0; k--) {
         HIPCHK(c, launch_set_positions(c, xs + (size_t)k * 3 * (size_t)c->n));
-        HIPCHK(c, launch_finalize(c, kFinDisp, nullptr, nullptr));
-        HIPCHK(c, refresh_and_account(c));
+        HIPCHK(c, refresh_lists(c));
+        c->build_pending = false;
         const AdjOut o{xbar, vbar, fbar, floss[k], (double)dt, kVjpStep};
         HIPCHK(c, timed(c, "lj_vjp", [&] { return launch_lj_vjp(c, *p, fbar, vbar, o); }));
         if (gtheta) HIPCHK(c, launch_finalize(c, kFinVjp, gtheta, nullptr));
@@ -868,12 +872,26 @@ int fpm_step(fpm_ctx *c, const fpm_lj_params *p, float dt, int32_t nsteps, doubl
 int fpm_step_record(fpm_ctx *c, const fpm_lj_params *p, float dt, int32_t nsteps, float *xs) {
     int r = ready(c);
     if (r) return r;
+    if (!valid_lj(p)) return fail(c, FPM_EINVAL, "bad LJ params");
+    if (!isfinite(dt) || nsteps < 0) return fail(c, FPM_EINVAL, "bad dt or step count");
     if (nsteps > 0 && !xs) return fail(c, FPM_EINVAL, "null position record");
-    for (int32_t k = 0; k < nsteps; k++) {
-        r = fpm_step(c, p, dt, 1, nullptr);
-        if (r) return r;
-        HIPCHK(c, launch_gather_out(c, xs + (size_t)k * 3 * (size_t)c->n, nullptr, nullptr,
-                                    nullptr, nullptr));
+    if (nsteps == 0) return FPM_OK;
+    if (!c->forces_valid || c->build_pending || c->sph) {
+        HIPCHK(c, refresh_and_account(c));
+        HIPCHK(c, launch_lj_forces(c, *p));
+        c->forces_valid = true;
+    }
+    c->sph = false;
+    HIPCHK(c, launch_reset_step(c));
+    HIPCHK(c, launch_integrate(c, dt, kKickDriftFirst));
+    HIPCHK(c, launch_finalize(c, kFinDisp, nullptr, nullptr));
+    // the launches of fpm_step's loop (steps fused with the next one's opening
+    // half kick and drift, as bit for bit as separate calls), without graphs,
+    // each step's positions recorded
+    for (int32_t k0 = 0; k0 < nsteps; k0 += kPowSteps[0]) {
+        const int cnt = nsteps - k0 < kPowSteps[0] ? nsteps - k0 : kPowSteps[0];
+        HIPCHK(c, lj_steps_body(c, *p, dt, nullptr, k0 & 1, cnt, k0 + cnt == nsteps,
+                                xs + (size_t)k0 * 3 * (size_t)c->n));
     }
     return FPM_OK;
 }

@@ -207,11 +207,15 @@ __global__ void k_reset_step(SysCtl *sctl, int nsys) {
 
 // New positions in caller order for the current sorted state (type bits and
 // the neighbour structures are kept); the displacement since the last build
-// decides, as after a drift, whether they must be rebuilt.  hs: half the skin.
-__global__ __launch_bounds__(kBlock) void k_set_positions(State st, const float *pos, float hs) {
-    const SysDesc &d = st.sys[block_system(st)];
+// decides, as after a drift, whether they must be rebuilt: a wavefront with a
+// particle moved by more than half the skin raises the system's rebuild flag
+// (one lane, as the step kernel does).  hs: half the skin; thr: its square.
+__global__ __launch_bounds__(kBlock) void k_set_positions(State st, const float *pos, float hs,
+                                                          float thr) {
+    const int sys = block_system(st);
+    const SysDesc &d = st.sys[sys];
     const int64_t i = global_slot();
-    double d2 = 0.0;
+    bool over = false;
     if (i - d.slot_base < d.n) {
         const int64_t r = st.id[0][i];
         float4 p = st.pos[0][i];
@@ -220,19 +224,18 @@ __global__ __launch_bounds__(kBlock) void k_set_positions(State st, const float 
         p.z = pos[3 * r + 2];
         st.pos[0][i] = p;
         const Box &b = d.box;
-        d2 = dist2_pred(xyz(st.xbuild[i]), xyz(p), b);
+        over = dist2_pred(xyz(st.xbuild[i]), xyz(p), b) > thr;
         // a position more than half the skin outside [0, L) on a periodic axis
         // (moved by whole periods) forces the rebuild, which wraps it back: the
         // force kernels rely on every position lying within half the skin of
         // [0, L)
         const float c[3] = {p.x, p.y, p.z};
         for (int a = 0; a < 3; a++)
-            if (b.per[a] && !(c[a] >= -hs && c[a] < b.L[a] + hs)) d2 = 1e30;
+            if (b.per[a] && !(c[a] >= -hs && c[a] < b.L[a] + hs)) over = true;
         if (!isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z)) st.ctl->nonfinite = 1;
     }
-    double v1[1] = {d2};
-    const int s1[1] = {kSlotDisp}, o1[1] = {1};
-    block_partials<1>(v1, s1, o1, st.part, st.pstride);
+    const uint64_t m = __ballot(over);
+    if (m && (int)(threadIdx.x & 63) == __ffsll((long long)m) - 1) st.sctl[sys].rebuild[0] = 1;
 }
 
 // State back in caller order.
@@ -305,7 +308,7 @@ hipError_t launch_reset_step(fpm_ctx *c) {
 
 hipError_t launch_set_positions(fpm_ctx *c, const float *pos) {
     hipLaunchKernelGGL(k_set_positions, dim3(c->nblk), dim3(kBlock), 0, c->stream, c->st, pos,
-                       0.5f * c->skin);
+                       0.5f * c->skin, c->disp2_thr);
     return hipGetLastError();
 }
 

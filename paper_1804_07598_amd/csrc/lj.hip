@@ -497,11 +497,21 @@ template <int NT>
 __global__ __launch_bounds__(kBlock) void k_lj_vjp(State st, float rc2, double rc2lo,
                                                    double rc2hi, LJCoef cf, int cap4,
                                                    AdjOut o) {
-    const SysDesc &d = st.sys[block_system(st)];
+    const int sys = block_system(st);
+    const SysDesc &d = st.sys[sys];
     const Box b = d.box;
     const float4 *__restrict__ pos = st.pos[0];
     const int64_t i = global_slot();
     const bool active = i - d.slot_base < d.n;
+    if (threadIdx.x == 0 && pblock() == d.blk_base) {
+        // a rebuild that preceded this launch is complete: account it and
+        // clear its flag (nothing in this launch reads the flag)
+        SysCtl *sc = st.sctl + sys;
+        if (sc->rebuild[0]) {
+            sc->n_rebuilds += 1;
+            sc->rebuild[0] = 0;
+        }
+    }
     uint32_t nn = 0;
     float4 pi4 = make_float4(0.f, 0.f, 0.f, 0.f), li = pi4;
     if (active) {

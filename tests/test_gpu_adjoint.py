@@ -195,8 +195,9 @@ def test_segment_record_and_sweep_equal_the_per_call_sequence():
     """fpm_step_record and fpm_lj_adjoint_sweep (the device-side segment
     recomputation and reverse sweep) against the per-call sequence they stand
     for (fpm_step of one step + fpm_get_particles; fpm_set_positions +
-    fpm_lj_adjoint_step): positions and every cotangent equal bit for bit,
-    over a segment with list rebuilds and loss terms at some steps."""
+    fpm_lj_adjoint_step): positions, every cotangent and the rebuild count
+    equal bit for bit, over a segment of 30 steps (two groups of the step
+    loop) with list rebuilds and loss terms at some steps."""
     import torch
     from paper_1804_07598_amd import _lib as F
     s = mixture(3000, seed=11)
@@ -227,9 +228,11 @@ def test_segment_record_and_sweep_equal_the_per_call_sequence():
                 F.fpm_set_positions(sim.ctx, xs[k])
                 F.fpm_lj_adjoint_step(sim.ctx, prm, dt, floss[k], xbar, vbar, fbar, gt, 0)
         sim.check()
-        out.append([np_(t) for t in (xs, xbar, vbar, fbar, gt)])
+        counters = F.fpm_read_counters(sim.ctx)  # rebuilds, longest list, entries
+        out.append([np_(t) for t in (xs, xbar, vbar, fbar, gt)] + [np.array(counters)])
         sim.close()
     assert out[0][0].shape == (K, s.n, 3) and np.isfinite(out[0][1]).all()
+    assert out[0][-1][0] > 2  # the segment rebuilt its lists, forward and in reverse
     for a, b in zip(out[0], out[1]):
         assert np.array_equal(a, b)
 
