@@ -180,7 +180,10 @@ int fpm_set_positions(fpm_ctx *ctx, const float *d_pos);
  * build of the system: z-cells per workgroup of the column build (> 0), or
  * 0 particle by particle over whole cells, -1 particle by particle over
  * candidate windows, -2 lane groups over candidate windows, -3 lane groups
- * over whole cells}. */
+ * over whole cells (a grid of at most two cells per axis in a context built
+ * by lockstep windows: the whole system, in the lockstep launch), -4
+ * lockstep windows, -5 lockstep windows in ascending slot order (symmetric
+ * half lists)}. */
 int fpm_system_info(fpm_ctx *ctx, int32_t s, int64_t h_out[8]);
 /* SPH only: per-particle density (device, caller order, n entries). */
 int fpm_set_density(fpm_ctx *ctx, const float *d_rho);
