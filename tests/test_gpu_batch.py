@@ -83,6 +83,33 @@ def test_batch_matches_oracle_per_system(tuning):
         check_system(sim, k, s, np_(F), out, counts, cols)
 
 
+@pytest.mark.parametrize("tuning", [None, (5, 0, 8)])
+def test_set_positions_rebuilds_exactly_the_system_moved_past_half_the_skin(tuning):
+    """fpm_set_positions decides the rebuild per system, as a drift does: one
+    particle moved by just under half the skin (0.14 against 0.15) leaves
+    every list in place, moved by just over (0.16) it rebuilds its own system
+    only; the forces of every system match the oracle after each move."""
+    from types import SimpleNamespace
+    systems = systems_of([0, 1, 2])
+    sim = make_batch(systems, tuning=tuning)
+    sim.lj_forces()
+    r0 = sim.counters()[0]
+    base = np.concatenate([s.pos for s in systems]).astype(np.float32)
+    for d, extra in ((0.14, 0), (0.16, 1)):
+        p = base.copy()
+        p[sim.offsets[1] + 5, 0] += np.float32(d)
+        sim.set_positions(p)
+        out = np_(sim.lj_forces())
+        F_all = np_(sim.get()[2])
+        assert sim.counters()[0] == r0 + extra, d
+        for k, s in enumerate(systems):
+            a, b = sim.offsets[k], sim.offsets[k + 1]
+            moved = SimpleNamespace(pos=p[a:b], box=s.box)
+            check_system(sim, k, moved, F_all, out, None, None, sets=False)
+    sim.check()
+    sim.close()
+
+
 def test_batch_equals_single_system_runs():
     import torch
     from paper_1804_07598_amd.sim import ParticleSim
