@@ -449,6 +449,23 @@ __device__ __forceinline__ void vjp_pair(VjpAcc &a, float3 pi, double xi, double
     }
 }
 
+// Positions and cotangents of the four neighbours of one list group.
+__device__ __forceinline__ void vjp_gather(const float4 *__restrict__ pos,
+                                           const float4 *__restrict__ lam, int4 e, float4 (&q)[4],
+                                           float4 (&l)[4], const SlotRange &sr) {
+    const int jj[4] = {checked(sr, e.x), checked(sr, e.y), checked(sr, e.z), checked(sr, e.w)};
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        q[u] = pos[jj[u]];
+        l[u] = lam[jj[u]];
+    }
+}
+
+// Walks a list padded to a multiple of eight entries four at a time,
+// software-pipelined as the force walk: the next group's gathers are issued
+// before the current group's pairs (two register sets take turns; a group
+// past the end of the list re-reads one in range, which is harmless).  The
+// pairs are taken in list order, as without the pipeline.
 template <int NT, int IMG>
 __device__ __forceinline__ void vjp_walk(VjpAcc &a, const float4 *__restrict__ pos,
                                          const float4 *__restrict__ lam,
@@ -460,20 +477,21 @@ __device__ __forceinline__ void vjp_walk(VjpAcc &a, const float4 *__restrict__ p
     const double xi = pi.x, yi = pi.y, zi = pi.z;
     const LaneCoef lc = lane_coef<NT>(cf, __float_as_int(pi4.w));
     if (cnt <= 0) return;
-    int4 e = lst[0];  // the next group's entries are requested before this group's gathers
-    for (int k = 0; k < cnt; k += 4) {
-        const int jj[4] = {checked(sr, e.x), checked(sr, e.y), checked(sr, e.z),
-                           checked(sr, e.w)};
-        e = lst[((k + 4 < cnt ? k + 4 : k) >> 2) * 64];
-        float4 q[4], l[4];
-#pragma unroll
-        for (int u = 0; u < 4; u++) {
-            q[u] = pos[jj[u]];
-            l[u] = lam[jj[u]];
-        }
+    float4 q0[4], l0[4], q1[4], l1[4];
+    vjp_gather(pos, lam, lst[0], q0, l0, sr);
+    int4 nxt = lst[(4 < cnt ? 4 : 0) >> 2 << 6];
+    for (int k = 0; k < cnt; k += 8) {
+        vjp_gather(pos, lam, nxt, q1, l1, sr);
+        nxt = lst[((k + 8 < cnt ? k + 8 : k) >> 2) * 64];
 #pragma unroll
         for (int u = 0; u < 4; u++)
-            vjp_pair<NT, IMG>(a, pi, xi, yi, zi, lc, li, q[u], l[u], b, rc2, rc2lo, rc2hi, sd);
+            vjp_pair<NT, IMG>(a, pi, xi, yi, zi, lc, li, q0[u], l0[u], b, rc2, rc2lo, rc2hi, sd);
+        if (k + 4 >= cnt) break;
+        vjp_gather(pos, lam, nxt, q0, l0, sr);
+        nxt = lst[((k + 12 < cnt ? k + 12 : k) >> 2) * 64];
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            vjp_pair<NT, IMG>(a, pi, xi, yi, zi, lc, li, q1[u], l1[u], b, rc2, rc2lo, rc2hi, sd);
     }
 }
 
