@@ -349,7 +349,8 @@ hipError_t sph_step_body(fpm_ctx *c, const fpm_sph_params &p, double *hist, bool
     hipError_t e = p.scheme == 1
                        ? launch_sph_verlet(c, p)
                        : launch_sph_integrate(c, p, first ? kKickDriftFirst : kKickKickDrift);
-    if (e == hipSuccess) e = launch_finalize(c, kFinBuild | kFinDisp, nullptr, nullptr);
+    // the step kernel raised the rebuild flag if needed; the rates kernel
+    // accounts the rebuild and clears the flag
     if (e == hipSuccess) e = refresh_lists(c);
     if (e == hipSuccess) e = launch_sph_rates(c, p);
     if (e == hipSuccess) e = launch_sph_finalize(c, p, 1, nullptr, hist);

@@ -178,7 +178,17 @@ __device__ __forceinline__ void sph_walk(SphAcc &s, const float4 *__restrict__ p
 template <int KER, bool G7>
 __global__ __launch_bounds__(kBlock) void k_sph_rates(State st, float rc2, SphCoef k,
                                                       int cap4) {
-    const SysDesc &d = st.sys[block_system(st)];
+    const int sys = block_system(st);
+    const SysDesc &d = st.sys[sys];
+    if (threadIdx.x == 0 && pblock() == d.blk_base) {
+        // a rebuild that preceded this launch is complete: account it and
+        // clear its flag (nothing in this launch reads the flag)
+        SysCtl *sc = st.sctl + sys;
+        if (sc->rebuild[0]) {
+            sc->n_rebuilds += 1;
+            sc->rebuild[0] = 0;
+        }
+    }
     const Box b = d.box;
     const float4 *__restrict__ pos = st.pos[0];
     const float4 *__restrict__ vel = st.vel[0];
@@ -226,16 +236,27 @@ __global__ __launch_bounds__(kBlock) void k_sph_rates(State st, float rc2, SphCo
 
 // Kick-drift-kick on (v, rho): the closing half kick of the previous step and
 // the opening half kick of this one are fused; boundary particles keep x and v.
+// Both step kernels raise the system's rebuild flag from a wavefront with a
+// particle moved by more than half the skin since the last build (one lane,
+// as the LJ step kernel does; thr: (skin/2)^2); the rates kernel that follows
+// the gated rebuild accounts it and clears the flag.
+__device__ __forceinline__ void raise_rebuild(const State &st, int sys, bool over) {
+    const uint64_t m = __ballot(over);
+    if (m && (int)(threadIdx.x & 63) == __ffsll((long long)m) - 1) st.sctl[sys].rebuild[0] = 1;
+}
+
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_sph_integrate(State st) {
-    const SysDesc &d = st.sys[block_system(st)];
+__global__ __launch_bounds__(kBlock) void k_sph_integrate(State st, float thr) {
+    const int sys = block_system(st);
+    const SysDesc &d = st.sys[sys];
     const Box b = d.box;
     const int64_t i = global_slot();
     const Ctl *ctl = st.ctl;
     const float dt = ctl->sph_dt, dtl = ctl->sph_dt_last;
     const float hk = MODE == kKickDriftFirst ? 0.5f * dt
                                              : (MODE == kKickOnly ? 0.5f * dtl : 0.5f * (dtl + dt));
-    double ke = 0.0, vmax = 0.0, d2 = 0.0;
+    double ke = 0.0, vmax = 0.0;
+    bool over = false;
     if (i - d.slot_base < d.n) {
         float4 v = st.vel[0][i];
         const float4 f = st.frc[i];
@@ -258,12 +279,13 @@ __global__ __launch_bounds__(kBlock) void k_sph_integrate(State st) {
         const double v2 = (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z;
         ke = 0.5 * v2;  // per unit mass; the finalize multiplies by m
         vmax = sqrt(v2);
-        if (MODE != kKickOnly) d2 = dist2_pred(xyz(st.xbuild[i]), xyz(p), b);
+        if (MODE != kKickOnly) over = dist2_pred(xyz(st.xbuild[i]), xyz(p), b) > thr;
     }
-    double v3[3] = {ke, vmax, d2};
-    const int slot[3] = {kSlotKE, kSlotVmax, kSlotDisp};
-    const int op[3] = {0, 1, 1};
-    block_partials<3>(v3, slot, op, st.part, st.pstride);
+    raise_rebuild(st, sys, over);
+    double v2[2] = {ke, vmax};
+    const int slot[2] = {kSlotKE, kSlotVmax};
+    const int op[2] = {0, 1};
+    block_partials<2>(v2, slot, op, st.part, st.pstride);
 }
 
 // One step of the Verlet scheme on (x, v, rho) with rates (a, D) of the
@@ -273,8 +295,9 @@ __global__ __launch_bounds__(kBlock) void k_sph_integrate(State st) {
 // or on every `every`-th step since the state was set (the first one
 // included) the Euler form v' = v + dt a, rho' = rho + dt D.  The state
 // before the step becomes the previous one.  Boundary particles keep x, v.
-__global__ __launch_bounds__(kBlock) void k_sph_verlet(State st, int every) {
-    const SysDesc &d = st.sys[block_system(st)];
+__global__ __launch_bounds__(kBlock) void k_sph_verlet(State st, int every, float thr) {
+    const int sys = block_system(st);
+    const SysDesc &d = st.sys[sys];
     const Box b = d.box;
     const int64_t i = global_slot();
     const Ctl *ctl = st.ctl;
@@ -282,7 +305,8 @@ __global__ __launch_bounds__(kBlock) void k_sph_verlet(State st, int every) {
     const bool euler = ctl->sph_nstep % every == 0;
     const float f2 = euler ? dt : 2.0f * dt;
     const float hdt2 = 0.5f * dt * dt;
-    double ke = 0.0, vmax = 0.0, d2 = 0.0;
+    double ke = 0.0, vmax = 0.0;
+    bool over = false;
     if (i - d.slot_base < d.n) {
         const float4 v = st.vel[0][i];  // (v, rho) now
         const float4 o = st.old[0][i];  // (v, rho) one step before
@@ -306,12 +330,13 @@ __global__ __launch_bounds__(kBlock) void k_sph_verlet(State st, int every) {
         const double v2 = (double)nv.x * nv.x + (double)nv.y * nv.y + (double)nv.z * nv.z;
         ke = 0.5 * v2;  // per unit mass; the finalize multiplies by m
         vmax = sqrt(v2);
-        d2 = dist2_pred(xyz(st.xbuild[i]), xyz(p), b);
+        over = dist2_pred(xyz(st.xbuild[i]), xyz(p), b) > thr;
     }
-    double v3[3] = {ke, vmax, d2};
-    const int slot[3] = {kSlotKE, kSlotVmax, kSlotDisp};
-    const int op[3] = {0, 1, 1};
-    block_partials<3>(v3, slot, op, st.part, st.pstride);
+    raise_rebuild(st, sys, over);
+    double v2[2] = {ke, vmax};
+    const int slot[2] = {kSlotKE, kSlotVmax};
+    const int op[2] = {0, 1};
+    block_partials<2>(v2, slot, op, st.part, st.pstride);
 }
 
 __global__ void k_sph_restart(Ctl *ctl) {
@@ -424,7 +449,7 @@ hipError_t launch_sph_rates(fpm_ctx *c, const fpm_sph_params &p) {
 
 hipError_t launch_sph_verlet(fpm_ctx *c, const fpm_sph_params &p) {
     hipLaunchKernelGGL(k_sph_verlet, dim3(c->nblk), dim3(kBlock), 0, c->stream, c->st,
-                       p.verlet_every);
+                       p.verlet_every, c->disp2_thr);
     return hipGetLastError();
 }
 
@@ -437,11 +462,13 @@ hipError_t launch_sph_integrate(fpm_ctx *c, const fpm_sph_params &p, int mode) {
     (void)p;
     const dim3 g((unsigned)c->nblk), t(kBlock);
     if (mode == kKickDriftFirst)
-        hipLaunchKernelGGL(k_sph_integrate<kKickDriftFirst>, g, t, 0, c->stream, c->st);
+        hipLaunchKernelGGL(k_sph_integrate<kKickDriftFirst>, g, t, 0, c->stream, c->st,
+                           c->disp2_thr);
     else if (mode == kKickKickDrift)
-        hipLaunchKernelGGL(k_sph_integrate<kKickKickDrift>, g, t, 0, c->stream, c->st);
+        hipLaunchKernelGGL(k_sph_integrate<kKickKickDrift>, g, t, 0, c->stream, c->st,
+                           c->disp2_thr);
     else
-        hipLaunchKernelGGL(k_sph_integrate<kKickOnly>, g, t, 0, c->stream, c->st);
+        hipLaunchKernelGGL(k_sph_integrate<kKickOnly>, g, t, 0, c->stream, c->st, c->disp2_thr);
     return hipGetLastError();
 }
 
