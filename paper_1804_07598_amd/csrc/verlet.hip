@@ -929,7 +929,7 @@ __device__ __forceinline__ bool column_of(const Box &b, int ix, int iy, float x,
 // at most eight entries, so a row never holds more than kFlushAt + 7 and the
 // final padding to eight fits as well.
 constexpr int kRowInts = 36;  // ints per lane (16-byte aligned rows)
-constexpr int kFlushAt = 16;
+constexpr int kFlushAt = 24;
 static_assert(kFlushAt + 7 + 4 <= kRowInts, "a lane's row must hold a round and a group read");
 
 // Entries are held as byte offsets into the position buffer (slot * 16, the
