@@ -928,8 +928,8 @@ __device__ __forceinline__ bool column_of(const Box &b, int ix, int iy, float x,
 // and moves the rest, at most three, to the front of its row.  A round adds
 // at most eight entries, so a row never holds more than kFlushAt + 7 and the
 // final padding to eight fits as well.
-constexpr int kRowInts = 36;  // ints per lane (16-byte aligned rows)
-constexpr int kFlushAt = 24;
+constexpr int kRowInts = 40;  // ints per lane (16-byte aligned rows)
+constexpr int kFlushAt = 28;
 static_assert(kFlushAt + 7 + 4 <= kRowInts, "a lane's row must hold a round and a group read");
 
 // Entries are held as byte offsets into the position buffer (slot * 16, the
